@@ -1,0 +1,379 @@
+"""Pins for the FP64 oracle: each test checks it against something other than
+itself - a library routine, a closed form, an exact discrete invariant, an
+independent quadrature, or a known solution of the Boltzmann equation.
+
+Section/equation references are to Haack & Gamba, arXiv:1211.0540.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1211_0540_amd import workloads as W
+
+
+# ----------------------------------------------------------------------------
+# Mesh and quadrature (Sec. 3.1)
+# ----------------------------------------------------------------------------
+def test_mesh_spacing_and_duality():
+    for N, L in [(8, 4.0), (16, 6.0), (24, 7.0), (32, 8.0)]:
+        v, z, dv, dz = O.grid(N, L)
+        assert dv == pytest.approx(2 * L / N, rel=1e-15)
+        assert dz == pytest.approx(np.pi / L, rel=1e-15)
+        assert dv * dz == pytest.approx(2 * np.pi / N, rel=1e-15)
+        assert v[N // 2] == 0.0 and z[N // 2] == 0.0
+        assert v[0] == pytest.approx(-L) and v[-1] == pytest.approx(L - dv)
+
+
+def test_gauss_legendre_matches_numpy():
+    for n in (5, 64, 400):
+        x, w = O.gauss_legendre(n)
+        xr, wr = np.polynomial.legendre.leggauss(n)
+        assert np.max(np.abs(x - xr)) < 1e-13
+        assert np.max(np.abs(w - wr)) < 1e-13
+
+
+# ----------------------------------------------------------------------------
+# Transform pair (Sec. 2.2 / 3.2)
+# ----------------------------------------------------------------------------
+def _numpy_transform(f, L):
+    """(2pi)^{-3/2} dv^3 sum_j f_j exp(-2 pi i (k-N/2)(j-N/2)/N): a centred FFT."""
+    N = f.shape[0]
+    dv = 2 * L / N
+    return (2 * np.pi) ** -1.5 * dv ** 3 * np.fft.fftshift(np.fft.fftn(np.fft.ifftshift(f)))
+
+
+@pytest.mark.parametrize("N,L", [(8, 4.0), (12, 5.0), (16, 6.0), (24, 7.0)])
+def test_forward_transform_is_centred_fft(N, L):
+    rng = np.random.default_rng(N)
+    f = rng.standard_normal((N, N, N))
+    fh = O.dft_forward(f, L)
+    ref = _numpy_transform(f, L)
+    assert np.max(np.abs(fh - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("N,L", [(8, 4.0), (16, 6.0)])
+def test_inverse_roundtrip_and_parseval(N, L):
+    rng = np.random.default_rng(7 + N)
+    f = rng.standard_normal((N, N, N))
+    fh = O.dft_forward(f, L)
+    back, mi = O.dft_inverse(fh, L)
+    assert np.max(np.abs(back - f)) < 1e-12
+    assert mi < 1e-12  # a real input comes back real
+    _, _, dv, dz = O.grid(N, L)
+    assert (np.abs(f) ** 2).sum() * dv ** 3 == pytest.approx((np.abs(fh) ** 2).sum() * dz ** 3, rel=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# Convolution weights, eq. (GHat_calc): quadrature vs closed form
+# ----------------------------------------------------------------------------
+def _I2(a, b, L, lam):
+    """int_0^L r^{lam+2} sinc(a r) sinc(b r) dr in closed form (lam = 0, 1)."""
+    def c0(w):      # int_0^L cos(w r) dr
+        return L if abs(w) < 1e-9 else np.sin(w * L) / w
+
+    def c1(w):      # int_0^L r cos(w r) dr, with cos x - 1 = -2 sin^2(x/2) to avoid cancellation
+        return L * L / 2 if abs(w) < 1e-9 else L * np.sin(w * L) / w - 2 * np.sin(w * L / 2) ** 2 / w ** 2
+
+    if a == 0 and b == 0:
+        return L ** (lam + 3) / (lam + 3)
+    if a == 0 or b == 0:
+        c = a + b
+        if lam == 0:
+            return (np.sin(c * L) - c * L * np.cos(c * L)) / c ** 3
+        return (-L * L * np.cos(c * L) / c + 2 * L * np.sin(c * L) / c ** 2
+                + 2 * (np.cos(c * L) - 1) / c ** 3) / c
+    cf = c0 if lam == 0 else c1
+    return (cf(a - b) - cf(a + b)) / (2 * a * b)
+
+
+@pytest.mark.parametrize("lam", [0.0, 1.0])
+@pytest.mark.parametrize("N,L", [(16, 6.0), (32, 8.0)])
+def test_ghat_quadrature_matches_closed_form(N, L, lam):
+    o = O.Oracle(N, L, lam)
+    _, z, _, _ = O.grid(N, L)
+    rng = np.random.default_rng(int(N + 10 * lam))
+    c = 4 * np.pi / (2 * np.pi) ** 1.5
+    worst = 0.0
+    for _ in range(300):
+        k = rng.integers(0, N, 3)
+        # a valid pair: the partner index k - m + N/2 stays on the mesh
+        m = np.array([rng.integers(max(0, kd - N // 2 + 1), min(N - 1, kd + N // 2) + 1) for kd in k])
+        zeta, xi = z[k], z[m]
+        ref = c * (_I2(np.linalg.norm(zeta) / 2, np.linalg.norm(xi - zeta / 2), L, int(lam))
+                   - _I2(np.linalg.norm(xi), 0.0, L, int(lam)))
+        worst = max(worst, abs(o.ghat_idx(k, m) - ref))
+    assert worst < 1e-11 * L ** (lam + 3)
+
+
+def test_ghat_vanishes_at_zero_frequency_and_is_even():
+    N, L = 16, 6.0
+    _, z, _, _ = O.grid(N, L)
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        xi = z[rng.integers(1, N, 3)]
+        zeta = z[rng.integers(1, N, 3)]
+        for lam in (0.0, 1.0):
+            assert abs(O.ghat(xi, np.zeros(3), lam, L)) < 1e-13
+            assert O.ghat(-xi, -zeta, lam, L) == pytest.approx(O.ghat(xi, zeta, lam, L), abs=1e-13)
+            p = rng.permutation(3)
+            assert O.ghat(xi[p], zeta[p], lam, L) == pytest.approx(O.ghat(xi, zeta, lam, L), abs=1e-13)
+
+
+# ----------------------------------------------------------------------------
+# Weighted convolution (Sec. 3.2): exact discrete invariants
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("N", [8, 12, 16])
+def test_pair_count(N):
+    o = O.Oracle(N, 5.0, 1.0)
+    _, pairs = o.collide_hat(np.ones((N, N, N), complex))
+    assert pairs == (3 * N * N // 4) ** 3
+
+
+@pytest.mark.parametrize("lam", [0.0, 1.0])
+def test_qhat_zero_frequency_and_mass(lam):
+    N, L = 16, 6.0
+    f = W.single_cell_mixture(N, L)
+    o = O.Oracle(N, L, lam)
+    qh, _ = o.collide_hat(O.dft_forward(f, L))
+    assert qh[N // 2, N // 2, N // 2] == 0
+    qt, _ = O.dft_inverse(qh, L)
+    assert abs(qt.sum()) * (2 * L / N) ** 3 < 1e-15
+
+
+def _smooth_random(N, L, seed):
+    return W.random_smooth_cells(1, N, L, seed=seed, umax=0.5)[0]
+
+
+def test_axis_permutation_equivariance():
+    N, L = 12, 5.0
+    f = _smooth_random(N, L, 11)
+    o = O.Oracle(N, L, 1.0)
+    _, q, _, _ = o.collide(f)
+    for p in itertools.permutations(range(3)):
+        _, qp, _, _ = o.collide(np.transpose(f, p))
+        assert np.max(np.abs(qp - np.transpose(q, p))) < 1e-13 * np.max(np.abs(q))
+
+
+def test_cyclic_shift_equivariance():
+    """If f vanishes on the planes that wrap, rolling f rolls Qt (phases factor out)."""
+    N, L = 12, 5.0
+    f = _smooth_random(N, L, 12)
+    f[-2:, :, :] = 0.0
+    f[:, 0, :] = 0.0
+    o = O.Oracle(N, L, 1.0)
+    qt, _, _, _ = o.collide(f)
+    qt2, _, _, _ = o.collide(np.roll(np.roll(f, 2, axis=0), -1, axis=1))
+    assert np.max(np.abs(qt2 - np.roll(np.roll(qt, 2, axis=0), -1, axis=1))) < 1e-13 * np.max(np.abs(qt))
+
+
+def test_bilinearity():
+    N, L = 12, 5.0
+    f = _smooth_random(N, L, 13)
+    o = O.Oracle(N, L, 1.0)
+    qt, _, _, _ = o.collide(f)
+    qt3, _, _, _ = o.collide(3.0 * f)
+    assert np.max(np.abs(qt3 - 9.0 * qt)) < 1e-12 * np.max(np.abs(qt3))
+
+
+def test_reflection_symmetry_is_discretisation_level():
+    """v1 -> -v1 is exact only away from the -N/2 plane; the defect shrinks with N."""
+    errs = []
+    for N in (12, 16):
+        L = 6.0
+        f = W.single_cell_mixture(N, L) * (1 + 0.1 * W.velocity_mesh(N, L)[:, None, None])
+        o = O.Oracle(N, L, 1.0)
+        _, q, _, _ = o.collide(f)
+        fr = np.zeros_like(f)
+        fr[1:] = f[1:][::-1]
+        fr[0] = f[0]
+        _, qr, _, _ = o.collide(fr)
+        qrr = np.zeros_like(q)
+        qrr[1:] = qr[1:][::-1]
+        qrr[0] = qr[0]
+        errs.append(np.linalg.norm((qrr - q)[1:]) / np.linalg.norm(q))
+    assert errs[0] < 2e-2 and errs[1] < errs[0]
+
+
+# ----------------------------------------------------------------------------
+# Equilibria and closed-form solutions
+# ----------------------------------------------------------------------------
+def test_maxwellian_is_discrete_equilibrium():
+    res = []
+    for N in (16, 24):
+        L = 6.0
+        o = O.Oracle(N, L, 1.0)
+        _, qm, _, _ = o.collide(W.maxwellian(N, L, 1.0, (0, 0, 0), 1.0))
+        _, qf, _, _ = o.collide(W.single_cell_mixture(N, L))
+        res.append(np.linalg.norm(qm) / np.linalg.norm(qf))
+    assert res[0] < 2e-3 and res[1] < 0.5 * res[0]
+
+
+def test_drifting_maxwellian_is_discrete_equilibrium():
+    N, L = 16, 6.0
+    o = O.Oracle(N, L, 1.0)
+    _, qd, _, _ = o.collide(W.maxwellian(N, L, 1.0, (0.7, -0.3, 0.2), 1.0))
+    _, qf, _, _ = o.collide(W.single_cell_mixture(N, L))
+    assert np.linalg.norm(qd) / np.linalg.norm(qf) < 2e-3
+
+
+@pytest.mark.parametrize("N,L,tol", [(16, 6.0, 1.2e-2), (24, 6.0, 4e-4)])
+def test_bkw_exact_solution(N, L, tol):
+    """Maxwell molecules: Q(f_BKW) = d f_BKW / dt, K(t) = 1 - exp(-t/6)."""
+    t0 = 5.5
+    o = O.Oracle(N, L, 0.0)
+    _, q, _, _ = o.collide(W.bkw_state(N, L, t0))
+    h = 1e-4
+    exact = (W.bkw_state(N, L, t0 + h) - W.bkw_state(N, L, t0 - h)) / (2 * h)
+    assert np.linalg.norm(q - exact) / np.linalg.norm(exact) < tol
+
+
+def test_maxwell_molecule_temperature_relaxation_rate():
+    """d(rho T_x)/dt = -(rho^2/2)(T_x - T) for Maxwell molecules with isotropic b."""
+    N, L = 24, 8.0
+    f = W.relaxation_cell(N, L)
+    o = O.Oracle(N, L, 0.0)
+    _, q, _, _ = o.collide(f)
+    v, _, dv, _ = O.grid(N, L)
+    rho, u, T, Td = O.moments(f, L)
+    rate = (v[:, None, None] ** 2 * q).sum() * dv ** 3
+    assert rate == pytest.approx(-0.5 * rho * rho * (Td[0] - T), rel=4e-3)
+
+
+def test_heun_rk2_is_second_order_in_time():
+    """BKW in time (Maxwell molecules): halving dt cuts the RK2 error about 4x."""
+    N, L, t0, T = 16, 6.0, 5.5, 0.6
+    o = O.Oracle(N, L, 0.0)
+    f0 = W.bkw_state(N, L, t0)
+    sols = [o.rk2(f0, T / n, 1.0, n) for n in (2, 4, 8)]
+    e1 = np.linalg.norm(sols[0] - sols[2])
+    e2 = np.linalg.norm(sols[1] - sols[2])
+    assert 3.0 < (e1 / e2 - 1.0) * 1.0 + 1.0 < 6.5   # Richardson ratio (4 + 1) / 1 ~ 5
+
+
+# ----------------------------------------------------------------------------
+# Conservation projection (Sec. 3.3)
+# ----------------------------------------------------------------------------
+def _constraints(N, L):
+    v, _, dv, _ = O.grid(N, L)
+    V = np.meshgrid(v, v, v, indexing="ij")
+    rows = [np.ones_like(V[0]), V[0], V[1], V[2], V[0] ** 2 + V[1] ** 2 + V[2] ** 2]
+    return np.stack([r.ravel() * dv ** 3 for r in rows])
+
+
+@pytest.mark.parametrize("N,L", [(8, 4.0), (16, 6.0)])
+def test_projection_is_the_constrained_minimiser(N, L):
+    rng = np.random.default_rng(N)
+    qt = rng.standard_normal((N, N, N))
+    q = O.project(qt, L)
+    C = _constraints(N, L)
+    # constraints hold to the per-invariant relative bound
+    for a in range(5):
+        assert abs(C[a] @ q.ravel()) <= 1e-12 * (np.abs(C[a]) @ np.abs(q.ravel()))
+    # idempotent, and the identity on the constraint null space
+    assert np.max(np.abs(O.project(q, L) - q)) < 1e-12 * np.max(np.abs(q))
+    # Qt - Q lies in range(C^T)
+    d = (qt - q).ravel()
+    coef, *_ = np.linalg.lstsq(C.T, d, rcond=None)
+    assert np.linalg.norm(C.T @ coef - d) < 1e-10 * np.linalg.norm(d)
+    if N == 8:
+        # KKT system [I C^T; C 0][Q; lam] = [Qt; 0] solved by numpy
+        M = C.shape[1]
+        K = np.block([[np.eye(M), C.T], [C, np.zeros((5, 5))]])
+        sol = np.linalg.lstsq(K, np.concatenate([qt.ravel(), np.zeros(5)]), rcond=None)[0]
+        assert np.max(np.abs(sol[:M] - q.ravel())) < 1e-11
+
+
+def test_projected_collision_conserves_invariants():
+    N, L = 16, 6.0
+    o = O.Oracle(N, L, 1.0)
+    _, q, _, _ = o.collide(W.single_cell_mixture(N, L))
+    C = _constraints(N, L)
+    for a in range(5):
+        assert abs(C[a] @ q.ravel()) <= 1e-12 * (np.abs(C[a]) @ np.abs(q.ravel()))
+
+
+# ----------------------------------------------------------------------------
+# Independent discretisation: weak form (eq. collision_weakform) in velocity space
+# ----------------------------------------------------------------------------
+def _weak_form_bruteforce(f, L, lam, zetas):
+    """Qhat(zeta) = (2pi)^{-3/2} dv^6 sum_{v, v*} f f* |u|^lam 1{|u| <= L}
+    [exp(-i zeta.(v+v*)/2) sinc(|zeta||u|/2) - exp(-i zeta.v)]  (b = 1/4pi, r0 = L)."""
+    N = f.shape[0]
+    v = W.velocity_mesh(N, L)
+    dv = 2 * L / N
+    V = np.stack(np.meshgrid(v, v, v, indexing="ij"), -1).reshape(-1, 3)
+    F = f.reshape(-1)
+    keep = F > 1e-14 * F.max()
+    V, F = V[keep], F[keep]
+    U = V[:, None, :] - V[None, :, :]
+    ua = np.linalg.norm(U, axis=-1)
+    Vc = 0.5 * (V[:, None, :] + V[None, :, :])
+    FF = F[:, None] * F[None, :] * ua ** lam * (ua <= L)
+    out = []
+    for z in zetas:
+        s = np.sinc(np.linalg.norm(z) * ua / (2 * np.pi))
+        g = np.exp(-1j * (Vc @ z)) * s - np.exp(-1j * (V @ z))[:, None]
+        out.append((2 * np.pi) ** -1.5 * dv ** 6 * (FF * g).sum())
+    return np.array(out)
+
+
+@pytest.mark.parametrize("lam,tol8,tol12", [(0.0, 0.2, 0.02), (1.0, 0.5, 0.25)])
+def test_weak_form_bruteforce_agreement_improves_with_N(lam, tol8, tol12):
+    L = 4.0
+    rng = np.random.default_rng(5)
+    errs = []
+    for N in (8, 12):
+        f = 0.5 * W.maxwellian(N, L, 1, (0.6, 0, 0), 0.4) + 0.5 * W.maxwellian(N, L, 1, (-0.6, 0, 0), 0.4)
+        o = O.Oracle(N, L, lam)
+        qh, _ = o.collide_hat(O.dft_forward(f, L))
+        _, z, _, _ = O.grid(N, L)
+        allk = np.array(list(itertools.product(range(N), repeat=3)))
+        ks = allk[rng.choice(len(allk), 16, replace=False)]
+        bf = _weak_form_bruteforce(f, L, lam, z[ks])
+        sp = np.array([qh[tuple(k)] for k in ks])
+        errs.append(np.linalg.norm(sp - bf) / np.linalg.norm(bf))
+    assert errs[0] < tol8 and errs[1] < tol12 and errs[1] < 0.6 * errs[0]
+
+
+# ----------------------------------------------------------------------------
+# Pin strength: each planted mistake in the oracle is caught by a pin above
+# ----------------------------------------------------------------------------
+def _pins_pass():
+    N, L = 16, 6.0
+    ok = []
+    # BKW (Maxwell molecules)
+    o = O.Oracle(N, L, 0.0)
+    _, q, _, _ = o.collide(W.bkw_state(N, L, 5.5))
+    h = 1e-4
+    ex = (W.bkw_state(N, L, 5.5 + h) - W.bkw_state(N, L, 5.5 - h)) / (2 * h)
+    ok.append(np.linalg.norm(q - ex) / np.linalg.norm(ex) < 1.2e-2)
+    # Maxwellian equilibrium
+    oh = O.Oracle(N, L, 1.0)
+    _, qm, _, _ = oh.collide(W.maxwellian(N, L, 1.0, (0, 0, 0), 1.0))
+    _, qf, _, _ = oh.collide(W.single_cell_mixture(N, L))
+    ok.append(np.linalg.norm(qm) / np.linalg.norm(qf) < 2e-3)
+    # a drifting Maxwellian is an equilibrium too
+    _, qd, _, _ = oh.collide(W.maxwellian(N, L, 1.0, (0.7, -0.3, 0.2), 1.0))
+    ok.append(np.linalg.norm(qd) / np.linalg.norm(qf) < 2e-3)
+    # conservation after projection
+    C = _constraints(N, L)
+    ok.append(all(abs(C[a] @ qf.ravel()) <= 1e-12 * (np.abs(C[a]) @ np.abs(qf.ravel())) for a in range(5)))
+    # transform vs library
+    f = W.single_cell_mixture(N, L)
+    ok.append(np.max(np.abs(O.dft_forward(f, L) - _numpy_transform(f, L))) < 1e-13)
+    return all(ok)
+
+
+def test_pins_pass_unmutated():
+    assert _pins_pass()
+
+
+@pytest.mark.parametrize("mutation", [1, 2, 3, 4, 5, 6])
+def test_planted_mistake_is_caught(mutation):
+    O.set_mutation(mutation)
+    try:
+        assert not _pins_pass()
+    finally:
+        O.set_mutation(0)
