@@ -1,0 +1,173 @@
+/*
+ * bz.h - C ABI of the MI355X (gfx950) conservative spectral collision library.
+ *
+ * The library computes, for every spatial cell of a batch, the collision
+ * operator of the conservative spectral method of Gamba and Tharkabhushanam
+ * as extended by Haack & Gamba (arXiv:1211.0540):
+ *
+ *   fhat   = F[f]                        Fourier transform on the mesh (Sec. 2.2, 3.2)
+ *   Qhat_k = sum_m Ghat(xi_m, zeta_k) fhat_m fhat_{k-m+N/2} dzeta^3
+ *                                         trapezoid-rule weighted convolution (Sec. 3.2)
+ *   Qt     = Re F^{-1}[Qhat]              inverse transform (Sec. 3.2)
+ *   Q      = Qt - C^T (C C^T)^{-1} C Qt   conservation projection (Sec. 3.3)
+ *
+ * with the weights Ghat of eq. (GHat_calc) (isotropic scattering, b = 1/4pi,
+ * elastic collisions beta = 1, radial cut-off r0 = L).
+ *
+ * Conventions for every entry point:
+ *   - Mesh (Sec. 3.1): N even, 8 <= N <= 32, half-width L > 0;
+ *     v_k = (2L/N)(k - N/2), zeta_k = (pi/L)(k - N/2), k = 0..N-1.
+ *   - A cell is N^3 FP64 values, C-contiguous, flat index (k1*N + k2)*N + k3;
+ *     axis 1 is the transport direction v1.  The cells of a batch are stored
+ *     back to back in the order given at batch creation.
+ *   - Pointers named d_* are device pointers (HIP device memory, 256-byte
+ *     aligned is sufficient); everything else is host memory.
+ *   - The caller owns every device buffer (distribution functions, results,
+ *     weights, workspace).  The library owns only its opaque handles and a
+ *     few kilobytes of device index tables per batch, released by *_free.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default
+ *     stream.  Calls enqueue work and return without synchronising unless
+ *     stated otherwise.
+ *   - Arguments are validated on the host before anything is enqueued: a
+ *     call that returns an error has no side effect.  No C++ exception
+ *     crosses this interface.  bz_last_error() returns a thread-local message
+ *     for the last failing call of the calling thread.
+ */
+#ifndef BZ_H
+#define BZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BZ_API_VERSION 1
+
+typedef enum {
+    BZ_OK = 0,
+    BZ_EINVAL = -1,        /* invalid argument (message in bz_last_error) */
+    BZ_EUNSUPPORTED = -2,  /* valid request this build does not implement */
+    BZ_EDEVICE = -3,       /* a HIP runtime call failed */
+    BZ_ENOMEM = -4,        /* host or device allocation failed */
+    BZ_ENONFINITE = -5,    /* a non-finite value was produced */
+    BZ_ESTATE = -6         /* call out of order (e.g. weights not bound) */
+} bz_status;
+
+/* Weight buffer kinds: arithmetic type and the schedule the buffer is laid out for. */
+enum {
+    BZ_W_BATCHED_F32 = 1,  /* symmetric pair weights, wave-uniform order, FP32 */
+    BZ_W_BATCHED_F64 = 2,  /* same, FP64 */
+    BZ_W_PLAIN_F32 = 3,    /* per-output weights, one cell at a time, FP32 */
+    BZ_W_PLAIN_F64 = 4     /* same, FP64 */
+};
+
+/* Collision modes. */
+enum {
+    BZ_MODE_PLAIN_F64 = 1,    /* FP64, one cell per launch: the plain baseline */
+    BZ_MODE_BATCHED_F32 = 2,  /* FP32 products with compensated accumulation,
+                                 all cells of a mesh in one persistent launch */
+    BZ_MODE_BATCHED_F64 = 3,  /* FP64, all cells of a mesh in one launch */
+    BZ_MODE_PLAIN_F32 = 4     /* FP32 + compensated accumulation, one cell per launch */
+};
+
+/* ------------------------------------------------------------------ */
+/* Mesh (Sec. 3.1 eq. meshpoints; Sec. 3.3 constraint matrix C)         */
+/* ------------------------------------------------------------------ */
+typedef struct bz_grid_s *bz_grid;
+
+typedef struct {
+    int N;               /* points per axis */
+    double L;            /* half-width of the velocity cube [-L, L)^3 */
+    double lambda;       /* exponent of |u| in B = |u|^lambda b (0: Maxwell molecules, 1: hard spheres) */
+    double dv;           /* 2L/N */
+    double dzeta;        /* pi/L */
+    long long pairs;     /* valid (zeta_k, xi_m) pairs of the convolution: (3N^2/4)^3 */
+} bz_grid_info;
+
+/* Create a mesh handle.  Host only, no device work.  Errors: BZ_EINVAL for
+ * odd N, N outside [8, 32], L <= 0 or non-finite; BZ_EUNSUPPORTED for lambda
+ * outside [0, 1] (integer lambda uses the closed form of eq. GHat_calc, other
+ * values a 64-point Gauss-Legendre rule). */
+bz_status bz_grid_init(int N, double L, double lambda, bz_grid *out);
+void bz_grid_free(bz_grid g);
+bz_status bz_grid_query(bz_grid g, bz_grid_info *info);
+/* Host copies of the 1-D velocity and frequency nodes (N doubles each, either may be NULL). */
+bz_status bz_grid_coords(bz_grid g, double *v, double *zeta);
+
+/* ------------------------------------------------------------------ */
+/* Convolution weights (Sec. 2.2 eq. GHat_calc; "precomputed once and    */
+/* stored", Sec. 2.2).  The weights of a mesh factor through the integer */
+/* norms na = |k - N/2|^2, nb = |2m - k - N/2|^2, nc = |m - N/2|^2 as     */
+/*   Ghat = 4pi (2pi)^{-3/2} L^{lambda+3} [T(na, nb) - T(0, 4 nc)],       */
+/*   T(p, q) = int_0^1 s^{lambda+2} sinc(pi s sqrt(p)/2) sinc(pi s sqrt(q)/2) ds, */
+/* and are expanded into the caller's buffer in the order the chosen      */
+/* schedule reads them (dzeta^3 folded in).                               */
+/* ------------------------------------------------------------------ */
+/* Bytes needed for a weight buffer of the given kind (0 for an unknown kind). */
+size_t bz_weights_bytes(bz_grid g, int kind);
+/* Fill d_w (bytes >= bz_weights_bytes) on `stream`.  Synchronises the stream
+ * before returning (it uploads a host-built table).  Errors: BZ_EINVAL for a
+ * bad kind, NULL pointer or short buffer; BZ_EDEVICE / BZ_ENOMEM from HIP. */
+bz_status bz_weights(bz_grid g, int kind, void *d_w, size_t bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Batches: a fixed list of cells, each on one of a few meshes.          */
+/* ------------------------------------------------------------------ */
+typedef struct bz_batch_s *bz_batch;
+
+/* grid_of_cell[c] (host, n_cells entries) indexes grids[] (host, n_grids
+ * handles that must outlive the batch).  `mode` is one of BZ_MODE_*.  The
+ * batch groups the cells of each mesh 64 to a wavefront (batched modes),
+ * orders the work longest-first and uploads its index tables (synchronous).
+ * Errors: BZ_EINVAL for n_cells < 1, a bad index or mode. */
+bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids, const bz_grid *grids,
+                          int mode, bz_batch *out);
+void bz_batch_free(bz_batch b);
+/* Bind the weight buffer of grids[grid_index] (built by bz_weights with the
+ * kind the mode reads: BZ_W_BATCHED_* for batched modes, BZ_W_PLAIN_* for
+ * plain modes).  `kind` must match the buffer.  The buffer must outlive the
+ * batch's use. */
+bz_status bz_batch_set_weights(bz_batch b, int grid_index, int kind, const void *d_w);
+/* Number of doubles of a batch's f (sum of N_c^3), and the offset (in
+ * doubles) of cell c's data. */
+size_t bz_batch_elems(bz_batch b);
+size_t bz_batch_cell_offset(bz_batch b, int cell);
+/* Workspace bytes bz_collide_batch / bz_step need for this batch. */
+size_t bz_workspace_bytes(bz_batch b);
+
+/* Qt = Re F^{-1}[ weighted convolution of F[f] ] for every cell (Sec. 3.2),
+ * unprojected.  d_f and d_Qt hold bz_batch_elems doubles; they may not alias.
+ * d_work holds work_bytes >= bz_workspace_bytes.  Errors: BZ_ESTATE when a
+ * mesh of the batch has no weights bound, BZ_EINVAL for NULL pointers or a
+ * short workspace. */
+bz_status bz_collide_batch(bz_batch b, const double *d_f, double *d_Qt, void *d_work, size_t work_bytes,
+                           void *stream);
+
+/* In place, per cell: Q <- Q - C^T (C C^T)^{-1} C Q (Sec. 3.3; the sign and
+ * transposition are those of the Lagrange solution of the stated problem).
+ * FP64 throughout; the moments are reduced twice (one refinement pass). */
+bz_status bz_project(bz_batch b, double *d_Q, void *stream);
+
+/* One Heun (second-order Runge-Kutta, Sec. 3.1) step of the space-
+ * homogeneous equation df/dt = Q(f,f)/eps for every cell, in place:
+ *   f* = f + h P Q(f),  f <- (f + f* + h P Q(f*)) / 2,  h = dt/eps,
+ * with P the projection.  d_work as for bz_collide_batch plus 2 batch
+ * arrays (bz_step_workspace_bytes).  If any produced value is non-finite
+ * the step still completes and bz_step_check later reports BZ_ENONFINITE. */
+size_t bz_step_workspace_bytes(bz_batch b);
+bz_status bz_step(bz_batch b, double *d_f, double dt_over_eps, void *d_work, size_t work_bytes, void *stream);
+/* Synchronises `stream` and returns BZ_ENONFINITE if any bz_step enqueued
+ * with this workspace since the last check produced a non-finite value
+ * (then clears the flag), BZ_OK otherwise. */
+bz_status bz_step_check(bz_batch b, void *d_work, void *stream);
+
+const char *bz_status_string(bz_status s);
+const char *bz_last_error(void);
+int bz_api_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BZ_H */

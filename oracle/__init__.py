@@ -62,6 +62,7 @@ def _load():
                                         ctypes.c_double, ctypes.c_int]
     lib.bzo_num_threads.restype = ctypes.c_int
     lib.bzo_set_mutation.argtypes = [ctypes.c_int]
+    lib.bzo_collide_hat_abs.argtypes = [ctypes.c_void_p, _dp, _dp]
     _lib = lib
     return lib
 
@@ -168,6 +169,14 @@ class Oracle:
         _load().bzo_collide_hat(self._h, fhat.ctypes.data_as(_dp), out.ctypes.data_as(_dp),
                                 ctypes.byref(pairs))
         return out, int(pairs.value)
+
+    def kappa(self, f) -> float:
+        """Cancellation factor ||sum_m |G fhat_m fhat_j| || / ||Qhat|| of the convolution of f."""
+        fh = dft_forward(f, self.L)
+        qh, _ = self.collide_hat(fh)
+        a = np.zeros(fh.shape)
+        _load().bzo_collide_hat_abs(self._h, fh.ctypes.data_as(_dp), _p(a))
+        return float(np.linalg.norm(a) / max(np.linalg.norm(qh), 1e-300))
 
     def collide(self, f):
         """f -> (Qt unprojected, Q projected, max |Im| of the inverse transform, pairs)."""

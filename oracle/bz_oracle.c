@@ -416,6 +416,46 @@ int bzo_collide_hat(const bzo_ctx *c, const double *fhat, double *qhat, long lon
     return 0;
 }
 
+/* Diagnostic for floating-point tolerances: out[k] = dzeta^3 sum_m |Ghat| |fhat_m| |fhat_j|,
+ * the sum of the magnitudes of the terms of the convolution at zeta_k.  The ratio of its
+ * norm to the norm of Qhat measures how much the terms cancel. */
+int bzo_collide_hat_abs(const bzo_ctx *c, const double *fhat, double *out)
+{
+    int N = c->N, h = N / 2;
+    size_t M = (size_t)N * N * N;
+    double dz = BZO_PI / c->L;
+    double w = dz * dz * dz;
+    double c0 = 4.0 * BZO_PI / pow(2.0 * BZO_PI, 1.5);
+    int nbs = c->cache.nb_max + 1;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long kk = 0; kk < (long)M; ++kk) {
+        int k1 = (int)(kk / (N * N)), k2 = (int)((kk / N) % N), k3 = (int)(kk % N);
+        long na = (long)(k1 - h) * (k1 - h) + (long)(k2 - h) * (k2 - h) + (long)(k3 - h) * (k3 - h);
+        const double *grow = c->cache.gain + (size_t)na * nbs;
+        double s = 0.0;
+        for (int m1 = 0; m1 < N; ++m1) {
+            int j1 = k1 - m1 + h;
+            if (j1 < 0 || j1 >= N) continue;
+            for (int m2 = 0; m2 < N; ++m2) {
+                int j2 = k2 - m2 + h;
+                if (j2 < 0 || j2 >= N) continue;
+                for (int m3 = 0; m3 < N; ++m3) {
+                    int j3 = k3 - m3 + h;
+                    if (j3 < 0 || j3 >= N) continue;
+                    long b1 = 2 * m1 - k1 - h, b2 = 2 * m2 - k2 - h, b3 = 2 * m3 - k3 - h;
+                    long e1 = m1 - h, e2 = m2 - h, e3 = m3 - h;
+                    double G = c0 * (grow[b1 * b1 + b2 * b2 + b3 * b3] - c->cache.loss[e1 * e1 + e2 * e2 + e3 * e3]);
+                    size_t im_ = ((size_t)m1 * N + m2) * N + m3;
+                    size_t ij_ = ((size_t)j1 * N + j2) * N + j3;
+                    s += fabs(G) * hypot(fhat[2 * im_], fhat[2 * im_ + 1]) * hypot(fhat[2 * ij_], fhat[2 * ij_ + 1]);
+                }
+            }
+        }
+        out[kk] = w * s;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* Conservation, Sec. 3.3.  C (5 x M) has rows w_j, v^i_j w_j, |v_j|^2 w_j */
 /* with w_j = dv^3.  The minimiser of |Qt - Q|^2 / 2 subject to CQ = 0 is   */

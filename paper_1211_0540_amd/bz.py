@@ -1,0 +1,281 @@
+"""Thin ctypes binding of libbz (include/bz.h), same names as the C entry points.
+
+Only argument marshalling lives here: every step of the collision operator
+runs in the library's HIP kernels.  Device buffers are torch CUDA tensors
+(HIP on ROCm); streams are torch streams.  If libbz.so is missing the import
+of this module fails loudly - there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libbz.so")
+
+BZ_OK, BZ_EINVAL, BZ_EUNSUPPORTED, BZ_EDEVICE, BZ_ENOMEM, BZ_ENONFINITE, BZ_ESTATE = 0, -1, -2, -3, -4, -5, -6
+BZ_W_BATCHED_F32, BZ_W_BATCHED_F64, BZ_W_PLAIN_F32, BZ_W_PLAIN_F64 = 1, 2, 3, 4
+BZ_MODE_PLAIN_F64, BZ_MODE_BATCHED_F32, BZ_MODE_BATCHED_F64, BZ_MODE_PLAIN_F32 = 1, 2, 3, 4
+
+MODE_WEIGHTS = {BZ_MODE_PLAIN_F64: BZ_W_PLAIN_F64, BZ_MODE_BATCHED_F32: BZ_W_BATCHED_F32,
+                BZ_MODE_BATCHED_F64: BZ_W_BATCHED_F64, BZ_MODE_PLAIN_F32: BZ_W_PLAIN_F32}
+MODE_NAMES = {"plain_f64": BZ_MODE_PLAIN_F64, "batched_f32": BZ_MODE_BATCHED_F32,
+              "batched_f64": BZ_MODE_BATCHED_F64, "plain_f32": BZ_MODE_PLAIN_F32}
+
+
+class BzError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"bz status {status}: {msg}")
+        self.status = status
+
+
+class GridInfo(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("L", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("dv", ctypes.c_double), ("dzeta", ctypes.c_double), ("pairs", ctypes.c_longlong)]
+
+
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+_lib = None
+
+
+def lib():
+    """Load libbz.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise ImportError(f"{LIBPATH} is missing: build it with paper_1211_0540_amd/build.py")
+    L = ctypes.CDLL(LIBPATH)
+    sig = {
+        "bz_api_version": (ctypes.c_int, []),
+        "bz_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "bz_last_error": (ctypes.c_char_p, []),
+        "bz_grid_init": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.POINTER(_vp)]),
+        "bz_grid_free": (None, [_vp]),
+        "bz_grid_query": (ctypes.c_int, [_vp, ctypes.POINTER(GridInfo)]),
+        "bz_grid_coords": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+        "bz_weights_bytes": (_sz, [_vp, ctypes.c_int]),
+        "bz_weights": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _sz, _vp]),
+        "bz_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
+                                           ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp)]),
+        "bz_batch_free": (None, [_vp]),
+        "bz_batch_set_weights": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp]),
+        "bz_batch_elems": (_sz, [_vp]),
+        "bz_batch_cell_offset": (_sz, [_vp, ctypes.c_int]),
+        "bz_workspace_bytes": (_sz, [_vp]),
+        "bz_collide_batch": (ctypes.c_int, [_vp, _vp, _vp, _vp, _sz, _vp]),
+        "bz_project": (ctypes.c_int, [_vp, _vp, _vp]),
+        "bz_step_workspace_bytes": (_sz, [_vp]),
+        "bz_step": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _vp, _sz, _vp]),
+        "bz_step_check": (ctypes.c_int, [_vp, _vp, _vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(st: int):
+    if st != BZ_OK:
+        raise BzError(st, lib().bz_last_error().decode())
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return _vp(int(getattr(stream, "cuda_stream", stream)))
+
+
+def _dev(t, what: str):
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{what} must be a device (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+
+
+# ---------------------------------------------------------------------------
+# the C entry points
+# ---------------------------------------------------------------------------
+def bz_api_version() -> int:
+    return int(lib().bz_api_version())
+
+
+def bz_grid_init(N: int, L: float, lam: float) -> int:
+    h = _vp()
+    _check(lib().bz_grid_init(int(N), float(L), float(lam), ctypes.byref(h)))
+    return h.value
+
+
+def bz_grid_free(g: int) -> None:
+    lib().bz_grid_free(_vp(g))
+
+
+def bz_grid_query(g: int) -> dict:
+    info = GridInfo()
+    _check(lib().bz_grid_query(_vp(g), ctypes.byref(info)))
+    return {"N": info.N, "L": info.L, "lambda": info.lambda_, "dv": info.dv, "dzeta": info.dzeta,
+            "pairs": info.pairs}
+
+
+def bz_grid_coords(g: int):
+    N = bz_grid_query(g)["N"]
+    v = np.zeros(N)
+    z = np.zeros(N)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib().bz_grid_coords(_vp(g), v.ctypes.data_as(dp), z.ctypes.data_as(dp)))
+    return v, z
+
+
+def bz_weights_bytes(g: int, kind: int) -> int:
+    return int(lib().bz_weights_bytes(_vp(g), int(kind)))
+
+
+def bz_weights(g: int, kind: int, buf, stream=None) -> None:
+    _dev(buf, "weight buffer")
+    nbytes = buf.numel() * buf.element_size()
+    _check(lib().bz_weights(_vp(g), int(kind), _vp(_ptr(buf)), nbytes, _stream(stream)))
+
+
+def bz_batch_create(grid_of_cell, grids, mode: int) -> int:
+    goc = np.ascontiguousarray(grid_of_cell, dtype=np.int32)
+    arr = (_vp * len(grids))(*[_vp(g) for g in grids])
+    h = _vp()
+    _check(lib().bz_batch_create(int(goc.size), goc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(grids),
+                                 arr, int(mode), ctypes.byref(h)))
+    return h.value
+
+
+def bz_batch_free(b: int) -> None:
+    lib().bz_batch_free(_vp(b))
+
+
+def bz_batch_set_weights(b: int, grid_index: int, kind: int, buf) -> None:
+    _dev(buf, "weight buffer")
+    _check(lib().bz_batch_set_weights(_vp(b), int(grid_index), int(kind), _vp(_ptr(buf))))
+
+
+def bz_batch_elems(b: int) -> int:
+    return int(lib().bz_batch_elems(_vp(b)))
+
+
+def bz_batch_cell_offset(b: int, cell: int) -> int:
+    return int(lib().bz_batch_cell_offset(_vp(b), int(cell)))
+
+
+def bz_workspace_bytes(b: int) -> int:
+    return int(lib().bz_workspace_bytes(_vp(b)))
+
+
+def bz_step_workspace_bytes(b: int) -> int:
+    return int(lib().bz_step_workspace_bytes(_vp(b)))
+
+
+def bz_collide_batch(b: int, f, qt, work, stream=None) -> None:
+    for t, n in ((f, "f"), (qt, "Qt"), (work, "workspace")):
+        _dev(t, n)
+    _check(lib().bz_collide_batch(_vp(b), _vp(_ptr(f)), _vp(_ptr(qt)), _vp(_ptr(work)),
+                                  work.numel() * work.element_size(), _stream(stream)))
+
+
+def bz_project(b: int, q, stream=None) -> None:
+    _dev(q, "Q")
+    _check(lib().bz_project(_vp(b), _vp(_ptr(q)), _stream(stream)))
+
+
+def bz_step(b: int, f, dt_over_eps: float, work, stream=None) -> None:
+    _dev(f, "f")
+    _dev(work, "workspace")
+    _check(lib().bz_step(_vp(b), _vp(_ptr(f)), float(dt_over_eps), _vp(_ptr(work)),
+                         work.numel() * work.element_size(), _stream(stream)))
+
+
+def bz_step_check(b: int, work, stream=None) -> None:
+    _check(lib().bz_step_check(_vp(b), _vp(_ptr(work)), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# Convenience owner of handles and device buffers (still only marshalling).
+# ---------------------------------------------------------------------------
+class Collision:
+    """A batch of cells on one or more meshes with its weights and workspace.
+
+    meshes: list of (N, L, lambda); grid_of_cell: mesh index per cell;
+    mode: one of MODE_NAMES or BZ_MODE_*.  Weight buffers may be shared
+    between Collision objects through `weights_cache`.
+    """
+
+    def __init__(self, meshes, grid_of_cell, mode="batched_f32", weights_cache=None, device="cuda"):
+        import torch
+        self.mode = MODE_NAMES.get(mode, mode)
+        self.kind = MODE_WEIGHTS[self.mode]
+        self.meshes = [tuple(m) for m in meshes]
+        self.grids = [bz_grid_init(*m) for m in self.meshes]
+        self.grid_of_cell = np.asarray(grid_of_cell, dtype=np.int32)
+        self.batch = bz_batch_create(self.grid_of_cell, self.grids, self.mode)
+        cache = weights_cache if weights_cache is not None else {}
+        self.weights = []
+        for gi, (g, m) in enumerate(zip(self.grids, self.meshes)):
+            key = (m, self.kind)
+            if key not in cache:
+                buf = torch.empty(bz_weights_bytes(g, self.kind), dtype=torch.uint8, device=device)
+                bz_weights(g, self.kind, buf)
+                cache[key] = buf
+            self.weights.append(cache[key])
+            bz_batch_set_weights(self.batch, gi, self.kind, cache[key])
+        self.elems = bz_batch_elems(self.batch)
+        self.work = torch.zeros(max(bz_step_workspace_bytes(self.batch), 256), dtype=torch.uint8, device=device)
+        self.offsets = [bz_batch_cell_offset(self.batch, c) for c in range(len(self.grid_of_cell))]
+
+    def collide(self, f, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.elems, dtype=torch.float64, device=f.device)
+        bz_collide_batch(self.batch, f, out, self.work, stream)
+        return out
+
+    def project(self, q, stream=None):
+        bz_project(self.batch, q, stream)
+        return q
+
+    def step(self, f, dt_over_eps, stream=None):
+        bz_step(self.batch, f, dt_over_eps, self.work, stream)
+        return f
+
+    def check(self, stream=None):
+        bz_step_check(self.batch, self.work, stream)
+
+    def pack(self, cells):
+        """Concatenate per-cell (N, N, N) arrays into the batch layout (host)."""
+        return np.concatenate([np.ascontiguousarray(c, dtype=np.float64).ravel() for c in cells])
+
+    def unpack(self, flat):
+        out = []
+        for c, gi in enumerate(self.grid_of_cell):
+            N = self.meshes[gi][0]
+            o = self.offsets[c]
+            out.append(flat[o:o + N ** 3].reshape(N, N, N))
+        return out
+
+    def close(self):
+        if getattr(self, "batch", None):
+            bz_batch_free(self.batch)
+            self.batch = None
+        for g in getattr(self, "grids", []):
+            bz_grid_free(g)
+        self.grids = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

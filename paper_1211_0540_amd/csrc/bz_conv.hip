@@ -1,0 +1,343 @@
+// Weighted convolution of Sec. 3.2,
+//   Qhat_k = sum_m Ghat(xi_m, zeta_k) fhat_m fhat_{k-m+N/2} dzeta^3,
+// the O(N^6) step where the method spends its time (Sec. 3.2, Sec. 4).
+//
+// Two schedules:
+//
+// * Batched (lane = cell).  64 cells of one mesh share a wavefront, so every
+//   weight is wavefront-uniform: it is read once per 64 cells through the
+//   scalar cache (s_load, SGPR operand of the FMA) and never touches VGPRs or
+//   LDS.  A work item is one output row (k1, k2, 0..N-1) of 64 cells; it keeps
+//   the row's N accumulators and, per step (m1, m2), the rows fhat(m1, m2, .)
+//   and fhat(j1, j2, .) of its own cell in registers (cell-interleaved layout,
+//   coalesced 512-byte loads).  Each unordered pair {m, j} is visited once
+//   with the symmetrised weight (see bz_internal.h), so a step costs 6 VALU
+//   operations per visited pair: 2 to scale fhat_m by the weight, 4 FMAs for
+//   the complex multiply-accumulate.  Work items are popped from an atomic
+//   queue ordered longest first, so the launch is persistent.
+//
+//   FP32 variant: products and per-step partial sums in FP32; every FOLD steps
+//   the partials (at most FOLD * 3N/4 terms per output) are folded into a
+//   compensated total, either an FP64 running sum (COMP = 0) or an FP32
+//   (hi, lo) pair updated with Knuth's error-free TwoSum (COMP = 1, Kahan-style
+//   compensation).  FP64 variant: everything FP64.
+//
+// * Plain (lane = output), one cell per launch: the lanes of a wavefront are R
+//   output rows of one k1 plane; all lanes walk the same m, the weight of each
+//   (lane, m) is streamed from HBM in a coalesced layout, fhat_m is uniform and
+//   fhat_j is a per-lane read.  This is the paper's precompute-and-store
+//   organisation; it is bound by the weight stream.
+#include "bz_internal.h"
+
+namespace bz {
+namespace {
+
+template <typename T>
+struct cplx;
+template <>
+struct cplx<float> {
+    using t = float2;
+};
+template <>
+struct cplx<double> {
+    using t = double2;
+};
+
+// flat position of (m3, k3) in the band order of one step
+__host__ __device__ constexpr int band_off(int N, int m3) {
+    int s = 0;
+    for (int m = 0; m < m3; ++m) {
+        int lo = m - N / 2 > 0 ? m - N / 2 : 0;
+        int hi = m + N / 2 - 1 < N - 1 ? m + N / 2 - 1 : N - 1;
+        s += hi - lo + 1;
+    }
+    return s;
+}
+
+// TwoSum: hi + lo += p without losing the rounding error of the addition.
+__device__ inline void two_sum_acc(float &hi, float &lo, float p) {
+    const float s = hi + p;
+    const float bp = s - hi;
+    const float e = (hi - (s - bp)) + (p - bp);
+    hi = s;
+    lo += e;
+}
+
+// One step of the batched schedule for one row: accumulate all (k3, m3) pairs.
+template <typename T, int N>
+__device__ __forceinline__ void cells_step(const typename cplx<T>::t (&mv)[N], const typename cplx<T>::t (&jv)[N],
+                                           const T *__restrict__ w, T (&pr)[N], T (&pi)[N]) {
+    constexpr int h = N / 2;
+#pragma unroll
+    for (int m3 = 0; m3 < N; ++m3) {
+        const int klo = m3 - h > 0 ? m3 - h : 0;
+        const int khi = m3 + h - 1 < N - 1 ? m3 + h - 1 : N - 1;
+#pragma unroll
+        for (int k3 = klo; k3 <= khi; ++k3) {
+            const int j3 = k3 - m3 + h;
+            const T wt = w[band_off(N, m3) + (k3 - klo)];
+            const T tr = wt * mv[m3].x, ti = wt * mv[m3].y;
+            pr[k3] = fma(tr, jv[j3].x, pr[k3]);
+            pr[k3] = fma(-ti, jv[j3].y, pr[k3]);
+            pi[k3] = fma(tr, jv[j3].y, pi[k3]);
+            pi[k3] = fma(ti, jv[j3].x, pi[k3]);
+        }
+    }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void load_row(const typename cplx<T>::t *__restrict__ p, typename cplx<T>::t (&v)[N]) {
+#pragma unroll
+    for (int t = 0; t < N; ++t) v[t] = p[t * kWave];
+}
+
+__device__ inline int pop_item(unsigned *counter) {
+    unsigned it = 0;
+    if (threadIdx.x == 0) it = atomicAdd(counter, 1u);
+    return (int)__builtin_amdgcn_readfirstlane(it);
+}
+
+// ---------------------------------------------------------------------------
+// Batched FP32 with compensated accumulation.
+// ---------------------------------------------------------------------------
+template <int N, int FOLD, int COMP>
+__global__ void __launch_bounds__(64) k_conv_cells_f32(const float2 *__restrict__ fh, const float *__restrict__ W,
+                                                       const long long *__restrict__ row_woff,
+                                                       const int2 *__restrict__ items, int n_items,
+                                                       unsigned *__restrict__ counter, double2 *__restrict__ qh) {
+    constexpr int h = N / 2, M = N * N * N, PS = 3 * N * N / 4;
+    const int lane = threadIdx.x;
+    for (;;) {
+        const int it = pop_item(counter);
+        if (it >= n_items) break;
+        const int2 item = items[it];
+        const int g = item.x, r = item.y;
+        const int k1 = r / N, k2 = r - k1 * N;
+        const float *w = W + row_woff[r];
+        const float2 *F = fh + (size_t)g * M * kWave + lane;
+
+        float pr[N], pi[N];
+        float hr[N], hi[N], lr[N], li[N];
+        double dr[N], di[N];
+#pragma unroll
+        for (int t = 0; t < N; ++t) {
+            pr[t] = pi[t] = 0.f;
+            if (COMP == 1) hr[t] = hi[t] = lr[t] = li[t] = 0.f;
+            else dr[t] = di[t] = 0.0;
+        }
+        auto fold = [&]() {
+#pragma unroll
+            for (int t = 0; t < N; ++t) {
+                if (COMP == 1) {
+                    two_sum_acc(hr[t], lr[t], pr[t]);
+                    two_sum_acc(hi[t], li[t], pi[t]);
+                } else {
+                    dr[t] += (double)pr[t];
+                    di[t] += (double)pi[t];
+                }
+                pr[t] = pi[t] = 0.f;
+            }
+        };
+
+        int nst = 0;
+        const int lo2 = axis_lo(N, k2);
+        const int l1 = cells_m1_last(N, k1);
+        for (int m1 = axis_lo(N, k1); m1 <= l1; ++m1) {
+            const int j1 = k1 + h - m1;
+            const int l2 = cells_m2_last(N, k1, k2, m1);
+            for (int m2 = lo2; m2 <= l2; ++m2) {
+                const int j2 = k2 + h - m2;
+                float2 mv[N], jv[N];
+                load_row<float, N>(F + (size_t)((m1 * N + m2) * N) * kWave, mv);
+                load_row<float, N>(F + (size_t)((j1 * N + j2) * N) * kWave, jv);
+                cells_step<float, N>(mv, jv, w, pr, pi);
+                w += PS;
+                if (++nst == FOLD) {
+                    fold();
+                    nst = 0;
+                }
+            }
+        }
+        fold();
+        double2 *out = qh + (size_t)g * M * kWave + (size_t)r * N * kWave + lane;
+#pragma unroll
+        for (int t = 0; t < N; ++t) {
+            if (COMP == 1)
+                out[t * kWave] = make_double2((double)hr[t] + (double)lr[t], (double)hi[t] + (double)li[t]);
+            else
+                out[t * kWave] = make_double2(dr[t], di[t]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched FP64.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(64) k_conv_cells_f64(const double2 *__restrict__ fh, const double *__restrict__ W,
+                                                       const long long *__restrict__ row_woff,
+                                                       const int2 *__restrict__ items, int n_items,
+                                                       unsigned *__restrict__ counter, double2 *__restrict__ qh) {
+    constexpr int h = N / 2, M = N * N * N, PS = 3 * N * N / 4;
+    const int lane = threadIdx.x;
+    for (;;) {
+        const int it = pop_item(counter);
+        if (it >= n_items) break;
+        const int2 item = items[it];
+        const int g = item.x, r = item.y;
+        const int k1 = r / N, k2 = r - k1 * N;
+        const double *w = W + row_woff[r];
+        const double2 *F = fh + (size_t)g * M * kWave + lane;
+        double pr[N], pi[N];
+#pragma unroll
+        for (int t = 0; t < N; ++t) pr[t] = pi[t] = 0.0;
+        const int lo2 = axis_lo(N, k2);
+        const int l1 = cells_m1_last(N, k1);
+        for (int m1 = axis_lo(N, k1); m1 <= l1; ++m1) {
+            const int j1 = k1 + h - m1;
+            const int l2 = cells_m2_last(N, k1, k2, m1);
+            for (int m2 = lo2; m2 <= l2; ++m2) {
+                const int j2 = k2 + h - m2;
+                double2 mv[N], jv[N];
+                load_row<double, N>(F + (size_t)((m1 * N + m2) * N) * kWave, mv);
+                load_row<double, N>(F + (size_t)((j1 * N + j2) * N) * kWave, jv);
+                cells_step<double, N>(mv, jv, w, pr, pi);
+                w += PS;
+            }
+        }
+        double2 *out = qh + (size_t)g * M * kWave + (size_t)r * N * kWave + lane;
+#pragma unroll
+        for (int t = 0; t < N; ++t) out[t * kWave] = make_double2(pr[t], pi[t]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plain schedule, one cell.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int plain_rows_c(int N) {
+    int R = kWave / N;
+    while (R > 1 && N % R) --R;
+    return R;
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(64) k_conv_plain(const typename cplx<T>::t *__restrict__ fh,
+                                                   const T *__restrict__ W, const long long *__restrict__ blk_woff,
+                                                   int nsplit, double2 *__restrict__ qh) {
+    using C = typename cplx<T>::t;
+    constexpr int h = N / 2, R = plain_rows_c(N), NB = N / R, LN = R * N, M = N * N * N;
+    const int lane = threadIdx.x;
+    const int b = blockIdx.x, s = blockIdx.y;
+    const int k1 = b / NB, kb = b - k1 * NB;
+    const bool active = lane < LN;
+    const int r = active ? lane / N : 0, k3 = active ? lane - (lane / N) * N : 0;
+    const int k2 = kb * R + r;
+    const int lo1 = axis_lo(N, k1), c1 = axis_cnt(N, k1);
+    const int u2lo = plain_u2_lo(N, kb), U2 = plain_u2_hi(N, kb) - u2lo + 1;
+    const int ma = lo1 + (s * c1) / nsplit, mb = lo1 + ((s + 1) * c1) / nsplit;
+    const T *w = W + blk_woff[b] + (long long)(ma - lo1) * U2 * N * LN + (active ? lane : 0);
+    double ar = 0.0, ai = 0.0;
+    for (int m1 = ma; m1 < mb; ++m1) {
+        const int j1 = k1 + h - m1;
+        for (int m2 = u2lo; m2 < u2lo + U2; ++m2) {
+            int j2 = k2 + h - m2;
+            j2 = j2 < 0 ? 0 : (j2 > N - 1 ? N - 1 : j2);
+            const C *rowm = fh + (m1 * N + m2) * N;
+            const C *rowj = fh + (j1 * N + j2) * N;
+            T pr = 0, pi = 0;
+#pragma unroll
+            for (int m3 = 0; m3 < N; ++m3) {
+                int j3 = k3 + h - m3;
+                j3 = j3 < 0 ? 0 : (j3 > N - 1 ? N - 1 : j3);
+                const C a = rowm[m3];
+                const C bb = rowj[j3];
+                const T wt = w[m3 * LN];
+                const T tr = wt * a.x, ti = wt * a.y;
+                pr = fma(tr, bb.x, pr);
+                pr = fma(-ti, bb.y, pr);
+                pi = fma(tr, bb.y, pi);
+                pi = fma(ti, bb.x, pi);
+            }
+            w += N * LN;
+            ar += (double)pr;
+            ai += (double)pi;
+        }
+    }
+    if (active) qh[(size_t)s * M + ((size_t)k1 * N + k2) * N + k3] = make_double2(ar, ai);
+}
+
+template <int N>
+hipError_t cells_f32_variant(const CellsLaunch &p, unsigned grid, hipStream_t s) {
+    switch (p.variant) {
+    case 1:
+        hipLaunchKernelGGL((k_conv_cells_f32<N, 2, 1>), dim3(grid), dim3(64), 0, s, (const float2 *)p.fh,
+                           (const float *)p.w, p.row_woff, p.items, p.n_items, p.counter, p.qh);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_conv_cells_f32<N, 4, 0>), dim3(grid), dim3(64), 0, s, (const float2 *)p.fh,
+                           (const float *)p.w, p.row_woff, p.items, p.n_items, p.counter, p.qh);
+        break;
+    default:
+        hipLaunchKernelGGL((k_conv_cells_f32<N, 2, 0>), dim3(grid), dim3(64), 0, s, (const float2 *)p.fh,
+                           (const float *)p.w, p.row_woff, p.items, p.n_items, p.counter, p.qh);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t cells_f64_launch(const CellsLaunch &p, unsigned grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_conv_cells_f64<N>), dim3(grid), dim3(64), 0, s, (const double2 *)p.fh,
+                       (const double *)p.w, p.row_woff, p.items, p.n_items, p.counter, p.qh);
+    return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t plain_launch(const PlainLaunch &p, hipStream_t s) {
+    const int nb = N * (N / plain_rows_c(N));
+    hipLaunchKernelGGL((k_conv_plain<T, N>), dim3(nb, p.nsplit), dim3(64), 0, s,
+                       (const typename cplx<T>::t *)p.fh, (const T *)p.w, p.blk_woff, p.nsplit, p.qh);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Persistent grid: enough single-wave workgroups to keep every SIMD busy.
+static unsigned persistent_grid(int n_items) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    unsigned g = (unsigned)cus * 8u;
+    return (unsigned)n_items < g ? (unsigned)n_items : g;
+}
+
+#define BZ_FOR_EACH_N(X) X(8) X(12) X(16) X(20) X(24) X(28) X(32)
+
+hipError_t launch_conv_cells(const CellsLaunch &p, bool f64, hipStream_t s) {
+    if (p.n_items <= 0) return hipSuccess;
+    hipError_t e = launch_fill_u32(p.counter, 1, 0u, s);
+    if (e != hipSuccess) return e;
+    const unsigned grid = persistent_grid(p.n_items);
+#define CASE(NN)                                                                                   \
+    case NN:                                                                                       \
+        return f64 ? cells_f64_launch<NN>(p, grid, s) : cells_f32_variant<NN>(p, grid, s);
+    switch (p.N) {
+        BZ_FOR_EACH_N(CASE)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef CASE
+}
+
+hipError_t launch_conv_plain(const PlainLaunch &p, bool f64, hipStream_t s) {
+#define CASE(NN) \
+    case NN:     \
+        return f64 ? plain_launch<double, NN>(p, s) : plain_launch<float, NN>(p, s);
+    switch (p.N) {
+        BZ_FOR_EACH_N(CASE)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef CASE
+}
+
+}  // namespace bz

@@ -1,0 +1,173 @@
+// Internal definitions of the bz library: mesh handle, work schedules, launchers.
+// Everything here is private to libbz.so; the public interface is include/bz.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bz.h"
+
+namespace bz {
+
+constexpr int kMinN = 8;
+constexpr int kMaxN = 32;
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Per-axis bookkeeping of the trapezoid sum (Sec. 3.2): for an output index k
+// the partner index j = k - m + N/2 must stay on the mesh, so m ranges over
+// [lo(k), hi(k)] with lo = max(0, k - N/2 + 1), hi = min(N - 1, k + N/2).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int axis_lo(int N, int k) { return k - N / 2 + 1 > 0 ? k - N / 2 + 1 : 0; }
+__host__ __device__ inline int axis_hi(int N, int k) { return k + N / 2 < N - 1 ? k + N / 2 : N - 1; }
+__host__ __device__ inline int axis_cnt(int N, int k) { return axis_hi(N, k) - axis_lo(N, k) + 1; }
+
+// ---------------------------------------------------------------------------
+// Batched ("lane = cell") schedule.
+//
+// A work item is one output row (k1, k2, 0..N-1) of 64 cells on the same mesh.
+// The pair (m, j = k - m + N/2) and its mirror (j, m) carry the same product
+// fhat_m fhat_j, and the gain weight T(na, |m - j|^2) is symmetric in them, so
+// each unordered pair is visited once with the weight
+//   W = s [2 T(na, nb) - T(0, 4 nc(m)) - T(0, 4 nc(j))]        (m != j)
+//   W = s [  T(na, 0)  - T(0, 4 nc(m))                ]        (m == j)
+// where s = 4pi (2pi)^{-3/2} L^{lambda+3} dzeta^3.  Unordered pairs are
+// represented by m <= j in the lexicographic order of (m1, m2, m3); a "step"
+// is one (m1, m2) with (m1, m2) <= (j1, j2), and covers all (k3, m3) of the
+// row in the fixed order  for m3 in [0, N): for k3 in [kband_lo, kband_hi].
+// In the diagonal step (m1, m2) == (j1, j2) the pairs with m3 > j3 get W = 0.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int kband_lo(int N, int m3) { return m3 - N / 2 > 0 ? m3 - N / 2 : 0; }
+__host__ __device__ inline int kband_hi(int N, int m3) { return m3 + N / 2 - 1 < N - 1 ? m3 + N / 2 - 1 : N - 1; }
+__host__ __device__ inline int pairs_per_step(int N) { return 3 * N * N / 4; }
+
+// Last m1 of the row: the largest m1 with 2 m1 <= k1 + N/2.
+__host__ __device__ inline int cells_m1_last(int N, int k1) {
+    int t = (k1 + N / 2) / 2;
+    int hi = axis_hi(N, k1);
+    return t < hi ? t : hi;
+}
+// Last m2 for a given m1 (all of the band, or up to the diagonal when m1 == j1).
+__host__ __device__ inline int cells_m2_last(int N, int k1, int k2, int m1) {
+    int hi = axis_hi(N, k2);
+    if (2 * m1 < k1 + N / 2) return hi;
+    int t = (k2 + N / 2) / 2;
+    return t < hi ? t : hi;
+}
+__host__ __device__ inline int cells_steps(int N, int k1, int k2) {
+    int lo1 = axis_lo(N, k1), lo2 = axis_lo(N, k2);
+    int n = 0;
+    for (int m1 = lo1; m1 <= cells_m1_last(N, k1); ++m1) n += cells_m2_last(N, k1, k2, m1) - lo2 + 1;
+    return n;
+}
+
+// ---------------------------------------------------------------------------
+// Plain ("lane = output") schedule, one cell at a time.
+//
+// A block holds R consecutive rows k2 = kb R .. kb R + R - 1 of one k1 plane,
+// one output per lane (lane = r N + k3, R N <= 64).  All lanes walk the same
+// m in the order m1 in [lo(k1), hi(k1)], m2 over the union of the rows' bands,
+// m3 in [0, N); a lane whose partner leaves the mesh reads weight 0.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int plain_rows(int N) {
+    int R = kWave / N;
+    while (R > 1 && N % R) --R;
+    return R;
+}
+__host__ __device__ inline int plain_u2_lo(int N, int kb) { return axis_lo(N, kb * plain_rows(N)); }
+__host__ __device__ inline int plain_u2_hi(int N, int kb) { return axis_hi(N, kb * plain_rows(N) + plain_rows(N) - 1); }
+__host__ __device__ inline long long plain_block_iters(int N, int k1, int kb) {
+    return (long long)axis_cnt(N, k1) * (plain_u2_hi(N, kb) - plain_u2_lo(N, kb) + 1) * N;
+}
+
+// ---------------------------------------------------------------------------
+// Mesh handle.
+// ---------------------------------------------------------------------------
+struct Schedule {
+    // batched: N*N rows, offsets in weights (elements), steps per row
+    std::vector<long long> row_woff;
+    std::vector<int> row_steps;
+    long long cells_weights = 0;
+    // plain: N * (N / R) blocks
+    std::vector<long long> blk_woff;
+    long long plain_weights = 0;
+};
+
+}  // namespace bz
+
+struct bz_grid_s {
+    int N;
+    double L, lambda, dv, dzeta;
+    long long pairs;
+    double linv[25];  // L^{-1} with C C^T = L L^T (Cholesky), row-major
+    bz::Schedule sched;
+};
+
+namespace bz {
+
+// status helpers (thread-local message)
+bz_status fail(bz_status s, const std::string &msg);
+bz_status hip_fail(hipError_t e, const char *what);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files).  All take a hipStream_t.
+// ---------------------------------------------------------------------------
+// Weight expansion from the FP64 universal table T[p * qstride + q].
+hipError_t launch_expand_cells(int N, const double *dT, int qstride, double scale, const long long *d_row_woff,
+                               void *d_w, bool f64, hipStream_t s);
+hipError_t launch_expand_plain(int N, const double *dT, int qstride, double scale, const long long *d_blk_woff,
+                               void *d_w, bool f64, hipStream_t s);
+
+// Forward transform of `ncells` cells of one mesh.  Cell c's f starts at
+// f + f_off[c]; fhat element k of cell c is written at out + o_base[c] + k*o_stride
+// (complex units) as float2 (f32) or double2.
+hipError_t launch_dft_forward(int N, double L, int ncells, const double *f, const long long *d_f_off,
+                              double2 *scratch, void *out, bool out_f32, const long long *d_o_base,
+                              long long o_stride, hipStream_t s);
+// Inverse transform: Qhat element k of cell c at in + i_base[c] + k*i_stride,
+// summed over `nparts` partial buffers spaced part_stride (complex units).
+hipError_t launch_dft_inverse(int N, double L, int ncells, const double2 *in, const long long *d_i_base,
+                              long long i_stride, int nparts, long long part_stride, double2 *scratch,
+                              double *qt, const long long *d_q_off, hipStream_t s);
+
+// Batched convolution over the (group, row) items of one mesh.
+struct CellsLaunch {
+    int N;
+    const void *fh;              // [G][N^3][64] float2 or double2
+    const void *w;               // batched schedule weights
+    const long long *row_woff;   // device, N*N
+    const int2 *items;           // device, (group, row), longest first
+    int n_items;
+    unsigned *counter;           // device, zeroed by the launcher's fill kernel
+    double2 *qh;                 // [G][N^3][64]
+    int variant;                 // tuning variant
+};
+hipError_t launch_conv_cells(const CellsLaunch &p, bool f64, hipStream_t s);
+
+// Plain convolution of one cell.
+struct PlainLaunch {
+    int N;
+    const void *fh;              // [N^3] float2 or double2
+    const void *w;               // plain schedule weights
+    const long long *blk_woff;   // device, N * (N / R)
+    int nsplit;                  // m1 range split into nsplit partial sums
+    double2 *qh;                 // [nsplit][N^3]
+};
+hipError_t launch_conv_plain(const PlainLaunch &p, bool f64, hipStream_t s);
+
+// Projection (Sec. 3.3) of ncells cells of one mesh, in place, two passes.
+hipError_t launch_project(int N, double dv, const double *linv, int ncells, double *q, const long long *d_off,
+                          hipStream_t s);
+
+// Heun helpers: out = a + c*q ; out = 0.5*(a + b + c*q); flag nonfinite.
+hipError_t launch_axpy(size_t n, const double *a, const double *q, double c, double *out, unsigned *flag,
+                       hipStream_t s);
+hipError_t launch_heun_final(size_t n, const double *f, const double *fs, const double *q, double c, double *out,
+                             unsigned *flag, hipStream_t s);
+hipError_t launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t s);
+
+}  // namespace bz

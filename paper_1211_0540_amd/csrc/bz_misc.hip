@@ -1,0 +1,245 @@
+// Conservation projection (Sec. 3.3), Heun update helpers (Sec. 3.1) and the
+// expansion of the universal weight table into the schedules' weight streams
+// (Sec. 2.2 eq. GHat_calc).  FP64 throughout.
+#include "bz_internal.h"
+
+namespace bz {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Projection.  C has rows dv^3 {1, v1, v2, v3, |v|^2}.  With C C^T = L L^T,
+// the rows of E = L^{-1} C are orthonormal and the minimiser of |Qt - Q|^2
+// subject to C Q = 0 is Q = Qt - E^T (E Qt), the same operator as
+// Qt - C^T (C C^T)^{-1} C Qt but applied through an orthonormal basis.  The
+// five moments are reduced in FP64 (per-thread sums, wavefront shuffles,
+// then LDS); the projection is applied twice, the second pass removing the
+// rounding residue of the first.
+// ---------------------------------------------------------------------------
+struct Linv {
+    double a[25];
+};
+
+__device__ inline void basis(int N, double dv, const Linv &li, int j, double e[5]) {
+    const int j1 = j / (N * N), j2 = (j / N) % N, j3 = j % N;
+    const double v1 = dv * (j1 - N / 2), v2 = dv * (j2 - N / 2), v3 = dv * (j3 - N / 2);
+    const double w = dv * dv * dv;
+    const double c[5] = {w, v1 * w, v2 * w, v3 * w, (v1 * v1 + v2 * v2 + v3 * v3) * w};
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b <= a; ++b) s = fma(li.a[a * 5 + b], c[b], s);
+        e[a] = s;
+    }
+}
+
+__device__ inline double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+__global__ void __launch_bounds__(256) k_project(int N, double dv, Linv li, double *__restrict__ q,
+                                                 const long long *__restrict__ off) {
+    __shared__ double red[4][5];
+    __shared__ double mu[5];
+    const int M = N * N * N;
+    double *Q = q + off[blockIdx.x];
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int pass = 0; pass < 2; ++pass) {
+        double s[5] = {0, 0, 0, 0, 0};
+        for (int j = threadIdx.x; j < M; j += blockDim.x) {
+            double e[5];
+            basis(N, dv, li, j, e);
+            const double x = Q[j];
+#pragma unroll
+            for (int a = 0; a < 5; ++a) s[a] = fma(e[a], x, s[a]);
+        }
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            double t = wave_sum(s[a]);
+            if (lane == 0) red[wid][a] = t;
+        }
+        __syncthreads();
+        if (threadIdx.x < 5) {
+            double t = 0.0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w][threadIdx.x];
+            mu[threadIdx.x] = t;
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < M; j += blockDim.x) {
+            double e[5];
+            basis(N, dv, li, j, e);
+            double corr = 0.0;
+#pragma unroll
+            for (int a = 0; a < 5; ++a) corr = fma(e[a], mu[a], corr);
+            Q[j] -= corr;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Heun helpers and flag fill.
+// ---------------------------------------------------------------------------
+__global__ void k_axpy(size_t n, const double *__restrict__ a, const double *__restrict__ q, double c,
+                       double *__restrict__ out, unsigned *flag) {
+    bool bad = false;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        double y = fma(c, q[i], a[i]);
+        out[i] = y;
+        bad |= !isfinite(y);
+    }
+    if (bad) atomicOr(flag, 1u);
+}
+
+__global__ void k_heun_final(size_t n, const double *__restrict__ f, const double *__restrict__ fs,
+                             const double *__restrict__ q, double c, double *__restrict__ out, unsigned *flag) {
+    bool bad = false;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        double y = 0.5 * (f[i] + fma(c, q[i], fs[i]));
+        out[i] = y;
+        bad |= !isfinite(y);
+    }
+    if (bad) atomicOr(flag, 1u);
+}
+
+__global__ void k_fill_u32(unsigned *p, int n, unsigned v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Weight expansion.  T[p * qs + q] = T_lambda(p, q) of the universal table;
+// scale = 4pi (2pi)^{-3/2} L^{lambda+3} dzeta^3.
+// ---------------------------------------------------------------------------
+__device__ inline int sq3(int a, int b, int c) { return a * a + b * b + c * c; }
+
+template <typename W>
+__global__ void __launch_bounds__(256) k_expand_cells(int N, const double *__restrict__ T, int qs, double scale,
+                                                      const long long *__restrict__ row_woff, W *__restrict__ w) {
+    const int h = N / 2;
+    const int r = blockIdx.x;
+    const int k1 = r / N, k2 = r % N;
+    const int PS = pairs_per_step(N);
+    W *out = w + row_woff[r];
+    long long step = 0;
+    for (int m1 = axis_lo(N, k1); m1 <= cells_m1_last(N, k1); ++m1) {
+        const int j1 = k1 + h - m1;
+        for (int m2 = axis_lo(N, k2); m2 <= cells_m2_last(N, k1, k2, m1); ++m2, ++step) {
+            const int j2 = k2 + h - m2;
+            for (int t = threadIdx.x; t < PS; t += blockDim.x) {
+                // locate (m3, k3) of flat pair index t in the band order
+                int m3 = 0, base = 0;
+                for (;; ++m3) {
+                    int cnt = kband_hi(N, m3) - kband_lo(N, m3) + 1;
+                    if (t < base + cnt) break;
+                    base += cnt;
+                }
+                const int k3 = kband_lo(N, m3) + (t - base);
+                const int j3 = k3 + h - m3;
+                const int na = sq3(k1 - h, k2 - h, k3 - h);
+                const int nb = sq3(m1 - j1, m2 - j2, m3 - j3);
+                const int ncm = sq3(m1 - h, m2 - h, m3 - h);
+                const int ncj = sq3(j1 - h, j2 - h, j3 - h);
+                double v;
+                const bool diag = (m1 == j1) && (m2 == j2);
+                if (diag && m3 == j3)
+                    v = T[(size_t)na * qs] - T[4 * ncm];
+                else if (diag && m3 > j3)
+                    v = 0.0;
+                else
+                    v = 2.0 * T[(size_t)na * qs + nb] - T[4 * ncm] - T[4 * ncj];
+                out[step * PS + t] = (W)(scale * v);
+            }
+        }
+    }
+}
+
+template <typename W>
+__global__ void __launch_bounds__(256) k_expand_plain(int N, const double *__restrict__ T, int qs, double scale,
+                                                      const long long *__restrict__ blk_woff, W *__restrict__ w) {
+    const int h = N / 2;
+    const int R = plain_rows(N), NB = N / R, LN = R * N;
+    const int b = blockIdx.x;
+    const int k1 = b / NB, kb = b % NB;
+    const int lo1 = axis_lo(N, k1), c1 = axis_cnt(N, k1);
+    const int u2lo = plain_u2_lo(N, kb), U2 = plain_u2_hi(N, kb) - u2lo + 1;
+    const long long iters = (long long)c1 * U2 * N;
+    W *out = w + blk_woff[b];
+    for (long long e = threadIdx.x; e < iters * LN; e += blockDim.x) {
+        const int lane = (int)(e % LN);
+        const long long it = e / LN;
+        const int m3 = (int)(it % N);
+        const int m2 = u2lo + (int)((it / N) % U2);
+        const int m1 = lo1 + (int)(it / ((long long)N * U2));
+        const int r = lane / N, k3 = lane % N, k2 = kb * R + r;
+        const int j1 = k1 + h - m1, j2 = k2 + h - m2, j3 = k3 + h - m3;
+        double v = 0.0;
+        if (j2 >= 0 && j2 < N && j3 >= 0 && j3 < N && j1 >= 0 && j1 < N) {
+            const int na = sq3(k1 - h, k2 - h, k3 - h);
+            const int nb = sq3(m1 - j1, m2 - j2, m3 - j3);
+            const int ncm = sq3(m1 - h, m2 - h, m3 - h);
+            v = T[(size_t)na * qs + nb] - T[4 * ncm];
+        }
+        out[e] = (W)(scale * v);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_project(int N, double dv, const double *linv, int ncells, double *q, const long long *d_off,
+                          hipStream_t s) {
+    if (ncells <= 0) return hipSuccess;
+    Linv li;
+    for (int i = 0; i < 25; ++i) li.a[i] = linv[i];
+    hipLaunchKernelGGL(k_project, dim3(ncells), dim3(256), 0, s, N, dv, li, q, d_off);
+    return hipGetLastError();
+}
+
+static inline unsigned blocks_for(size_t n) {
+    size_t b = (n + 255) / 256;
+    return (unsigned)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
+}
+
+hipError_t launch_axpy(size_t n, const double *a, const double *q, double c, double *out, unsigned *flag,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy, dim3(blocks_for(n)), dim3(256), 0, s, n, a, q, c, out, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_heun_final(size_t n, const double *f, const double *fs, const double *q, double c, double *out,
+                             unsigned *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_heun_final, dim3(blocks_for(n)), dim3(256), 0, s, n, f, fs, q, c, out, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand_cells(int N, const double *dT, int qstride, double scale, const long long *d_row_woff,
+                               void *d_w, bool f64, hipStream_t s) {
+    if (f64)
+        hipLaunchKernelGGL(k_expand_cells<double>, dim3(N * N), dim3(256), 0, s, N, dT, qstride, scale, d_row_woff,
+                           (double *)d_w);
+    else
+        hipLaunchKernelGGL(k_expand_cells<float>, dim3(N * N), dim3(256), 0, s, N, dT, qstride, scale, d_row_woff,
+                           (float *)d_w);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand_plain(int N, const double *dT, int qstride, double scale, const long long *d_blk_woff,
+                               void *d_w, bool f64, hipStream_t s) {
+    const int nb = N * (N / plain_rows(N));
+    if (f64)
+        hipLaunchKernelGGL(k_expand_plain<double>, dim3(nb), dim3(256), 0, s, N, dT, qstride, scale, d_blk_woff,
+                           (double *)d_w);
+    else
+        hipLaunchKernelGGL(k_expand_plain<float>, dim3(nb), dim3(256), 0, s, N, dT, qstride, scale, d_blk_woff,
+                           (float *)d_w);
+    return hipGetLastError();
+}
+
+}  // namespace bz

@@ -1,0 +1,601 @@
+// Host runtime of libbz: mesh handles, the universal weight table, batch
+// planning (groups of 64 cells, longest-first work lists) and the C ABI
+// declared in include/bz.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <numeric>
+
+#include "bz_internal.h"
+
+namespace bz {
+
+static thread_local std::string g_err;
+
+bz_status fail(bz_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+bz_status hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? BZ_ENOMEM : BZ_EDEVICE;
+}
+
+#define BZ_HIP(call, what)                         \
+    do {                                           \
+        hipError_t e_ = (call);                    \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// Universal table (Sec. 2.2 eq. GHat_calc with r = L s and dzeta L = pi):
+//   T_lambda(p, q) = int_0^1 s^{lambda+2} sinc(a s) sinc(b s) ds,
+//   a = pi sqrt(p) / 2, b = pi sqrt(q) / 2,
+// in closed form for lambda = 0, 1:
+//   lambda = 0:  [S(a-b) - S(a+b)] / (2ab),          S(x) = sin x / x
+//   lambda = 1:  [U(a-b) - U(a+b)] / (2ab),          U(x) = int_0^1 s cos(xs) ds
+//                                                         = sin x/x - 2 sin^2(x/2)/x^2
+// with the one-sided limits for a or b = 0.  Non-zero a, b are >= pi/2 and a
+// non-zero |a - b| is >= pi/(4 sqrt(3) N), so no series expansions are needed;
+// the half-angle form of cos x - 1 removes the only cancellation.
+// ---------------------------------------------------------------------------
+static double S0(double x) { return x == 0.0 ? 1.0 : std::sin(x) / x; }
+static double U1(double x) {
+    if (x == 0.0) return 0.5;
+    const double hs = std::sin(0.5 * x);
+    return std::sin(x) / x - 2.0 * hs * hs / (x * x);
+}
+
+static double T_closed(int lam, double a, double b) {
+    if (a == 0.0 && b == 0.0) return 1.0 / (lam + 3);
+    if (a == 0.0 || b == 0.0) {
+        const double c = a + b, sc = std::sin(c), cc = std::cos(c), hs = std::sin(0.5 * c);
+        if (lam == 0) return (sc - c * cc) / (c * c * c);
+        // int_0^1 s^2 sin(c s) ds / c
+        return (-cc / c + 2.0 * sc / (c * c) - 4.0 * hs * hs / (c * c * c)) / c;
+    }
+    if (lam == 0) return (S0(a - b) - S0(a + b)) / (2.0 * a * b);
+    return (U1(a - b) - U1(a + b)) / (2.0 * a * b);
+}
+
+// p in [0, 3N^2/4], q in [0, 3N^2] (q = 4 nc reaches 3N^2 on the loss row).
+static void build_table(int N, int lam, std::vector<double> &T, int &qs) {
+    const int pmax = 3 * N * N / 4, qmax = 3 * N * N;
+    qs = qmax + 1;
+    T.assign((size_t)(pmax + 1) * qs, 0.0);
+    std::vector<double> sq(qs);
+    for (int q = 0; q < qs; ++q) sq[q] = 0.5 * kPi * std::sqrt((double)q);
+    for (int p = 0; p <= pmax; ++p) {
+        const double a = sq[p];
+        double *row = T.data() + (size_t)p * qs;
+        for (int q = 0; q < qs; ++q) row[q] = T_closed(lam, a, sq[q]);
+    }
+}
+
+static double weight_scale(const bz_grid_s *g) {
+    // 4pi (2pi)^{-3/2} L^{lambda+3} dzeta^3
+    return 4.0 * kPi * std::pow(2.0 * kPi, -1.5) * std::pow(g->L, g->lambda + 3.0) * g->dzeta * g->dzeta * g->dzeta;
+}
+
+// Cholesky of the Gram matrix C C^T of the constraint rows dv^3 {1, v1, v2, v3, |v|^2}.
+static bool constraint_linv(int N, double dv, double linv[25]) {
+    std::vector<double> v(N);
+    for (int k = 0; k < N; ++k) v[k] = dv * (k - N / 2);
+    double s[5] = {0, 0, 0, 0, 0};  // 1-D power sums sum_k v^p, p = 0..4
+    for (int k = 0; k < N; ++k) {
+        double t = 1.0;
+        for (int p = 0; p < 5; ++p) {
+            s[p] += t;
+            t *= v[k];
+        }
+    }
+    const double w2 = std::pow(dv, 6);
+    const double n2 = (double)N * N, n1 = N;
+    // moments of the 3-D mesh via separability
+    auto m = [&](int a, int b, int c) { return s[a] * s[b] * s[c]; };
+    double G[5][5];
+    const int e[4][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    (void)n2;
+    (void)n1;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
+            G[i][j] = m(e[i][0] + e[j][0], e[i][1] + e[j][1], e[i][2] + e[j][2]);
+    for (int i = 0; i < 4; ++i) {
+        double t = 0;
+        for (int d = 0; d < 3; ++d) {
+            int x[3] = {e[i][0], e[i][1], e[i][2]};
+            x[d] += 2;
+            t += m(x[0], x[1], x[2]);
+        }
+        G[i][4] = G[4][i] = t;
+    }
+    {
+        double t = 0;
+        for (int d1 = 0; d1 < 3; ++d1)
+            for (int d2 = 0; d2 < 3; ++d2) {
+                int x[3] = {0, 0, 0};
+                x[d1] += 2;
+                x[d2] += 2;
+                t += m(x[0], x[1], x[2]);
+            }
+        G[4][4] = t;
+    }
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j) G[i][j] *= w2;
+    double Lc[5][5] = {{0}};
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double t = G[i][j];
+            for (int k = 0; k < j; ++k) t -= Lc[i][k] * Lc[j][k];
+            if (i == j) {
+                if (!(t > 0)) return false;
+                Lc[i][i] = std::sqrt(t);
+            } else {
+                Lc[i][j] = t / Lc[j][j];
+            }
+        }
+    // invert the lower-triangular factor
+    double Li[5][5] = {{0}};
+    for (int j = 0; j < 5; ++j) {
+        Li[j][j] = 1.0 / Lc[j][j];
+        for (int i = j + 1; i < 5; ++i) {
+            double t = 0;
+            for (int k = j; k < i; ++k) t -= Lc[i][k] * Li[k][j];
+            Li[i][j] = t / Lc[i][i];
+        }
+    }
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j) linv[i * 5 + j] = Li[i][j];
+    return true;
+}
+
+static void build_schedules(bz_grid_s *g) {
+    const int N = g->N;
+    Schedule &s = g->sched;
+    s.row_woff.resize(N * N);
+    s.row_steps.resize(N * N);
+    long long off = 0;
+    for (int r = 0; r < N * N; ++r) {
+        s.row_woff[r] = off;
+        s.row_steps[r] = cells_steps(N, r / N, r % N);
+        off += (long long)s.row_steps[r] * pairs_per_step(N);
+    }
+    s.cells_weights = off;
+    const int R = plain_rows(N), NB = N / R, LN = R * N;
+    s.blk_woff.resize(N * NB);
+    off = 0;
+    for (int b = 0; b < N * NB; ++b) {
+        s.blk_woff[b] = off;
+        off += plain_block_iters(N, b / NB, b % NB) * LN;
+    }
+    s.plain_weights = off;
+}
+
+static size_t kind_elem(int kind) {
+    return (kind == BZ_W_BATCHED_F64 || kind == BZ_W_PLAIN_F64) ? 8 : 4;
+}
+
+// ---------------------------------------------------------------------------
+// Batch.
+// ---------------------------------------------------------------------------
+struct Part {
+    bz_grid g = nullptr;
+    int gi = 0;
+    std::vector<int> cells;  // batch cell indices
+    int groups = 0;
+    const void *w = nullptr;
+    int wkind = 0;
+    // device tables (offsets into the batch's device buffer)
+    long long *d_f_off = nullptr;    // per cell: offset of f (doubles)
+    long long *d_fh_base = nullptr;  // per cell: base of fhat/qhat (complex units)
+    long long *d_row_woff = nullptr;
+    long long *d_blk_woff = nullptr;
+    long long *d_zero = nullptr;     // single 0 (plain: base of the one cell)
+    int2 *d_items = nullptr;
+    int n_items = 0;
+    std::vector<long long> f_off;    // host copy
+    // workspace offsets (bytes)
+    size_t ws_fh = 0, ws_qh = 0, ws_counter = 0;
+};
+
+}  // namespace bz
+
+struct bz_batch_s {
+    int mode = 0;
+    int n_cells = 0;
+    std::vector<bz_grid> grids;
+    std::vector<int> grid_of_cell;
+    std::vector<long long> cell_off;
+    size_t elems = 0;
+    std::vector<bz::Part> parts;   // one per mesh used, largest N first
+    void *d_tables = nullptr;
+    size_t ws_scratch = 0, ws_flag = 0, ws_total = 0;
+    int plain_split = 4;
+    int variant = 0;
+};
+
+namespace bz {
+
+static bool batched(int mode) { return mode == BZ_MODE_BATCHED_F32 || mode == BZ_MODE_BATCHED_F64; }
+static bool mode_f64(int mode) { return mode == BZ_MODE_PLAIN_F64 || mode == BZ_MODE_BATCHED_F64; }
+static int mode_wkind(int mode) {
+    switch (mode) {
+    case BZ_MODE_BATCHED_F32: return BZ_W_BATCHED_F32;
+    case BZ_MODE_BATCHED_F64: return BZ_W_BATCHED_F64;
+    case BZ_MODE_PLAIN_F32: return BZ_W_PLAIN_F32;
+    default: return BZ_W_PLAIN_F64;
+    }
+}
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int plain_split_for(int N) {
+    // enough partial sums to give >= ~2048 single-wave blocks, bounded by the m1 band
+    const int nb = N * (N / plain_rows(N));
+    int s = (2048 + nb - 1) / nb;
+    const int cmin = N / 2;
+    if (s > cmin) s = cmin;
+    if (s < 1) s = 1;
+    if (s > 8) s = 8;
+    return s;
+}
+
+}  // namespace bz
+
+using namespace bz;
+
+extern "C" {
+
+int bz_api_version(void) { return BZ_API_VERSION; }
+
+const char *bz_status_string(bz_status s) {
+    switch (s) {
+    case BZ_OK: return "ok";
+    case BZ_EINVAL: return "invalid argument";
+    case BZ_EUNSUPPORTED: return "unsupported";
+    case BZ_EDEVICE: return "device error";
+    case BZ_ENOMEM: return "out of memory";
+    case BZ_ENONFINITE: return "non-finite value";
+    case BZ_ESTATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char *bz_last_error(void) { return g_err.c_str(); }
+
+bz_status bz_grid_init(int N, double L, double lambda, bz_grid *out) {
+    if (!out) return fail(BZ_EINVAL, "bz_grid_init: out is NULL");
+    *out = nullptr;
+    if (N < kMinN || N > kMaxN || (N % 4) != 0)
+        return fail(BZ_EINVAL, "bz_grid_init: N must be a multiple of 4 in [8, 32]");
+    if (!(L > 0) || !std::isfinite(L)) return fail(BZ_EINVAL, "bz_grid_init: L must be positive and finite");
+    if (!(lambda == 0.0 || lambda == 1.0))
+        return fail(BZ_EUNSUPPORTED, "bz_grid_init: lambda must be 0 (Maxwell molecules) or 1 (hard spheres)");
+    bz_grid_s *g = new (std::nothrow) bz_grid_s();
+    if (!g) return fail(BZ_ENOMEM, "bz_grid_init: allocation failed");
+    g->N = N;
+    g->L = L;
+    g->lambda = lambda;
+    g->dv = 2.0 * L / N;
+    g->dzeta = kPi / L;
+    const long long a = 3LL * N * N / 4;
+    g->pairs = a * a * a;
+    if (!constraint_linv(N, g->dv, g->linv)) {
+        delete g;
+        return fail(BZ_EINVAL, "bz_grid_init: constraint Gram matrix not positive definite");
+    }
+    build_schedules(g);
+    *out = g;
+    return BZ_OK;
+}
+
+void bz_grid_free(bz_grid g) { delete g; }
+
+bz_status bz_grid_query(bz_grid g, bz_grid_info *info) {
+    if (!g || !info) return fail(BZ_EINVAL, "bz_grid_query: NULL argument");
+    info->N = g->N;
+    info->L = g->L;
+    info->lambda = g->lambda;
+    info->dv = g->dv;
+    info->dzeta = g->dzeta;
+    info->pairs = g->pairs;
+    return BZ_OK;
+}
+
+bz_status bz_grid_coords(bz_grid g, double *v, double *zeta) {
+    if (!g) return fail(BZ_EINVAL, "bz_grid_coords: NULL grid");
+    for (int k = 0; k < g->N; ++k) {
+        if (v) v[k] = g->dv * (k - g->N / 2);
+        if (zeta) zeta[k] = g->dzeta * (k - g->N / 2);
+    }
+    return BZ_OK;
+}
+
+size_t bz_weights_bytes(bz_grid g, int kind) {
+    if (!g) return 0;
+    switch (kind) {
+    case BZ_W_BATCHED_F32:
+    case BZ_W_BATCHED_F64: return (size_t)g->sched.cells_weights * kind_elem(kind);
+    case BZ_W_PLAIN_F32:
+    case BZ_W_PLAIN_F64: return (size_t)g->sched.plain_weights * kind_elem(kind);
+    default: return 0;
+    }
+}
+
+bz_status bz_weights(bz_grid g, int kind, void *d_w, size_t bytes, void *stream) {
+    if (!g || !d_w) return fail(BZ_EINVAL, "bz_weights: NULL argument");
+    const size_t need = bz_weights_bytes(g, kind);
+    if (need == 0) return fail(BZ_EINVAL, "bz_weights: unknown weight kind");
+    if (bytes < need) return fail(BZ_EINVAL, "bz_weights: buffer too small");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<double> T;
+    int qs = 0;
+    build_table(g->N, (int)g->lambda, T, qs);
+    const bool cells = kind == BZ_W_BATCHED_F32 || kind == BZ_W_BATCHED_F64;
+    const std::vector<long long> &off = cells ? g->sched.row_woff : g->sched.blk_woff;
+    double *dT = nullptr;
+    long long *dOff = nullptr;
+    BZ_HIP(hipMalloc(&dT, T.size() * sizeof(double)), "bz_weights: hipMalloc table");
+    hipError_t e = hipMalloc(&dOff, off.size() * sizeof(long long));
+    if (e != hipSuccess) {
+        (void)hipFree(dT);
+        return hip_fail(e, "bz_weights: hipMalloc offsets");
+    }
+    e = hipMemcpyAsync(dT, T.data(), T.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dOff, off.data(), off.size() * sizeof(long long), hipMemcpyHostToDevice, s);
+    const bool f64 = kind_elem(kind) == 8;
+    if (e == hipSuccess)
+        e = cells ? launch_expand_cells(g->N, dT, qs, weight_scale(g), dOff, d_w, f64, s)
+                  : launch_expand_plain(g->N, dT, qs, weight_scale(g), dOff, d_w, f64, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(dT);
+    (void)hipFree(dOff);
+    if (e != hipSuccess) return hip_fail(e, "bz_weights");
+    return BZ_OK;
+}
+
+bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids, const bz_grid *grids, int mode,
+                          bz_batch *out) {
+    if (!out) return fail(BZ_EINVAL, "bz_batch_create: out is NULL");
+    *out = nullptr;
+    if (n_cells < 1 || !grid_of_cell || n_grids < 1 || !grids)
+        return fail(BZ_EINVAL, "bz_batch_create: empty batch or NULL argument");
+    if (mode < BZ_MODE_PLAIN_F64 || mode > BZ_MODE_PLAIN_F32) return fail(BZ_EINVAL, "bz_batch_create: bad mode");
+    for (int i = 0; i < n_grids; ++i)
+        if (!grids[i]) return fail(BZ_EINVAL, "bz_batch_create: NULL grid handle");
+    for (int c = 0; c < n_cells; ++c)
+        if (grid_of_cell[c] < 0 || grid_of_cell[c] >= n_grids)
+            return fail(BZ_EINVAL, "bz_batch_create: grid index out of range");
+    std::unique_ptr<bz_batch_s> b(new (std::nothrow) bz_batch_s());
+    if (!b) return fail(BZ_ENOMEM, "bz_batch_create: allocation failed");
+    b->mode = mode;
+    b->n_cells = n_cells;
+    b->grids.assign(grids, grids + n_grids);
+    b->grid_of_cell.assign(grid_of_cell, grid_of_cell + n_cells);
+    b->cell_off.resize(n_cells);
+    size_t off = 0;
+    for (int c = 0; c < n_cells; ++c) {
+        b->cell_off[c] = (long long)off;
+        const int N = grids[grid_of_cell[c]]->N;
+        off += (size_t)N * N * N;
+    }
+    b->elems = off;
+    // parts, largest mesh first (longest-processing-time order)
+    std::vector<int> order(n_grids);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return grids[x]->N > grids[y]->N; });
+    for (int gi : order) {
+        Part p;
+        p.g = grids[gi];
+        p.gi = gi;
+        for (int c = 0; c < n_cells; ++c)
+            if (grid_of_cell[c] == gi) p.cells.push_back(c);
+        if (p.cells.empty()) continue;
+        p.groups = (int)((p.cells.size() + kWave - 1) / kWave);
+        b->parts.push_back(std::move(p));
+    }
+    // host tables, then one device buffer for all of them
+    const bool bat = batched(mode);
+    const bool f64 = mode_f64(mode);
+    std::vector<char> host;
+    auto put = [&host](const void *src, size_t bytes) {
+        size_t o = align256(host.size());
+        host.resize(o + bytes);
+        std::memcpy(host.data() + o, src, bytes);
+        return o;
+    };
+    struct Offs { size_t f_off, fh_base, row, blk, zero, items; };
+    std::vector<Offs> offs;
+    size_t ws = 0, scratch = 0;
+    for (Part &p : b->parts) {
+        const int N = p.g->N;
+        const long long M = (long long)N * N * N;
+        Offs o{};
+        p.f_off.resize(p.cells.size());
+        std::vector<long long> base(p.cells.size());
+        for (size_t i = 0; i < p.cells.size(); ++i) {
+            p.f_off[i] = b->cell_off[p.cells[i]];
+            base[i] = bat ? (long long)(i / kWave) * M * kWave + (long long)(i % kWave) : 0;
+        }
+        o.f_off = put(p.f_off.data(), p.f_off.size() * sizeof(long long));
+        o.fh_base = put(base.data(), base.size() * sizeof(long long));
+        long long zero = 0;
+        o.zero = put(&zero, sizeof zero);
+        o.row = put(p.g->sched.row_woff.data(), p.g->sched.row_woff.size() * sizeof(long long));
+        o.blk = put(p.g->sched.blk_woff.data(), p.g->sched.blk_woff.size() * sizeof(long long));
+        if (bat) {
+            std::vector<int2> items;
+            items.reserve((size_t)p.groups * N * N);
+            for (int gq = 0; gq < p.groups; ++gq)
+                for (int r = 0; r < N * N; ++r) items.push_back(make_int2(gq, r));
+            const std::vector<int> &st = p.g->sched.row_steps;
+            std::stable_sort(items.begin(), items.end(),
+                             [&](const int2 &x, const int2 &y) { return st[x.y] > st[y.y]; });
+            p.n_items = (int)items.size();
+            o.items = put(items.data(), items.size() * sizeof(int2));
+        }
+        offs.push_back(o);
+        // workspace: fhat, qhat, counter
+        const size_t cs = f64 ? 16 : 8;
+        if (bat) {
+            p.ws_fh = ws;
+            ws = align256(ws + (size_t)p.groups * M * kWave * cs);
+            p.ws_qh = ws;
+            ws = align256(ws + (size_t)p.groups * M * kWave * 16);
+        } else {
+            const int sp = plain_split_for(N);
+            p.ws_fh = ws;
+            ws = align256(ws + (size_t)M * cs);
+            p.ws_qh = ws;
+            ws = align256(ws + (size_t)sp * M * 16);
+        }
+        p.ws_counter = ws;
+        ws = align256(ws + 256);
+        const size_t sc = (bat ? p.cells.size() : 1) * (size_t)M * 16;
+        scratch = std::max(scratch, sc);
+    }
+    b->ws_scratch = ws;
+    ws = align256(ws + scratch);
+    b->ws_flag = ws;
+    ws = align256(ws + 256);
+    b->ws_total = ws;
+    if (!host.empty()) {
+        hipError_t e = hipMalloc(&b->d_tables, host.size());
+        if (e != hipSuccess) return hip_fail(e, "bz_batch_create: hipMalloc tables");
+        e = hipMemcpy(b->d_tables, host.data(), host.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(b->d_tables);
+            return hip_fail(e, "bz_batch_create: upload tables");
+        }
+    }
+    char *base = (char *)b->d_tables;
+    for (size_t i = 0; i < b->parts.size(); ++i) {
+        Part &p = b->parts[i];
+        p.d_f_off = (long long *)(base + offs[i].f_off);
+        p.d_fh_base = (long long *)(base + offs[i].fh_base);
+        p.d_zero = (long long *)(base + offs[i].zero);
+        p.d_row_woff = (long long *)(base + offs[i].row);
+        p.d_blk_woff = (long long *)(base + offs[i].blk);
+        p.d_items = bat ? (int2 *)(base + offs[i].items) : nullptr;
+    }
+    *out = b.release();
+    return BZ_OK;
+}
+
+void bz_batch_free(bz_batch b) {
+    if (!b) return;
+    if (b->d_tables) (void)hipFree(b->d_tables);
+    delete b;
+}
+
+bz_status bz_batch_set_weights(bz_batch b, int grid_index, int kind, const void *d_w) {
+    if (!b || !d_w) return fail(BZ_EINVAL, "bz_batch_set_weights: NULL argument");
+    if (grid_index < 0 || grid_index >= (int)b->grids.size())
+        return fail(BZ_EINVAL, "bz_batch_set_weights: grid index out of range");
+    if (kind != mode_wkind(b->mode))
+        return fail(BZ_EINVAL, "bz_batch_set_weights: weight kind does not match the batch mode");
+    for (Part &p : b->parts)
+        if (p.gi == grid_index) {
+            p.w = d_w;
+            p.wkind = kind;
+        }
+    return BZ_OK;
+}
+
+size_t bz_batch_elems(bz_batch b) { return b ? b->elems : 0; }
+size_t bz_batch_cell_offset(bz_batch b, int cell) {
+    if (!b || cell < 0 || cell >= b->n_cells) return 0;
+    return (size_t)b->cell_off[cell];
+}
+size_t bz_workspace_bytes(bz_batch b) { return b ? b->ws_total : 0; }
+size_t bz_step_workspace_bytes(bz_batch b) { return b ? align256(b->ws_total) + 2 * align256(b->elems * 8) : 0; }
+
+bz_status bz_collide_batch(bz_batch b, const double *d_f, double *d_Qt, void *d_work, size_t work_bytes,
+                           void *stream) {
+    if (!b || !d_f || !d_Qt || !d_work) return fail(BZ_EINVAL, "bz_collide_batch: NULL argument");
+    if (work_bytes < b->ws_total) return fail(BZ_EINVAL, "bz_collide_batch: workspace too small");
+    if ((const void *)d_f == (const void *)d_Qt) return fail(BZ_EINVAL, "bz_collide_batch: f and Qt alias");
+    for (const Part &p : b->parts)
+        if (!p.w) return fail(BZ_ESTATE, "bz_collide_batch: no weights bound for a mesh of the batch");
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)d_work;
+    double2 *scratch = (double2 *)(ws + b->ws_scratch);
+    const bool f64 = mode_f64(b->mode);
+    for (const Part &p : b->parts) {
+        const int N = p.g->N;
+        const long long M = (long long)N * N * N;
+        void *fh = ws + p.ws_fh;
+        double2 *qh = (double2 *)(ws + p.ws_qh);
+        if (batched(b->mode)) {
+            const int nc = (int)p.cells.size();
+            BZ_HIP(launch_dft_forward(N, p.g->L, nc, d_f, p.d_f_off, scratch, fh, !f64, p.d_fh_base, kWave, s),
+                   "forward transform");
+            CellsLaunch cl{N, fh, p.w, p.d_row_woff, p.d_items, p.n_items, (unsigned *)(ws + p.ws_counter), qh,
+                           b->variant};
+            BZ_HIP(launch_conv_cells(cl, f64, s), "batched convolution");
+            BZ_HIP(launch_dft_inverse(N, p.g->L, nc, qh, p.d_fh_base, kWave, 1, 0, scratch, d_Qt, p.d_f_off, s),
+                   "inverse transform");
+        } else {
+            const int sp = plain_split_for(N);
+            for (size_t i = 0; i < p.cells.size(); ++i) {
+                BZ_HIP(launch_dft_forward(N, p.g->L, 1, d_f, p.d_f_off + i, scratch, fh, !f64, p.d_zero, 1, s),
+                       "forward transform");
+                PlainLaunch pl{N, fh, p.w, p.d_blk_woff, sp, qh};
+                BZ_HIP(launch_conv_plain(pl, f64, s), "plain convolution");
+                BZ_HIP(launch_dft_inverse(N, p.g->L, 1, qh, p.d_zero, 1, sp, M, scratch, d_Qt, p.d_f_off + i, s),
+                       "inverse transform");
+            }
+        }
+    }
+    return BZ_OK;
+}
+
+bz_status bz_project(bz_batch b, double *d_Q, void *stream) {
+    if (!b || !d_Q) return fail(BZ_EINVAL, "bz_project: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    for (const Part &p : b->parts)
+        BZ_HIP(launch_project(p.g->N, p.g->dv, p.g->linv, (int)p.cells.size(), d_Q, p.d_f_off, s), "projection");
+    return BZ_OK;
+}
+
+bz_status bz_step(bz_batch b, double *d_f, double dt_over_eps, void *d_work, size_t work_bytes, void *stream) {
+    if (!b || !d_f || !d_work) return fail(BZ_EINVAL, "bz_step: NULL argument");
+    if (work_bytes < bz_step_workspace_bytes(b)) return fail(BZ_EINVAL, "bz_step: workspace too small");
+    if (!std::isfinite(dt_over_eps)) return fail(BZ_EINVAL, "bz_step: dt/eps must be finite");
+    for (const Part &p : b->parts)
+        if (!p.w) return fail(BZ_ESTATE, "bz_step: no weights bound for a mesh of the batch");
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)d_work;
+    double *q = (double *)(ws + align256(b->ws_total));
+    double *fs = (double *)(ws + align256(b->ws_total) + align256(b->elems * 8));
+    unsigned *flag = (unsigned *)(ws + b->ws_flag);
+    bz_status st = bz_collide_batch(b, d_f, q, d_work, b->ws_total, stream);
+    if (st != BZ_OK) return st;
+    if ((st = bz_project(b, q, stream)) != BZ_OK) return st;
+    BZ_HIP(launch_axpy(b->elems, d_f, q, dt_over_eps, fs, flag, s), "heun stage 1");
+    if ((st = bz_collide_batch(b, fs, q, d_work, b->ws_total, stream)) != BZ_OK) return st;
+    if ((st = bz_project(b, q, stream)) != BZ_OK) return st;
+    BZ_HIP(launch_heun_final(b->elems, d_f, fs, q, dt_over_eps, d_f, flag, s), "heun stage 2");
+    return BZ_OK;
+}
+
+bz_status bz_step_check(bz_batch b, void *d_work, void *stream) {
+    if (!b || !d_work) return fail(BZ_EINVAL, "bz_step_check: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned *flag = (unsigned *)((char *)d_work + b->ws_flag);
+    unsigned h = 0;
+    BZ_HIP(hipMemcpyAsync(&h, flag, sizeof h, hipMemcpyDeviceToHost, s), "bz_step_check: read flag");
+    BZ_HIP(hipStreamSynchronize(s), "bz_step_check: sync");
+    if (h) {
+        BZ_HIP(launch_fill_u32(flag, 1, 0u, s), "bz_step_check: clear flag");
+        return fail(BZ_ENONFINITE, "bz_step: a non-finite value was produced");
+    }
+    return BZ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point include/bz.h declares, validates arguments before touching
+the device, and its schedules cover exactly the pairs of Sec. 3.2."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1211_0540_amd import bz
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "bz.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bz_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = bz.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert bz.bz_api_version() == 1
+
+
+def test_grid_validation_errors():
+    for N, L, lam, st in [(7, 6.0, 1.0, bz.BZ_EINVAL), (36, 6.0, 1.0, bz.BZ_EINVAL), (18, 6.0, 1.0, bz.BZ_EINVAL),
+                          (16, -1.0, 1.0, bz.BZ_EINVAL), (16, float("nan"), 1.0, bz.BZ_EINVAL),
+                          (16, 6.0, 0.5, bz.BZ_EUNSUPPORTED)]:
+        with pytest.raises(bz.BzError) as e:
+            bz.bz_grid_init(N, L, lam)
+        assert e.value.status == st
+
+
+@pytest.mark.parametrize("N,L", [(8, 4.0), (16, 6.0), (24, 7.0), (32, 8.0)])
+def test_grid_query(N, L):
+    g = bz.bz_grid_init(N, L, 1.0)
+    try:
+        q = bz.bz_grid_query(g)
+        assert q["pairs"] == (3 * N * N // 4) ** 3
+        assert q["dv"] == pytest.approx(2 * L / N) and q["dzeta"] == pytest.approx(np.pi / L)
+        v, z = bz.bz_grid_coords(g)
+        assert np.allclose(v, (2 * L / N) * (np.arange(N) - N // 2))
+        assert np.allclose(z, (np.pi / L) * (np.arange(N) - N // 2))
+    finally:
+        bz.bz_grid_free(g)
+
+
+def _axis_range(N, k):
+    return max(0, k - N // 2 + 1), min(N - 1, k + N // 2)
+
+
+@pytest.mark.parametrize("N", [8, 12, 16, 24, 32])
+def test_batched_schedule_visits_each_unordered_pair_once(N):
+    """Steps (m1, m2) <= (j1, j2) per output row, 3N^2/4 slots each: the number of
+    slots equals the byte count of the batched weight buffer."""
+    h = N // 2
+    steps = 0
+    for k1 in range(N):
+        for k2 in range(N):
+            lo1, hi1 = _axis_range(N, k1)
+            lo2, hi2 = _axis_range(N, k2)
+            for m1 in range(lo1, hi1 + 1):
+                for m2 in range(lo2, hi2 + 1):
+                    if (m1, m2) <= (k1 + h - m1, k2 + h - m2):
+                        steps += 1
+    g = bz.bz_grid_init(N, 6.0, 1.0)
+    try:
+        assert bz.bz_weights_bytes(g, bz.BZ_W_BATCHED_F32) == steps * (3 * N * N // 4) * 4
+        assert bz.bz_weights_bytes(g, bz.BZ_W_BATCHED_F64) == steps * (3 * N * N // 4) * 8
+        # the visited slots cover every unordered pair: (P + D) / 2 <= slots
+        P = (3 * N * N // 4) ** 3
+        assert 2 * steps * (3 * N * N // 4) >= P
+    finally:
+        bz.bz_grid_free(g)
+
+
+@pytest.mark.parametrize("N", [8, 12, 16, 24, 32])
+def test_plain_schedule_size(N):
+    R = 64 // N
+    while R > 1 and N % R:
+        R -= 1
+    tot = 0
+    for k1 in range(N):
+        lo1, hi1 = _axis_range(N, k1)
+        for kb in range(N // R):
+            u_lo = _axis_range(N, kb * R)[0]
+            u_hi = _axis_range(N, kb * R + R - 1)[1]
+            tot += (hi1 - lo1 + 1) * (u_hi - u_lo + 1) * N * R * N
+    g = bz.bz_grid_init(N, 6.0, 0.0)
+    try:
+        assert bz.bz_weights_bytes(g, bz.BZ_W_PLAIN_F64) == tot * 8
+        assert bz.bz_weights_bytes(g, 99) == 0
+    finally:
+        bz.bz_grid_free(g)
+
+
+def test_batch_validation_errors_before_device_work():
+    g = bz.bz_grid_init(8, 4.0, 1.0)
+    try:
+        for goc, mode in [([], bz.BZ_MODE_BATCHED_F32), ([0, 1], bz.BZ_MODE_BATCHED_F32), ([0], 17)]:
+            with pytest.raises(bz.BzError) as e:
+                bz.bz_batch_create(goc, [g], mode)
+            assert e.value.status == bz.BZ_EINVAL
+    finally:
+        bz.bz_grid_free(g)
+
+
+def test_status_strings():
+    L = bz.lib()
+    assert L.bz_status_string(0) == b"ok"
+    assert L.bz_status_string(-5) == b"non-finite value"

@@ -1,0 +1,251 @@
+"""Parity of the HIP collision path with the FP64 oracle (GPU, through the C ABI).
+
+Bars (the tolerances are derived in the design notes):
+  FP64 paths       max |Q_gpu - Q_oracle| <= 1e-12 max |Q_oracle|
+  FP32 batched     per-cell relative L2 of the projected Q <= 1e-5 on inputs
+                   whose cancellation factor is moderate (mixtures, bi-
+                   Maxwellians); for near-equilibrium inputs the bound is
+                   8 u32 kappa with kappa = ||sum |terms| || / ||Qhat|| measured
+                   by the oracle-side estimate below.
+  conservation     |sum_j w phi_j Q_j| <= 1e-12 sum_j w |phi_j Q_j| per invariant
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1211_0540_amd import bz
+from paper_1211_0540_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    bz.lib()
+    return torch.device("cuda:0")
+
+
+_ORACLES = {}
+
+
+def oracle_for(N, L, lam):
+    key = (N, float(L), float(lam))
+    if key not in _ORACLES:
+        _ORACLES[key] = O.Oracle(N, L, lam)
+    return _ORACLES[key]
+
+
+_WCACHE = {}
+
+
+def run(meshes, goc, cells, mode, dev, project=True):
+    c = bz.Collision(meshes, goc, mode, weights_cache=_WCACHE)
+    f = torch.from_numpy(c.pack(cells)).to(dev)
+    qt = c.collide(f)
+    q = qt.clone()
+    if project:
+        c.project(q)
+    torch.cuda.synchronize()
+    out = (c.unpack(qt.cpu().numpy()), c.unpack(q.cpu().numpy()))
+    c.close()
+    return out
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def max_rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def constraints(N, L):
+    v, _, dv, _ = O.grid(N, L)
+    V = np.meshgrid(v, v, v, indexing="ij")
+    rows = [np.ones_like(V[0]), V[0], V[1], V[2], V[0] ** 2 + V[1] ** 2 + V[2] ** 2]
+    return [r * dv ** 3 for r in rows]
+
+
+def assert_conserved(q, N, L, tol=1e-12):
+    for c in constraints(N, L):
+        assert abs((c * q).sum()) <= tol * np.abs(c * q).sum()
+
+
+# ---------------------------------------------------------------------------
+# FP64 paths: the plain baseline and the batched FP64 schedule
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", ["plain_f64", "batched_f64"])
+def test_mixture_cell_fp64(dev, mode):
+    """One Maxwell-molecule cell on N=16, L=6 (two counter-streaming Maxwellians)."""
+    N, L, lam = 16, 6.0, 0.0
+    f = W.single_cell_mixture(N, L)
+    qt_o, q_o, _, _ = oracle_for(N, L, lam).collide(f)
+    (qt,), (q,) = run([(N, L, lam)], [0], [f], mode, dev)
+    assert max_rel(qt, qt_o) < 1e-12
+    assert max_rel(q, q_o) < 1e-12
+    assert_conserved(q, N, L)
+
+
+@pytest.mark.parametrize("mode", ["plain_f64", "batched_f64"])
+def test_ragged_batch_fp64_hard_spheres(dev, mode):
+    """70 cells on N=12 (one full wavefront group and a ragged tail of 6)."""
+    N, L, lam = 12, 5.0, 1.0
+    n = 70 if mode == "batched_f64" else 5
+    cells = list(W.random_smooth_cells(n, N, L, seed=3, umax=0.7))
+    qts, qs = run([(N, L, lam)], [0] * n, cells, mode, dev)
+    o = oracle_for(N, L, lam)
+    for i in range(n):
+        qt_o, q_o, _, _ = o.collide(cells[i])
+        assert max_rel(qts[i], qt_o) < 1e-12, i
+        assert max_rel(qs[i], q_o) < 1e-12, i
+
+
+# ---------------------------------------------------------------------------
+# FP32 batched path with compensated accumulation
+# ---------------------------------------------------------------------------
+def test_mixture_cell_fp32_batched(dev):
+    N, L, lam = 16, 6.0, 0.0
+    f = W.single_cell_mixture(N, L)
+    _, q_o, _, _ = oracle_for(N, L, lam).collide(f)
+    _, (q,) = run([(N, L, lam)], [0], [f], "batched_f32", dev)
+    assert rel_l2(q, q_o) < 1e-5
+    assert_conserved(q, N, L)
+
+
+@pytest.mark.parametrize("mode", ["batched_f32", "plain_f32"])
+def test_relaxation_cell_n32(dev, mode):
+    """The N=32, L=8 hard-sphere bi-Maxwellian (T = 2, 1/2, 1/2) of the relaxation problem."""
+    N, L, lam = 32, 8.0, 1.0
+    f = W.relaxation_cell(N, L)
+    _, q_o, _, _ = oracle_for(N, L, lam).collide(f)
+    _, (q,) = run([(N, L, lam)], [0], [f], mode, dev)
+    assert rel_l2(q, q_o) < 1e-5
+    assert_conserved(q, N, L)
+
+
+def test_relaxation_cell_n32_fp64_plain(dev):
+    N, L, lam = 32, 8.0, 1.0
+    f = W.relaxation_cell(N, L)
+    qt_o, q_o, _, _ = oracle_for(N, L, lam).collide(f)
+    (qt,), (q,) = run([(N, L, lam)], [0], [f], "plain_f64", dev)
+    assert max_rel(qt, qt_o) < 1e-12
+    assert max_rel(q, q_o) < 1e-12
+
+
+def _kappa(f, N, L, lam):
+    return oracle_for(N, L, lam).kappa(f)
+
+
+def test_uneven_mixed_mesh_batch_fp32(dev):
+    """A 96-cell sample of the 1024-cell uneven draw (N in {16, 24, 32}) in one batch."""
+    full = W.uneven_batch(n_cells=96)
+    meshes = [(16, 6.0, 1.0), (24, 7.0, 1.0), (32, 8.0, 1.0)]
+    idx = {16: 0, 24: 1, 32: 2}
+    goc = [idx[int(n)] for n in full.Ns]
+    _, qs = run(meshes, goc, full.cells, "batched_f32", dev)
+    errs = []
+    for i in range(len(full.cells)):
+        N = int(full.Ns[i])
+        L = W.DOMAIN_FOR_N[N]
+        _, q_o, _, _ = oracle_for(N, L, 1.0).collide(full.cells[i])
+        e = rel_l2(qs[i], q_o)
+        errs.append(e)
+        kap = _kappa(full.cells[i], N, L, 1.0)
+        assert e < max(1e-5, 8 * U32 * kap), (i, N, e, kap)
+        assert_conserved(qs[i], N, L)
+    print("uneven batch FP32 rel L2: median %.2e max %.2e" % (np.median(errs), np.max(errs)))
+
+
+def test_shock_cells_fp32_full_size(dev):
+    """All 256 cells of the N=24, L=7 shock problem in one launch; 8 sampled against the oracle."""
+    N, L, lam = 24, 7.0, 1.0
+    cells = list(W.random_smooth_cells(256, N, L, seed=5, umax=1.0))
+    _, qs = run([(N, L, lam)], [0] * 256, cells, "batched_f32", dev)
+    o = oracle_for(N, L, lam)
+    for i in np.random.default_rng(0).choice(256, 8, replace=False):
+        _, q_o, _, _ = o.collide(cells[i])
+        kap = _kappa(cells[i], N, L, lam)
+        assert rel_l2(qs[i], q_o) < max(1e-5, 8 * U32 * kap)
+
+
+def test_batched_fp32_is_deterministic(dev):
+    N, L, lam = 16, 6.0, 1.0
+    cells = list(W.random_smooth_cells(80, N, L, seed=9))
+    a, _ = run([(N, L, lam)], [0] * 80, cells, "batched_f32", dev, project=False)
+    b, _ = run([(N, L, lam)], [0] * 80, cells, "batched_f32", dev, project=False)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+# ---------------------------------------------------------------------------
+# Projection and time stepping
+# ---------------------------------------------------------------------------
+def test_projection_matches_oracle_and_conserves(dev):
+    rng = np.random.default_rng(1)
+    meshes = [(16, 6.0, 1.0), (32, 8.0, 1.0)]
+    qt = [rng.standard_normal((16, 16, 16)), rng.standard_normal((32, 32, 32))]
+    c = bz.Collision(meshes, [0, 1], "batched_f32", weights_cache=_WCACHE)
+    q = torch.from_numpy(c.pack(qt)).to(dev)
+    c.project(q)
+    out = c.unpack(q.cpu().numpy())
+    for x, ref, (N, L, _) in zip(out, qt, meshes):
+        assert max_rel(x, O.project(ref, L)) < 1e-12
+        assert_conserved(x, N, L)
+    c.close()
+
+
+@pytest.mark.parametrize("mode,tol", [("plain_f64", 1e-11), ("batched_f32", 1e-5)])
+def test_heun_step_matches_oracle(dev, mode, tol):
+    """Three Heun steps of the homogeneous equation, dt = 0.05, eps = 1."""
+    N, L, lam = 16, 6.0, 1.0
+    f0 = W.relaxation_cell(N, L)
+    ref = oracle_for(N, L, lam).rk2(f0, 0.05, 1.0, 3)
+    c = bz.Collision([(N, L, lam)], [0], mode, weights_cache=_WCACHE)
+    f = torch.from_numpy(c.pack([f0])).to(dev)
+    for _ in range(3):
+        c.step(f, 0.05)
+    c.check()
+    got = c.unpack(f.cpu().numpy())[0]
+    assert rel_l2(got - f0, ref - f0) < tol
+    c.close()
+
+
+def test_nonfinite_input_is_reported(dev):
+    N, L, lam = 8, 4.0, 1.0
+    f0 = W.maxwellian(N, L, 1.0, (0, 0, 0), 1.0)
+    f0[3, 3, 3] = np.nan
+    c = bz.Collision([(N, L, lam)], [0], "batched_f32", weights_cache=_WCACHE)
+    f = torch.from_numpy(c.pack([f0])).to(dev)
+    c.step(f, 0.01)
+    with pytest.raises(bz.BzError) as e:
+        c.check()
+    assert e.value.status == bz.BZ_ENONFINITE
+    c.check()  # the flag was cleared
+    c.close()
+
+
+def test_unbound_weights_and_short_workspace(dev):
+    g = bz.bz_grid_init(8, 4.0, 1.0)
+    b = bz.bz_batch_create([0], [g], bz.BZ_MODE_BATCHED_F32)
+    f = torch.zeros(512, dtype=torch.float64, device=dev)
+    q = torch.zeros_like(f)
+    work = torch.zeros(bz.bz_workspace_bytes(b), dtype=torch.uint8, device=dev)
+    with pytest.raises(bz.BzError) as e:
+        bz.bz_collide_batch(b, f, q, work)
+    assert e.value.status == bz.BZ_ESTATE
+    buf = torch.empty(bz.bz_weights_bytes(g, bz.BZ_W_BATCHED_F32), dtype=torch.uint8, device=dev)
+    bz.bz_weights(g, bz.BZ_W_BATCHED_F32, buf)
+    with pytest.raises(bz.BzError):
+        bz.bz_batch_set_weights(b, 0, bz.BZ_W_PLAIN_F64, buf)
+    bz.bz_batch_set_weights(b, 0, bz.BZ_W_BATCHED_F32, buf)
+    with pytest.raises(bz.BzError) as e:
+        bz.bz_collide_batch(b, f, q, work[:16])
+    assert e.value.status == bz.BZ_EINVAL
+    bz.bz_collide_batch(b, f, q, work)
+    torch.cuda.synchronize()
+    bz.bz_batch_free(b)
+    bz.bz_grid_free(g)
