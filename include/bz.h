@@ -163,6 +163,31 @@ bz_status bz_step(bz_batch b, double *d_f, double dt_over_eps, void *d_work, siz
  * (then clears the flag), BZ_OK otherwise. */
 bz_status bz_step_check(bz_batch b, void *d_work, void *stream);
 
+/* ------------------------------------------------------------------ */
+/* Tuning and measurement.                                               */
+/* ------------------------------------------------------------------ */
+/* Select the convolution kernel variant for the cells of grids[grid_index]
+ * (batched modes; 0 is the default, bz_variant_count() variants exist).
+ * Every variant computes the same sums; they differ in compensation, fold
+ * interval and how weights reach the arithmetic units. */
+int bz_variant_count(void);
+bz_status bz_batch_set_variant(bz_batch b, int grid_index, int variant);
+int bz_batch_get_variant(bz_batch b, int grid_index);
+/* Time every variant on this batch's data (d_f, d_work as for
+ * bz_collide_batch; d_Qt receives a result), `reps` launches each, with HIP
+ * events on `stream`, and keep the fastest per mesh.  Synchronous.  The
+ * result is also remembered per (N, number of wavefront groups, mode) for
+ * the rest of the process. */
+bz_status bz_batch_autotune(bz_batch b, const double *d_f, double *d_Qt, void *d_work, size_t work_bytes,
+                            int reps, void *stream);
+/* enable = 1: record a HIP event pair around every convolution launch of
+ * this batch (on the stream the launch uses); enable = 0: stop recording.
+ * bz_batch_timer_read synchronises on the recorded events, returns the
+ * summed kernel time in milliseconds and the number of launches, and clears
+ * the record. */
+bz_status bz_batch_timer(bz_batch b, int enable);
+bz_status bz_batch_timer_read(bz_batch b, double *conv_ms, int *launches);
+
 const char *bz_status_string(bz_status s);
 const char *bz_last_error(void);
 int bz_api_version(void);

@@ -71,6 +71,12 @@ def lib():
         "bz_step_workspace_bytes": (_sz, [_vp]),
         "bz_step": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _vp, _sz, _vp]),
         "bz_step_check": (ctypes.c_int, [_vp, _vp, _vp]),
+        "bz_variant_count": (ctypes.c_int, []),
+        "bz_batch_set_variant": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+        "bz_batch_get_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "bz_batch_autotune": (ctypes.c_int, [_vp, _vp, _vp, _vp, _sz, ctypes.c_int, _vp]),
+        "bz_batch_timer": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "bz_batch_timer_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -203,6 +209,34 @@ def bz_step_check(b: int, work, stream=None) -> None:
     _check(lib().bz_step_check(_vp(b), _vp(_ptr(work)), _stream(stream)))
 
 
+def bz_variant_count() -> int:
+    return int(lib().bz_variant_count())
+
+
+def bz_batch_set_variant(b: int, grid_index: int, variant: int) -> None:
+    _check(lib().bz_batch_set_variant(_vp(b), int(grid_index), int(variant)))
+
+
+def bz_batch_get_variant(b: int, grid_index: int) -> int:
+    return int(lib().bz_batch_get_variant(_vp(b), int(grid_index)))
+
+
+def bz_batch_autotune(b: int, f, qt, work, reps: int = 2, stream=None) -> None:
+    _check(lib().bz_batch_autotune(_vp(b), _vp(_ptr(f)), _vp(_ptr(qt)), _vp(_ptr(work)),
+                                   work.numel() * work.element_size(), int(reps), _stream(stream)))
+
+
+def bz_batch_timer(b: int, enable: bool) -> None:
+    _check(lib().bz_batch_timer(_vp(b), 1 if enable else 0))
+
+
+def bz_batch_timer_read(b: int):
+    ms = ctypes.c_double()
+    n = ctypes.c_int()
+    _check(lib().bz_batch_timer_read(_vp(b), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
 # ---------------------------------------------------------------------------
 # Convenience owner of handles and device buffers (still only marshalling).
 # ---------------------------------------------------------------------------
@@ -250,6 +284,16 @@ class Collision:
     def step(self, f, dt_over_eps, stream=None):
         bz_step(self.batch, f, dt_over_eps, self.work, stream)
         return f
+
+    def set_variant(self, variant: int, grid_index=None):
+        for gi in range(len(self.grids)) if grid_index is None else [grid_index]:
+            bz_batch_set_variant(self.batch, gi, variant)
+
+    def autotune(self, f, reps: int = 2, stream=None):
+        import torch
+        q = torch.empty(self.elems, dtype=torch.float64, device=f.device)
+        bz_batch_autotune(self.batch, f, q, self.work, reps, stream)
+        return [bz_batch_get_variant(self.batch, gi) for gi in range(len(self.grids))]
 
     def check(self, stream=None):
         bz_step_check(self.batch, self.work, stream)

@@ -5,9 +5,14 @@
 // Two schedules:
 //
 // * Batched (lane = cell).  64 cells of one mesh share a wavefront, so every
-//   weight is wavefront-uniform: it is read once per 64 cells through the
-//   scalar cache (s_load, SGPR operand of the FMA) and never touches VGPRs or
-//   LDS.  A work item is one output row (k1, k2, 0..N-1) of 64 cells; it keeps
+//   weight is wavefront-uniform and is read once per 64 cells.  The weights of
+//   a step are contiguous; while a step runs, the next step's weights are
+//   copied HBM -> LDS by one coalesced direct-to-LDS load per 1 KiB
+//   (global_load_lds_dwordx4) into the other half of a per-wave double buffer,
+//   and the running step reads its weights with broadcast LDS reads.  (Reading
+//   them through the scalar cache instead leaves only a few 64-byte requests in
+//   flight and stalls every step on HBM latency.)  A work item is a range of
+//   steps of one output row (k1, k2, 0..N-1) of 64 cells; it keeps
 //   the row's N accumulators and, per step (m1, m2), the rows fhat(m1, m2, .)
 //   and fhat(j1, j2, .) of its own cell in registers (cell-interleaved layout,
 //   coalesced 512-byte loads).  Each unordered pair {m, j} is visited once
@@ -64,9 +69,9 @@ __device__ inline void two_sum_acc(float &hi, float &lo, float p) {
 }
 
 // One step of the batched schedule for one row: accumulate all (k3, m3) pairs.
-template <typename T, int N>
+template <typename T, int N, typename WP>
 __device__ __forceinline__ void cells_step(const typename cplx<T>::t (&mv)[N], const typename cplx<T>::t (&jv)[N],
-                                           const T *__restrict__ w, T (&pr)[N], T (&pi)[N]) {
+                                           WP w, T (&pr)[N], T (&pi)[N]) {
     constexpr int h = N / 2;
 #pragma unroll
     for (int m3 = 0; m3 < N; ++m3) {
@@ -91,6 +96,31 @@ __device__ __forceinline__ void load_row(const typename cplx<T>::t *__restrict__
     for (int t = 0; t < N; ++t) v[t] = p[t * kWave];
 }
 
+// Copy `chunks` KiB of a step's weights from global memory to LDS: each lane
+// moves 16 bytes per chunk, the wave 1 KiB, landing contiguously at dst.
+template <int CHUNKS>
+__device__ __forceinline__ void prefetch_weights(const void *src, void *dst) {
+    const char *g = (const char *)src + threadIdx.x * 16;
+#pragma unroll
+    for (int c = 0; c < CHUNKS; ++c)
+        __builtin_amdgcn_global_load_lds((const void *)(g + c * 1024),
+                                         (__attribute__((address_space(3))) void *)((char *)dst + c * 1024), 16, 0, 0);
+}
+
+// Position (m1, m2) of step index s0 in the row's step enumeration.
+template <int N>
+__device__ __forceinline__ void seek_step(int k1, int k2, int s0, int &m1, int &m2) {
+    const int lo2 = axis_lo(N, k2);
+    m1 = axis_lo(N, k1);
+    for (;;) {
+        const int cnt = cells_m2_last(N, k1, k2, m1) - lo2 + 1;
+        if (s0 < cnt) break;
+        s0 -= cnt;
+        ++m1;
+    }
+    m2 = lo2 + s0;
+}
+
 __device__ inline int pop_item(unsigned *counter) {
     unsigned it = 0;
     if (threadIdx.x == 0) it = atomicAdd(counter, 1u);
@@ -100,20 +130,23 @@ __device__ inline int pop_item(unsigned *counter) {
 // ---------------------------------------------------------------------------
 // Batched FP32 with compensated accumulation.
 // ---------------------------------------------------------------------------
-template <int N, int FOLD, int COMP>
+template <int N, int FOLD, int COMP, int WP>
 __global__ void __launch_bounds__(64) k_conv_cells_f32(const float2 *__restrict__ fh, const float *__restrict__ W,
                                                        const long long *__restrict__ row_woff,
-                                                       const int2 *__restrict__ items, int n_items,
-                                                       unsigned *__restrict__ counter, double2 *__restrict__ qh) {
+                                                       const int4 *__restrict__ items, int n_items,
+                                                       unsigned *__restrict__ counter, double2 *__restrict__ qh,
+                                                       long long part_stride) {
     constexpr int h = N / 2, M = N * N * N, PS = 3 * N * N / 4;
+    constexpr int CH = (PS * 4 + 1023) / 1024;
+    __shared__ __attribute__((aligned(16))) float wbuf[2][CH * 256];
     const int lane = threadIdx.x;
     for (;;) {
         const int it = pop_item(counter);
         if (it >= n_items) break;
-        const int2 item = items[it];
-        const int g = item.x, r = item.y;
+        const int4 item = items[it];
+        const int g = item.x, r = item.y & 0xffff, part = item.y >> 16, s0 = item.z, s1 = item.w;
         const int k1 = r / N, k2 = r - k1 * N;
-        const float *w = W + row_woff[r];
+        const float *w = W + row_woff[r] + (long long)s0 * PS;
         const float2 *F = fh + (size_t)g * M * kWave + lane;
 
         float pr[N], pi[N];
@@ -139,27 +172,46 @@ __global__ void __launch_bounds__(64) k_conv_cells_f32(const float2 *__restrict_
             }
         };
 
-        int nst = 0;
+        int m1, m2;
+        seek_step<N>(k1, k2, s0, m1, m2);
         const int lo2 = axis_lo(N, k2);
-        const int l1 = cells_m1_last(N, k1);
-        for (int m1 = axis_lo(N, k1); m1 <= l1; ++m1) {
-            const int j1 = k1 + h - m1;
-            const int l2 = cells_m2_last(N, k1, k2, m1);
-            for (int m2 = lo2; m2 <= l2; ++m2) {
-                const int j2 = k2 + h - m2;
-                float2 mv[N], jv[N];
-                load_row<float, N>(F + (size_t)((m1 * N + m2) * N) * kWave, mv);
-                load_row<float, N>(F + (size_t)((j1 * N + j2) * N) * kWave, jv);
+        prefetch_weights<CH>(w, wbuf[0]);
+        __builtin_amdgcn_s_waitcnt(0);
+        int buf = 0, nst = 0;
+        for (int s = s0; s < s1; ++s) {
+            const int j1 = k1 + h - m1, j2 = k2 + h - m2;
+            float2 mv[N], jv[N];
+            load_row<float, N>(F + (size_t)((m1 * N + m2) * N) * kWave, mv);
+            load_row<float, N>(F + (size_t)((j1 * N + j2) * N) * kWave, jv);
+            if (WP == 0) {
+                // next step's weights into the other LDS half; this step reads its half
+                prefetch_weights<CH>(w + PS, wbuf[buf ^ 1]);
+                cells_step<float, N>(mv, jv, (const float *)wbuf[buf], pr, pi);
+            } else if (WP == 1) {
+                // next step's weights pulled into L2 (the LDS copy is discarded); this
+                // step's weights, pulled last step, are read through the scalar cache
+                prefetch_weights<CH>(w + PS, wbuf[1]);
+                cells_step<float, N>(mv, jv, (const __attribute__((address_space(4))) float *)w, pr, pi);
+            } else {
+                // as 1, but the weights are read by uniform-address vector loads
+                prefetch_weights<CH>(w + PS, wbuf[1]);
                 cells_step<float, N>(mv, jv, w, pr, pi);
-                w += PS;
-                if (++nst == FOLD) {
-                    fold();
-                    nst = 0;
-                }
             }
+            w += PS;
+            buf ^= 1;
+            if (++nst == FOLD) {
+                fold();
+                nst = 0;
+            }
+            // next (m1, m2) in the row's step order
+            if (++m2 > cells_m2_last(N, k1, k2, m1)) {
+                ++m1;
+                m2 = lo2;
+            }
+            __builtin_amdgcn_s_waitcnt(0);
         }
         fold();
-        double2 *out = qh + (size_t)g * M * kWave + (size_t)r * N * kWave + lane;
+        double2 *out = qh + part * part_stride + (size_t)g * M * kWave + (size_t)r * N * kWave + lane;
 #pragma unroll
         for (int t = 0; t < N; ++t) {
             if (COMP == 1)
@@ -176,36 +228,46 @@ __global__ void __launch_bounds__(64) k_conv_cells_f32(const float2 *__restrict_
 template <int N>
 __global__ void __launch_bounds__(64) k_conv_cells_f64(const double2 *__restrict__ fh, const double *__restrict__ W,
                                                        const long long *__restrict__ row_woff,
-                                                       const int2 *__restrict__ items, int n_items,
-                                                       unsigned *__restrict__ counter, double2 *__restrict__ qh) {
+                                                       const int4 *__restrict__ items, int n_items,
+                                                       unsigned *__restrict__ counter, double2 *__restrict__ qh,
+                                                       long long part_stride) {
     constexpr int h = N / 2, M = N * N * N, PS = 3 * N * N / 4;
+    constexpr int CH = (PS * 8 + 1023) / 1024;
+    __shared__ __attribute__((aligned(16))) double wbuf[2][CH * 128];
     const int lane = threadIdx.x;
     for (;;) {
         const int it = pop_item(counter);
         if (it >= n_items) break;
-        const int2 item = items[it];
-        const int g = item.x, r = item.y;
+        const int4 item = items[it];
+        const int g = item.x, r = item.y & 0xffff, part = item.y >> 16, s0 = item.z, s1 = item.w;
         const int k1 = r / N, k2 = r - k1 * N;
-        const double *w = W + row_woff[r];
+        const double *w = W + row_woff[r] + (long long)s0 * PS;
         const double2 *F = fh + (size_t)g * M * kWave + lane;
         double pr[N], pi[N];
 #pragma unroll
         for (int t = 0; t < N; ++t) pr[t] = pi[t] = 0.0;
+        int m1, m2;
+        seek_step<N>(k1, k2, s0, m1, m2);
         const int lo2 = axis_lo(N, k2);
-        const int l1 = cells_m1_last(N, k1);
-        for (int m1 = axis_lo(N, k1); m1 <= l1; ++m1) {
-            const int j1 = k1 + h - m1;
-            const int l2 = cells_m2_last(N, k1, k2, m1);
-            for (int m2 = lo2; m2 <= l2; ++m2) {
-                const int j2 = k2 + h - m2;
-                double2 mv[N], jv[N];
-                load_row<double, N>(F + (size_t)((m1 * N + m2) * N) * kWave, mv);
-                load_row<double, N>(F + (size_t)((j1 * N + j2) * N) * kWave, jv);
-                cells_step<double, N>(mv, jv, w, pr, pi);
-                w += PS;
+        prefetch_weights<CH>(w, wbuf[0]);
+        __builtin_amdgcn_s_waitcnt(0);
+        int buf = 0;
+        for (int s = s0; s < s1; ++s) {
+            const int j1 = k1 + h - m1, j2 = k2 + h - m2;
+            prefetch_weights<CH>(w + PS, wbuf[buf ^ 1]);
+            double2 mv[N], jv[N];
+            load_row<double, N>(F + (size_t)((m1 * N + m2) * N) * kWave, mv);
+            load_row<double, N>(F + (size_t)((j1 * N + j2) * N) * kWave, jv);
+            cells_step<double, N>(mv, jv, (const double *)wbuf[buf], pr, pi);
+            w += PS;
+            buf ^= 1;
+            if (++m2 > cells_m2_last(N, k1, k2, m1)) {
+                ++m1;
+                m2 = lo2;
             }
+            __builtin_amdgcn_s_waitcnt(0);
         }
-        double2 *out = qh + (size_t)g * M * kWave + (size_t)r * N * kWave + lane;
+        double2 *out = qh + part * part_stride + (size_t)g * M * kWave + (size_t)r * N * kWave + lane;
 #pragma unroll
         for (int t = 0; t < N; ++t) out[t * kWave] = make_double2(pr[t], pi[t]);
     }
@@ -266,29 +328,32 @@ __global__ void __launch_bounds__(64) k_conv_plain(const typename cplx<T>::t *__
     if (active) qh[(size_t)s * M + ((size_t)k1 * N + k2) * N + k3] = make_double2(ar, ai);
 }
 
+// Tuning variants of the batched FP32 kernel: (fold interval, compensation, weight path).
+//   0: FOLD 2, FP64 total, LDS double-buffered weights       (default)
+//   1: FOLD 2, TwoSum (hi, lo) FP32 total, LDS double-buffered weights
+//   2: FOLD 4, FP64 total, scalar weights + L2 prefetch
+//   3: FOLD 2, FP64 total, scalar weights + L2 prefetch
+//   4: FOLD 2, FP64 total, uniform vector loads of the weights + L2 prefetch
 template <int N>
 hipError_t cells_f32_variant(const CellsLaunch &p, unsigned grid, hipStream_t s) {
+#define BZ_CELLS_F32(F, C, WPV)                                                                          \
+    hipLaunchKernelGGL((k_conv_cells_f32<N, F, C, WPV>), dim3(grid), dim3(64), 0, s, (const float2 *)p.fh, \
+                       (const float *)p.w, p.row_woff, p.items, p.n_items, p.counter, p.qh, p.part_stride)
     switch (p.variant) {
-    case 1:
-        hipLaunchKernelGGL((k_conv_cells_f32<N, 2, 1>), dim3(grid), dim3(64), 0, s, (const float2 *)p.fh,
-                           (const float *)p.w, p.row_woff, p.items, p.n_items, p.counter, p.qh);
-        break;
-    case 2:
-        hipLaunchKernelGGL((k_conv_cells_f32<N, 4, 0>), dim3(grid), dim3(64), 0, s, (const float2 *)p.fh,
-                           (const float *)p.w, p.row_woff, p.items, p.n_items, p.counter, p.qh);
-        break;
-    default:
-        hipLaunchKernelGGL((k_conv_cells_f32<N, 2, 0>), dim3(grid), dim3(64), 0, s, (const float2 *)p.fh,
-                           (const float *)p.w, p.row_woff, p.items, p.n_items, p.counter, p.qh);
-        break;
+    case 1: BZ_CELLS_F32(2, 1, 0); break;
+    case 2: BZ_CELLS_F32(4, 0, 1); break;
+    case 3: BZ_CELLS_F32(2, 0, 1); break;
+    case 4: BZ_CELLS_F32(2, 0, 2); break;
+    default: BZ_CELLS_F32(2, 0, 0); break;
     }
+#undef BZ_CELLS_F32
     return hipGetLastError();
 }
 
 template <int N>
 hipError_t cells_f64_launch(const CellsLaunch &p, unsigned grid, hipStream_t s) {
     hipLaunchKernelGGL((k_conv_cells_f64<N>), dim3(grid), dim3(64), 0, s, (const double2 *)p.fh,
-                       (const double *)p.w, p.row_woff, p.items, p.n_items, p.counter, p.qh);
+                       (const double *)p.w, p.row_woff, p.items, p.n_items, p.counter, p.qh, p.part_stride);
     return hipGetLastError();
 }
 
@@ -305,7 +370,9 @@ hipError_t plain_launch(const PlainLaunch &p, hipStream_t s) {
 // Persistent grid: enough single-wave workgroups to keep every SIMD busy.
 static unsigned persistent_grid(int n_items) {
     int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
     unsigned g = (unsigned)cus * 8u;
     return (unsigned)n_items < g ? (unsigned)n_items : g;
 }

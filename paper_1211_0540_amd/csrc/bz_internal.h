@@ -134,16 +134,21 @@ hipError_t launch_dft_inverse(int N, double L, int ncells, const double2 *in, co
                               long long i_stride, int nparts, long long part_stride, double2 *scratch,
                               double *qt, const long long *d_q_off, hipStream_t s);
 
-// Batched convolution over the (group, row) items of one mesh.
+// Weight streams are padded so that the prefetch of the step after a row's last
+// step (1 KiB granules) stays inside the buffer.
+constexpr size_t kWeightPadBytes = 16384;
+
+// Batched convolution over the (group, row, step range) items of one mesh.
 struct CellsLaunch {
     int N;
     const void *fh;              // [G][N^3][64] float2 or double2
     const void *w;               // batched schedule weights
     const long long *row_woff;   // device, N*N
-    const int2 *items;           // device, (group, row), longest first
+    const int4 *items;           // device, (group, row | part << 16, first step, end step), longest first
     int n_items;
     unsigned *counter;           // device, zeroed by the launcher's fill kernel
-    double2 *qh;                 // [G][N^3][64]
+    double2 *qh;                 // [parts][G][N^3][64]
+    long long part_stride;       // complex elements between partial-sum buffers
     int variant;                 // tuning variant
 };
 hipError_t launch_conv_cells(const CellsLaunch &p, bool f64, hipStream_t s);

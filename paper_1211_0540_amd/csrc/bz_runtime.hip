@@ -96,13 +96,10 @@ static bool constraint_linv(int N, double dv, double linv[25]) {
         }
     }
     const double w2 = std::pow(dv, 6);
-    const double n2 = (double)N * N, n1 = N;
     // moments of the 3-D mesh via separability
     auto m = [&](int a, int b, int c) { return s[a] * s[b] * s[c]; };
     double G[5][5];
     const int e[4][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
-    (void)n2;
-    (void)n1;
     for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j)
             G[i][j] = m(e[i][0] + e[j][0], e[i][1] + e[j][1], e[i][2] + e[j][2]);
@@ -197,8 +194,10 @@ struct Part {
     long long *d_row_woff = nullptr;
     long long *d_blk_woff = nullptr;
     long long *d_zero = nullptr;     // single 0 (plain: base of the one cell)
-    int2 *d_items = nullptr;
+    int4 *d_items = nullptr;
     int n_items = 0;
+    int parts = 1;                   // partial-sum buffers of the batched schedule
+    int variant = 0;                 // convolution kernel variant
     std::vector<long long> f_off;    // host copy
     // workspace offsets (bytes)
     size_t ws_fh = 0, ws_qh = 0, ws_counter = 0;
@@ -217,7 +216,9 @@ struct bz_batch_s {
     void *d_tables = nullptr;
     size_t ws_scratch = 0, ws_flag = 0, ws_total = 0;
     int plain_split = 4;
-    int variant = 0;
+    // convolution timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
 };
 
 namespace bz {
@@ -244,6 +245,26 @@ static int plain_split_for(int N) {
     if (s > 8) s = 8;
     return s;
 }
+
+static bool timer_pair(bz_batch_s *b, std::pair<hipEvent_t, hipEvent_t> &ev) {
+    if (b->ev_free.empty()) {
+        hipEvent_t a, c;
+        if (hipEventCreate(&a) != hipSuccess) return false;
+        if (hipEventCreate(&c) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return false;
+        }
+        b->ev_free.emplace_back(a, c);
+    }
+    ev = b->ev_free.back();
+    b->ev_free.pop_back();
+    b->ev_used.push_back(ev);
+    return true;
+}
+
+// variant chosen per (N, groups, mode) by bz_batch_autotune in this process
+static std::vector<std::pair<long long, int>> g_tuned;
+static long long tune_key(int N, int groups, int mode) { return ((long long)N << 40) | ((long long)groups << 8) | mode; }
 
 }  // namespace bz
 
@@ -320,7 +341,7 @@ size_t bz_weights_bytes(bz_grid g, int kind) {
     if (!g) return 0;
     switch (kind) {
     case BZ_W_BATCHED_F32:
-    case BZ_W_BATCHED_F64: return (size_t)g->sched.cells_weights * kind_elem(kind);
+    case BZ_W_BATCHED_F64: return (size_t)g->sched.cells_weights * kind_elem(kind) + kWeightPadBytes;
     case BZ_W_PLAIN_F32:
     case BZ_W_PLAIN_F64: return (size_t)g->sched.plain_weights * kind_elem(kind);
     default: return 0;
@@ -397,6 +418,8 @@ bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids,
             if (grid_of_cell[c] == gi) p.cells.push_back(c);
         if (p.cells.empty()) continue;
         p.groups = (int)((p.cells.size() + kWave - 1) / kWave);
+        for (auto &kv : g_tuned)
+            if (kv.first == tune_key(p.g->N, p.groups, mode)) p.variant = kv.second;
         b->parts.push_back(std::move(p));
     }
     // host tables, then one device buffer for all of them
@@ -429,15 +452,25 @@ bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids,
         o.row = put(p.g->sched.row_woff.data(), p.g->sched.row_woff.size() * sizeof(long long));
         o.blk = put(p.g->sched.blk_woff.data(), p.g->sched.blk_woff.size() * sizeof(long long));
         if (bat) {
-            std::vector<int2> items;
-            items.reserve((size_t)p.groups * N * N);
-            for (int gq = 0; gq < p.groups; ++gq)
-                for (int r = 0; r < N * N; ++r) items.push_back(make_int2(gq, r));
+            // split every row's steps into `parts` contiguous ranges so that there are
+            // enough work items to fill the chip; order longest first
+            const long long rows = (long long)p.groups * N * N;
+            int parts = (int)((8192 + rows - 1) / rows);
+            parts = std::max(1, std::min(parts, 8));
+            p.parts = parts;
+            std::vector<int4> items;
+            items.reserve((size_t)rows * parts);
             const std::vector<int> &st = p.g->sched.row_steps;
+            for (int gq = 0; gq < p.groups; ++gq)
+                for (int r = 0; r < N * N; ++r)
+                    for (int q = 0; q < parts; ++q) {
+                        const int a = (int)((long long)st[r] * q / parts), e = (int)((long long)st[r] * (q + 1) / parts);
+                        items.push_back(make_int4(gq, r | (q << 16), a, e));
+                    }
             std::stable_sort(items.begin(), items.end(),
-                             [&](const int2 &x, const int2 &y) { return st[x.y] > st[y.y]; });
+                             [](const int4 &x, const int4 &y) { return x.w - x.z > y.w - y.z; });
             p.n_items = (int)items.size();
-            o.items = put(items.data(), items.size() * sizeof(int2));
+            o.items = put(items.data(), items.size() * sizeof(int4));
         }
         offs.push_back(o);
         // workspace: fhat, qhat, counter
@@ -446,7 +479,7 @@ bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids,
             p.ws_fh = ws;
             ws = align256(ws + (size_t)p.groups * M * kWave * cs);
             p.ws_qh = ws;
-            ws = align256(ws + (size_t)p.groups * M * kWave * 16);
+            ws = align256(ws + (size_t)p.parts * p.groups * M * kWave * 16);
         } else {
             const int sp = plain_split_for(N);
             p.ws_fh = ws;
@@ -481,7 +514,7 @@ bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids,
         p.d_zero = (long long *)(base + offs[i].zero);
         p.d_row_woff = (long long *)(base + offs[i].row);
         p.d_blk_woff = (long long *)(base + offs[i].blk);
-        p.d_items = bat ? (int2 *)(base + offs[i].items) : nullptr;
+        p.d_items = bat ? (int4 *)(base + offs[i].items) : nullptr;
     }
     *out = b.release();
     return BZ_OK;
@@ -490,6 +523,14 @@ bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids,
 void bz_batch_free(bz_batch b) {
     if (!b) return;
     if (b->d_tables) (void)hipFree(b->d_tables);
+    for (auto &e : b->ev_used) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    for (auto &e : b->ev_free) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
     delete b;
 }
 
@@ -504,6 +545,104 @@ bz_status bz_batch_set_weights(bz_batch b, int grid_index, int kind, const void 
             p.w = d_w;
             p.wkind = kind;
         }
+    return BZ_OK;
+}
+
+int bz_variant_count(void) { return 5; }
+
+bz_status bz_batch_set_variant(bz_batch b, int grid_index, int variant) {
+    if (!b) return fail(BZ_EINVAL, "bz_batch_set_variant: NULL batch");
+    if (variant < 0 || variant >= bz_variant_count()) return fail(BZ_EINVAL, "bz_batch_set_variant: bad variant");
+    if (grid_index < 0 || grid_index >= (int)b->grids.size())
+        return fail(BZ_EINVAL, "bz_batch_set_variant: grid index out of range");
+    for (Part &p : b->parts)
+        if (p.gi == grid_index) p.variant = variant;
+    return BZ_OK;
+}
+
+int bz_batch_get_variant(bz_batch b, int grid_index) {
+    if (!b) return -1;
+    for (Part &p : b->parts)
+        if (p.gi == grid_index) return p.variant;
+    return -1;
+}
+
+bz_status bz_batch_timer(bz_batch b, int enable) {
+    if (!b) return fail(BZ_EINVAL, "bz_batch_timer: NULL batch");
+    b->timing = enable != 0;
+    return BZ_OK;
+}
+
+bz_status bz_batch_timer_read(bz_batch b, double *conv_ms, int *launches) {
+    if (!b) return fail(BZ_EINVAL, "bz_batch_timer_read: NULL batch");
+    double tot = 0.0;
+    for (auto &e : b->ev_used) {
+        BZ_HIP(hipEventSynchronize(e.second), "bz_batch_timer_read: sync");
+        float ms = 0.f;
+        BZ_HIP(hipEventElapsedTime(&ms, e.first, e.second), "bz_batch_timer_read: elapsed");
+        tot += ms;
+    }
+    if (conv_ms) *conv_ms = tot;
+    if (launches) *launches = (int)b->ev_used.size();
+    b->ev_free.insert(b->ev_free.end(), b->ev_used.begin(), b->ev_used.end());
+    b->ev_used.clear();
+    return BZ_OK;
+}
+
+bz_status bz_batch_autotune(bz_batch b, const double *d_f, double *d_Qt, void *d_work, size_t work_bytes, int reps,
+                            void *stream) {
+    if (!b || !d_f || !d_Qt || !d_work) return fail(BZ_EINVAL, "bz_batch_autotune: NULL argument");
+    if (reps < 1) reps = 1;
+    if (!batched(b->mode)) return BZ_OK;  // the plain schedule has no variants
+    const bool was = b->timing;
+    std::vector<int> saved;
+    for (Part &p : b->parts) saved.push_back(p.variant);
+    // time every variant for all parts at once (each part's launch is timed separately)
+    const int nv = bz_variant_count();
+    std::vector<std::vector<double>> t(b->parts.size(), std::vector<double>(nv, 0.0));
+    b->timing = true;
+    bz_status st = BZ_OK;
+    for (int v = 0; v < nv && st == BZ_OK; ++v) {
+        if (mode_f64(b->mode) && v > 0) break;  // the FP64 kernel has one variant
+        for (Part &p : b->parts) p.variant = v;
+        st = bz_collide_batch(b, d_f, d_Qt, d_work, work_bytes, stream);  // warm-up
+        double junk;
+        if (st == BZ_OK) st = bz_batch_timer_read(b, &junk, nullptr);
+        for (int r = 0; r < reps && st == BZ_OK; ++r) st = bz_collide_batch(b, d_f, d_Qt, d_work, work_bytes, stream);
+        if (st != BZ_OK) break;
+        // events are recorded in part order, reps times
+        const size_t np = b->parts.size();
+        for (size_t i = 0; i < b->ev_used.size(); ++i) {
+            auto &e = b->ev_used[i];
+            BZ_HIP(hipEventSynchronize(e.second), "autotune sync");
+            float ms = 0.f;
+            BZ_HIP(hipEventElapsedTime(&ms, e.first, e.second), "autotune elapsed");
+            t[i % np][v] += ms;
+        }
+        b->ev_free.insert(b->ev_free.end(), b->ev_used.begin(), b->ev_used.end());
+        b->ev_used.clear();
+    }
+    b->timing = was;
+    if (st != BZ_OK) {
+        for (size_t i = 0; i < b->parts.size(); ++i) b->parts[i].variant = saved[i];
+        return st;
+    }
+    for (size_t i = 0; i < b->parts.size(); ++i) {
+        Part &p = b->parts[i];
+        int best = 0;
+        const int nvv = mode_f64(b->mode) ? 1 : nv;
+        for (int v = 1; v < nvv; ++v)
+            if (t[i][v] < t[i][best]) best = v;
+        p.variant = best;
+        const long long key = tune_key(p.g->N, p.groups, b->mode);
+        bool found = false;
+        for (auto &kv : g_tuned)
+            if (kv.first == key) {
+                kv.second = best;
+                found = true;
+            }
+        if (!found) g_tuned.emplace_back(key, best);
+    }
     return BZ_OK;
 }
 
@@ -535,10 +674,19 @@ bz_status bz_collide_batch(bz_batch b, const double *d_f, double *d_Qt, void *d_
             const int nc = (int)p.cells.size();
             BZ_HIP(launch_dft_forward(N, p.g->L, nc, d_f, p.d_f_off, scratch, fh, !f64, p.d_fh_base, kWave, s),
                    "forward transform");
+            const long long pstride = (long long)p.groups * M * kWave;
             CellsLaunch cl{N, fh, p.w, p.d_row_woff, p.d_items, p.n_items, (unsigned *)(ws + p.ws_counter), qh,
-                           b->variant};
+                           pstride, 0};
+            std::pair<hipEvent_t, hipEvent_t> ev{};
+            if (b->timing) {
+                if (!timer_pair(b, ev)) return fail(BZ_EDEVICE, "bz_collide_batch: hipEventCreate failed");
+                BZ_HIP(hipEventRecord(ev.first, s), "timer start");
+            }
+            cl.variant = p.variant;
             BZ_HIP(launch_conv_cells(cl, f64, s), "batched convolution");
-            BZ_HIP(launch_dft_inverse(N, p.g->L, nc, qh, p.d_fh_base, kWave, 1, 0, scratch, d_Qt, p.d_f_off, s),
+            if (b->timing) BZ_HIP(hipEventRecord(ev.second, s), "timer stop");
+            BZ_HIP(launch_dft_inverse(N, p.g->L, nc, qh, p.d_fh_base, kWave, p.parts, pstride, scratch, d_Qt,
+                                      p.d_f_off, s),
                    "inverse transform");
         } else {
             const int sp = plain_split_for(N);
@@ -546,7 +694,13 @@ bz_status bz_collide_batch(bz_batch b, const double *d_f, double *d_Qt, void *d_
                 BZ_HIP(launch_dft_forward(N, p.g->L, 1, d_f, p.d_f_off + i, scratch, fh, !f64, p.d_zero, 1, s),
                        "forward transform");
                 PlainLaunch pl{N, fh, p.w, p.d_blk_woff, sp, qh};
+                std::pair<hipEvent_t, hipEvent_t> ev{};
+                if (b->timing) {
+                    if (!timer_pair(b, ev)) return fail(BZ_EDEVICE, "bz_collide_batch: hipEventCreate failed");
+                    BZ_HIP(hipEventRecord(ev.first, s), "timer start");
+                }
                 BZ_HIP(launch_conv_plain(pl, f64, s), "plain convolution");
+                if (b->timing) BZ_HIP(hipEventRecord(ev.second, s), "timer stop");
                 BZ_HIP(launch_dft_inverse(N, p.g->L, 1, qh, p.d_zero, 1, sp, M, scratch, d_Qt, p.d_f_off + i, s),
                        "inverse transform");
             }

@@ -70,8 +70,8 @@ def test_batched_schedule_visits_each_unordered_pair_once(N):
                         steps += 1
     g = bz.bz_grid_init(N, 6.0, 1.0)
     try:
-        assert bz.bz_weights_bytes(g, bz.BZ_W_BATCHED_F32) == steps * (3 * N * N // 4) * 4
-        assert bz.bz_weights_bytes(g, bz.BZ_W_BATCHED_F64) == steps * (3 * N * N // 4) * 8
+        assert bz.bz_weights_bytes(g, bz.BZ_W_BATCHED_F32) == steps * (3 * N * N // 4) * 4 + 16384
+        assert bz.bz_weights_bytes(g, bz.BZ_W_BATCHED_F64) == steps * (3 * N * N // 4) * 8 + 16384
         # the visited slots cover every unordered pair: (P + D) / 2 <= slots
         P = (3 * N * N // 4) ** 3
         assert 2 * steps * (3 * N * N // 4) >= P

@@ -249,3 +249,34 @@ def test_unbound_weights_and_short_workspace(dev):
     torch.cuda.synchronize()
     bz.bz_batch_free(b)
     bz.bz_grid_free(g)
+
+
+@pytest.mark.parametrize("variant", range(5))
+def test_every_batched_fp32_variant_matches_oracle(dev, variant):
+    """Each tuning variant computes the same sums: 70 cells on N=24 (a ragged second group)."""
+    N, L, lam = 24, 7.0, 1.0
+    cells = list(W.random_smooth_cells(70, N, L, seed=21, umax=1.0))
+    c = bz.Collision([(N, L, lam)], [0] * 70, "batched_f32", weights_cache=_WCACHE)
+    c.set_variant(variant)
+    f = torch.from_numpy(c.pack(cells)).to(dev)
+    q = c.collide(f)
+    c.project(q)
+    got = c.unpack(q.cpu().numpy())
+    c.close()
+    o = oracle_for(N, L, lam)
+    for i in (0, 33, 63, 64, 69):
+        _, q_o, _, _ = o.collide(cells[i])
+        assert rel_l2(got[i], q_o) < max(1e-5, 8 * U32 * _kappa(cells[i], N, L, lam)), (variant, i)
+
+
+def test_autotune_keeps_results(dev):
+    N, L, lam = 16, 6.0, 1.0
+    cells = list(W.random_smooth_cells(64, N, L, seed=2))
+    c = bz.Collision([(N, L, lam)], [0] * 64, "batched_f32", weights_cache=_WCACHE)
+    f = torch.from_numpy(c.pack(cells)).to(dev)
+    q0 = c.collide(f).cpu().numpy()
+    best = c.autotune(f, reps=1)
+    assert 0 <= best[0] < bz.bz_variant_count()
+    q1 = c.collide(f).cpu().numpy()
+    assert rel_l2(q1, q0) < 1e-6
+    c.close()
