@@ -98,13 +98,22 @@ __device__ __forceinline__ void load_row(const typename cplx<T>::t *__restrict__
 
 // Copy `chunks` KiB of a step's weights from global memory to LDS: each lane
 // moves 16 bytes per chunk, the wave 1 KiB, landing contiguously at dst.
+typedef __attribute__((address_space(3))) char lds_char;
+
+// LDS address of a __shared__ object, taken directly so that no generic-to-LDS
+// conversion of a computed pointer is needed.
+template <typename T>
+__device__ __forceinline__ lds_char *lds_ptr(T *shared_obj) {
+    return (lds_char *)shared_obj;
+}
+
 template <int CHUNKS>
-__device__ __forceinline__ void prefetch_weights(const void *src, void *dst) {
+__device__ __forceinline__ void prefetch_weights(const void *src, lds_char *dst) {
     const char *g = (const char *)src + threadIdx.x * 16;
 #pragma unroll
     for (int c = 0; c < CHUNKS; ++c)
-        __builtin_amdgcn_global_load_lds((const void *)(g + c * 1024),
-                                         (__attribute__((address_space(3))) void *)((char *)dst + c * 1024), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const void *)(g + c * 1024), (void __attribute__((address_space(3))) *)(dst + c * 1024),
+                                         16, 0, 0);
 }
 
 // Position (m1, m2) of step index s0 in the row's step enumeration.
@@ -130,15 +139,19 @@ __device__ inline int pop_item(unsigned *counter) {
 // ---------------------------------------------------------------------------
 // Batched FP32 with compensated accumulation.
 // ---------------------------------------------------------------------------
-template <int N, int FOLD, int COMP, int WP>
+template <int N, int FOLD, int COMP, int WP, int RP>
 __global__ void __launch_bounds__(64) k_conv_cells_f32(const float2 *__restrict__ fh, const float *__restrict__ W,
                                                        const long long *__restrict__ row_woff,
                                                        const int4 *__restrict__ items, int n_items,
                                                        unsigned *__restrict__ counter, double2 *__restrict__ qh,
                                                        long long part_stride) {
     constexpr int h = N / 2, M = N * N * N, PS = 3 * N * N / 4;
-    constexpr int CH = (PS * 4 + 1023) / 1024;
+    constexpr int CH = (PS * 4 + 1023) / 1024;       // KiB per step of weights
+    constexpr int RCH = N * kWave * 8 / 1024;        // KiB per fhat row of 64 cells
     __shared__ __attribute__((aligned(16))) float wbuf[2][CH * 256];
+    __shared__ __attribute__((aligned(16))) float2 rbuf[RP ? 2 * N * kWave : 2];
+    lds_char *const wl = lds_ptr(&wbuf[0][0]);
+    lds_char *const rl = lds_ptr(&rbuf[0]);
     const int lane = threadIdx.x;
     for (;;) {
         const int it = pop_item(counter);
@@ -147,7 +160,8 @@ __global__ void __launch_bounds__(64) k_conv_cells_f32(const float2 *__restrict_
         const int g = item.x, r = item.y & 0xffff, part = item.y >> 16, s0 = item.z, s1 = item.w;
         const int k1 = r / N, k2 = r - k1 * N;
         const float *w = W + row_woff[r] + (long long)s0 * PS;
-        const float2 *F = fh + (size_t)g * M * kWave + lane;
+        const float2 *G = fh + (size_t)g * M * kWave;   // this group's fhat
+        const float2 *F = G + lane;
 
         float pr[N], pi[N];
         float hr[N], hi[N], lr[N], li[N];
@@ -171,30 +185,52 @@ __global__ void __launch_bounds__(64) k_conv_cells_f32(const float2 *__restrict_
                 pr[t] = pi[t] = 0.f;
             }
         };
+        // rows of step (m1, m2): fhat(m1, m2, .) and fhat(j1, j2, .) of the 64 cells, N/2 KiB each
+        auto prefetch_rows = [&](int a1, int a2) {
+            prefetch_weights<RCH>(G + (size_t)((a1 * N + a2) * N) * kWave, rl);
+            prefetch_weights<RCH>(G + (size_t)(((k1 + h - a1) * N + (k2 + h - a2)) * N) * kWave, rl + RCH * 1024);
+        };
 
         int m1, m2;
         seek_step<N>(k1, k2, s0, m1, m2);
         const int lo2 = axis_lo(N, k2);
-        prefetch_weights<CH>(w, wbuf[0]);
+        prefetch_weights<CH>(w, wl);
+        if (RP && s0 < s1) prefetch_rows(m1, m2);
         __builtin_amdgcn_s_waitcnt(0);
         int buf = 0, nst = 0;
         for (int s = s0; s < s1; ++s) {
             const int j1 = k1 + h - m1, j2 = k2 + h - m2;
+            // (m1, m2) of the next step in the row's order
+            int n1 = m1, n2 = m2 + 1;
+            if (n2 > cells_m2_last(N, k1, k2, m1)) {
+                ++n1;
+                n2 = lo2;
+            }
             float2 mv[N], jv[N];
-            load_row<float, N>(F + (size_t)((m1 * N + m2) * N) * kWave, mv);
-            load_row<float, N>(F + (size_t)((j1 * N + j2) * N) * kWave, jv);
+            if (RP) {
+#pragma unroll
+                for (int t = 0; t < N; ++t) {
+                    mv[t] = rbuf[t * kWave + lane];
+                    jv[t] = rbuf[N * kWave + t * kWave + lane];
+                }
+                __builtin_amdgcn_s_waitcnt(0);        // rows are in registers: the buffer is free
+                if (s + 1 < s1) prefetch_rows(n1, n2);
+            } else {
+                load_row<float, N>(F + (size_t)((m1 * N + m2) * N) * kWave, mv);
+                load_row<float, N>(F + (size_t)((j1 * N + j2) * N) * kWave, jv);
+            }
             if (WP == 0) {
                 // next step's weights into the other LDS half; this step reads its half
-                prefetch_weights<CH>(w + PS, wbuf[buf ^ 1]);
+                prefetch_weights<CH>(w + PS, wl + (buf ^ 1) * CH * 1024);
                 cells_step<float, N>(mv, jv, (const float *)wbuf[buf], pr, pi);
             } else if (WP == 1) {
                 // next step's weights pulled into L2 (the LDS copy is discarded); this
                 // step's weights, pulled last step, are read through the scalar cache
-                prefetch_weights<CH>(w + PS, wbuf[1]);
+                prefetch_weights<CH>(w + PS, wl + CH * 1024);
                 cells_step<float, N>(mv, jv, (const __attribute__((address_space(4))) float *)w, pr, pi);
             } else {
                 // as 1, but the weights are read by uniform-address vector loads
-                prefetch_weights<CH>(w + PS, wbuf[1]);
+                prefetch_weights<CH>(w + PS, wl + CH * 1024);
                 cells_step<float, N>(mv, jv, w, pr, pi);
             }
             w += PS;
@@ -203,11 +239,8 @@ __global__ void __launch_bounds__(64) k_conv_cells_f32(const float2 *__restrict_
                 fold();
                 nst = 0;
             }
-            // next (m1, m2) in the row's step order
-            if (++m2 > cells_m2_last(N, k1, k2, m1)) {
-                ++m1;
-                m2 = lo2;
-            }
+            m1 = n1;
+            m2 = n2;
             __builtin_amdgcn_s_waitcnt(0);
         }
         fold();
@@ -234,6 +267,7 @@ __global__ void __launch_bounds__(64) k_conv_cells_f64(const double2 *__restrict
     constexpr int h = N / 2, M = N * N * N, PS = 3 * N * N / 4;
     constexpr int CH = (PS * 8 + 1023) / 1024;
     __shared__ __attribute__((aligned(16))) double wbuf[2][CH * 128];
+    lds_char *const wl = lds_ptr(&wbuf[0][0]);
     const int lane = threadIdx.x;
     for (;;) {
         const int it = pop_item(counter);
@@ -249,12 +283,12 @@ __global__ void __launch_bounds__(64) k_conv_cells_f64(const double2 *__restrict
         int m1, m2;
         seek_step<N>(k1, k2, s0, m1, m2);
         const int lo2 = axis_lo(N, k2);
-        prefetch_weights<CH>(w, wbuf[0]);
+        prefetch_weights<CH>(w, wl);
         __builtin_amdgcn_s_waitcnt(0);
         int buf = 0;
         for (int s = s0; s < s1; ++s) {
             const int j1 = k1 + h - m1, j2 = k2 + h - m2;
-            prefetch_weights<CH>(w + PS, wbuf[buf ^ 1]);
+            prefetch_weights<CH>(w + PS, wl + (buf ^ 1) * CH * 1024);
             double2 mv[N], jv[N];
             load_row<double, N>(F + (size_t)((m1 * N + m2) * N) * kWave, mv);
             load_row<double, N>(F + (size_t)((j1 * N + j2) * N) * kWave, jv);
@@ -328,23 +362,26 @@ __global__ void __launch_bounds__(64) k_conv_plain(const typename cplx<T>::t *__
     if (active) qh[(size_t)s * M + ((size_t)k1 * N + k2) * N + k3] = make_double2(ar, ai);
 }
 
-// Tuning variants of the batched FP32 kernel: (fold interval, compensation, weight path).
-//   0: FOLD 2, FP64 total, LDS double-buffered weights       (default)
-//   1: FOLD 2, TwoSum (hi, lo) FP32 total, LDS double-buffered weights
-//   2: FOLD 4, FP64 total, scalar weights + L2 prefetch
-//   3: FOLD 2, FP64 total, scalar weights + L2 prefetch
-//   4: FOLD 2, FP64 total, uniform vector loads of the weights + L2 prefetch
+// Tuning variants of the batched FP32 kernel: (fold interval, compensation, weight path, row path).
+//   0: FOLD 2, FP64 total,   LDS double-buffered weights, rows prefetched to LDS   (default)
+//   1: FOLD 2, TwoSum total, LDS double-buffered weights, rows prefetched to LDS
+//   2: FOLD 2, FP64 total,   LDS double-buffered weights, rows loaded per step
+//   3: FOLD 2, TwoSum total, LDS double-buffered weights, rows loaded per step
+//   4: FOLD 2, FP64 total,   scalar weights + L2 prefetch, rows prefetched to LDS
+//   5: FOLD 4, FP64 total,   LDS double-buffered weights, rows prefetched to LDS
 template <int N>
 hipError_t cells_f32_variant(const CellsLaunch &p, unsigned grid, hipStream_t s) {
-#define BZ_CELLS_F32(F, C, WPV)                                                                          \
-    hipLaunchKernelGGL((k_conv_cells_f32<N, F, C, WPV>), dim3(grid), dim3(64), 0, s, (const float2 *)p.fh, \
-                       (const float *)p.w, p.row_woff, p.items, p.n_items, p.counter, p.qh, p.part_stride)
+#define BZ_CELLS_F32(F, C, WPV, RPV)                                                                        \
+    hipLaunchKernelGGL((k_conv_cells_f32<N, F, C, WPV, RPV>), dim3(grid), dim3(64), 0, s,                   \
+                       (const float2 *)p.fh, (const float *)p.w, p.row_woff, p.items, p.n_items, p.counter, \
+                       p.qh, p.part_stride)
     switch (p.variant) {
-    case 1: BZ_CELLS_F32(2, 1, 0); break;
-    case 2: BZ_CELLS_F32(4, 0, 1); break;
-    case 3: BZ_CELLS_F32(2, 0, 1); break;
-    case 4: BZ_CELLS_F32(2, 0, 2); break;
-    default: BZ_CELLS_F32(2, 0, 0); break;
+    case 1: BZ_CELLS_F32(2, 1, 0, 1); break;
+    case 2: BZ_CELLS_F32(2, 0, 0, 0); break;
+    case 3: BZ_CELLS_F32(2, 1, 0, 0); break;
+    case 4: BZ_CELLS_F32(2, 0, 1, 1); break;
+    case 5: BZ_CELLS_F32(4, 0, 0, 1); break;
+    default: BZ_CELLS_F32(2, 0, 0, 1); break;
     }
 #undef BZ_CELLS_F32
     return hipGetLastError();
