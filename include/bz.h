@@ -164,6 +164,36 @@ bz_status bz_step(bz_batch b, double *d_f, double dt_over_eps, void *d_work, siz
 bz_status bz_step_check(bz_batch b, void *d_work, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* 1-D transport (Sec. 3.4, eq. upwind) with a diffuse wall (Sec. 2.1,    */
+/* eq. BC) and the Strang-split step (Sec. 3.1).                          */
+/* ------------------------------------------------------------------ */
+typedef struct bz_transport_s *bz_transport;
+
+/* nx uniform cells of width x_length/nx along x (axis 1 of the velocity
+ * mesh of `g` is the transport direction).  Left end: diffuse Maxwell wall
+ * at rest with temperature T_wall; two ghost cells copy the first cell (its
+ * minmod slope is 0) and the wall face emits sigma_w M_wall for v1 > 0 with
+ * sigma_w = sum_{v1<0}|v1| f_0 / sum_{v1>0} v1 M_wall (discrete, so the net
+ * wall mass flux is zero).  Right end: two ghost cells hold the far-field
+ * Maxwellian M(far_rho, (far_u1, 0, 0), far_T).  Uploads two N^3 tables
+ * (owned by the handle).  Errors: BZ_EINVAL for nx < 1, non-positive
+ * length or temperatures, negative density. */
+bz_status bz_transport_create(bz_grid g, int nx, double x_length, double T_wall, double far_rho, double far_u1,
+                              double far_T, bz_transport *out);
+void bz_transport_free(bz_transport t);
+size_t bz_transport_workspace_bytes(bz_transport t);
+/* Heun RK2 over dt of df/dt + v1 df/dx = 0 for the nx cells of d_f (layout
+ * [cell][velocity], nx * N^3 doubles), in place, second-order upwind fluxes
+ * with minmod slopes. */
+bz_status bz_transport_step(bz_transport t, double *d_f, double dt, void *d_work, size_t work_bytes, void *stream);
+/* Strang step T(dt/2) C(dt) T(dt/2): transport half steps around one Heun
+ * collision step (bz_step with dt/eps) of the batch `b`, which must hold the
+ * nx cells of the transport mesh in x order. */
+size_t bz_strang_workspace_bytes(bz_batch b, bz_transport t);
+bz_status bz_strang_step(bz_batch b, bz_transport t, double *d_f, double dt, double eps, void *d_work,
+                         size_t work_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
 /* Tuning and measurement.                                               */
 /* ------------------------------------------------------------------ */
 /* Select the convolution kernel variant for the cells of grids[grid_index]

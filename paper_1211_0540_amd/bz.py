@@ -71,6 +71,13 @@ def lib():
         "bz_step_workspace_bytes": (_sz, [_vp]),
         "bz_step": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _vp, _sz, _vp]),
         "bz_step_check": (ctypes.c_int, [_vp, _vp, _vp]),
+        "bz_transport_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_double, ctypes.POINTER(_vp)]),
+        "bz_transport_free": (None, [_vp]),
+        "bz_transport_workspace_bytes": (_sz, [_vp]),
+        "bz_transport_step": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _vp, _sz, _vp]),
+        "bz_strang_workspace_bytes": (_sz, [_vp, _vp]),
+        "bz_strang_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _sz, _vp]),
         "bz_variant_count": (ctypes.c_int, []),
         "bz_batch_set_variant": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
         "bz_batch_get_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -209,6 +216,40 @@ def bz_step_check(b: int, work, stream=None) -> None:
     _check(lib().bz_step_check(_vp(b), _vp(_ptr(work)), _stream(stream)))
 
 
+def bz_transport_create(g: int, nx: int, x_length: float, T_wall: float, far_rho: float, far_u1: float,
+                        far_T: float) -> int:
+    h = _vp()
+    _check(lib().bz_transport_create(_vp(g), int(nx), float(x_length), float(T_wall), float(far_rho),
+                                     float(far_u1), float(far_T), ctypes.byref(h)))
+    return h.value
+
+
+def bz_transport_free(t: int) -> None:
+    lib().bz_transport_free(_vp(t))
+
+
+def bz_transport_workspace_bytes(t: int) -> int:
+    return int(lib().bz_transport_workspace_bytes(_vp(t)))
+
+
+def bz_transport_step(t: int, f, dt: float, work, stream=None) -> None:
+    _dev(f, "f")
+    _dev(work, "workspace")
+    _check(lib().bz_transport_step(_vp(t), _vp(_ptr(f)), float(dt), _vp(_ptr(work)),
+                                   work.numel() * work.element_size(), _stream(stream)))
+
+
+def bz_strang_workspace_bytes(b: int, t: int) -> int:
+    return int(lib().bz_strang_workspace_bytes(_vp(b), _vp(t)))
+
+
+def bz_strang_step(b: int, t: int, f, dt: float, eps: float, work, stream=None) -> None:
+    _dev(f, "f")
+    _dev(work, "workspace")
+    _check(lib().bz_strang_step(_vp(b), _vp(t), _vp(_ptr(f)), float(dt), float(eps), _vp(_ptr(work)),
+                                work.numel() * work.element_size(), _stream(stream)))
+
+
 def bz_variant_count() -> int:
     return int(lib().bz_variant_count())
 
@@ -297,6 +338,15 @@ class Collision:
 
     def check(self, stream=None):
         bz_step_check(self.batch, self.work, stream)
+
+    def strang_step(self, transport, dt, eps, f, stream=None):
+        """T(dt/2) C(dt) T(dt/2) on the batch's cells (must be the transport's nx cells)."""
+        need = bz_strang_workspace_bytes(self.batch, transport)
+        if self.work.numel() < need:
+            import torch
+            self.work = torch.zeros(need, dtype=torch.uint8, device=self.work.device)
+        bz_strang_step(self.batch, transport, f, dt, eps, self.work, stream)
+        return f
 
     def pack(self, cells):
         """Concatenate per-cell (N, N, N) arrays into the batch layout (host)."""

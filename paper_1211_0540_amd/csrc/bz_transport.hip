@@ -1,0 +1,200 @@
+// 1-D-in-space transport (Sec. 3.4, eq. upwind) with a diffuse Maxwell wall
+// (Sec. 2.1, eq. BC) and far-field ghost cells, advanced with Heun's RK2, and
+// the Strang-split step T(dt/2) C(dt) T(dt/2) of Sec. 3.1.
+//
+// Layout: f[j][k], cell j = 0..nx-1 along x (uniform dx), k the flat velocity
+// index of the cell's N^3 mesh; v1 = dv (k1 - N/2) is the transport velocity.
+// Fluxes at face j-1/2:  v1 (f_{j-1} + dx/2 s_{j-1})  if v1 >= 0,
+//                        v1 (f_j     - dx/2 s_j)      otherwise,
+// s_j = minmod((f_j - f_{j-1})/dx, (f_{j+1} - f_j)/dx).  Left end: two ghost
+// cells copy cell 0 (slope 0 there); the wall face flux is v1 sigma_w M_w for
+// v1 > 0 and v1 f_0 for v1 < 0 with sigma_w = sum_{v1<0}|v1| f_0 / sum_{v1>0} v1 M_w,
+// so the net wall mass flux is zero.  Right end: ghosts hold M_far.
+// Memory-bound (5 reads + 1-2 reads + 1 write of 8 bytes per (cell, velocity));
+// negligible next to the collision step.
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "bz_internal.h"
+
+struct bz_transport_s {
+    int N = 0, nx = 0;
+    double L = 0, dx = 0, T_wall = 0, in_norm = 0;
+    double *d_tab = nullptr;  // [2][N^3]: M_wall, M_far
+};
+
+namespace bz {
+namespace {
+
+__device__ inline double minmod(double a, double b) {
+    return a * b > 0.0 ? (a > 0.0 ? fmin(a, b) : fmax(a, b)) : 0.0;
+}
+
+// sigma_w = sum_{v1 < 0} |v1| f_0 dv^3 / in_norm, one block, fixed reduction order.
+__global__ void __launch_bounds__(256) k_wall_sigma(int N, double dv, const double *__restrict__ f0, double in_norm,
+                                                    double *__restrict__ sigma) {
+    __shared__ double red[4];
+    const int M = N * N * N;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < M; k += blockDim.x) {
+        const double v1 = dv * (k / (N * N) - N / 2);
+        if (v1 < 0.0) s = fma(-v1, f0[k], s);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+        sigma[0] = t * dv * dv * dv / in_norm;
+    }
+}
+
+__device__ inline double cellv(const double *__restrict__ f, const double *__restrict__ mfar, int nx, int M, int j,
+                               int k) {
+    if (j < 0) return f[k];
+    if (j >= nx) return mfar[k];
+    return f[(size_t)j * M + k];
+}
+
+// out = alpha * base + beta * (fin + dt * rhs(fin)) at every (cell, velocity).
+__global__ void __launch_bounds__(256) k_transport_stage(int N, int nx, double dv, double dx, double dt,
+                                                         const double *__restrict__ fin,
+                                                         const double *__restrict__ base, double alpha, double beta,
+                                                         const double *__restrict__ tab,
+                                                         const double *__restrict__ sigma, double *__restrict__ out) {
+    const int M = N * N * N;
+    const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (idx >= (size_t)nx * M) return;
+    const int j = (int)(idx / M), k = (int)(idx - (size_t)j * M);
+    const double *mwall = tab, *mfar = tab + M;
+    const double v1 = dv * (k / (N * N) - N / 2);
+    const double a = cellv(fin, mfar, nx, M, j - 2, k), b = cellv(fin, mfar, nx, M, j - 1, k);
+    const double c = cellv(fin, mfar, nx, M, j, k), d = cellv(fin, mfar, nx, M, j + 1, k);
+    const double e = cellv(fin, mfar, nx, M, j + 2, k);
+    const double sb = minmod((b - a) / dx, (c - b) / dx);
+    const double sc = minmod((c - b) / dx, (d - c) / dx);
+    const double sd = minmod((d - c) / dx, (e - d) / dx);
+    // face j-1/2
+    double Fl;
+    if (j == 0)
+        Fl = v1 > 0.0 ? v1 * sigma[0] * mwall[k] : v1 * c;
+    else
+        Fl = v1 >= 0.0 ? v1 * (b + 0.5 * dx * sb) : v1 * (c - 0.5 * dx * sc);
+    // face j+1/2
+    const double Fr = v1 >= 0.0 ? v1 * (c + 0.5 * dx * sc) : v1 * (d - 0.5 * dx * sd);
+    const double y = c + dt * (-(Fr - Fl) / dx);
+    out[idx] = (alpha != 0.0 ? alpha * base[idx] : 0.0) + beta * y;
+}
+
+}  // namespace
+
+static hipError_t transport_rk2(const bz_transport_s *t, double *f, double dt, double *fs, double *sigma,
+                                hipStream_t s) {
+    const int M = t->N * t->N * t->N;
+    const double dv = 2.0 * t->L / t->N;
+    const size_t n = (size_t)t->nx * M;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_wall_sigma, dim3(1), dim3(256), 0, s, t->N, dv, f, t->in_norm, sigma);
+    hipLaunchKernelGGL(k_transport_stage, dim3(blocks), dim3(256), 0, s, t->N, t->nx, dv, t->dx, dt, f, f, 0.0, 1.0,
+                       t->d_tab, sigma, fs);
+    hipLaunchKernelGGL(k_wall_sigma, dim3(1), dim3(256), 0, s, t->N, dv, fs, t->in_norm, sigma);
+    // each thread reads f and fs at its own index only for the base term, so f may be the output
+    hipLaunchKernelGGL(k_transport_stage, dim3(blocks), dim3(256), 0, s, t->N, t->nx, dv, t->dx, dt, fs, f, 0.5, 0.5,
+                       t->d_tab, sigma, f);
+    return hipGetLastError();
+}
+
+}  // namespace bz
+
+using namespace bz;
+
+extern "C" {
+
+bz_status bz_transport_create(bz_grid g, int nx, double x_length, double T_wall, double far_rho, double far_u1,
+                              double far_T, bz_transport *out) {
+    if (!out) return fail(BZ_EINVAL, "bz_transport_create: out is NULL");
+    *out = nullptr;
+    if (!g) return fail(BZ_EINVAL, "bz_transport_create: NULL grid");
+    if (nx < 1) return fail(BZ_EINVAL, "bz_transport_create: nx must be >= 1");
+    if (!(x_length > 0) || !std::isfinite(x_length)) return fail(BZ_EINVAL, "bz_transport_create: bad length");
+    if (!(T_wall > 0) || !(far_T > 0) || !(far_rho >= 0) || !std::isfinite(far_u1))
+        return fail(BZ_EINVAL, "bz_transport_create: bad wall or far-field state");
+    bz_transport_s *t = new (std::nothrow) bz_transport_s();
+    if (!t) return fail(BZ_ENOMEM, "bz_transport_create: allocation failed");
+    const int N = g->N, M = N * N * N;
+    t->N = N;
+    t->L = g->L;
+    t->nx = nx;
+    t->dx = x_length / nx;
+    t->T_wall = T_wall;
+    std::vector<double> tab(2 * (size_t)M);
+    const double dv = g->dv;
+    double in_norm = 0.0;
+    for (int k = 0; k < M; ++k) {
+        const double v1 = dv * (k / (N * N) - N / 2), v2 = dv * ((k / N) % N - N / 2), v3 = dv * (k % N - N / 2);
+        const double r2 = v1 * v1 + v2 * v2 + v3 * v3;
+        tab[k] = std::pow(2.0 * M_PI * T_wall, -1.5) * std::exp(-r2 / (2.0 * T_wall));
+        const double q2 = (v1 - far_u1) * (v1 - far_u1) + v2 * v2 + v3 * v3;
+        tab[M + k] = far_rho * std::pow(2.0 * M_PI * far_T, -1.5) * std::exp(-q2 / (2.0 * far_T));
+        if (v1 > 0.0) in_norm += v1 * tab[k];
+    }
+    t->in_norm = in_norm * dv * dv * dv;
+    hipError_t e = hipMalloc(&t->d_tab, tab.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(t->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (t->d_tab) (void)hipFree(t->d_tab);
+        delete t;
+        return hip_fail(e, "bz_transport_create: upload wall and far-field tables");
+    }
+    *out = t;
+    return BZ_OK;
+}
+
+void bz_transport_free(bz_transport t) {
+    if (!t) return;
+    if (t->d_tab) (void)hipFree(t->d_tab);
+    delete t;
+}
+
+size_t bz_transport_workspace_bytes(bz_transport t) {
+    if (!t) return 0;
+    return ((size_t)t->nx * t->N * t->N * t->N * 8 + 255) / 256 * 256 + 256;
+}
+
+bz_status bz_transport_step(bz_transport t, double *d_f, double dt, void *d_work, size_t work_bytes, void *stream) {
+    if (!t || !d_f || !d_work) return fail(BZ_EINVAL, "bz_transport_step: NULL argument");
+    if (work_bytes < bz_transport_workspace_bytes(t)) return fail(BZ_EINVAL, "bz_transport_step: workspace too small");
+    if (!std::isfinite(dt)) return fail(BZ_EINVAL, "bz_transport_step: dt must be finite");
+    const size_t arr = ((size_t)t->nx * t->N * t->N * t->N * 8 + 255) / 256 * 256;
+    double *fs = (double *)d_work;
+    double *sigma = (double *)((char *)d_work + arr);
+    hipError_t e = transport_rk2(t, d_f, dt, fs, sigma, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "bz_transport_step");
+    return BZ_OK;
+}
+
+size_t bz_strang_workspace_bytes(bz_batch b, bz_transport t) {
+    if (!b || !t) return 0;
+    return (bz_step_workspace_bytes(b) + 255) / 256 * 256 + bz_transport_workspace_bytes(t);
+}
+
+bz_status bz_strang_step(bz_batch b, bz_transport t, double *d_f, double dt, double eps, void *d_work,
+                         size_t work_bytes, void *stream) {
+    if (!b || !t || !d_f || !d_work) return fail(BZ_EINVAL, "bz_strang_step: NULL argument");
+    if (!(eps > 0) || !std::isfinite(dt)) return fail(BZ_EINVAL, "bz_strang_step: need finite dt and eps > 0");
+    if (work_bytes < bz_strang_workspace_bytes(b, t)) return fail(BZ_EINVAL, "bz_strang_step: workspace too small");
+    if (bz_batch_elems(b) != (size_t)t->nx * t->N * t->N * t->N)
+        return fail(BZ_EINVAL, "bz_strang_step: the batch must hold the nx cells of the transport mesh");
+    // the transport scratch follows the collision-step workspace (whose flag word must survive)
+    const size_t a = (bz_step_workspace_bytes(b) + 255) / 256 * 256;
+    char *tw = (char *)d_work + a;
+    bz_status st = bz_transport_step(t, d_f, 0.5 * dt, tw, work_bytes - a, stream);
+    if (st != BZ_OK) return st;
+    if ((st = bz_step(b, d_f, dt / eps, d_work, a, stream)) != BZ_OK) return st;
+    return bz_transport_step(t, d_f, 0.5 * dt, tw, work_bytes - a, stream);
+}
+
+}  // extern "C"
