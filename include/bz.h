@@ -194,6 +194,96 @@ bz_status bz_strang_step(bz_batch b, bz_transport t, double *d_f, double dt, dou
                          size_t work_bytes, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* Learned closure: network kernels.  A 3-layer perceptron                */
+/*   n_in -> n_hidden -> n_hidden -> n_out, exact-erf GELU after the two  */
+/* hidden layers, BF16 weights and activations on the matrix cores with   */
+/* FP32 accumulation, FP32 master weights and Adam (beta 0.9 / 0.999,     */
+/* eps 1e-8), loss = mean squared error.  Weights are stored [out][in].   */
+/* ------------------------------------------------------------------ */
+typedef struct bz_mlp_s *bz_mlp;
+
+/* Host handle (sizes only).  n_in, n_hidden and n_out must be multiples of 32
+ * (the GEMM's k-tile); BZ_EINVAL otherwise. */
+bz_status bz_mlp_create(int n_in, int n_hidden, int n_out, bz_mlp *out);
+void bz_mlp_free(bz_mlp n);
+/* FP32 master parameter count, laid out [W1 b1 W2 b2 W3 b3]. */
+size_t bz_mlp_param_count(bz_mlp n);
+/* Bytes of the caller's parameter buffer (master, Adam moments, BF16 copies). */
+size_t bz_mlp_param_bytes(bz_mlp n);
+/* Bytes of the caller's workspace for a batch of `batch` samples. */
+size_t bz_mlp_workspace_bytes(bz_mlp n, int batch);
+/* Upload host FP32 master weights (param_count floats), zero the Adam moments,
+ * derive the BF16 copies.  Synchronous. */
+bz_status bz_mlp_set_params(bz_mlp n, void *d_params, const float *master, void *stream);
+/* Download the FP32 master weights.  Synchronous. */
+bz_status bz_mlp_get_params(bz_mlp n, const void *d_params, float *master, void *stream);
+/* d_y[batch][n_out] (FP32) = network(d_x[batch][n_in] (BF16 bit patterns)). */
+bz_status bz_mlp_forward(bz_mlp n, const void *d_params, const uint16_t *d_x, int batch, float *d_y, void *d_work,
+                         size_t work_bytes, void *stream);
+/* Gradients of the loss against d_target[batch][n_out] (FP32) into d_grad
+ * (param_count floats, master layout); d_loss (may be NULL) receives the
+ * loss as one float.  batch must be a multiple of 32. */
+bz_status bz_mlp_backward(bz_mlp n, const void *d_params, const uint16_t *d_x, const float *d_target, int batch,
+                          float *d_grad, float *d_loss, void *d_work, size_t work_bytes, void *stream);
+/* One Adam step (step number >= 1) with learning rate lr, then refresh the BF16 copies. */
+bz_status bz_mlp_adam(bz_mlp n, void *d_params, const float *d_grad, int step, float lr, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Gated learned closure around the collision step.                      */
+/* ------------------------------------------------------------------ */
+/* Per cell: rho, u, T (FP64 moments), the local Maxwellian M, the deviation
+ * d = |f - M|_2 / |M|_2.  Cells with d < gate are served by the network:
+ * x = (f - M) / (rho s_in) in BF16, Q_s = rho^2 s_out net(x) (the density
+ * scales out of the bilinear Q exactly).  The others take the weighted
+ * convolution.  One gated cell in judge_every (rotating over evaluations) is
+ * also convolved, compared after projection,
+ *   err = |P(Q_s - Q_c)|_2 / (|P Q_c|_2 + judge_floor rho |M|_2)
+ * (the floor is on the scale of the loss term, so that cells at equilibrium,
+ * whose Q is only the discretisation residual, are judged against the
+ * collision rate),
+ * counted as failed if err > judge_tol, and keeps the convolution result.
+ * The FP64 projection of Sec. 3.3 is always applied.  Requires a batch on one
+ * mesh with n_in = n_out = N^3. */
+typedef struct {
+    bz_mlp net;
+    const void *d_params;   /* network parameters (bz_mlp_set_params / training) */
+    double gate;
+    double s_in, s_out;
+    int judge_every;        /* 0: no judged cells */
+    double judge_tol;
+    double judge_floor;
+} bz_closure;
+
+typedef struct {
+    unsigned served;        /* cells that took the network's result */
+    unsigned judged;        /* gated cells also convolved and compared */
+    unsigned failed;        /* judged cells with err > judge_tol */
+    float max_err;          /* largest judged err */
+} bz_closure_stats;
+
+/* Workspace of the closure calls: bz_step_workspace_bytes plus the closure's
+ * per-cell state, network input and output and the network workspace. */
+size_t bz_closure_workspace_bytes(bz_batch b, const bz_closure *c);
+/* Gate and network input for every cell (used to harvest training data):
+ * d_state[n_cells][10] = (rho, u1, u2, u3, T, d, gated, 0, |M|_2, 0),
+ * d_x[n_cells][N^3] BF16. */
+bz_status bz_closure_prepare(bz_batch b, const double *d_f, double gate, double s_in, double *d_state,
+                             uint16_t *d_x, void *stream);
+/* Training targets d_y[n_cells][N^3] = Q / (rho^2 s_out) from a projected Q. */
+bz_status bz_closure_targets(bz_batch b, const double *d_state, const double *d_Q, double s_out, float *d_y,
+                             void *stream);
+/* Qt of every cell with the gate applied (unprojected, like bz_collide_batch). */
+bz_status bz_closure_collide(bz_batch b, const bz_closure *c, const double *d_f, double *d_Qt, void *d_work,
+                             size_t work_bytes, void *stream);
+/* bz_step and bz_strang_step with the closure in every collision evaluation. */
+bz_status bz_closure_step(bz_batch b, const bz_closure *c, double *d_f, double dt_over_eps, void *d_work,
+                          size_t work_bytes, void *stream);
+bz_status bz_closure_strang_step(bz_batch b, bz_transport t, const bz_closure *c, double *d_f, double dt,
+                                 double eps, void *d_work, size_t work_bytes, void *stream);
+/* Counters accumulated since the last read (synchronises `stream`, then clears them). */
+bz_status bz_closure_read_stats(bz_batch b, const bz_closure *c, void *d_work, bz_closure_stats *out, void *stream);
+
+/* ------------------------------------------------------------------ */
 /* Tuning and measurement.                                               */
 /* ------------------------------------------------------------------ */
 /* Select the convolution kernel variant for the cells of grids[grid_index]

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbz.so")
-SOURCES = ["bz_runtime.hip", "bz_dft.hip", "bz_misc.hip", "bz_conv.hip", "bz_transport.hip"]
+SOURCES = ["bz_runtime.hip", "bz_dft.hip", "bz_misc.hip", "bz_conv.hip", "bz_transport.hip", "bz_mlp.hip", "bz_surrogate.hip"]
 ARCH = os.environ.get("BZ_OFFLOAD_ARCH", "gfx950")
 
 

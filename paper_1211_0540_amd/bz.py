@@ -41,6 +41,17 @@ _sz = ctypes.c_size_t
 _lib = None
 
 
+class ClosureDesc(ctypes.Structure):
+    _fields_ = [("net", ctypes.c_void_p), ("d_params", ctypes.c_void_p), ("gate", ctypes.c_double),
+                ("s_in", ctypes.c_double), ("s_out", ctypes.c_double), ("judge_every", ctypes.c_int),
+                ("judge_tol", ctypes.c_double), ("judge_floor", ctypes.c_double)]
+
+
+class ClosureStats(ctypes.Structure):
+    _fields_ = [("served", ctypes.c_uint), ("judged", ctypes.c_uint), ("failed", ctypes.c_uint),
+                ("max_err", ctypes.c_float)]
+
+
 def lib():
     """Load libbz.so (raises if it has not been built)."""
     global _lib
@@ -78,6 +89,25 @@ def lib():
         "bz_transport_step": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _vp, _sz, _vp]),
         "bz_strang_workspace_bytes": (_sz, [_vp, _vp]),
         "bz_strang_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _sz, _vp]),
+        "bz_mlp_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]),
+        "bz_mlp_free": (None, [_vp]),
+        "bz_mlp_param_count": (_sz, [_vp]),
+        "bz_mlp_param_bytes": (_sz, [_vp]),
+        "bz_mlp_workspace_bytes": (_sz, [_vp, ctypes.c_int]),
+        "bz_mlp_set_params": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+        "bz_mlp_get_params": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+        "bz_mlp_forward": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
+        "bz_mlp_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp, _sz, _vp]),
+        "bz_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_float, _vp]),
+        "bz_closure_workspace_bytes": (_sz, [_vp, ctypes.POINTER(ClosureDesc)]),
+        "bz_closure_prepare": (ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp, _vp]),
+        "bz_closure_targets": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp]),
+        "bz_closure_collide": (ctypes.c_int, [_vp, ctypes.POINTER(ClosureDesc), _vp, _vp, _vp, _sz, _vp]),
+        "bz_closure_step": (ctypes.c_int, [_vp, ctypes.POINTER(ClosureDesc), _vp, ctypes.c_double, _vp, _sz, _vp]),
+        "bz_closure_strang_step": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ClosureDesc), _vp, ctypes.c_double,
+                                                  ctypes.c_double, _vp, _sz, _vp]),
+        "bz_closure_read_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ClosureDesc), _vp, ctypes.POINTER(ClosureStats),
+                                                 _vp]),
         "bz_variant_count": (ctypes.c_int, []),
         "bz_batch_set_variant": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
         "bz_batch_get_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -248,6 +278,115 @@ def bz_strang_step(b: int, t: int, f, dt: float, eps: float, work, stream=None) 
     _dev(work, "workspace")
     _check(lib().bz_strang_step(_vp(b), _vp(t), _vp(_ptr(f)), float(dt), float(eps), _vp(_ptr(work)),
                                 work.numel() * work.element_size(), _stream(stream)))
+
+
+def bz_mlp_create(n_in: int, n_hidden: int, n_out: int) -> int:
+    h = _vp()
+    _check(lib().bz_mlp_create(int(n_in), int(n_hidden), int(n_out), ctypes.byref(h)))
+    return h.value
+
+
+def bz_mlp_free(n: int) -> None:
+    lib().bz_mlp_free(_vp(n))
+
+
+def bz_mlp_param_count(n: int) -> int:
+    return int(lib().bz_mlp_param_count(_vp(n)))
+
+
+def bz_mlp_param_bytes(n: int) -> int:
+    return int(lib().bz_mlp_param_bytes(_vp(n)))
+
+
+def bz_mlp_workspace_bytes(n: int, batch: int) -> int:
+    return int(lib().bz_mlp_workspace_bytes(_vp(n), int(batch)))
+
+
+def bz_mlp_set_params(n: int, params, master: np.ndarray, stream=None) -> None:
+    _dev(params, "parameter buffer")
+    m = np.ascontiguousarray(master, dtype=np.float32)
+    if m.size != bz_mlp_param_count(n):
+        raise ValueError("master weight vector has the wrong length")
+    _check(lib().bz_mlp_set_params(_vp(n), _vp(_ptr(params)), _vp(m.ctypes.data), _stream(stream)))
+
+
+def bz_mlp_get_params(n: int, params, stream=None) -> np.ndarray:
+    out = np.empty(bz_mlp_param_count(n), dtype=np.float32)
+    _check(lib().bz_mlp_get_params(_vp(n), _vp(_ptr(params)), _vp(out.ctypes.data), _stream(stream)))
+    return out
+
+
+def bz_mlp_forward(n: int, params, x_bf16, batch: int, y, work, stream=None) -> None:
+    _check(lib().bz_mlp_forward(_vp(n), _vp(_ptr(params)), _vp(_ptr(x_bf16)), int(batch), _vp(_ptr(y)),
+                                _vp(_ptr(work)), work.numel() * work.element_size(), _stream(stream)))
+
+
+def bz_mlp_backward(n: int, params, x_bf16, target, batch: int, grad, loss, work, stream=None) -> None:
+    _check(lib().bz_mlp_backward(_vp(n), _vp(_ptr(params)), _vp(_ptr(x_bf16)), _vp(_ptr(target)), int(batch),
+                                 _vp(_ptr(grad)), _vp(_ptr(loss)), _vp(_ptr(work)),
+                                 work.numel() * work.element_size(), _stream(stream)))
+
+
+def bz_mlp_adam(n: int, params, grad, step: int, lr: float, stream=None) -> None:
+    _check(lib().bz_mlp_adam(_vp(n), _vp(_ptr(params)), _vp(_ptr(grad)), int(step), float(lr), _stream(stream)))
+
+
+def closure_desc(net: int, params, gate: float, s_in: float, s_out: float, judge_every: int = 16,
+                 judge_tol: float = 1e-2, judge_floor: float = 1e-3) -> ClosureDesc:
+    return ClosureDesc(_vp(net), _vp(_ptr(params)), float(gate), float(s_in), float(s_out), int(judge_every),
+                       float(judge_tol), float(judge_floor))
+
+
+def bz_closure_workspace_bytes(b: int, desc: ClosureDesc) -> int:
+    return int(lib().bz_closure_workspace_bytes(_vp(b), ctypes.byref(desc)))
+
+
+def bz_closure_prepare(b: int, f, gate: float, s_in: float, state, x, stream=None) -> None:
+    _check(lib().bz_closure_prepare(_vp(b), _vp(_ptr(f)), float(gate), float(s_in), _vp(_ptr(state)),
+                                    _vp(_ptr(x)), _stream(stream)))
+
+
+def bz_closure_targets(b: int, state, q, s_out: float, y, stream=None) -> None:
+    _check(lib().bz_closure_targets(_vp(b), _vp(_ptr(state)), _vp(_ptr(q)), float(s_out), _vp(_ptr(y)),
+                                    _stream(stream)))
+
+
+def bz_closure_collide(b: int, desc: ClosureDesc, f, qt, work, stream=None) -> None:
+    _check(lib().bz_closure_collide(_vp(b), ctypes.byref(desc), _vp(_ptr(f)), _vp(_ptr(qt)), _vp(_ptr(work)),
+                                    work.numel() * work.element_size(), _stream(stream)))
+
+
+def bz_closure_step(b: int, desc: ClosureDesc, f, dt_over_eps: float, work, stream=None) -> None:
+    _check(lib().bz_closure_step(_vp(b), ctypes.byref(desc), _vp(_ptr(f)), float(dt_over_eps), _vp(_ptr(work)),
+                                 work.numel() * work.element_size(), _stream(stream)))
+
+
+def bz_closure_strang_step(b: int, t: int, desc: ClosureDesc, f, dt: float, eps: float, work, stream=None) -> None:
+    _check(lib().bz_closure_strang_step(_vp(b), _vp(t), ctypes.byref(desc), _vp(_ptr(f)), float(dt), float(eps),
+                                        _vp(_ptr(work)), work.numel() * work.element_size(), _stream(stream)))
+
+
+def bz_closure_read_stats(b: int, desc: ClosureDesc, work, stream=None) -> dict:
+    st = ClosureStats()
+    _check(lib().bz_closure_read_stats(_vp(b), ctypes.byref(desc), _vp(_ptr(work)), ctypes.byref(st),
+                                       _stream(stream)))
+    return {"served": st.served, "judged": st.judged, "failed": st.failed, "max_err": st.max_err}
+
+
+def mlp_pack(p: dict) -> np.ndarray:
+    """Concatenate oracle-style parameters into the library's master layout."""
+    return np.concatenate([np.asarray(p[k], dtype=np.float32).ravel() for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+
+def mlp_unpack(v: np.ndarray, n_in: int, n_hidden: int, n_out: int) -> dict:
+    shapes = [("W1", (n_hidden, n_in)), ("b1", (n_hidden,)), ("W2", (n_hidden, n_hidden)), ("b2", (n_hidden,)),
+              ("W3", (n_out, n_hidden)), ("b3", (n_out,))]
+    out, o = {}, 0
+    for k, sh in shapes:
+        sz = int(np.prod(sh))
+        out[k] = v[o:o + sz].reshape(sh).astype(np.float64)
+        o += sz
+    return out
 
 
 def bz_variant_count() -> int:

@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(64) k_conv_cells_f32(const float2 *__restrict_
                                                        const long long *__restrict__ row_woff,
                                                        const int4 *__restrict__ items, int n_items,
                                                        unsigned *__restrict__ counter, double2 *__restrict__ qh,
-                                                       long long part_stride) {
+                                                       long long part_stride, const unsigned char *__restrict__ skip) {
     constexpr int h = N / 2, M = N * N * N, PS = 3 * N * N / 4;
     constexpr int CH = (PS * 4 + 1023) / 1024;       // KiB per step of weights
     constexpr int RCH = N * kWave * 8 / 1024;        // KiB per fhat row of 64 cells
@@ -159,6 +159,13 @@ __global__ void __launch_bounds__(64) k_conv_cells_f32(const float2 *__restrict_
         const int4 item = items[it];
         const int g = item.x, r = item.y & 0xffff, part = item.y >> 16, s0 = item.z, s1 = item.w;
         const int k1 = r / N, k2 = r - k1 * N;
+        if (skip && skip[g]) {
+            // every cell of the group is served elsewhere: leave zeros in this item's outputs
+            double2 *o = qh + part * part_stride + (size_t)g * M * kWave + (size_t)r * N * kWave + lane;
+#pragma unroll
+            for (int t = 0; t < N; ++t) o[t * kWave] = make_double2(0.0, 0.0);
+            continue;
+        }
         const float *w = W + row_woff[r] + (long long)s0 * PS;
         const float2 *G = fh + (size_t)g * M * kWave;   // this group's fhat
         const float2 *F = G + lane;
@@ -263,7 +270,7 @@ __global__ void __launch_bounds__(64) k_conv_cells_f64(const double2 *__restrict
                                                        const long long *__restrict__ row_woff,
                                                        const int4 *__restrict__ items, int n_items,
                                                        unsigned *__restrict__ counter, double2 *__restrict__ qh,
-                                                       long long part_stride) {
+                                                       long long part_stride, const unsigned char *__restrict__ skip) {
     constexpr int h = N / 2, M = N * N * N, PS = 3 * N * N / 4;
     constexpr int CH = (PS * 8 + 1023) / 1024;
     __shared__ __attribute__((aligned(16))) double wbuf[2][CH * 128];
@@ -275,6 +282,13 @@ __global__ void __launch_bounds__(64) k_conv_cells_f64(const double2 *__restrict
         const int4 item = items[it];
         const int g = item.x, r = item.y & 0xffff, part = item.y >> 16, s0 = item.z, s1 = item.w;
         const int k1 = r / N, k2 = r - k1 * N;
+        if (skip && skip[g]) {
+            // every cell of the group is served elsewhere: leave zeros in this item's outputs
+            double2 *o = qh + part * part_stride + (size_t)g * M * kWave + (size_t)r * N * kWave + lane;
+#pragma unroll
+            for (int t = 0; t < N; ++t) o[t * kWave] = make_double2(0.0, 0.0);
+            continue;
+        }
         const double *w = W + row_woff[r] + (long long)s0 * PS;
         const double2 *F = fh + (size_t)g * M * kWave + lane;
         double pr[N], pi[N];
@@ -374,7 +388,7 @@ hipError_t cells_f32_variant(const CellsLaunch &p, unsigned grid, hipStream_t s)
 #define BZ_CELLS_F32(F, C, WPV, RPV)                                                                        \
     hipLaunchKernelGGL((k_conv_cells_f32<N, F, C, WPV, RPV>), dim3(grid), dim3(64), 0, s,                   \
                        (const float2 *)p.fh, (const float *)p.w, p.row_woff, p.items, p.n_items, p.counter, \
-                       p.qh, p.part_stride)
+                       p.qh, p.part_stride, p.skip)
     switch (p.variant) {
     case 1: BZ_CELLS_F32(2, 1, 0, 1); break;
     case 2: BZ_CELLS_F32(2, 0, 0, 0); break;
@@ -390,7 +404,7 @@ hipError_t cells_f32_variant(const CellsLaunch &p, unsigned grid, hipStream_t s)
 template <int N>
 hipError_t cells_f64_launch(const CellsLaunch &p, unsigned grid, hipStream_t s) {
     hipLaunchKernelGGL((k_conv_cells_f64<N>), dim3(grid), dim3(64), 0, s, (const double2 *)p.fh,
-                       (const double *)p.w, p.row_woff, p.items, p.n_items, p.counter, p.qh, p.part_stride);
+                       (const double *)p.w, p.row_woff, p.items, p.n_items, p.counter, p.qh, p.part_stride, p.skip);
     return hipGetLastError();
 }
 

@@ -113,6 +113,12 @@ namespace bz {
 bz_status fail(bz_status s, const std::string &msg);
 bz_status hip_fail(hipError_t e, const char *what);
 
+#define BZ_HIP(call, what)                               \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files).  All take a hipStream_t.
 // ---------------------------------------------------------------------------
@@ -150,6 +156,7 @@ struct CellsLaunch {
     double2 *qh;                 // [parts][G][N^3][64]
     long long part_stride;       // complex elements between partial-sum buffers
     int variant;                 // tuning variant
+    const unsigned char *skip;   // device, per group: 1 = outputs not needed (may be NULL)
 };
 hipError_t launch_conv_cells(const CellsLaunch &p, bool f64, hipStream_t s);
 
@@ -174,5 +181,16 @@ hipError_t launch_axpy(size_t n, const double *a, const double *q, double c, dou
 hipError_t launch_heun_final(size_t n, const double *f, const double *fs, const double *q, double c, double *out,
                              unsigned *flag, hipStream_t s);
 hipError_t launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t s);
+
+// Gated closure helpers (bz_surrogate.hip).
+hipError_t launch_sur_prepare(int N, double dv, int n, const double *f, const long long *f_off, double gate,
+                              double s_in, int judge_every, int phase, double *state, unsigned short *x,
+                              hipStream_t s);
+hipError_t launch_group_skip(int n, const double *state, unsigned char *skip, hipStream_t s);
+hipError_t launch_sur_finish(int N, double dv, const double *linv, int n, const double *state, const float *y,
+                             double s_out, double floor_, double tol, const long long *q_off, double *q,
+                             unsigned *stats, hipStream_t s);
+hipError_t launch_sur_targets(int N, int n, const double *state, const double *q, const long long *q_off,
+                              double s_out, float *y, hipStream_t s);
 
 }  // namespace bz

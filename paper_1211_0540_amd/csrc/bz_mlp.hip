@@ -1,0 +1,457 @@
+// Learned closure: a 3-layer perceptron n_in -> n_hid -> n_hid -> n_out with
+// exact-erf GELU, BF16 operands and FP32 accumulation on the CDNA4 matrix
+// cores, trained with mean-squared error and Adam (FP32 master weights).
+//
+// One GEMM form serves forward and backward: C[M x N] = alpha * A[M x K] B^T,
+// A [M x K] and B [N x K] both row-major BF16 with K contiguous, so that the
+// fragments of v_mfma_f32_16x16x32_bf16 (8 consecutive k per lane: A row
+// lane%16, B column lane%16, k block lane/16) are single 16-byte LDS reads.
+//   forward   Z1 = X W1^T, Z2 = A1 W2^T, Y = A2 W3^T         (weights stored [out][in])
+//   backward  dA2 = dY W3, dA1 = dZ2 W2                       (transposed copies W3, W2)
+//             dW3 = dY^T A2, dW2 = dZ2^T A1, dW1 = dZ1^T X     (transposed activations)
+// Tile 128 x 128 x 32 per 256-thread workgroup (4 waves of 64 x 64, 16 MFMAs
+// each per k step), next k tile prefetched into registers while the current
+// one is consumed from LDS.  K must be a multiple of 32.
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "bz_internal.h"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct bz_mlp_s {
+    int n_in = 0, n_hid = 0, n_out = 0;
+    // offsets (elements) into the FP32 master block
+    size_t oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, oW3 = 0, ob3 = 0, n_params = 0;
+};
+
+namespace bz {
+namespace {
+
+__device__ inline unsigned short f2bf(float x) {
+    // round to nearest even (finite inputs)
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ inline float bf2f(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
+
+__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ inline float gelu_prime(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.3989422804014327f;
+}
+
+enum { EPI_F32 = 0, EPI_GELU = 1 };
+
+constexpr int TBM = 128, TBN = 128, TBK = 32, LDSK = TBK + 8;
+
+// EPI_F32:  C32[m][n] = alpha * acc + (bias ? bias[n] : 0)
+// EPI_GELU: Z = acc + bias[n]; C32 = Z; Cbf = bf16(gelu(Z))
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const unsigned short *__restrict__ A, int lda,
+                                                 const unsigned short *__restrict__ B, int ldb, float alpha,
+                                                 const float *__restrict__ bias, float *__restrict__ C32, int ldc,
+                                                 unsigned short *__restrict__ Cbf, int ldcb) {
+    __shared__ __attribute__((aligned(16))) unsigned short As[TBM * LDSK];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[TBN * LDSK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
+    // global -> register loads: thread t moves row t/2, k half (t%2)*16 of each tile (2 x 16 bytes)
+    const int lr = tid >> 1, lk = (tid & 1) * 16;
+    const int am = m0 + lr, bn = n0 + lr;
+    const bool aok = am < M, bok = bn < N;
+    const uint4 *ap = (const uint4 *)(A + (size_t)(aok ? am : 0) * lda + lk);
+    const uint4 *bp = (const uint4 *)(B + (size_t)(bok ? bn : 0) * ldb + lk);
+    const uint4 z4 = make_uint4(0, 0, 0, 0);
+    uint4 ra0 = aok ? ap[0] : z4, ra1 = aok ? ap[1] : z4;
+    uint4 rb0 = bok ? bp[0] : z4, rb1 = bok ? bp[1] : z4;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int nk = K / TBK;
+    for (int kt = 0; kt < nk; ++kt) {
+        __syncthreads();
+        *(uint4 *)(As + lr * LDSK + lk) = ra0;
+        *(uint4 *)(As + lr * LDSK + lk + 8) = ra1;
+        *(uint4 *)(Bs + lr * LDSK + lk) = rb0;
+        *(uint4 *)(Bs + lr * LDSK + lk + 8) = rb1;
+        __syncthreads();
+        if (kt + 1 < nk) {
+            const int o = (kt + 1) * TBK / 8;  // in uint4 units
+            ra0 = aok ? ap[o] : z4;
+            ra1 = aok ? ap[o + 1] : z4;
+            rb0 = bok ? bp[o] : z4;
+            rb1 = bok ? bp[o + 1] : z4;
+        }
+        bf16x8 af[4], bfr[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = wm * 64 + i * 16 + (lane & 15);
+            af[i] = *(const bf16x8 *)(As + row * LDSK + (lane >> 4) * 8);
+            const int col = wn * 64 + i * 16 + (lane & 15);
+            bfr[i] = *(const bf16x8 *)(Bs + col * LDSK + (lane >> 4) * 8);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+            if (col >= N) continue;
+            const float bcol = bias ? bias[col] : 0.f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + r;
+                if (row >= M) continue;
+                const float z = alpha * acc[i][j][r] + bcol;
+                if (EPI == EPI_GELU) {
+                    C32[(size_t)row * ldc + col] = z;
+                    Cbf[(size_t)row * ldcb + col] = f2bf(gelu(z));
+                } else {
+                    C32[(size_t)row * ldc + col] = z;
+                }
+            }
+        }
+}
+
+// out[c][r] = in[r][c] for an R x C BF16 matrix (32 x 32 tiles through LDS).
+__global__ void __launch_bounds__(256) k_transpose_bf16(int R, int C, const unsigned short *__restrict__ in,
+                                                        unsigned short *__restrict__ out) {
+    __shared__ unsigned short t[32][33];
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int y = ty; y < 32; y += 8) {
+        const int r = r0 + y, c = c0 + tx;
+        t[y][tx] = (r < R && c < C) ? in[(size_t)r * C + c] : 0;
+    }
+    __syncthreads();
+    for (int y = ty; y < 32; y += 8) {
+        const int c = c0 + y, r = r0 + tx;
+        if (c < C && r < R) out[(size_t)c * R + r] = t[tx][y];
+    }
+}
+
+__global__ void k_f32_to_bf16(size_t n, const float *__restrict__ in, unsigned short *__restrict__ out) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = f2bf(in[i]);
+}
+
+// dY = bf16(scale (Y - T)); per-block partial sums of (Y - T)^2 into part[blockIdx.x]
+__global__ void __launch_bounds__(256) k_mse_grad(size_t n, const float *__restrict__ Y, const float *__restrict__ T,
+                                                  float scale, unsigned short *__restrict__ dY,
+                                                  double *__restrict__ part) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float d = Y[i] - T[i];
+        dY[i] = f2bf(scale * d);
+        s += (double)d * d;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_sum_parts(int n, const double *__restrict__ part, double inv_n, float *__restrict__ loss) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += part[i];
+        loss[0] = (float)(s * inv_n);
+    }
+}
+
+// dZ = bf16(dA * gelu'(Z))
+__global__ void k_gelu_bwd(size_t n, const float *__restrict__ dA, const float *__restrict__ Z,
+                           unsigned short *__restrict__ dZ) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dZ[i] = f2bf(dA[i] * gelu_prime(Z[i]));
+}
+
+// db[n] = alpha * sum_m bf2f(D[m][n])  (D is rows x cols BF16)
+__global__ void k_col_sums(int rows, int cols, const unsigned short *__restrict__ D, float alpha, float *__restrict__ db) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    float s = 0.f;
+    for (int r = 0; r < rows; ++r) s += bf2f(D[(size_t)r * cols + c]);
+    db[c] = alpha * s;
+}
+
+__global__ void k_adam(size_t n, float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, float lr, float b1, float b2, float eps, float c1, float c2) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        w[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    }
+}
+
+__global__ void k_fill_f32(size_t n, float *__restrict__ p, float v) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+inline unsigned grid1(size_t n) {
+    size_t b = (n + 255) / 256;
+    return (unsigned)(b > 16384 ? 16384 : (b < 1 ? 1 : b));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Buffer layouts.
+//   params (caller-owned, bz_mlp_param_bytes): FP32 master [W1 b1 W2 b2 W3 b3],
+//     Adam m and v (same layout), then BF16 W1, W2, W3 ([out][in]) and BF16
+//     transposed W2^T, W3^T ([in][out]).
+//   workspace (bz_mlp_workspace_bytes(batch)): activations and gradients.
+// ---------------------------------------------------------------------------
+struct ParamView {
+    float *master, *m, *v;
+    unsigned short *W1, *W2, *W3, *W2t, *W3t;
+};
+
+static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static ParamView param_view(const bz_mlp_s *n, void *p) {
+    char *c = (char *)p;
+    ParamView v;
+    const size_t fb = a256(n->n_params * 4);
+    v.master = (float *)c;
+    v.m = (float *)(c + fb);
+    v.v = (float *)(c + 2 * fb);
+    char *b = c + 3 * fb;
+    v.W1 = (unsigned short *)b;
+    b += a256((size_t)n->n_hid * n->n_in * 2);
+    v.W2 = (unsigned short *)b;
+    b += a256((size_t)n->n_hid * n->n_hid * 2);
+    v.W3 = (unsigned short *)b;
+    b += a256((size_t)n->n_out * n->n_hid * 2);
+    v.W2t = (unsigned short *)b;
+    b += a256((size_t)n->n_hid * n->n_hid * 2);
+    v.W3t = (unsigned short *)b;
+    return v;
+}
+
+static size_t param_bytes(const bz_mlp_s *n) {
+    return 3 * a256(n->n_params * 4) + a256((size_t)n->n_hid * n->n_in * 2) + 2 * a256((size_t)n->n_hid * n->n_hid * 2) +
+           2 * a256((size_t)n->n_out * n->n_hid * 2);
+}
+
+struct WorkView {
+    float *Z1, *Z2, *Y, *dA;     // FP32
+    unsigned short *A1, *A2;     // BF16 activations
+    unsigned short *dY, *dZ;     // BF16 gradients (dZ reused for layers 2 and 1)
+    unsigned short *tA, *tB;     // transposes
+    double *part;
+    float *loss;
+};
+
+static WorkView work_view(const bz_mlp_s *n, int B, void *w) {
+    char *c = (char *)w;
+    WorkView v;
+    auto take = [&c](size_t bytes) {
+        char *p = c;
+        c += a256(bytes);
+        return p;
+    };
+    const size_t H = n->n_hid, O = n->n_out, I = n->n_in;
+    v.Z1 = (float *)take((size_t)B * H * 4);
+    v.Z2 = (float *)take((size_t)B * H * 4);
+    v.Y = (float *)take((size_t)B * O * 4);
+    v.dA = (float *)take((size_t)B * H * 4);
+    v.A1 = (unsigned short *)take((size_t)B * H * 2);
+    v.A2 = (unsigned short *)take((size_t)B * H * 2);
+    v.dY = (unsigned short *)take((size_t)B * O * 2);
+    v.dZ = (unsigned short *)take((size_t)B * H * 2);
+    const size_t big = std::max(std::max(O, I), H) * (size_t)B * 2;
+    v.tA = (unsigned short *)take(big);
+    v.tB = (unsigned short *)take(big);
+    v.part = (double *)take(16384 * 8);
+    v.loss = (float *)take(256);
+    return v;
+}
+
+static size_t work_bytes(const bz_mlp_s *n, int B) {
+    const size_t H = n->n_hid, O = n->n_out, I = n->n_in;
+    return a256((size_t)B * H * 4) * 3 + a256((size_t)B * O * 4) + a256((size_t)B * H * 2) * 3 +
+           a256((size_t)B * O * 2) + 2 * a256(std::max(std::max(O, I), H) * (size_t)B * 2) + a256(16384 * 8) + 256;
+}
+
+static hipError_t gemm(int epi, int M, int N, int K, const unsigned short *A, int lda, const unsigned short *B, int ldb,
+                       float alpha, const float *bias, float *C32, int ldc, unsigned short *Cbf, int ldcb, hipStream_t s) {
+    dim3 grid((N + TBN - 1) / TBN, (M + TBM - 1) / TBM);
+    if (epi == EPI_GELU)
+        hipLaunchKernelGGL(k_gemm_nt<EPI_GELU>, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, alpha, bias, C32, ldc,
+                           Cbf, ldcb);
+    else
+        hipLaunchKernelGGL(k_gemm_nt<EPI_F32>, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, alpha, bias, C32, ldc,
+                           Cbf, ldcb);
+    return hipGetLastError();
+}
+
+static hipError_t transpose(int R, int C, const unsigned short *in, unsigned short *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_transpose_bf16, dim3((C + 31) / 32, (R + 31) / 32), dim3(256), 0, s, R, C, in, out);
+    return hipGetLastError();
+}
+
+static hipError_t refresh_bf16(const bz_mlp_s *n, const ParamView &pv, hipStream_t s) {
+    const size_t H = n->n_hid, O = n->n_out, I = n->n_in;
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid1(H * I)), dim3(256), 0, s, H * I, pv.master + n->oW1, pv.W1);
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid1(H * H)), dim3(256), 0, s, H * H, pv.master + n->oW2, pv.W2);
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid1(O * H)), dim3(256), 0, s, O * H, pv.master + n->oW3, pv.W3);
+    hipError_t e = transpose((int)H, (int)H, pv.W2, pv.W2t, s);
+    if (e == hipSuccess) e = transpose((int)O, (int)H, pv.W3, pv.W3t, s);
+    return e == hipSuccess ? hipGetLastError() : e;
+}
+
+static hipError_t forward(const bz_mlp_s *n, const ParamView &pv, const unsigned short *X, int B, const WorkView &wv,
+                          float *Y, hipStream_t s) {
+    const int H = n->n_hid, O = n->n_out, I = n->n_in;
+    hipError_t e = gemm(EPI_GELU, B, H, I, X, I, pv.W1, I, 1.f, pv.master + n->ob1, wv.Z1, H, wv.A1, H, s);
+    if (e == hipSuccess) e = gemm(EPI_GELU, B, H, H, wv.A1, H, pv.W2, H, 1.f, pv.master + n->ob2, wv.Z2, H, wv.A2, H, s);
+    if (e == hipSuccess) e = gemm(EPI_F32, B, O, H, wv.A2, H, pv.W3, H, 1.f, pv.master + n->ob3, Y, O, nullptr, 0, s);
+    return e;
+}
+
+// gradients of mean((Y - T)^2) into g (FP32, master layout); dY is kept as bf16(Y - T),
+// the factor 2 / (B n_out) is applied in the weight-gradient GEMMs and bias sums.
+static hipError_t backward(const bz_mlp_s *n, const ParamView &pv, const unsigned short *X, const float *T, int B,
+                           const WorkView &wv, float *g, hipStream_t s) {
+    const int H = n->n_hid, O = n->n_out, I = n->n_in;
+    const size_t nY = (size_t)B * O;
+    const float gs = 2.0f / (float)nY;
+    hipLaunchKernelGGL(k_mse_grad, dim3(grid1(nY) > 4096 ? 4096 : grid1(nY)), dim3(256), 0, s, nY, wv.Y, T, 1.0f,
+                       wv.dY, wv.part);
+    const int nparts = grid1(nY) > 4096 ? 4096 : (int)grid1(nY);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, nparts, wv.part, 1.0 / (double)nY, wv.loss);
+    // layer 3: dW3 = gs dY^T A2 ([O x B] x [H x B]^T), db3 = gs colsum(dY), dA2 = dY W3 (via W3t [H x O])
+    hipError_t e = transpose(B, O, wv.dY, wv.tA, s);
+    if (e == hipSuccess) e = transpose(B, H, wv.A2, wv.tB, s);
+    if (e == hipSuccess) e = gemm(EPI_F32, O, H, B, wv.tA, B, wv.tB, B, gs, nullptr, g + n->oW3, H, nullptr, 0, s);
+    hipLaunchKernelGGL(k_col_sums, dim3((O + 255) / 256), dim3(256), 0, s, B, O, wv.dY, gs, g + n->ob3);
+    if (e == hipSuccess) e = gemm(EPI_F32, B, H, O, wv.dY, O, pv.W3t, O, gs, nullptr, wv.dA, H, nullptr, 0, s);
+    hipLaunchKernelGGL(k_gelu_bwd, dim3(grid1((size_t)B * H)), dim3(256), 0, s, (size_t)B * H, wv.dA, wv.Z2, wv.dZ);
+    // layer 2 (dZ holds the true gradient dL/dZ2)
+    if (e == hipSuccess) e = transpose(B, H, wv.dZ, wv.tA, s);
+    if (e == hipSuccess) e = transpose(B, H, wv.A1, wv.tB, s);
+    if (e == hipSuccess) e = gemm(EPI_F32, H, H, B, wv.tA, B, wv.tB, B, 1.f, nullptr, g + n->oW2, H, nullptr, 0, s);
+    hipLaunchKernelGGL(k_col_sums, dim3((H + 255) / 256), dim3(256), 0, s, B, H, wv.dZ, 1.f, g + n->ob2);
+    if (e == hipSuccess) e = gemm(EPI_F32, B, H, H, wv.dZ, H, pv.W2t, H, 1.f, nullptr, wv.dA, H, nullptr, 0, s);
+    hipLaunchKernelGGL(k_gelu_bwd, dim3(grid1((size_t)B * H)), dim3(256), 0, s, (size_t)B * H, wv.dA, wv.Z1, wv.dZ);
+    // layer 1
+    if (e == hipSuccess) e = transpose(B, H, wv.dZ, wv.tA, s);
+    if (e == hipSuccess) e = transpose(B, I, X, wv.tB, s);
+    if (e == hipSuccess) e = gemm(EPI_F32, H, I, B, wv.tA, B, wv.tB, B, 1.f, nullptr, g + n->oW1, I, nullptr, 0, s);
+    hipLaunchKernelGGL(k_col_sums, dim3((H + 255) / 256), dim3(256), 0, s, B, H, wv.dZ, 1.f, g + n->ob1);
+    return e == hipSuccess ? hipGetLastError() : e;
+}
+
+}  // namespace bz
+
+using namespace bz;
+
+extern "C" {
+
+bz_status bz_mlp_create(int n_in, int n_hidden, int n_out, bz_mlp *out) {
+    if (!out) return fail(BZ_EINVAL, "bz_mlp_create: out is NULL");
+    *out = nullptr;
+    if (n_in < 32 || n_hidden < 32 || n_out < 32 || n_in % 32 || n_hidden % 32 || n_out % 32)
+        return fail(BZ_EINVAL, "bz_mlp_create: n_in, n_hidden and n_out must be multiples of 32");
+    bz_mlp_s *n = new (std::nothrow) bz_mlp_s();
+    if (!n) return fail(BZ_ENOMEM, "bz_mlp_create: allocation failed");
+    n->n_in = n_in;
+    n->n_hid = n_hidden;
+    n->n_out = n_out;
+    size_t o = 0;
+    n->oW1 = o; o += (size_t)n_hidden * n_in;
+    n->ob1 = o; o += n_hidden;
+    n->oW2 = o; o += (size_t)n_hidden * n_hidden;
+    n->ob2 = o; o += n_hidden;
+    n->oW3 = o; o += (size_t)n_out * n_hidden;
+    n->ob3 = o; o += n_out;
+    n->n_params = o;
+    *out = n;
+    return BZ_OK;
+}
+
+void bz_mlp_free(bz_mlp n) { delete n; }
+size_t bz_mlp_param_count(bz_mlp n) { return n ? n->n_params : 0; }
+size_t bz_mlp_param_bytes(bz_mlp n) { return n ? param_bytes(n) : 0; }
+size_t bz_mlp_workspace_bytes(bz_mlp n, int batch) { return (n && batch > 0) ? work_bytes(n, batch) : 0; }
+
+bz_status bz_mlp_set_params(bz_mlp n, void *d_params, const float *master, void *stream) {
+    if (!n || !d_params || !master) return fail(BZ_EINVAL, "bz_mlp_set_params: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    ParamView pv = param_view(n, d_params);
+    BZ_HIP(hipMemcpyAsync(pv.master, master, n->n_params * 4, hipMemcpyHostToDevice, s), "upload weights");
+    hipLaunchKernelGGL(k_fill_f32, dim3(grid1(n->n_params)), dim3(256), 0, s, n->n_params, pv.m, 0.f);
+    hipLaunchKernelGGL(k_fill_f32, dim3(grid1(n->n_params)), dim3(256), 0, s, n->n_params, pv.v, 0.f);
+    BZ_HIP(hipGetLastError(), "zero Adam moments");
+    BZ_HIP(refresh_bf16(n, pv, s), "bf16 copies");
+    BZ_HIP(hipStreamSynchronize(s), "bz_mlp_set_params sync");
+    return BZ_OK;
+}
+
+bz_status bz_mlp_get_params(bz_mlp n, const void *d_params, float *master, void *stream) {
+    if (!n || !d_params || !master) return fail(BZ_EINVAL, "bz_mlp_get_params: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    BZ_HIP(hipMemcpyAsync(master, d_params, n->n_params * 4, hipMemcpyDeviceToHost, s), "download weights");
+    BZ_HIP(hipStreamSynchronize(s), "bz_mlp_get_params sync");
+    return BZ_OK;
+}
+
+bz_status bz_mlp_forward(bz_mlp n, const void *d_params, const uint16_t *d_x, int batch, float *d_y, void *d_work,
+                         size_t work_bytes_, void *stream) {
+    if (!n || !d_params || !d_x || !d_y || !d_work) return fail(BZ_EINVAL, "bz_mlp_forward: NULL argument");
+    if (batch < 1) return fail(BZ_EINVAL, "bz_mlp_forward: batch must be >= 1");
+    if (work_bytes_ < work_bytes(n, batch)) return fail(BZ_EINVAL, "bz_mlp_forward: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    ParamView pv = param_view(n, (void *)d_params);
+    WorkView wv = work_view(n, batch, d_work);
+    BZ_HIP(forward(n, pv, (const unsigned short *)d_x, batch, wv, d_y, s), "bz_mlp_forward");
+    return BZ_OK;
+}
+
+bz_status bz_mlp_backward(bz_mlp n, const void *d_params, const uint16_t *d_x, const float *d_target, int batch,
+                          float *d_grad, float *d_loss, void *d_work, size_t work_bytes_, void *stream) {
+    if (!n || !d_params || !d_x || !d_target || !d_grad || !d_work)
+        return fail(BZ_EINVAL, "bz_mlp_backward: NULL argument");
+    if (batch < 32 || batch % 32) return fail(BZ_EINVAL, "bz_mlp_backward: batch must be a multiple of 32");
+    if (work_bytes_ < work_bytes(n, batch)) return fail(BZ_EINVAL, "bz_mlp_backward: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    ParamView pv = param_view(n, (void *)d_params);
+    WorkView wv = work_view(n, batch, d_work);
+    const unsigned short *X = (const unsigned short *)d_x;
+    BZ_HIP(forward(n, pv, X, batch, wv, wv.Y, s), "bz_mlp_backward: forward");
+    BZ_HIP(backward(n, pv, X, d_target, batch, wv, d_grad, s), "bz_mlp_backward");
+    if (d_loss) BZ_HIP(hipMemcpyAsync(d_loss, wv.loss, 4, hipMemcpyDeviceToDevice, s), "copy loss");
+    return BZ_OK;
+}
+
+bz_status bz_mlp_adam(bz_mlp n, void *d_params, const float *d_grad, int step, float lr, void *stream) {
+    if (!n || !d_params || !d_grad) return fail(BZ_EINVAL, "bz_mlp_adam: NULL argument");
+    if (step < 1 || !(lr >= 0)) return fail(BZ_EINVAL, "bz_mlp_adam: step >= 1 and lr >= 0 required");
+    hipStream_t s = (hipStream_t)stream;
+    ParamView pv = param_view(n, d_params);
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f / (1.0f - std::pow(b1, (float)step)), c2 = 1.0f / (1.0f - std::pow(b2, (float)step));
+    hipLaunchKernelGGL(k_adam, dim3(grid1(n->n_params)), dim3(256), 0, s, n->n_params, pv.master, pv.m, pv.v, d_grad,
+                       lr, b1, b2, 1e-8f, c1, c2);
+    BZ_HIP(hipGetLastError(), "bz_mlp_adam");
+    BZ_HIP(refresh_bf16(n, pv, s), "bz_mlp_adam: bf16 copies");
+    return BZ_OK;
+}
+
+}  // extern "C"

@@ -25,12 +25,6 @@ bz_status hip_fail(hipError_t e, const char *what) {
     return e == hipErrorOutOfMemory ? BZ_ENOMEM : BZ_EDEVICE;
 }
 
-#define BZ_HIP(call, what)                         \
-    do {                                           \
-        hipError_t e_ = (call);                    \
-        if (e_ != hipSuccess) return hip_fail(e_, what); \
-    } while (0)
-
 constexpr double kPi = 3.14159265358979323846;
 
 // ---------------------------------------------------------------------------
@@ -219,6 +213,7 @@ struct bz_batch_s {
     // convolution timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
+    int closure_phase = 0;
 };
 
 namespace bz {
@@ -654,8 +649,16 @@ size_t bz_batch_cell_offset(bz_batch b, int cell) {
 size_t bz_workspace_bytes(bz_batch b) { return b ? b->ws_total : 0; }
 size_t bz_step_workspace_bytes(bz_batch b) { return b ? align256(b->ws_total) + 2 * align256(b->elems * 8) : 0; }
 
+static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void *d_work, size_t work_bytes,
+                              void *stream, const unsigned char *skip);
+
 bz_status bz_collide_batch(bz_batch b, const double *d_f, double *d_Qt, void *d_work, size_t work_bytes,
                            void *stream) {
+    return collide_impl(b, d_f, d_Qt, d_work, work_bytes, stream, nullptr);
+}
+
+static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void *d_work, size_t work_bytes,
+                              void *stream, const unsigned char *skip) {
     if (!b || !d_f || !d_Qt || !d_work) return fail(BZ_EINVAL, "bz_collide_batch: NULL argument");
     if (work_bytes < b->ws_total) return fail(BZ_EINVAL, "bz_collide_batch: workspace too small");
     if ((const void *)d_f == (const void *)d_Qt) return fail(BZ_EINVAL, "bz_collide_batch: f and Qt alias");
@@ -676,7 +679,7 @@ bz_status bz_collide_batch(bz_batch b, const double *d_f, double *d_Qt, void *d_
                    "forward transform");
             const long long pstride = (long long)p.groups * M * kWave;
             CellsLaunch cl{N, fh, p.w, p.d_row_woff, p.d_items, p.n_items, (unsigned *)(ws + p.ws_counter), qh,
-                           pstride, 0};
+                           pstride, 0, skip};
             std::pair<hipEvent_t, hipEvent_t> ev{};
             if (b->timing) {
                 if (!timer_pair(b, ev)) return fail(BZ_EDEVICE, "bz_collide_batch: hipEventCreate failed");
@@ -749,6 +752,167 @@ bz_status bz_step_check(bz_batch b, void *d_work, void *stream) {
         BZ_HIP(launch_fill_u32(flag, 1, 0u, s), "bz_step_check: clear flag");
         return fail(BZ_ENONFINITE, "bz_step: a non-finite value was produced");
     }
+    return BZ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Gated closure.  Workspace: [step workspace][state n*8 doubles][skip groups]
+// [x n*M bf16][y n*M float][stats 4 uint][network workspace for batch n].
+// ---------------------------------------------------------------------------
+struct ClosureView {
+    double *state;
+    unsigned char *skip;
+    unsigned short *x;
+    float *y;
+    unsigned *stats;
+    char *mlp_work;
+    size_t mlp_bytes;
+    size_t total;
+};
+
+static ClosureView closure_view(bz_batch b, const bz_closure *c, void *d_work) {
+    ClosureView v{};
+    const Part &p = b->parts[0];
+    const size_t n = p.cells.size(), M = (size_t)p.g->N * p.g->N * p.g->N;
+    size_t o = align256(bz_step_workspace_bytes(b));
+    char *w = (char *)d_work;
+    auto take = [&](size_t bytes) {
+        char *q = w ? w + o : nullptr;
+        o = align256(o + bytes);
+        return q;
+    };
+    v.state = (double *)take(n * 10 * sizeof(double));
+    v.skip = (unsigned char *)take((size_t)p.groups);
+    v.x = (unsigned short *)take(n * M * 2);
+    v.y = (float *)take(n * M * 4);
+    v.stats = (unsigned *)take(256);
+    v.mlp_bytes = bz_mlp_workspace_bytes(c->net, (int)n);
+    v.mlp_work = take(v.mlp_bytes);
+    v.total = o;
+    return v;
+}
+
+static bz_status closure_check(bz_batch b, const bz_closure *c, const char *who) {
+    if (!b || !c || !c->net || !c->d_params) return fail(BZ_EINVAL, std::string(who) + ": NULL argument");
+    if (b->parts.size() != 1) return fail(BZ_EUNSUPPORTED, std::string(who) + ": the closure needs a one-mesh batch");
+    const size_t M = (size_t)b->parts[0].g->N * b->parts[0].g->N * b->parts[0].g->N;
+    if (bz_mlp_param_count(c->net) == 0) return fail(BZ_EINVAL, std::string(who) + ": bad network");
+    // n_in and n_out must both be N^3: check through the parameter count of a square-ended net
+    size_t hid = 0;
+    {
+        // count = h*M + h + h*h + h + M*h + M  ->  solve h^2 + (2M + 2) h + M - count = 0
+        const double cnt = (double)bz_mlp_param_count(c->net), A = 2.0 * M + 2.0;
+        const double hh = (-A + std::sqrt(A * A + 4.0 * (cnt - (double)M))) / 2.0;
+        hid = (size_t)std::llround(hh);
+        if (hid * M + hid + hid * hid + hid + M * hid + M != (size_t)cnt)
+            return fail(BZ_EINVAL, std::string(who) + ": network input and output must be N^3 wide");
+    }
+    if (!(c->gate >= 0) || !(c->s_in > 0) || !(c->s_out > 0) || c->judge_every < 0)
+        return fail(BZ_EINVAL, std::string(who) + ": bad gate, scales or judge rate");
+    return BZ_OK;
+}
+
+static bz_status closure_collide_impl(bz_batch b, const bz_closure *c, const double *d_f, double *d_Qt, void *d_work,
+                                      hipStream_t s) {
+    const Part &p = b->parts[0];
+    const int n = (int)p.cells.size(), N = p.g->N;
+    ClosureView v = closure_view(b, c, d_work);
+    BZ_HIP(launch_sur_prepare(N, p.g->dv, n, d_f, p.d_f_off, c->gate, c->s_in, c->judge_every, b->closure_phase++,
+                              v.state, v.x, s),
+           "closure prepare");
+    const unsigned char *skip = nullptr;
+    if (batched(b->mode)) {
+        BZ_HIP(launch_group_skip(n, v.state, v.skip, s), "closure group skip");
+        skip = v.skip;
+    }
+    bz_status st = collide_impl(b, d_f, d_Qt, d_work, b->ws_total, s, skip);
+    if (st != BZ_OK) return st;
+    st = bz_mlp_forward(c->net, c->d_params, v.x, n, v.y, v.mlp_work, v.mlp_bytes, s);
+    if (st != BZ_OK) return st;
+    BZ_HIP(launch_sur_finish(N, p.g->dv, p.g->linv, n, v.state, v.y, c->s_out, c->judge_floor, c->judge_tol,
+                             p.d_f_off, d_Qt, v.stats, s),
+           "closure finish");
+    return BZ_OK;
+}
+
+size_t bz_closure_workspace_bytes(bz_batch b, const bz_closure *c) {
+    if (closure_check(b, c, "bz_closure_workspace_bytes") != BZ_OK) return 0;
+    return closure_view(b, c, nullptr).total;
+}
+
+bz_status bz_closure_prepare(bz_batch b, const double *d_f, double gate, double s_in, double *d_state, uint16_t *d_x,
+                             void *stream) {
+    if (!b || !d_f || !d_state || !d_x) return fail(BZ_EINVAL, "bz_closure_prepare: NULL argument");
+    if (b->parts.size() != 1) return fail(BZ_EUNSUPPORTED, "bz_closure_prepare: needs a one-mesh batch");
+    if (!(s_in > 0)) return fail(BZ_EINVAL, "bz_closure_prepare: s_in must be positive");
+    const Part &p = b->parts[0];
+    BZ_HIP(launch_sur_prepare(p.g->N, p.g->dv, (int)p.cells.size(), d_f, p.d_f_off, gate, s_in, 0, 0, d_state,
+                              (unsigned short *)d_x, (hipStream_t)stream),
+           "bz_closure_prepare");
+    return BZ_OK;
+}
+
+bz_status bz_closure_targets(bz_batch b, const double *d_state, const double *d_Q, double s_out, float *d_y,
+                             void *stream) {
+    if (!b || !d_state || !d_Q || !d_y) return fail(BZ_EINVAL, "bz_closure_targets: NULL argument");
+    if (b->parts.size() != 1) return fail(BZ_EUNSUPPORTED, "bz_closure_targets: needs a one-mesh batch");
+    if (!(s_out > 0)) return fail(BZ_EINVAL, "bz_closure_targets: s_out must be positive");
+    const Part &p = b->parts[0];
+    BZ_HIP(launch_sur_targets(p.g->N, (int)p.cells.size(), d_state, d_Q, p.d_f_off, s_out, d_y, (hipStream_t)stream),
+           "bz_closure_targets");
+    return BZ_OK;
+}
+
+bz_status bz_closure_collide(bz_batch b, const bz_closure *c, const double *d_f, double *d_Qt, void *d_work,
+                             size_t work_bytes, void *stream) {
+    bz_status st = closure_check(b, c, "bz_closure_collide");
+    if (st != BZ_OK) return st;
+    if (!d_f || !d_Qt || !d_work) return fail(BZ_EINVAL, "bz_closure_collide: NULL argument");
+    if (work_bytes < closure_view(b, c, nullptr).total) return fail(BZ_EINVAL, "bz_closure_collide: workspace too small");
+    for (const Part &p : b->parts)
+        if (!p.w) return fail(BZ_ESTATE, "bz_closure_collide: no weights bound");
+    return closure_collide_impl(b, c, d_f, d_Qt, d_work, (hipStream_t)stream);
+}
+
+bz_status bz_closure_step(bz_batch b, const bz_closure *c, double *d_f, double dt_over_eps, void *d_work,
+                          size_t work_bytes, void *stream) {
+    bz_status st = closure_check(b, c, "bz_closure_step");
+    if (st != BZ_OK) return st;
+    if (!d_f || !d_work) return fail(BZ_EINVAL, "bz_closure_step: NULL argument");
+    if (work_bytes < closure_view(b, c, nullptr).total) return fail(BZ_EINVAL, "bz_closure_step: workspace too small");
+    if (!std::isfinite(dt_over_eps)) return fail(BZ_EINVAL, "bz_closure_step: dt/eps must be finite");
+    for (const Part &p : b->parts)
+        if (!p.w) return fail(BZ_ESTATE, "bz_closure_step: no weights bound");
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)d_work;
+    double *q = (double *)(ws + align256(b->ws_total));
+    double *fs = (double *)(ws + align256(b->ws_total) + align256(b->elems * 8));
+    unsigned *flag = (unsigned *)(ws + b->ws_flag);
+    if ((st = closure_collide_impl(b, c, d_f, q, d_work, s)) != BZ_OK) return st;
+    if ((st = bz_project(b, q, stream)) != BZ_OK) return st;
+    BZ_HIP(launch_axpy(b->elems, d_f, q, dt_over_eps, fs, flag, s), "closure heun stage 1");
+    if ((st = closure_collide_impl(b, c, fs, q, d_work, s)) != BZ_OK) return st;
+    if ((st = bz_project(b, q, stream)) != BZ_OK) return st;
+    BZ_HIP(launch_heun_final(b->elems, d_f, fs, q, dt_over_eps, d_f, flag, s), "closure heun stage 2");
+    return BZ_OK;
+}
+
+bz_status bz_closure_read_stats(bz_batch b, const bz_closure *c, void *d_work, bz_closure_stats *out, void *stream) {
+    bz_status st = closure_check(b, c, "bz_closure_read_stats");
+    if (st != BZ_OK) return st;
+    if (!d_work || !out) return fail(BZ_EINVAL, "bz_closure_read_stats: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    ClosureView v = closure_view(b, c, d_work);
+    unsigned h[4] = {0, 0, 0, 0};
+    BZ_HIP(hipMemcpyAsync(h, v.stats, sizeof h, hipMemcpyDeviceToHost, s), "read closure stats");
+    BZ_HIP(hipStreamSynchronize(s), "read closure stats sync");
+    out->served = h[0];
+    out->judged = h[1];
+    float e;
+    std::memcpy(&e, &h[2], sizeof e);
+    out->max_err = e;
+    out->failed = h[3];
+    BZ_HIP(launch_fill_u32(v.stats, 4, 0u, s), "clear closure stats");
     return BZ_OK;
 }
 

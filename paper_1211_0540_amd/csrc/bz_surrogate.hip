@@ -1,0 +1,214 @@
+// Gated learned closure around the collision step.
+//
+// For every cell:  rho, u, T (FP64 moments on the mesh), the local Maxwellian
+// M = rho (2 pi T)^{-3/2} exp(-|v-u|^2 / 2T), the deviation d = |f - M|_2 / |M|_2
+// and the gate d < gate.  The network maps x = (f - M) / (rho s_in) (BF16) to
+// y (FP32); the closure is Q_s = rho^2 s_out y (Q is bilinear, so the density
+// scales out exactly).  Gated cells take Q_s, the others the weighted
+// convolution; a rotating sample of gated cells ("judged" cells) is also
+// convolved and compared after projection,
+//   err = |P(Q_s - Q_c)|_2 / (|P Q_c|_2 + floor rho |M|_2),
+// (the floor is on the scale of the loss term rho nu f, so that cells at
+// equilibrium, whose Q is only the discretisation residual, are judged
+// against the collision rate rather than against that residual)
+// and keeps the convolution result (fallback).  The FP64 projection of
+// Sec. 3.3 is applied to every cell afterwards.  Convolution work groups whose
+// live cells are all gated and unjudged are skipped.
+#include <cmath>
+#include <new>
+
+#include "bz_internal.h"
+
+namespace bz {
+namespace {
+
+constexpr int kState = 10;  // rho, u1, u2, u3, T, d, gated, judged, |M|_2, unused
+
+__device__ inline double block_sum(double x, double *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    return t;
+}
+
+__device__ inline unsigned short f2bf(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+// one block per cell
+__global__ void __launch_bounds__(256) k_prepare(int N, double dv, const double *__restrict__ f,
+                                                 const long long *__restrict__ f_off, double gate, double inv_s_in,
+                                                 int judge_every, int phase, double *__restrict__ state,
+                                                 unsigned short *__restrict__ x) {
+    __shared__ double red[4];
+    const int c = blockIdx.x, M = N * N * N;
+    const double *F = f + f_off[c];
+    const double w = dv * dv * dv;
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        const double v1 = dv * (j / (N * N) - N / 2), v2 = dv * ((j / N) % N - N / 2), v3 = dv * (j % N - N / 2);
+        const double q = F[j];
+        s0 += q;
+        s1 += v1 * q;
+        s2 += v2 * q;
+        s3 += v3 * q;
+        s4 += (v1 * v1 + v2 * v2 + v3 * v3) * q;
+    }
+    const double rho = block_sum(s0, red) * w;
+    const double u1 = block_sum(s1, red) * w / rho, u2 = block_sum(s2, red) * w / rho, u3 = block_sum(s3, red) * w / rho;
+    const double e = block_sum(s4, red) * w / rho;
+    const double T = (e - (u1 * u1 + u2 * u2 + u3 * u3)) / 3.0;
+    const double nrm = rho * pow(2.0 * M_PI * T, -1.5);
+    double dd = 0, mm = 0;
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        const double a = dv * (j / (N * N) - N / 2) - u1, b = dv * ((j / N) % N - N / 2) - u2,
+                     cc = dv * (j % N - N / 2) - u3;
+        const double Mj = nrm * exp(-(a * a + b * b + cc * cc) / (2.0 * T));
+        const double dj = F[j] - Mj;
+        dd += dj * dj;
+        mm += Mj * Mj;
+        x[(size_t)c * M + j] = f2bf((float)(dj / rho * inv_s_in));
+    }
+    const double D2 = block_sum(dd, red), M2 = block_sum(mm, red);
+    if (threadIdx.x == 0) {
+        const double d = sqrt(D2 / M2);
+        const bool gated = d < gate && rho > 0 && T > 0;
+        const bool judged = gated && judge_every > 0 && (c % judge_every) == (phase % judge_every);
+        double *st = state + (size_t)c * kState;
+        st[0] = rho;
+        st[1] = u1;
+        st[2] = u2;
+        st[3] = u3;
+        st[4] = T;
+        st[5] = d;
+        st[6] = gated ? 1.0 : 0.0;
+        st[7] = judged ? 1.0 : 0.0;
+        st[8] = sqrt(M2);
+        st[9] = 0.0;
+    }
+}
+
+// skip[g] = every live cell of group g gated and not judged
+__global__ void k_group_skip(int n_cells, const double *__restrict__ state, unsigned char *__restrict__ skip) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int groups = (n_cells + kWave - 1) / kWave;
+    if (g >= groups) return;
+    bool s = true;
+    for (int c = g * kWave; c < n_cells && c < (g + 1) * kWave; ++c) {
+        const double *st = state + (size_t)c * kState;
+        s = s && st[6] != 0.0 && st[7] == 0.0;
+    }
+    skip[g] = s ? 1 : 0;
+}
+
+struct Basis {
+    double a[25];
+};
+
+__device__ inline void basis5(int N, double dv, const Basis &li, int j, double e[5]) {
+    const int j1 = j / (N * N), j2 = (j / N) % N, j3 = j % N;
+    const double v1 = dv * (j1 - N / 2), v2 = dv * (j2 - N / 2), v3 = dv * (j3 - N / 2);
+    const double w = dv * dv * dv;
+    const double c[5] = {w, v1 * w, v2 * w, v3 * w, (v1 * v1 + v2 * v2 + v3 * v3) * w};
+    for (int a = 0; a < 5; ++a) {
+        double s = 0.0;
+        for (int b = 0; b <= a; ++b) s = fma(li.a[a * 5 + b], c[b], s);
+        e[a] = s;
+    }
+}
+
+// one block per cell: select the closure or the convolution, judge sampled cells
+__global__ void __launch_bounds__(256) k_finish(int N, double dv, Basis li, const double *__restrict__ state,
+                                                const float *__restrict__ y, double s_out, double floor_,
+                                                double tol, const long long *__restrict__ q_off,
+                                                double *__restrict__ q, unsigned *__restrict__ stats) {
+    __shared__ double red[4];
+    const int c = blockIdx.x, M = N * N * N;
+    const double *st = state + (size_t)c * kState;
+    const bool gated = st[6] != 0.0, judged = st[7] != 0.0;
+    if (!gated) return;
+    double *Q = q + q_off[c];
+    const double sc = st[0] * st[0] * s_out;
+    const float *Y = y + (size_t)c * M;
+    if (!judged) {
+        for (int j = threadIdx.x; j < M; j += blockDim.x) Q[j] = sc * (double)Y[j];
+        if (threadIdx.x == 0) atomicAdd(&stats[0], 1u);
+        return;
+    }
+    // judged: |P D|^2 = |D|^2 - sum_a (e_a . D)^2 with D = Q_s - Q_c, same for Q_c
+    double dd = 0, cc = 0, md[5] = {0, 0, 0, 0, 0}, mc[5] = {0, 0, 0, 0, 0};
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        double e[5];
+        basis5(N, dv, li, j, e);
+        const double qc = Q[j], dj = sc * (double)Y[j] - qc;
+        dd += dj * dj;
+        cc += qc * qc;
+        for (int a = 0; a < 5; ++a) {
+            md[a] = fma(e[a], dj, md[a]);
+            mc[a] = fma(e[a], qc, mc[a]);
+        }
+    }
+    double D2 = block_sum(dd, red), C2 = block_sum(cc, red);
+    for (int a = 0; a < 5; ++a) {
+        const double ta = block_sum(md[a], red), tc = block_sum(mc[a], red);
+        D2 -= ta * ta;
+        C2 -= tc * tc;
+    }
+    if (threadIdx.x == 0) {
+        const double err = sqrt(fmax(D2, 0.0)) / (sqrt(fmax(C2, 0.0)) + floor_ * st[0] * st[8]);
+        const float ef = (float)err;
+        atomicMax(&stats[2], __float_as_uint(ef));  // non-negative floats order as unsigned
+        atomicAdd(&stats[1], 1u);
+        if (err > tol) atomicAdd(&stats[3], 1u);
+    }
+    // the judged cell keeps the convolution result (fallback)
+}
+
+// y = Q / (rho^2 s_out) for harvesting training targets
+__global__ void k_targets(int N, const double *__restrict__ state, const double *__restrict__ q,
+                          const long long *__restrict__ q_off, double inv_s_out, float *__restrict__ y) {
+    const int c = blockIdx.y, M = N * N * N;
+    const double r = state[(size_t)c * kState];
+    const double sc = inv_s_out / (r * r);
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < M; j += gridDim.x * blockDim.x)
+        y[(size_t)c * M + j] = (float)(q[q_off[c] + j] * sc);
+}
+
+}  // namespace
+
+hipError_t launch_sur_prepare(int N, double dv, int n, const double *f, const long long *f_off, double gate,
+                              double s_in, int judge_every, int phase, double *state, unsigned short *x,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_prepare, dim3(n), dim3(256), 0, s, N, dv, f, f_off, gate, 1.0 / s_in, judge_every, phase,
+                       state, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_skip(int n, const double *state, unsigned char *skip, hipStream_t s) {
+    const int groups = (n + kWave - 1) / kWave;
+    hipLaunchKernelGGL(k_group_skip, dim3((groups + 63) / 64), dim3(64), 0, s, n, state, skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_finish(int N, double dv, const double *linv, int n, const double *state, const float *y,
+                             double s_out, double floor_, double tol, const long long *q_off, double *q,
+                             unsigned *stats, hipStream_t s) {
+    Basis li;
+    for (int i = 0; i < 25; ++i) li.a[i] = linv[i];
+    hipLaunchKernelGGL(k_finish, dim3(n), dim3(256), 0, s, N, dv, li, state, y, s_out, floor_, tol, q_off, q, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_targets(int N, int n, const double *state, const double *q, const long long *q_off,
+                              double s_out, float *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_targets, dim3(16, n), dim3(256), 0, s, N, state, q, q_off, 1.0 / s_out, y);
+    return hipGetLastError();
+}
+
+}  // namespace bz

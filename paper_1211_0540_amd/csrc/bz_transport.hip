@@ -197,4 +197,21 @@ bz_status bz_strang_step(bz_batch b, bz_transport t, double *d_f, double dt, dou
     return bz_transport_step(t, d_f, 0.5 * dt, tw, work_bytes - a, stream);
 }
 
+bz_status bz_closure_strang_step(bz_batch b, bz_transport t, const bz_closure *c, double *d_f, double dt,
+                                 double eps, void *d_work, size_t work_bytes, void *stream) {
+    if (!b || !t || !c || !d_f || !d_work) return fail(BZ_EINVAL, "bz_closure_strang_step: NULL argument");
+    if (!(eps > 0) || !std::isfinite(dt)) return fail(BZ_EINVAL, "bz_closure_strang_step: need finite dt and eps > 0");
+    const size_t a = (bz_closure_workspace_bytes(b, c) + 255) / 256 * 256;
+    if (a == 0) return fail(BZ_EINVAL, "bz_closure_strang_step: bad closure description");
+    if (work_bytes < a + bz_transport_workspace_bytes(t))
+        return fail(BZ_EINVAL, "bz_closure_strang_step: workspace too small");
+    if (bz_batch_elems(b) != (size_t)t->nx * t->N * t->N * t->N)
+        return fail(BZ_EINVAL, "bz_closure_strang_step: the batch must hold the nx cells of the transport mesh");
+    char *tw = (char *)d_work + a;
+    bz_status st = bz_transport_step(t, d_f, 0.5 * dt, tw, work_bytes - a, stream);
+    if (st != BZ_OK) return st;
+    if ((st = bz_closure_step(b, c, d_f, dt / eps, d_work, a, stream)) != BZ_OK) return st;
+    return bz_transport_step(t, d_f, 0.5 * dt, tw, work_bytes - a, stream);
+}
+
 }  // extern "C"

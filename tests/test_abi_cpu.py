@@ -114,3 +114,13 @@ def test_status_strings():
     L = bz.lib()
     assert L.bz_status_string(0) == b"ok"
     assert L.bz_status_string(-5) == b"non-finite value"
+
+
+def test_mlp_shape_validation():
+    for shape in [(48, 64, 64), (64, 40, 64), (64, 64, 48), (0, 64, 64)]:
+        with pytest.raises(bz.BzError) as e:
+            bz.bz_mlp_create(*shape)
+        assert e.value.status == bz.BZ_EINVAL
+    n = bz.bz_mlp_create(13824, 1024, 13824)
+    assert bz.bz_mlp_param_count(n) == 13824 * 1024 + 1024 + 1024 * 1024 + 1024 + 13824 * 1024 + 13824
+    bz.bz_mlp_free(n)

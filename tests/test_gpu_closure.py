@@ -1,0 +1,122 @@
+"""Gated learned closure on the GPU: gate and inputs against the oracle's
+moments, the exact fallbacks (gate closed; judge failing on every cell), and
+a small harvest -> train -> serve run on the wall-heating shock problem."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1211_0540_amd import bz
+from paper_1211_0540_amd import workloads as W
+from paper_1211_0540_amd.closure import ClosureModel
+
+pytestmark = pytest.mark.gpu
+
+N, L, LAM = 24, 7.0, 1.0
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def model(dev):
+    return ClosureModel(N, L, LAM, hidden=1024, seed=3)
+
+
+def _cells(n, seed):
+    return list(W.random_smooth_cells(n, N, L, seed=seed, umax=1.0))
+
+
+def test_prepare_matches_oracle_moments(dev):
+    cells = _cells(70, 1)
+    c = bz.Collision([(N, L, LAM)], [0] * 70, "batched_f32")
+    f = torch.from_numpy(c.pack(cells)).to(dev)
+    state = torch.zeros(70 * 10, dtype=torch.float64, device=dev)
+    x = torch.zeros(70 * N ** 3, dtype=torch.int16, device=dev)
+    bz.bz_closure_prepare(c.batch, f, 0.05, 2.0 ** -9, state, x)
+    st = state.view(70, 10).cpu().numpy()
+    for i in (0, 31, 69):
+        rho, u, T, _ = O.moments(cells[i], L)
+        assert st[i, 0] == pytest.approx(rho, rel=1e-12)
+        assert np.allclose(st[i, 1:4], u, atol=1e-12)
+        assert st[i, 4] == pytest.approx(T, rel=1e-12)
+        M = W.maxwellian(N, L, rho, u, T)
+        assert st[i, 5] == pytest.approx(np.linalg.norm(cells[i] - M) / np.linalg.norm(M), rel=1e-9)
+        assert st[i, 6] == float(st[i, 5] < 0.05)
+    c.close()
+
+
+def _closure_run(dev, model, cells, gate, judge_every):
+    n = len(cells)
+    c = bz.Collision([(N, L, LAM)], [0] * n, "batched_f32", weights_cache=model.wcache)
+    f = torch.from_numpy(c.pack(cells)).to(dev)
+    model.s_in = model.s_in or 2.0 ** -9
+    model.s_out = model.s_out or 2.0 ** -6
+    d = model.desc(gate=gate, judge_every=judge_every)
+    work = torch.zeros(bz.bz_closure_workspace_bytes(c.batch, d), dtype=torch.uint8, device=dev)
+    q = torch.zeros(c.elems, dtype=torch.float64, device=dev)
+    bz.bz_closure_collide(c.batch, d, f, q, work)
+    stats = bz.bz_closure_read_stats(c.batch, d, work)
+    ref = c.collide(f)
+    torch.cuda.synchronize()
+    out = (q.cpu().numpy(), ref.cpu().numpy(), stats)
+    c.close()
+    return out
+
+
+def test_closed_gate_is_the_plain_collision(dev, model):
+    q, ref, st = _closure_run(dev, model, _cells(80, 2), gate=0.0, judge_every=16)
+    assert np.array_equal(q, ref)
+    assert st["served"] == 0 and st["judged"] == 0
+
+
+def test_failing_judge_falls_back_to_the_convolution(dev, model):
+    """Untrained network (zero output layer), every cell gated and judged: every judge
+    fails and every cell keeps the convolution result."""
+    q, ref, st = _closure_run(dev, model, _cells(80, 3), gate=1e30, judge_every=1)
+    assert np.array_equal(q, ref)
+    assert st["served"] == 0 and st["judged"] == 80 and st["failed"] == 80
+    assert st["max_err"] == pytest.approx(1.0, rel=1e-3)
+
+
+def test_open_gate_serves_the_network(dev, model):
+    q, ref, st = _closure_run(dev, model, _cells(64, 4), gate=1e30, judge_every=0)
+    assert st["served"] == 64 and st["judged"] == 0
+    assert np.all(q == 0.0)          # the untrained closure predicts zero
+
+
+def test_harvest_train_serve_shock(dev):
+    m = ClosureModel(N, L, LAM, hidden=1024, seed=11)
+    k1 = m.harvest_shock(snapshots=40, every=2, keep=0.1)
+    k2 = m.harvest_relaxation(cells=128, steps=8, keep=0.1)
+    assert k1 > 0 and k2 > 0 and m.dataset_size() == k1 + k2
+    hist = m.fit(steps=300, batch=256, lr=1e-3)
+    assert hist[-1][1] < 0.2 * hist[0][1]
+    val = m.validation_error()
+    m.release_data()
+    # serve: 10 Strang steps of the shock problem with and without the closure
+    nx, eps, dt = 256, 0.1, 0.5 / 256 / L
+    f0 = torch.from_numpy(W.shock_initial(nx, N, L).ravel().copy()).to(dev)
+    c = bz.Collision([(N, L, LAM)], [0] * nx, "batched_f32", weights_cache=m.wcache)
+    t = bz.bz_transport_create(c.grids[0], nx, 1.0, 2.0, 1.0, 0.0, 1.0)
+    d = m.desc(gate=0.05, judge_every=16)
+    work = torch.zeros(bz.bz_closure_workspace_bytes(c.batch, d) + bz.bz_transport_workspace_bytes(t) + 256,
+                       dtype=torch.uint8, device=dev)
+    fa, fb = f0.clone(), f0.clone()
+    for _ in range(10):
+        c.strang_step(t, dt, eps, fa)
+        bz.bz_closure_strang_step(c.batch, t, d, fb, dt, eps, work)
+    st = bz.bz_closure_read_stats(c.batch, d, work)
+    A = fa.cpu().numpy().reshape(nx, N, N, N)
+    B = fb.cpu().numpy().reshape(nx, N, N, N)
+    ma = np.array([O.moments(A[j], L)[2] for j in range(0, nx, 8)])
+    mb = np.array([O.moments(B[j], L)[2] for j in range(0, nx, 8)])
+    print(f"closure: val err {val:.3e}, served {st['served']}, judged {st['judged']}, failed {st['failed']}, "
+          f"max judge err {st['max_err']:.3e}, T-profile deviation {np.max(np.abs(ma - mb)):.3e}")
+    assert st["served"] > 0.5 * nx * 2 * 10
+    assert np.max(np.abs(ma - mb)) < 1e-2
+    bz.bz_transport_free(t)
+    c.close()
