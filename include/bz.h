@@ -235,8 +235,9 @@ bz_status bz_mlp_adam(bz_mlp n, void *d_params, const float *d_grad, int step, f
  * d = |f - M|_2 / |M|_2.  Cells with d < gate are served by the network:
  * x = (f - M) / (rho s_in) in BF16, Q_s = rho^2 s_out net(x) (the density
  * scales out of the bilinear Q exactly).  The others take the weighted
- * convolution.  One gated cell in judge_every (rotating over evaluations) is
- * also convolved, compared after projection,
+ * convolution.  The gated cells of the 64-cell groups g with
+ * g mod judge_every = (evaluation count) mod judge_every are also convolved
+ * ("judged"), compared after projection,
  *   err = |P(Q_s - Q_c)|_2 / (|P Q_c|_2 + judge_floor rho |M|_2)
  * (the floor is on the scale of the loss term, so that cells at equilibrium,
  * whose Q is only the discretisation residual, are judged against the

@@ -5,8 +5,9 @@
 // and the gate d < gate.  The network maps x = (f - M) / (rho s_in) (BF16) to
 // y (FP32); the closure is Q_s = rho^2 s_out y (Q is bilinear, so the density
 // scales out exactly).  Gated cells take Q_s, the others the weighted
-// convolution; a rotating sample of gated cells ("judged" cells) is also
-// convolved and compared after projection,
+// convolution; the gated cells of one 64-cell group in judge_every (rotating
+// over evaluations, "judged" cells) are also convolved and compared after
+// projection,
 //   err = |P(Q_s - Q_c)|_2 / (|P Q_c|_2 + floor rho |M|_2),
 // (the floor is on the scale of the loss term rho nu f, so that cells at
 // equilibrium, whose Q is only the discretisation residual, are judged
@@ -79,7 +80,9 @@ __global__ void __launch_bounds__(256) k_prepare(int N, double dv, const double 
     if (threadIdx.x == 0) {
         const double d = sqrt(D2 / M2);
         const bool gated = d < gate && rho > 0 && T > 0;
-        const bool judged = gated && judge_every > 0 && (c % judge_every) == (phase % judge_every);
+        // judge whole wavefront groups (one group in judge_every per evaluation, rotating) so
+        // that the groups that are not judged can skip the convolution
+        const bool judged = gated && judge_every > 0 && ((c / kWave) % judge_every) == (phase % judge_every);
         double *st = state + (size_t)c * kState;
         st[0] = rho;
         st[1] = u1;

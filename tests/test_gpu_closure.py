@@ -74,12 +74,12 @@ def test_closed_gate_is_the_plain_collision(dev, model):
 
 
 def test_failing_judge_falls_back_to_the_convolution(dev, model):
-    """Untrained network (zero output layer), every cell gated and judged: every judge
-    fails and every cell keeps the convolution result."""
+    """Untrained network (zero output layer), every cell gated and judged (judge_every = 1
+    judges every group): every judge fails and every cell keeps the convolution result."""
     q, ref, st = _closure_run(dev, model, _cells(80, 3), gate=1e30, judge_every=1)
     assert np.array_equal(q, ref)
     assert st["served"] == 0 and st["judged"] == 80 and st["failed"] == 80
-    assert st["max_err"] == pytest.approx(1.0, rel=1e-3)
+    assert 0.9 < st["max_err"] <= 1.0   # zero prediction: |PQ_c| / (|PQ_c| + floor rho |M|)
 
 
 def test_open_gate_serves_the_network(dev, model):
