@@ -54,6 +54,62 @@ def measured_traffic(cells):
     return d.get("traffic_bytes_per_launch")
 
 
+def closure_leg(args, torch, np, bz, W):
+    """Harvest (f, Q) pairs on the N=24 shock problem and homogeneous relaxations,
+    train the 13824-1024-1024-13824 network with the library's kernels, then time
+    Strang steps of the 256-cell shock problem with and without the gated closure
+    (gate 0.05, one group in 16 judged) and compare the temperature profiles."""
+    import oracle as O
+    from paper_1211_0540_amd.closure import ClosureModel
+    N, L, lam, nx, eps = 24, 7.0, 1.0, 256, 0.1
+    t0 = time.perf_counter()
+    m = ClosureModel(N, L, lam, hidden=1024, seed=1211)
+    rows = m.harvest_shock(snapshots=600, every=1, keep=0.1) + m.harvest_relaxation(cells=512, steps=40, keep=0.1)
+    torch.cuda.synchronize()
+    t_harvest = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    hist = m.fit(steps=3000, batch=512, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    val = m.validation_error(2048)
+    m.release_data()
+    dt = 0.5 / nx / L
+    f0 = torch.from_numpy(W.shock_initial(nx, N, L).ravel().copy()).cuda()
+    c = bz.Collision([(N, L, lam)], [0] * nx, "batched_f32", weights_cache=m.wcache)
+    t = bz.bz_transport_create(c.grids[0], nx, 1.0, 2.0, 1.0, 0.0, 1.0)
+    d = m.desc(gate=0.05, judge_every=16)
+    work = torch.zeros(bz.bz_closure_workspace_bytes(c.batch, d) + bz.bz_transport_workspace_bytes(t) + 256,
+                       dtype=torch.uint8, device="cuda")
+    K = 300
+    fa, fb = f0.clone(), f0.clone()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(K):
+        c.strang_step(t, dt, eps, fa)
+    torch.cuda.synchronize()
+    ta = time.perf_counter() - a
+    a = time.perf_counter()
+    for _ in range(K):
+        bz.bz_closure_strang_step(c.batch, t, d, fb, dt, eps, work)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - a
+    st = bz.bz_closure_read_stats(c.batch, d, work)
+    A = fa.cpu().numpy().reshape(nx, N, N, N)
+    B = fb.cpu().numpy().reshape(nx, N, N, N)
+    TA = np.array([O.moments(A[j], L)[2] for j in range(nx)])
+    TB = np.array([O.moments(B[j], L)[2] for j in range(nx)])
+    bz.bz_transport_free(t)
+    c.close()
+    evals = 2 * nx * K
+    return {"workload": "256-cell N=24 shock problem (wall T=2, Kn 0.1), 300 Strang steps",
+            "training_rows": rows, "harvest_s": t_harvest, "train_steps": 3000, "train_s": t_train,
+            "loss_first_last": [hist[0][1], hist[-1][1]], "validation_rel_l2": val,
+            "plain_fp32_ms_per_step": ta / K * 1e3, "closure_ms_per_step": tb / K * 1e3,
+            "speedup": ta / tb, "closure_cell_evals_per_s": evals / tb, "served_fraction": st["served"] / evals,
+            "judged": st["judged"], "judge_failed": st["failed"], "judge_max_rel_err": st["max_err"],
+            "max_abs_T_profile_deviation": float(np.max(np.abs(TA - TB)))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +117,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
     ap.add_argument("--profile-run", action="store_true",
                     help="timed steps only (default kernel variant, no comparisons, no CPU leg)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -124,6 +181,30 @@ def main():
     achieved = 10.0 * P * nc / (conv_avg_ms * 1e-3) / 1e12
     log(f"step {ms_step:.3f} ms, {value:.0f} evals/s, conv {conv_avg_ms:.3f} ms/launch ({conv_launches} launches)")
 
+    # the same step captured as a HIP graph and replayed
+    graph = None
+    try:
+        gs = torch.cuda.Stream()
+        fg = f.clone()
+        wg = torch.zeros_like(col.work)
+        with torch.cuda.stream(gs):
+            gh = bz.bz_graph_capture_step(col.batch, fg, dt_over_eps, wg, gs)
+        torch.cuda.synchronize()
+        for _ in range(2):
+            bz.bz_graph_launch(gh, gs)
+        gs.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(gs)
+        for _ in range(args.steps):
+            bz.bz_graph_launch(gh, gs)
+        e1.record(gs)
+        gs.synchronize()
+        graph = {"ms_per_step": e0.elapsed_time(e1) / args.steps}
+        bz.bz_graph_free(gh)
+        del fg, wg
+    except Exception as exc:  # reported, never fatal for the main line
+        graph = {"error": str(exc)}
+
     if args.copy_calibration:
         x = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)
@@ -169,7 +250,17 @@ def main():
     b64c.close()
     comp["fp32_batched_step_evals_per_s"] = value
     comp["speedup_fp32_batched_vs_fp64_plain"] = value / comp["plain_fp64_evals_per_s"]
+    comp["graph_replay"] = graph
     wcache.clear()
+    col.close()
+    torch.cuda.empty_cache()
+
+    # ---- learned closure on the N=24 shock problem ----------------------
+    if not args.no_closure:
+        try:
+            comp["closure_shock_n24"] = closure_leg(args, torch, np, bz, W)
+        except Exception as exc:
+            comp["closure_shock_n24"] = {"error": str(exc)}
 
     # ---- CPU oracle baseline ------------------------------------------
     cpu = None
@@ -211,7 +302,6 @@ def main():
         "comparisons": comp,
     }
     print(json.dumps(out), flush=True)
-    col.close()
     return 0
 
 

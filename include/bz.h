@@ -285,6 +285,22 @@ bz_status bz_closure_strang_step(bz_batch b, bz_transport t, const bz_closure *c
 bz_status bz_closure_read_stats(bz_batch b, const bz_closure *c, void *d_work, bz_closure_stats *out, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* HIP graphs of a whole step.                                           */
+/* ------------------------------------------------------------------ */
+/* Capture one bz_step (resp. bz_strang_step) with the given arguments on
+ * `stream` (which must not be the NULL stream) and instantiate it; replaying
+ * the graph re-runs the step on the same buffers.  The steps enqueue no
+ * memset nodes (counters are cleared by fill kernels) and no host
+ * synchronisation.  The convolution timer must be off while capturing. */
+typedef struct bz_graph_s *bz_graph;
+bz_status bz_graph_capture_step(bz_batch b, double *d_f, double dt_over_eps, void *d_work, size_t work_bytes,
+                                void *stream, bz_graph *out);
+bz_status bz_graph_capture_strang(bz_batch b, bz_transport t, double *d_f, double dt, double eps, void *d_work,
+                                  size_t work_bytes, void *stream, bz_graph *out);
+bz_status bz_graph_launch(bz_graph g, void *stream);
+void bz_graph_free(bz_graph g);
+
+/* ------------------------------------------------------------------ */
 /* Tuning and measurement.                                               */
 /* ------------------------------------------------------------------ */
 /* Select the convolution kernel variant for the cells of grids[grid_index]

@@ -108,6 +108,11 @@ def lib():
                                                   ctypes.c_double, _vp, _sz, _vp]),
         "bz_closure_read_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ClosureDesc), _vp, ctypes.POINTER(ClosureStats),
                                                  _vp]),
+        "bz_graph_capture_step": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+        "bz_graph_capture_strang": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _sz, _vp,
+                                                   ctypes.POINTER(_vp)]),
+        "bz_graph_launch": (ctypes.c_int, [_vp, _vp]),
+        "bz_graph_free": (None, [_vp]),
         "bz_variant_count": (ctypes.c_int, []),
         "bz_batch_set_variant": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
         "bz_batch_get_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -329,6 +334,28 @@ def bz_mlp_backward(n: int, params, x_bf16, target, batch: int, grad, loss, work
 
 def bz_mlp_adam(n: int, params, grad, step: int, lr: float, stream=None) -> None:
     _check(lib().bz_mlp_adam(_vp(n), _vp(_ptr(params)), _vp(_ptr(grad)), int(step), float(lr), _stream(stream)))
+
+
+def bz_graph_capture_step(b: int, f, dt_over_eps: float, work, stream) -> int:
+    h = _vp()
+    _check(lib().bz_graph_capture_step(_vp(b), _vp(_ptr(f)), float(dt_over_eps), _vp(_ptr(work)),
+                                       work.numel() * work.element_size(), _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def bz_graph_capture_strang(b: int, t: int, f, dt: float, eps: float, work, stream) -> int:
+    h = _vp()
+    _check(lib().bz_graph_capture_strang(_vp(b), _vp(t), _vp(_ptr(f)), float(dt), float(eps), _vp(_ptr(work)),
+                                         work.numel() * work.element_size(), _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def bz_graph_launch(g: int, stream=None) -> None:
+    _check(lib().bz_graph_launch(_vp(g), _stream(stream)))
+
+
+def bz_graph_free(g: int) -> None:
+    lib().bz_graph_free(_vp(g))
 
 
 def closure_desc(net: int, params, gate: float, s_in: float, s_out: float, judge_every: int = 16,

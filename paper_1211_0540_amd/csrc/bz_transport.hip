@@ -214,4 +214,72 @@ bz_status bz_closure_strang_step(bz_batch b, bz_transport t, const bz_closure *c
     return bz_transport_step(t, d_f, 0.5 * dt, tw, work_bytes - a, stream);
 }
 
+// ---------------------------------------------------------------------------
+// HIP graphs of one step.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct bz_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+template <typename F>
+static bz_status capture(void *stream, F &&enqueue, bz_graph *out) {
+    if (!out) return fail(BZ_EINVAL, "bz_graph_capture: out is NULL");
+    *out = nullptr;
+    if (!stream) return fail(BZ_EINVAL, "bz_graph_capture: cannot capture the NULL stream");
+    hipStream_t s = (hipStream_t)stream;
+    BZ_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed), "bz_graph_capture: begin");
+    bz_status st = enqueue();
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != BZ_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "bz_graph_capture: end");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "bz_graph_capture: instantiate");
+    }
+    bz_graph_s *h = new (std::nothrow) bz_graph_s();
+    if (!h) {
+        (void)hipGraphExecDestroy(x);
+        (void)hipGraphDestroy(g);
+        return fail(BZ_ENOMEM, "bz_graph_capture: allocation failed");
+    }
+    h->graph = g;
+    h->exec = x;
+    *out = h;
+    return BZ_OK;
+}
+
+extern "C" {
+
+bz_status bz_graph_capture_step(bz_batch b, double *d_f, double dt_over_eps, void *d_work, size_t work_bytes,
+                                void *stream, bz_graph *out) {
+    return capture(stream, [&]() { return bz_step(b, d_f, dt_over_eps, d_work, work_bytes, stream); }, out);
+}
+
+bz_status bz_graph_capture_strang(bz_batch b, bz_transport t, double *d_f, double dt, double eps, void *d_work,
+                                  size_t work_bytes, void *stream, bz_graph *out) {
+    return capture(stream, [&]() { return bz_strang_step(b, t, d_f, dt, eps, d_work, work_bytes, stream); }, out);
+}
+
+bz_status bz_graph_launch(bz_graph g, void *stream) {
+    if (!g) return fail(BZ_EINVAL, "bz_graph_launch: NULL graph");
+    BZ_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream), "bz_graph_launch");
+    return BZ_OK;
+}
+
+void bz_graph_free(bz_graph g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
 }  // extern "C"
