@@ -17,15 +17,19 @@
 //   and fhat(j1, j2, .) of its own cell in registers (cell-interleaved layout,
 //   coalesced 512-byte loads).  Each unordered pair {m, j} is visited once
 //   with the symmetrised weight (see bz_internal.h), so a step costs 6 VALU
-//   operations per visited pair: 2 to scale fhat_m by the weight, 4 FMAs for
-//   the complex multiply-accumulate.  Work items are popped from an atomic
+//   operations per visited pair: 4 for the complex product fhat_m fhat_j and 2
+//   FMAs that add its weighted parts to a fresh per-output partial of the step,
+//   plus 2 additions per output and step into the running sums.  Work items are popped from an atomic
 //   queue ordered longest first, so the launch is persistent.
 //
-//   FP32 variant: products and per-step partial sums in FP32; every FOLD steps
-//   the partials (at most FOLD * 3N/4 terms per output) are folded into a
-//   compensated total, either an FP64 running sum (COMP = 0) or an FP32
-//   (hi, lo) pair updated with Knuth's error-free TwoSum (COMP = 1, Kahan-style
-//   compensation).  FP64 variant: everything FP64.
+//   FP32 variant: products, per-step partials and a running sum over FOLD
+//   steps in FP32 (the running sum takes one rounding per output and step);
+//   every FOLD steps the running sum is folded into a compensated total:
+//   an FP64 total in registers (COMP = 0), an FP32 (hi, lo) pair updated with
+//   Knuth's error-free TwoSum (COMP = 1, Kahan-style compensation), or an FP64
+//   total kept in the item's own output slot and updated by read-modify-write
+//   (COMP = 2), which leaves the registers to fit two wavefronts per SIMD at
+//   N = 32.  FP64 variant: everything FP64.
 //
 // * Plain (lane = output), one cell per launch: the lanes of a wavefront are R
 //   output rows of one k1 plane; all lanes walk the same m, the weight of each
@@ -48,17 +52,6 @@ struct cplx<double> {
     using t = double2;
 };
 
-// flat position of (m3, k3) in the band order of one step
-__host__ __device__ constexpr int band_off(int N, int m3) {
-    int s = 0;
-    for (int m = 0; m < m3; ++m) {
-        int lo = m - N / 2 > 0 ? m - N / 2 : 0;
-        int hi = m + N / 2 - 1 < N - 1 ? m + N / 2 - 1 : N - 1;
-        s += hi - lo + 1;
-    }
-    return s;
-}
-
 // TwoSum: hi + lo += p without losing the rounding error of the addition.
 __device__ inline void two_sum_acc(float &hi, float &lo, float p) {
     const float s = hi + p;
@@ -68,25 +61,30 @@ __device__ inline void two_sum_acc(float &hi, float &lo, float p) {
     lo += e;
 }
 
-// One step of the batched schedule for one row: accumulate all (k3, m3) pairs.
+// One step of the batched schedule for one row: for each output k3 its terms
+// of the step are summed into a fresh partial, which is then added to the
+// running sum once (one rounding of the running sum per output and step).
 template <typename T, int N, typename WP>
 __device__ __forceinline__ void cells_step(const typename cplx<T>::t (&mv)[N], const typename cplx<T>::t (&jv)[N],
                                            WP w, T (&pr)[N], T (&pi)[N]) {
     constexpr int h = N / 2;
 #pragma unroll
-    for (int m3 = 0; m3 < N; ++m3) {
-        const int klo = m3 - h > 0 ? m3 - h : 0;
-        const int khi = m3 + h - 1 < N - 1 ? m3 + h - 1 : N - 1;
+    for (int k3 = 0; k3 < N; ++k3) {
+        const int mlo = k3 - h + 1 > 0 ? k3 - h + 1 : 0;
+        const int mhi = k3 + h < N - 1 ? k3 + h : N - 1;
+        T sr = 0, si = 0;
 #pragma unroll
-        for (int k3 = klo; k3 <= khi; ++k3) {
+        for (int m3 = mlo; m3 <= mhi; ++m3) {
             const int j3 = k3 - m3 + h;
-            const T wt = w[band_off(N, m3) + (k3 - klo)];
-            const T tr = wt * mv[m3].x, ti = wt * mv[m3].y;
-            pr[k3] = fma(tr, jv[j3].x, pr[k3]);
-            pr[k3] = fma(-ti, jv[j3].y, pr[k3]);
-            pi[k3] = fma(tr, jv[j3].y, pi[k3]);
-            pi[k3] = fma(ti, jv[j3].x, pi[k3]);
+            const T wt = w[step_koff(N, k3) + (m3 - mlo)];
+            // product fhat_m fhat_j first, then one rounding into each partial per term
+            const T px = fma(mv[m3].x, jv[j3].x, -(mv[m3].y * jv[j3].y));
+            const T py = fma(mv[m3].x, jv[j3].y, mv[m3].y * jv[j3].x);
+            sr = fma(wt, px, sr);
+            si = fma(wt, py, si);
         }
+        pr[k3] += sr;
+        pi[k3] += si;
     }
 }
 
@@ -140,7 +138,8 @@ __device__ inline int pop_item(unsigned *counter) {
 // Batched FP32 with compensated accumulation.
 // ---------------------------------------------------------------------------
 template <int N, int FOLD, int COMP, int WP, int RP>
-__global__ void __launch_bounds__(64) k_conv_cells_f32(const float2 *__restrict__ fh, const float *__restrict__ W,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(COMP == 2 ? 2 : 1)))
+k_conv_cells_f32(const float2 *__restrict__ fh, const float *__restrict__ W,
                                                        const long long *__restrict__ row_woff,
                                                        const int4 *__restrict__ items, int n_items,
                                                        unsigned *__restrict__ counter, double2 *__restrict__ qh,
@@ -170,6 +169,7 @@ __global__ void __launch_bounds__(64) k_conv_cells_f32(const float2 *__restrict_
         const float2 *G = fh + (size_t)g * M * kWave;   // this group's fhat
         const float2 *F = G + lane;
 
+        double2 *const out = qh + part * part_stride + (size_t)g * M * kWave + (size_t)r * N * kWave + lane;
         float pr[N], pi[N];
         float hr[N], hi[N], lr[N], li[N];
         double dr[N], di[N];
@@ -177,9 +177,24 @@ __global__ void __launch_bounds__(64) k_conv_cells_f32(const float2 *__restrict_
         for (int t = 0; t < N; ++t) {
             pr[t] = pi[t] = 0.f;
             if (COMP == 1) hr[t] = hi[t] = lr[t] = li[t] = 0.f;
-            else dr[t] = di[t] = 0.0;
+            else if (COMP == 0) dr[t] = di[t] = 0.0;
         }
+        bool first = true;
         auto fold = [&]() {
+            if (COMP == 2) {
+                // the FP64 total lives in this item's own output slot (no other item writes it)
+#pragma unroll
+                for (int t = 0; t < N; ++t) {
+                    double2 o = make_double2(0.0, 0.0);
+                    if (!first) o = out[t * kWave];
+                    o.x += (double)pr[t];
+                    o.y += (double)pi[t];
+                    out[t * kWave] = o;
+                    pr[t] = pi[t] = 0.f;
+                }
+                first = false;
+                return;
+            }
 #pragma unroll
             for (int t = 0; t < N; ++t) {
                 if (COMP == 1) {
@@ -251,7 +266,7 @@ __global__ void __launch_bounds__(64) k_conv_cells_f32(const float2 *__restrict_
             __builtin_amdgcn_s_waitcnt(0);
         }
         fold();
-        double2 *out = qh + part * part_stride + (size_t)g * M * kWave + (size_t)r * N * kWave + lane;
+        if (COMP == 2) continue;
 #pragma unroll
         for (int t = 0; t < N; ++t) {
             if (COMP == 1)
@@ -362,11 +377,10 @@ __global__ void __launch_bounds__(64) k_conv_plain(const typename cplx<T>::t *__
                 const C a = rowm[m3];
                 const C bb = rowj[j3];
                 const T wt = w[m3 * LN];
-                const T tr = wt * a.x, ti = wt * a.y;
-                pr = fma(tr, bb.x, pr);
-                pr = fma(-ti, bb.y, pr);
-                pi = fma(tr, bb.y, pi);
-                pi = fma(ti, bb.x, pi);
+                const T px = fma(a.x, bb.x, -(a.y * bb.y));
+                const T py = fma(a.x, bb.y, a.y * bb.x);
+                pr = fma(wt, px, pr);
+                pi = fma(wt, py, pi);
             }
             w += N * LN;
             ar += (double)pr;
@@ -383,6 +397,11 @@ __global__ void __launch_bounds__(64) k_conv_plain(const typename cplx<T>::t *__
 //   3: FOLD 2, TwoSum total, LDS double-buffered weights, rows loaded per step
 //   4: FOLD 2, FP64 total,   scalar weights + L2 prefetch, rows prefetched to LDS
 //   5: FOLD 4, FP64 total,   LDS double-buffered weights, rows prefetched to LDS
+//   6: FOLD 2, FP64 total kept in the output slot (read-modify-write per fold), LDS
+//      double-buffered weights, rows loaded per step; fits two wavefronts per SIMD
+//   7: as 6 with FOLD 4
+//   8: as 6 with FOLD 8
+//   9: as 6 with FOLD 16
 template <int N>
 hipError_t cells_f32_variant(const CellsLaunch &p, unsigned grid, hipStream_t s) {
 #define BZ_CELLS_F32(F, C, WPV, RPV)                                                                        \
@@ -395,6 +414,10 @@ hipError_t cells_f32_variant(const CellsLaunch &p, unsigned grid, hipStream_t s)
     case 3: BZ_CELLS_F32(2, 1, 0, 0); break;
     case 4: BZ_CELLS_F32(2, 0, 1, 1); break;
     case 5: BZ_CELLS_F32(4, 0, 0, 1); break;
+    case 6: BZ_CELLS_F32(2, 2, 0, 0); break;
+    case 7: BZ_CELLS_F32(4, 2, 0, 0); break;
+    case 8: BZ_CELLS_F32(8, 2, 0, 0); break;
+    case 9: BZ_CELLS_F32(16, 2, 0, 0); break;
     default: BZ_CELLS_F32(2, 0, 0, 1); break;
     }
 #undef BZ_CELLS_F32

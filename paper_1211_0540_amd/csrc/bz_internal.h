@@ -38,12 +38,21 @@ __host__ __device__ inline int axis_cnt(int N, int k) { return axis_hi(N, k) - a
 // where s = 4pi (2pi)^{-3/2} L^{lambda+3} dzeta^3.  Unordered pairs are
 // represented by m <= j in the lexicographic order of (m1, m2, m3); a "step"
 // is one (m1, m2) with (m1, m2) <= (j1, j2), and covers all (k3, m3) of the
-// row in the fixed order  for m3 in [0, N): for k3 in [kband_lo, kband_hi].
+// row in the fixed order  for k3 in [0, N): for m3 in [axis_lo(k3), axis_hi(k3)]
+// (output-major, so that the terms of one output in one step are contiguous).
 // In the diagonal step (m1, m2) == (j1, j2) the pairs with m3 > j3 get W = 0.
 // ---------------------------------------------------------------------------
-__host__ __device__ inline int kband_lo(int N, int m3) { return m3 - N / 2 > 0 ? m3 - N / 2 : 0; }
-__host__ __device__ inline int kband_hi(int N, int m3) { return m3 + N / 2 - 1 < N - 1 ? m3 + N / 2 - 1 : N - 1; }
 __host__ __device__ inline int pairs_per_step(int N) { return 3 * N * N / 4; }
+// offset of output k3's run in a step: sum of axis_cnt over k < k3
+__host__ __device__ constexpr int step_koff(int N, int k3) {
+    int s = 0;
+    for (int k = 0; k < k3; ++k) {
+        const int lo = k - N / 2 + 1 > 0 ? k - N / 2 + 1 : 0;
+        const int hi = k + N / 2 < N - 1 ? k + N / 2 : N - 1;
+        s += hi - lo + 1;
+    }
+    return s;
+}
 
 // Last m1 of the row: the largest m1 with 2 m1 <= k1 + N/2.
 __host__ __device__ inline int cells_m1_last(int N, int k1) {

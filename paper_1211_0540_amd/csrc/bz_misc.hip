@@ -129,14 +129,14 @@ __global__ void __launch_bounds__(256) k_expand_cells(int N, const double *__res
         for (int m2 = axis_lo(N, k2); m2 <= cells_m2_last(N, k1, k2, m1); ++m2, ++step) {
             const int j2 = k2 + h - m2;
             for (int t = threadIdx.x; t < PS; t += blockDim.x) {
-                // locate (m3, k3) of flat pair index t in the band order
-                int m3 = 0, base = 0;
-                for (;; ++m3) {
-                    int cnt = kband_hi(N, m3) - kband_lo(N, m3) + 1;
+                // locate (k3, m3) of flat pair index t in the output-major step order
+                int k3 = 0, base = 0;
+                for (;; ++k3) {
+                    const int cnt = axis_cnt(N, k3);
                     if (t < base + cnt) break;
                     base += cnt;
                 }
-                const int k3 = kband_lo(N, m3) + (t - base);
+                const int m3 = axis_lo(N, k3) + (t - base);
                 const int j3 = k3 + h - m3;
                 const int na = sq3(k1 - h, k2 - h, k3 - h);
                 const int nb = sq3(m1 - j1, m2 - j2, m3 - j3);

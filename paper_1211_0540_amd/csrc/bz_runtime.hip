@@ -543,7 +543,7 @@ bz_status bz_batch_set_weights(bz_batch b, int grid_index, int kind, const void 
     return BZ_OK;
 }
 
-int bz_variant_count(void) { return 6; }
+int bz_variant_count(void) { return 10; }
 
 bz_status bz_batch_set_variant(bz_batch b, int grid_index, int variant) {
     if (!b) return fail(BZ_EINVAL, "bz_batch_set_variant: NULL batch");
