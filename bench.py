@@ -40,16 +40,16 @@ def conv_source_sha():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic(cells):
+def measured_traffic(cells, variant):
     """HBM bytes per launch of the batched N=32 kernel from the committed counter
-    summary, if it was taken on the current kernel source and the same batch."""
+    summary, if it was taken on the current kernel source, variant and batch."""
     p = os.path.join(ROOT, "profiles", "conv_cells_f32_n32_traffic.json")
     try:
         with open(p) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_src_sha") != conv_source_sha() or d.get("cells") != cells:
+    if d.get("kernel_src_sha") != conv_source_sha() or d.get("cells") != cells or d.get("variant") != variant:
         return None
     return d.get("traffic_bytes_per_launch")
 
@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="use this convolution variant instead of autotuning (as a profiled run of the bench needs)")
     ap.add_argument("--profile-run", action="store_true",
                     help="timed steps only (default kernel variant, no comparisons, no CPU leg)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -145,7 +147,10 @@ def main():
     wcache = {}
     col = bz.Collision([(N, L, lam)], [0] * nc, "batched_f32", weights_cache=wcache)
     f0 = torch.from_numpy(col.pack(cells)).to(dev)
-    if args.profile_run:
+    if args.variant is not None:
+        col.set_variant(args.variant)
+        variant = args.variant
+    elif args.profile_run:
         variant = bz.bz_batch_get_variant(col.batch, 0)
     else:
         variant = col.autotune(f0, reps=1)[0]
@@ -276,7 +281,7 @@ def main():
                "sample": f"{done} of the {nc} N=32 cells, one FP64 evaluation each (transform, O(N^6) sum, "
                          f"inverse, projection), {el:.1f} s"}
 
-    traffic = measured_traffic(nc)
+    traffic = measured_traffic(nc, variant)
     out = {
         "metric": METRIC,
         "value": value,
