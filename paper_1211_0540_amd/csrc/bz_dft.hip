@@ -3,10 +3,17 @@
 //   Qt_j   = (2pi)^{-3/2} dzeta^3 Re sum_k Qhat_k exp(+i zeta_k . v_j)
 // On the mesh zeta_k . v_j = (2pi/N) sum_d (k_d - N/2)(j_d - N/2), so each
 // axis is an N-point DFT with the twiddle w^{((k-N/2)(j-N/2)) mod N},
-// w = exp(-2 pi i / N).  N <= 32 is small, so each axis is a direct sum done
-// out of LDS: pass A transforms the two fast axes of one plane, pass B the
-// slow axis of one (k2) slab.  FP64 throughout; the cost is O(N^4) per cell,
-// about 1% of the convolution.
+// w = exp(-2 pi i / N).  N <= 32 is small, so each axis is a direct sum.
+// FP64 throughout; the cost is O(N^4) per cell, about 1% of the convolution.
+//
+// Two organisations:
+// * one cell at a time (plain path): pass A transforms the two fast axes of
+//   one plane out of LDS, pass B the slow axis of one (k2) slab;
+// * cell-interleaved groups of 64 (batched paths, element (g, k, lane) at
+//   (g M + k) 64 + lane): one wavefront transforms one line of its 64 cells
+//   along one axis, lane = cell, so every read and write of the
+//   intermediate and spectral buffers is a whole 1 KiB line; three passes,
+//   one per axis.
 #include "bz_internal.h"
 
 namespace bz {
@@ -176,7 +183,254 @@ __global__ void __launch_bounds__(256) k_dft_inv_b(int N, double scale, const do
     }
 }
 
+// ---------------------------------------------------------------------------
+// Cell-interleaved groups (batched paths).  The loop over outputs k is kept
+// rolled; along the inputs j the twiddle index ((k - N/2)(j - N/2)) mod N
+// advances by (k - N/2) mod N, a wavefront-uniform add and wrap.
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ int tw_first(int k) {  // index for j = 0
+    return (((k - N / 2) * (-N / 2)) % N + N) % N;
+}
+template <int N>
+__device__ __forceinline__ int tw_step(int k) {
+    return (k - N / 2 + N) % N;
+}
+template <int N>
+__device__ __forceinline__ void tw_next(int &t, int step) {
+    t += step;
+    t = t >= N ? t - N : t;
+}
+
+// line index of this wavefront (4 per block) and its lane
+#define BZ_LINE_SETUP(SIGN)                                   \
+    __shared__ double2 roots[N];                              \
+    load_roots(roots, N, SIGN);                               \
+    __syncthreads();                                          \
+    constexpr int M = N * N * N;                              \
+    const int lane = threadIdx.x & (kWave - 1);               \
+    const int line = blockIdx.x * 4 + (threadIdx.x >> 6);     \
+    const int g = blockIdx.y;                                 \
+    const size_t gb = (size_t)g * M;                          \
+    (void)gb;
+
+// forward, axis 3: real f of cell g*64 + lane, line (j1, j2) -> S (j1, j2, k3)
+template <int N>
+__global__ void __launch_bounds__(256) k_dftg_fwd1(const double *__restrict__ f, const long long *__restrict__ f_off,
+                                                   int nc, double2 *__restrict__ S) {
+    BZ_LINE_SETUP(-1.0)
+    const int i = g * kWave + lane;
+    double x[N];
+    if (i < nc) {
+        const double *src = f + f_off[i] + (size_t)line * N;
+#pragma unroll
+        for (int j = 0; j < N; ++j) x[j] = src[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) x[j] = 0.0;
+    }
+    double2 *dst = S + (gb + (size_t)line * N) * kWave + lane;
+#pragma unroll 1
+    for (int k = 0; k < N; ++k) {
+        double re = 0.0, im = 0.0;
+        int t = tw_first<N>(k);
+        const int st = tw_step<N>(k);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const double2 w = roots[t];
+            re = fma(x[j], w.x, re);
+            im = fma(x[j], w.y, im);
+            tw_next<N>(t, st);
+        }
+        dst[(size_t)k * kWave] = make_double2(re, im);
+    }
+}
+
+// one complex line: out_k = sum_j in_j w^{twi(k, j)}; in/out strided by `stride` elements
+template <int N>
+__device__ __forceinline__ void line_dft(const double2 (&x)[N], const double2 *roots, double2 *dst, size_t stride,
+                                         double scale) {
+#pragma unroll 1
+    for (int k = 0; k < N; ++k) {
+        double re = 0.0, im = 0.0;
+        int t = tw_first<N>(k);
+        const int st = tw_step<N>(k);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const double2 w = roots[t];
+            re = fma(x[j].x, w.x, re);
+            re = fma(-x[j].y, w.y, re);
+            im = fma(x[j].x, w.y, im);
+            im = fma(x[j].y, w.x, im);
+            tw_next<N>(t, st);
+        }
+        dst[k * stride] = make_double2(re * scale, im * scale);
+    }
+}
+
+// forward, axis 2: line (j1, k3): S (j1, j2, k3) -> T (j1, k2, k3)
+template <int N>
+__global__ void __launch_bounds__(256) k_dftg_fwd2(const double2 *__restrict__ S, double2 *__restrict__ T) {
+    BZ_LINE_SETUP(-1.0)
+    const int j1 = line / N, k3 = line - j1 * N;
+    const size_t off = (gb + (size_t)j1 * N * N + k3) * kWave + lane;
+    double2 x[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) x[j] = S[off + (size_t)j * N * kWave];
+    line_dft<N>(x, roots, T + off, (size_t)N * kWave, 1.0);
+}
+
+// forward, axis 1: line (k2, k3): T (j1, k2, k3) -> fhat (k1, k2, k3), scaled, in the kernel's precision
+template <int N, typename Out>
+__global__ void __launch_bounds__(256) k_dftg_fwd3(const double2 *__restrict__ T, int nc, double scale,
+                                                   Out *__restrict__ fh) {
+    BZ_LINE_SETUP(-1.0)
+    const size_t off = (gb + (size_t)line) * kWave + lane;
+    double2 x[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) x[j] = T[off + (size_t)j * N * N * kWave];
+    const bool live = g * kWave + lane < nc;
+#pragma unroll 1
+    for (int k = 0; k < N; ++k) {
+        double re = 0.0, im = 0.0;
+        int t = tw_first<N>(k);
+        const int st = tw_step<N>(k);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const double2 w = roots[t];
+            re = fma(x[j].x, w.x, re);
+            re = fma(-x[j].y, w.y, re);
+            im = fma(x[j].x, w.y, im);
+            im = fma(x[j].y, w.x, im);
+            tw_next<N>(t, st);
+        }
+        Out v;
+        v.x = live ? re * scale : 0.0;
+        v.y = live ? im * scale : 0.0;
+        fh[off + (size_t)k * N * N * kWave] = v;
+    }
+}
+
+// inverse, axis 1: line (k2, k3): sum of the partial buffers (k1, k2, k3) -> S (j1, k2, k3)
+template <int N>
+__global__ void __launch_bounds__(256) k_dftg_inv1(const double2 *__restrict__ qh, int nparts, long long pstride,
+                                                   double2 *__restrict__ S) {
+    BZ_LINE_SETUP(+1.0)
+    const size_t off = (gb + (size_t)line) * kWave + lane;
+    double2 x[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double2 a = qh[off + (size_t)j * N * N * kWave];
+        for (int p = 1; p < nparts; ++p) {
+            const double2 b = qh[off + (size_t)j * N * N * kWave + (size_t)p * pstride];
+            a.x += b.x;
+            a.y += b.y;
+        }
+        x[j] = a;
+    }
+    line_dft<N>(x, roots, S + off, (size_t)N * N * kWave, 1.0);
+}
+
+// inverse, axis 2: line (j1, k3): S (j1, k2, k3) -> T (j1, j2, k3)
+template <int N>
+__global__ void __launch_bounds__(256) k_dftg_inv2(const double2 *__restrict__ S, double2 *__restrict__ T) {
+    BZ_LINE_SETUP(+1.0)
+    const int j1 = line / N, k3 = line - j1 * N;
+    const size_t off = (gb + (size_t)j1 * N * N + k3) * kWave + lane;
+    double2 x[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) x[j] = S[off + (size_t)j * N * kWave];
+    line_dft<N>(x, roots, T + off, (size_t)N * kWave, 1.0);
+}
+
+// inverse, axis 3: line (j1, j2): T (j1, j2, k3) -> Qt (j1, j2, j3) = scale Re(...) of cell g*64 + lane
+template <int N>
+__global__ void __launch_bounds__(256) k_dftg_inv3(const double2 *__restrict__ T, int nc, double scale,
+                                                   double *__restrict__ qt, const long long *__restrict__ q_off) {
+    BZ_LINE_SETUP(+1.0)
+    const int i = g * kWave + lane;
+    const size_t off = (gb + (size_t)line * N) * kWave + lane;
+    double2 x[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) x[j] = T[off + (size_t)j * kWave];
+    if (i >= nc) return;
+    double *dst = qt + q_off[i] + (size_t)line * N;
+#pragma unroll 1
+    for (int k = 0; k < N; ++k) {
+        double re = 0.0;
+        int t = tw_first<N>(k);
+        const int st = tw_step<N>(k);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const double2 w = roots[t];
+            re = fma(x[j].x, w.x, re);
+            re = fma(-x[j].y, w.y, re);
+            tw_next<N>(t, st);
+        }
+        dst[k] = re * scale;
+    }
+}
+#undef BZ_LINE_SETUP
+
+template <int N>
+hipError_t grouped_forward(double L, int nc, const double *f, const long long *f_off, double2 *S, double2 *T,
+                           void *fh, bool f32, hipStream_t s) {
+    const int groups = (nc + kWave - 1) / kWave;
+    const dim3 grid(N * N / 4, groups);
+    const double dv = 2.0 * L / N;
+    const double scale = pow(2.0 * kPi, -1.5) * dv * dv * dv;
+    hipLaunchKernelGGL(k_dftg_fwd1<N>, grid, dim3(256), 0, s, f, f_off, nc, S);
+    hipLaunchKernelGGL(k_dftg_fwd2<N>, grid, dim3(256), 0, s, S, T);
+    if (f32)
+        hipLaunchKernelGGL((k_dftg_fwd3<N, float2>), grid, dim3(256), 0, s, T, nc, scale, (float2 *)fh);
+    else
+        hipLaunchKernelGGL((k_dftg_fwd3<N, double2>), grid, dim3(256), 0, s, T, nc, scale, (double2 *)fh);
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t grouped_inverse(double L, int nc, const double2 *qh, int nparts, long long pstride, double2 *S,
+                           double2 *T, double *qt, const long long *q_off, hipStream_t s) {
+    const int groups = (nc + kWave - 1) / kWave;
+    const dim3 grid(N * N / 4, groups);
+    const double dz = kPi / L;
+    const double scale = pow(2.0 * kPi, -1.5) * dz * dz * dz;
+    hipLaunchKernelGGL(k_dftg_inv1<N>, grid, dim3(256), 0, s, qh, nparts, pstride, S);
+    hipLaunchKernelGGL(k_dftg_inv2<N>, grid, dim3(256), 0, s, S, T);
+    hipLaunchKernelGGL(k_dftg_inv3<N>, grid, dim3(256), 0, s, T, nc, scale, qt, q_off);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+#define BZ_FOR_EACH_N(X) X(8) X(12) X(16) X(20) X(24) X(28) X(32)
+
+hipError_t launch_dft_forward_grouped(int N, double L, int ncells, const double *f, const long long *d_f_off,
+                                      double2 *S, double2 *T, void *fh, bool out_f32, hipStream_t s) {
+    if (ncells <= 0) return hipSuccess;
+#define CASE(NN) \
+    case NN: return grouped_forward<NN>(L, ncells, f, d_f_off, S, T, fh, out_f32, s);
+    switch (N) {
+        BZ_FOR_EACH_N(CASE)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef CASE
+}
+
+hipError_t launch_dft_inverse_grouped(int N, double L, int ncells, const double2 *qh, int nparts, long long pstride,
+                                      double2 *S, double2 *T, double *qt, const long long *d_q_off, hipStream_t s) {
+    if (ncells <= 0) return hipSuccess;
+#define CASE(NN) \
+    case NN: return grouped_inverse<NN>(L, ncells, qh, nparts, pstride, S, T, qt, d_q_off, s);
+    switch (N) {
+        BZ_FOR_EACH_N(CASE)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef CASE
+}
+#undef BZ_FOR_EACH_N
 
 hipError_t launch_dft_forward(int N, double L, int ncells, const double *f, const long long *d_f_off,
                               double2 *scratch, void *out, bool out_f32, const long long *d_o_base,

@@ -140,6 +140,13 @@ hipError_t launch_expand_plain(int N, const double *dT, int qstride, double scal
 // Forward transform of `ncells` cells of one mesh.  Cell c's f starts at
 // f + f_off[c]; fhat element k of cell c is written at out + o_base[c] + k*o_stride
 // (complex units) as float2 (f32) or double2.
+// batched paths: cell-interleaved groups of 64; S and T are scratch buffers of
+// groups * N^3 * 64 double2 each (T may be the first partial buffer of qh for
+// the inverse, which reads qh only in its first pass)
+hipError_t launch_dft_forward_grouped(int N, double L, int ncells, const double *f, const long long *d_f_off,
+                                      double2 *S, double2 *T, void *fh, bool out_f32, hipStream_t s);
+hipError_t launch_dft_inverse_grouped(int N, double L, int ncells, const double2 *qh, int nparts, long long pstride,
+                                      double2 *S, double2 *T, double *qt, const long long *d_q_off, hipStream_t s);
 hipError_t launch_dft_forward(int N, double L, int ncells, const double *f, const long long *d_f_off,
                               double2 *scratch, void *out, bool out_f32, const long long *d_o_base,
                               long long o_stride, hipStream_t s);

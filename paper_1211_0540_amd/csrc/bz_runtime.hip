@@ -484,7 +484,7 @@ bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids,
         }
         p.ws_counter = ws;
         ws = align256(ws + 256);
-        const size_t sc = (bat ? p.cells.size() : 1) * (size_t)M * 16;
+        const size_t sc = (bat ? (size_t)p.groups * kWave : 1) * (size_t)M * 16;
         scratch = std::max(scratch, sc);
     }
     b->ws_scratch = ws;
@@ -675,7 +675,8 @@ static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void 
         double2 *qh = (double2 *)(ws + p.ws_qh);
         if (batched(b->mode)) {
             const int nc = (int)p.cells.size();
-            BZ_HIP(launch_dft_forward(N, p.g->L, nc, d_f, p.d_f_off, scratch, fh, !f64, p.d_fh_base, kWave, s),
+            // the first partial buffer of qh serves as the second scratch buffer of the transforms
+            BZ_HIP(launch_dft_forward_grouped(N, p.g->L, nc, d_f, p.d_f_off, scratch, qh, fh, !f64, s),
                    "forward transform");
             const long long pstride = (long long)p.groups * M * kWave;
             CellsLaunch cl{N, fh, p.w, p.d_row_woff, p.d_items, p.n_items, (unsigned *)(ws + p.ws_counter), qh,
@@ -688,8 +689,7 @@ static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void 
             cl.variant = p.variant;
             BZ_HIP(launch_conv_cells(cl, f64, s), "batched convolution");
             if (b->timing) BZ_HIP(hipEventRecord(ev.second, s), "timer stop");
-            BZ_HIP(launch_dft_inverse(N, p.g->L, nc, qh, p.d_fh_base, kWave, p.parts, pstride, scratch, d_Qt,
-                                      p.d_f_off, s),
+            BZ_HIP(launch_dft_inverse_grouped(N, p.g->L, nc, qh, p.parts, pstride, scratch, qh, d_Qt, p.d_f_off, s),
                    "inverse transform");
         } else {
             const int sp = plain_split_for(N);
