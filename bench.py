@@ -106,7 +106,8 @@ def closure_leg(args, torch, np, bz, W):
             "loss_first_last": [hist[0][1], hist[-1][1]], "validation_rel_l2": val,
             "plain_fp32_ms_per_step": ta / K * 1e3, "closure_ms_per_step": tb / K * 1e3,
             "speedup": ta / tb, "closure_cell_evals_per_s": evals / tb, "served_fraction": st["served"] / evals,
-            "judged": st["judged"], "judge_failed": st["failed"], "judge_max_rel_err": st["max_err"],
+            "judged": st["judged"], "judge_failed": st["failed"],
+            "judge_pass_fraction": 1.0 - st["failed"] / max(st["judged"], 1), "judge_max_rel_err": st["max_err"],
             "max_abs_T_profile_deviation": float(np.max(np.abs(TA - TB)))}
 
 

@@ -135,7 +135,7 @@ class ClosureModel:
         return sum(int(a.shape[0]) for a in self.xs)
 
     # ---------------------------------------------------------------- train
-    def fit(self, steps=1000, batch=256, lr=1e-3, seed=0, lr_min_frac=0.05):
+    def fit(self, steps=1000, batch=256, lr=1e-3, seed=0, lr_min_frac=0.05, calibrate=True):
         X = torch.cat(self.xs) if len(self.xs) > 1 else self.xs[0]
         Y = torch.cat(self.ys) if len(self.ys) > 1 else self.ys[0]
         self.xs, self.ys = [X], [Y]
@@ -162,7 +162,24 @@ class ClosureModel:
             bz.bz_mlp_adam(self.net, self.params, grad, self.step, lr_i)
             if i % 50 == 0 or i == steps - 1:
                 self.history.append((self.step, float(loss.item())))
+        if calibrate:
+            self.calibrate_zero()
         return self.history
+
+    def calibrate_zero(self):
+        """Shift the output-layer bias so that the network maps x = 0 (f equal to its
+        local Maxwellian) to exactly 0.  The collision operator vanishes on a
+        Maxwellian; an output bias left at x = 0 would push every equilibrium cell
+        away from equilibrium, step after step, into states never trained on.
+        Resets the Adam moments (the parameters are re-uploaded)."""
+        n = 32
+        x = torch.zeros(n * self.M, dtype=torch.int16, device=self.dev)
+        y = torch.zeros(n, self.M, dtype=torch.float32, device=self.dev)
+        work = torch.zeros(bz.bz_mlp_workspace_bytes(self.net, n), dtype=torch.uint8, device=self.dev)
+        bz.bz_mlp_forward(self.net, self.params, x, n, y, work)
+        master = bz.bz_mlp_get_params(self.net, self.params)
+        master[-self.M:] -= y[0].cpu().numpy()
+        bz.bz_mlp_set_params(self.net, self.params, master)
 
     def validation_error(self, rows=512):
         """Relative L2 error of the network on the last `rows` training rows."""

@@ -88,6 +88,32 @@ def test_open_gate_serves_the_network(dev, model):
     assert np.all(q == 0.0)          # the untrained closure predicts zero
 
 
+def test_zero_input_calibration(dev):
+    """After calibration the network maps the equilibrium input x = 0 to 0 (FP32 rounding of
+    the bias shift), and inputs away from 0 still reach the trained layers."""
+    M = N ** 3
+    m = ClosureModel(N, L, LAM, hidden=1024, seed=12)
+    master = bz.bz_mlp_get_params(m.net, m.params)
+    rng = np.random.default_rng(3)
+    # give the output layer (W3 [M, 1024], then b3 [M], last in the layout) non-zero
+    # weights and biases so that MLP(0) != 0
+    w3 = slice(len(master) - M - M * 1024, len(master) - M)
+    master[w3] = rng.uniform(-1e-2, 1e-2, M * 1024).astype(np.float32)
+    master[-M:] = rng.uniform(-0.5, 0.5, M).astype(np.float32)
+    bz.bz_mlp_set_params(m.net, m.params, master)
+    n = 32
+    work = torch.zeros(bz.bz_mlp_workspace_bytes(m.net, n), dtype=torch.uint8, device=dev)
+    x0 = torch.zeros(n * M, dtype=torch.int16, device=dev)
+    y = torch.zeros(n, M, dtype=torch.float32, device=dev)
+    bz.bz_mlp_forward(m.net, m.params, x0, n, y, work)
+    before = float(y[0].abs().max())
+    assert before > 0.1
+    m.calibrate_zero()
+    bz.bz_mlp_forward(m.net, m.params, x0, n, y, work)
+    assert float(y.abs().max()) <= 1e-6 * before
+    bz.bz_mlp_free(m.net)
+
+
 def test_harvest_train_serve_shock(dev):
     m = ClosureModel(N, L, LAM, hidden=1024, seed=11)
     k1 = m.harvest_shock(snapshots=40, every=2, keep=0.1)
