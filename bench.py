@@ -54,6 +54,76 @@ def measured_traffic(cells, variant):
     return d.get("traffic_bytes_per_launch")
 
 
+def relaxation_leg(torch, np, bz, W):
+    """Bi-Maxwellian relaxation on the N=32, L=8 mesh, hard spheres: 100 Heun steps
+    with dt = 0.01, batched FP32 against plain FP64; directional temperatures."""
+    N, L, steps, dt = 32, 8.0, 100, 0.01
+    f0 = W.relaxation_cell(N, L)
+    dv = 2 * L / N
+    v = dv * (np.arange(N) - N // 2)
+    V = np.meshgrid(v, v, v, indexing="ij")
+
+    def temps(f):
+        rho = f.sum()
+        u = [(V[d] * f).sum() / rho for d in range(3)]
+        return np.array([((V[d] - u[d]) ** 2 * f).sum() / rho for d in range(3)])
+
+    res = {}
+    for mode in ("plain_f64", "batched_f32"):
+        c = bz.Collision([(N, L, 1.0)], [0], mode)
+        f = torch.from_numpy(c.pack([f0])).cuda()
+        T = [temps(f0)]
+        ms = 0.0
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            c.step(f, dt)
+            torch.cuda.synchronize()
+            ms += (time.perf_counter() - a) * 1e3
+            T.append(temps(f.cpu().numpy().reshape(N, N, N)))
+        c.check()
+        c.close()
+        res[mode] = (np.array(T), ms / steps)
+    dT = np.abs(res["batched_f32"][0] - res["plain_f64"][0])
+    return {"workload": "one N=32 bi-Maxwellian cell (T = 2, 0.5, 0.5), hard spheres, 100 Heun steps, dt = 0.01",
+            "max_abs_dT_fp32_vs_fp64": float(dT.max()), "T_x_final_fp64": float(res["plain_f64"][0][-1, 0]),
+            "fp64_plain_ms_per_step": res["plain_f64"][1], "fp32_batched_ms_per_step": res["batched_f32"][1]}
+
+
+def uneven_leg(torch, np, bz, W, steps=5):
+    """All 1024 cells of the uneven draw (N = 16, 24, 32 in one batch): autotuned
+    FP32 Heun steps, and per-mesh FP32 vs batched-FP64 errors of one evaluation."""
+    batch = W.uneven_batch(n_cells=1024)
+    meshes = [(16, 6.0, 1.0), (24, 7.0, 1.0), (32, 8.0, 1.0)]
+    gidx = [{16: 0, 24: 1, 32: 2}[int(n)] for n in batch.Ns]
+    c32 = bz.Collision(meshes, gidx, "batched_f32")
+    f0 = torch.from_numpy(c32.pack(batch.cells)).cuda()
+    variants = c32.autotune(f0, reps=1)
+    q32 = c32.project(c32.collide(f0)).cpu().numpy()
+    c64 = bz.Collision(meshes, gidx, "batched_f64")
+    q64 = c64.project(c64.collide(f0)).cpu().numpy()
+    c64.close()
+    errs = {16: [], 24: [], 32: []}
+    for n, x, y in zip(batch.Ns, c32.unpack(q32), c32.unpack(q64)):
+        errs[int(n)].append(float(np.linalg.norm(x - y) / np.linalg.norm(y)))
+    f = f0.clone()
+    c32.step(f, 0.01)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(steps):
+        c32.step(f, 0.01)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - a) / steps * 1e3
+    c32.check()
+    c32.close()
+    return {"workload": "1024 cells of the seeded uneven draw (521 N=16, 313 N=24, 190 N=32), one batch",
+            "ms_per_step": ms, "cell_evals_per_s": 2 * len(batch.Ns) / ms * 1e3,
+            "variants_N16_N24_N32": variants,
+            "rel_l2_fp32_vs_fp64": {str(k): {"median": float(np.median(v)), "max": float(np.max(v)),
+                                             "frac_le_1e-5": float(np.mean(np.array(v) <= 1e-5))}
+                                    for k, v in errs.items()}}
+
+
 def closure_leg(args, torch, np, bz, W):
     """Harvest (f, Q) pairs on the N=24 shock problem and homogeneous relaxations,
     train the 13824-1024-1024-13824 network with the library's kernels, then time
@@ -260,6 +330,15 @@ def main():
     wcache.clear()
     col.close()
     torch.cuda.empty_cache()
+
+    # ---- homogeneous relaxation (N=32) and the whole uneven batch --------
+    for key, fn in (("relaxation_n32", lambda: relaxation_leg(torch, np, bz, W)),
+                    ("uneven_batch_1024", lambda: uneven_leg(torch, np, bz, W))):
+        try:
+            comp[key] = fn()
+        except Exception as exc:
+            comp[key] = {"error": str(exc)}
+        torch.cuda.empty_cache()
 
     # ---- learned closure on the N=24 shock problem ----------------------
     if not args.no_closure:
