@@ -312,9 +312,11 @@ bz_status bz_batch_set_variant(bz_batch b, int grid_index, int variant);
 int bz_batch_get_variant(bz_batch b, int grid_index);
 /* Time every variant on this batch's data (d_f, d_work as for
  * bz_collide_batch; d_Qt receives a result), `reps` launches each, with HIP
- * events on `stream`, and keep the fastest per mesh.  Synchronous.  The
- * result is also remembered per (N, number of wavefront groups, mode) for
- * the rest of the process. */
+ * events on `stream`, and keep per mesh, among the variants within 3% of the
+ * fastest, the one with the most accurate accumulation (more interleaved
+ * partials, then the shorter fold interval).  Synchronous.  The result is
+ * also remembered per (N, number of wavefront groups, mode) for the rest of
+ * the process. */
 bz_status bz_batch_autotune(bz_batch b, const double *d_f, double *d_Qt, void *d_work, size_t work_bytes,
                             int reps, void *stream);
 /* enable = 1: record a HIP event pair around every convolution launch of

@@ -62,9 +62,10 @@ __device__ inline void two_sum_acc(float &hi, float &lo, float p) {
 }
 
 // One step of the batched schedule for one row: for each output k3 its terms
-// of the step are summed into a fresh partial, which is then added to the
-// running sum once (one rounding of the running sum per output and step).
-template <typename T, int N, typename WP>
+// of the step are summed into fresh partials (SPLIT interleaved accumulators,
+// combined pairwise), which are then added to the running sum once (one
+// rounding of the running sum per output and step).
+template <typename T, int N, int SPLIT, typename WP>
 __device__ __forceinline__ void cells_step(const typename cplx<T>::t (&mv)[N], const typename cplx<T>::t (&jv)[N],
                                            WP w, T (&pr)[N], T (&pi)[N]) {
     constexpr int h = N / 2;
@@ -72,19 +73,29 @@ __device__ __forceinline__ void cells_step(const typename cplx<T>::t (&mv)[N], c
     for (int k3 = 0; k3 < N; ++k3) {
         const int mlo = k3 - h + 1 > 0 ? k3 - h + 1 : 0;
         const int mhi = k3 + h < N - 1 ? k3 + h : N - 1;
-        T sr = 0, si = 0;
+        T sr[SPLIT], si[SPLIT];
+#pragma unroll
+        for (int a = 0; a < SPLIT; ++a) sr[a] = si[a] = 0;
 #pragma unroll
         for (int m3 = mlo; m3 <= mhi; ++m3) {
             const int j3 = k3 - m3 + h;
+            const int a = (m3 - mlo) % SPLIT;
             const T wt = w[step_koff(N, k3) + (m3 - mlo)];
-            // product fhat_m fhat_j first, then one rounding into each partial per term
+            // product fhat_m fhat_j first, then one rounding into a partial per term
             const T px = fma(mv[m3].x, jv[j3].x, -(mv[m3].y * jv[j3].y));
             const T py = fma(mv[m3].x, jv[j3].y, mv[m3].y * jv[j3].x);
-            sr = fma(wt, px, sr);
-            si = fma(wt, py, si);
+            sr[a] = fma(wt, px, sr[a]);
+            si[a] = fma(wt, py, si[a]);
         }
-        pr[k3] += sr;
-        pi[k3] += si;
+#pragma unroll
+        for (int st = 1; st < SPLIT; st *= 2)
+#pragma unroll
+            for (int a = 0; a + st < SPLIT; a += 2 * st) {
+                sr[a] += sr[a + st];
+                si[a] += si[a + st];
+            }
+        pr[k3] += sr[0];
+        pi[k3] += si[0];
     }
 }
 
@@ -137,7 +148,7 @@ __device__ inline int pop_item(unsigned *counter) {
 // ---------------------------------------------------------------------------
 // Batched FP32 with compensated accumulation.
 // ---------------------------------------------------------------------------
-template <int N, int FOLD, int COMP, int WP, int RP>
+template <int N, int FOLD, int COMP, int WP, int RP, int SPLIT>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(COMP == 2 ? 2 : 1)))
 k_conv_cells_f32(const float2 *__restrict__ fh, const float *__restrict__ W,
                                                        const long long *__restrict__ row_woff,
@@ -244,16 +255,16 @@ k_conv_cells_f32(const float2 *__restrict__ fh, const float *__restrict__ W,
             if (WP == 0) {
                 // next step's weights into the other LDS half; this step reads its half
                 prefetch_weights<CH>(w + PS, wl + (buf ^ 1) * CH * 1024);
-                cells_step<float, N>(mv, jv, (const float *)wbuf[buf], pr, pi);
+                cells_step<float, N, SPLIT>(mv, jv, (const float *)wbuf[buf], pr, pi);
             } else if (WP == 1) {
                 // next step's weights pulled into L2 (the LDS copy is discarded); this
                 // step's weights, pulled last step, are read through the scalar cache
                 prefetch_weights<CH>(w + PS, wl + CH * 1024);
-                cells_step<float, N>(mv, jv, (const __attribute__((address_space(4))) float *)w, pr, pi);
+                cells_step<float, N, SPLIT>(mv, jv, (const __attribute__((address_space(4))) float *)w, pr, pi);
             } else {
                 // as 1, but the weights are read by uniform-address vector loads
                 prefetch_weights<CH>(w + PS, wl + CH * 1024);
-                cells_step<float, N>(mv, jv, w, pr, pi);
+                cells_step<float, N, SPLIT>(mv, jv, w, pr, pi);
             }
             w += PS;
             buf ^= 1;
@@ -321,7 +332,7 @@ __global__ void __launch_bounds__(64) k_conv_cells_f64(const double2 *__restrict
             double2 mv[N], jv[N];
             load_row<double, N>(F + (size_t)((m1 * N + m2) * N) * kWave, mv);
             load_row<double, N>(F + (size_t)((j1 * N + j2) * N) * kWave, jv);
-            cells_step<double, N>(mv, jv, (const double *)wbuf[buf], pr, pi);
+            cells_step<double, N, 1>(mv, jv, (const double *)wbuf[buf], pr, pi);
             w += PS;
             buf ^= 1;
             if (++m2 > cells_m2_last(N, k1, k2, m1)) {
@@ -402,23 +413,39 @@ __global__ void __launch_bounds__(64) k_conv_plain(const typename cplx<T>::t *__
 //   7: as 6 with FOLD 4
 //   8: as 6 with FOLD 8
 //   9: as 6 with FOLD 16
+//  10: as 9 with four interleaved partials per output and step (pairwise combined)
+//  11: as 10 with FOLD 8
+//  12: as 10 with two interleaved partials
+//  13: as 5 with four interleaved partials
+// Accumulation parameters of each variant (must match the switch below): the
+// autotuner prefers more interleaved partials, then a shorter fold interval.
+struct VariantAcc {
+    int fold, split;
+};
+constexpr VariantAcc kVariantAcc[] = {{2, 1}, {2, 1}, {2, 1}, {2, 1}, {2, 1},  {4, 1},  {2, 1},
+                                      {4, 1}, {8, 1}, {16, 1}, {16, 4}, {8, 4}, {16, 2}, {4, 4}};
+
 template <int N>
 hipError_t cells_f32_variant(const CellsLaunch &p, unsigned grid, hipStream_t s) {
-#define BZ_CELLS_F32(F, C, WPV, RPV)                                                                        \
-    hipLaunchKernelGGL((k_conv_cells_f32<N, F, C, WPV, RPV>), dim3(grid), dim3(64), 0, s,                   \
+#define BZ_CELLS_F32(F, C, WPV, RPV, SP)                                                                    \
+    hipLaunchKernelGGL((k_conv_cells_f32<N, F, C, WPV, RPV, SP>), dim3(grid), dim3(64), 0, s,               \
                        (const float2 *)p.fh, (const float *)p.w, p.row_woff, p.items, p.n_items, p.counter, \
                        p.qh, p.part_stride, p.skip)
     switch (p.variant) {
-    case 1: BZ_CELLS_F32(2, 1, 0, 1); break;
-    case 2: BZ_CELLS_F32(2, 0, 0, 0); break;
-    case 3: BZ_CELLS_F32(2, 1, 0, 0); break;
-    case 4: BZ_CELLS_F32(2, 0, 1, 1); break;
-    case 5: BZ_CELLS_F32(4, 0, 0, 1); break;
-    case 6: BZ_CELLS_F32(2, 2, 0, 0); break;
-    case 7: BZ_CELLS_F32(4, 2, 0, 0); break;
-    case 8: BZ_CELLS_F32(8, 2, 0, 0); break;
-    case 9: BZ_CELLS_F32(16, 2, 0, 0); break;
-    default: BZ_CELLS_F32(2, 0, 0, 1); break;
+    case 1: BZ_CELLS_F32(2, 1, 0, 1, 1); break;
+    case 2: BZ_CELLS_F32(2, 0, 0, 0, 1); break;
+    case 3: BZ_CELLS_F32(2, 1, 0, 0, 1); break;
+    case 4: BZ_CELLS_F32(2, 0, 1, 1, 1); break;
+    case 5: BZ_CELLS_F32(4, 0, 0, 1, 1); break;
+    case 6: BZ_CELLS_F32(2, 2, 0, 0, 1); break;
+    case 7: BZ_CELLS_F32(4, 2, 0, 0, 1); break;
+    case 8: BZ_CELLS_F32(8, 2, 0, 0, 1); break;
+    case 9: BZ_CELLS_F32(16, 2, 0, 0, 1); break;
+    case 10: BZ_CELLS_F32(16, 2, 0, 0, 4); break;
+    case 11: BZ_CELLS_F32(8, 2, 0, 0, 4); break;
+    case 12: BZ_CELLS_F32(16, 2, 0, 0, 2); break;
+    case 13: BZ_CELLS_F32(4, 0, 0, 1, 4); break;
+    default: BZ_CELLS_F32(2, 0, 0, 1, 1); break;
     }
 #undef BZ_CELLS_F32
     return hipGetLastError();
@@ -440,6 +467,13 @@ hipError_t plain_launch(const PlainLaunch &p, hipStream_t s) {
 }
 
 }  // namespace
+
+int conv_variant_count() { return (int)(sizeof(kVariantAcc) / sizeof(kVariantAcc[0])); }
+
+int conv_variant_accuracy_rank(int v) {
+    if (v < 0 || v >= conv_variant_count()) return -1;
+    return kVariantAcc[v].split * 1000 - kVariantAcc[v].fold;
+}
 
 // Persistent grid: enough single-wave workgroups to keep every SIMD busy.
 static unsigned persistent_grid(int n_items) {

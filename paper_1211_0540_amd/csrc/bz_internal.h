@@ -174,6 +174,10 @@ struct CellsLaunch {
     int variant;                 // tuning variant
     const unsigned char *skip;   // device, per group: 1 = outputs not needed (may be NULL)
 };
+// batched FP32 variants: count, and a rank that grows with the accuracy of the
+// accumulation (more interleaved partials, then shorter fold interval)
+int conv_variant_count();
+int conv_variant_accuracy_rank(int v);
 hipError_t launch_conv_cells(const CellsLaunch &p, bool f64, hipStream_t s);
 
 // Plain convolution of one cell.

@@ -543,7 +543,7 @@ bz_status bz_batch_set_weights(bz_batch b, int grid_index, int kind, const void 
     return BZ_OK;
 }
 
-int bz_variant_count(void) { return 10; }
+int bz_variant_count(void) { return conv_variant_count(); }
 
 bz_status bz_batch_set_variant(bz_batch b, int grid_index, int variant) {
     if (!b) return fail(BZ_EINVAL, "bz_batch_set_variant: NULL batch");
@@ -624,10 +624,17 @@ bz_status bz_batch_autotune(bz_batch b, const double *d_f, double *d_Qt, void *d
     }
     for (size_t i = 0; i < b->parts.size(); ++i) {
         Part &p = b->parts[i];
-        int best = 0;
+        int fastest = 0;
         const int nvv = mode_f64(b->mode) ? 1 : nv;
         for (int v = 1; v < nvv; ++v)
-            if (t[i][v] < t[i][best]) best = v;
+            if (t[i][v] < t[i][fastest]) fastest = v;
+        // within 3% of the fastest, prefer the more accurate accumulation
+        int best = fastest;
+        for (int v = 0; v < nvv; ++v) {
+            if (t[i][v] > 1.03 * t[i][fastest]) continue;
+            const int rv = conv_variant_accuracy_rank(v), rb = conv_variant_accuracy_rank(best);
+            if (rv > rb || (rv == rb && t[i][v] < t[i][best])) best = v;
+        }
         p.variant = best;
         const long long key = tune_key(p.g->N, p.groups, b->mode);
         bool found = false;
