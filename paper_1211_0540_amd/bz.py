@@ -18,6 +18,8 @@ LIBPATH = os.path.join(_HERE, "libbz.so")
 BZ_OK, BZ_EINVAL, BZ_EUNSUPPORTED, BZ_EDEVICE, BZ_ENOMEM, BZ_ENONFINITE, BZ_ESTATE = 0, -1, -2, -3, -4, -5, -6
 BZ_W_BATCHED_F32, BZ_W_BATCHED_F64, BZ_W_PLAIN_F32, BZ_W_PLAIN_F64 = 1, 2, 3, 4
 BZ_MODE_PLAIN_F64, BZ_MODE_BATCHED_F32, BZ_MODE_BATCHED_F64, BZ_MODE_PLAIN_F32 = 1, 2, 3, 4
+BZ_BATCH_FULL_SUM = 1
+SCHEDULES = {"symmetric": 0, "full": BZ_BATCH_FULL_SUM}
 
 MODE_WEIGHTS = {BZ_MODE_PLAIN_F64: BZ_W_PLAIN_F64, BZ_MODE_BATCHED_F32: BZ_W_BATCHED_F32,
                 BZ_MODE_BATCHED_F64: BZ_W_BATCHED_F64, BZ_MODE_PLAIN_F32: BZ_W_PLAIN_F32}
@@ -72,6 +74,8 @@ def lib():
         "bz_weights": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _sz, _vp]),
         "bz_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
                                            ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp)]),
+        "bz_batch_create_ex": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
+                                              ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]),
         "bz_batch_free": (None, [_vp]),
         "bz_batch_set_weights": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp]),
         "bz_batch_elems": (_sz, [_vp]),
@@ -200,6 +204,15 @@ def bz_batch_create(grid_of_cell, grids, mode: int) -> int:
     h = _vp()
     _check(lib().bz_batch_create(int(goc.size), goc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(grids),
                                  arr, int(mode), ctypes.byref(h)))
+    return h.value
+
+
+def bz_batch_create_ex(grid_of_cell, grids, mode: int, flags: int) -> int:
+    goc = np.ascontiguousarray(grid_of_cell, dtype=np.int32)
+    arr = (_vp * len(grids))(*[_vp(g) for g in grids])
+    h = _vp()
+    _check(lib().bz_batch_create_ex(int(goc.size), goc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                    len(grids), arr, int(mode), int(flags), ctypes.byref(h)))
     return h.value
 
 
@@ -451,18 +464,21 @@ class Collision:
     """A batch of cells on one or more meshes with its weights and workspace.
 
     meshes: list of (N, L, lambda); grid_of_cell: mesh index per cell;
-    mode: one of MODE_NAMES or BZ_MODE_*.  Weight buffers may be shared
-    between Collision objects through `weights_cache`.
+    mode: one of MODE_NAMES or BZ_MODE_*; schedule: "symmetric" (conjugate
+    symmetry halves the batched sum, the default) or "full".  Weight buffers
+    may be shared between Collision objects through `weights_cache`.
     """
 
-    def __init__(self, meshes, grid_of_cell, mode="batched_f32", weights_cache=None, device="cuda"):
+    def __init__(self, meshes, grid_of_cell, mode="batched_f32", weights_cache=None, device="cuda",
+                 schedule="symmetric"):
         import torch
         self.mode = MODE_NAMES.get(mode, mode)
         self.kind = MODE_WEIGHTS[self.mode]
         self.meshes = [tuple(m) for m in meshes]
         self.grids = [bz_grid_init(*m) for m in self.meshes]
         self.grid_of_cell = np.asarray(grid_of_cell, dtype=np.int32)
-        self.batch = bz_batch_create(self.grid_of_cell, self.grids, self.mode)
+        self.schedule = schedule
+        self.batch = bz_batch_create_ex(self.grid_of_cell, self.grids, self.mode, SCHEDULES[schedule])
         cache = weights_cache if weights_cache is not None else {}
         self.weights = []
         for gi, (g, m) in enumerate(zip(self.grids, self.meshes)):

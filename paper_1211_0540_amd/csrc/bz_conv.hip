@@ -139,6 +139,16 @@ __device__ __forceinline__ void seek_step(int k1, int k2, int s0, int &m1, int &
     m2 = lo2 + s0;
 }
 
+// The pass of an item (wavefront-uniform): its fhat copy, weights and output buffer.
+__device__ __forceinline__ ConvPass pick_pass(const ConvPasses &ps, int pass) {
+    ConvPass c = ps.p[0];
+    if (pass == kPassE1) c = ps.p[kPassE1];
+    if (pass == kPassE2) c = ps.p[kPassE2];
+    if (pass == kPassE3) c = ps.p[kPassE3];
+    if (pass == kPassZ) c = ps.p[kPassZ];
+    return c;
+}
+
 __device__ inline int pop_item(unsigned *counter) {
     unsigned it = 0;
     if (threadIdx.x == 0) it = atomicAdd(counter, 1u);
@@ -150,11 +160,9 @@ __device__ inline int pop_item(unsigned *counter) {
 // ---------------------------------------------------------------------------
 template <int N, int FOLD, int COMP, int WP, int RP, int SPLIT>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(COMP == 2 ? 2 : 1)))
-k_conv_cells_f32(const float2 *__restrict__ fh, const float *__restrict__ W,
-                                                       const long long *__restrict__ row_woff,
-                                                       const int4 *__restrict__ items, int n_items,
-                                                       unsigned *__restrict__ counter, double2 *__restrict__ qh,
-                                                       long long part_stride, const unsigned char *__restrict__ skip) {
+k_conv_cells_f32(const float2 *__restrict__ fh, const int4 *__restrict__ items, int n_items,
+                 unsigned *__restrict__ counter, double2 *__restrict__ qh, long long part_stride,
+                 const unsigned char *__restrict__ skip, const ConvPasses ps) {
     constexpr int h = N / 2, M = N * N * N, PS = 3 * N * N / 4;
     constexpr int CH = (PS * 4 + 1023) / 1024;       // KiB per step of weights
     constexpr int RCH = N * kWave * 8 / 1024;        // KiB per fhat row of 64 cells
@@ -167,20 +175,20 @@ k_conv_cells_f32(const float2 *__restrict__ fh, const float *__restrict__ W,
         const int it = pop_item(counter);
         if (it >= n_items) break;
         const int4 item = items[it];
-        const int g = item.x, r = item.y & 0xffff, part = item.y >> 16, s0 = item.z, s1 = item.w;
+        const int g = item.x, r = item.y & 0xffff, part = (item.y >> 16) & 0xf, s0 = item.z, s1 = item.w;
+        const ConvPass cp = pick_pass(ps, item.y >> 20);
         const int k1 = r / N, k2 = r - k1 * N;
+        double2 *const out = qh + cp.out_off + part * part_stride + (size_t)g * M * kWave + (size_t)r * N * kWave + lane;
         if (skip && skip[g]) {
             // every cell of the group is served elsewhere: leave zeros in this item's outputs
-            double2 *o = qh + part * part_stride + (size_t)g * M * kWave + (size_t)r * N * kWave + lane;
 #pragma unroll
-            for (int t = 0; t < N; ++t) o[t * kWave] = make_double2(0.0, 0.0);
+            for (int t = 0; t < N; ++t) out[t * kWave] = make_double2(0.0, 0.0);
             continue;
         }
-        const float *w = W + row_woff[r] + (long long)s0 * PS;
-        const float2 *G = fh + (size_t)g * M * kWave;   // this group's fhat
+        const float *w = (const float *)cp.w + cp.row_woff[r] + (long long)s0 * PS;
+        const float2 *G = fh + cp.fh_off + (size_t)g * M * kWave;   // this group's fhat (copy of the pass)
         const float2 *F = G + lane;
 
-        double2 *const out = qh + part * part_stride + (size_t)g * M * kWave + (size_t)r * N * kWave + lane;
         float pr[N], pi[N];
         float hr[N], hi[N], lr[N], li[N];
         double dr[N], di[N];
@@ -292,11 +300,10 @@ k_conv_cells_f32(const float2 *__restrict__ fh, const float *__restrict__ W,
 // Batched FP64.
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ void __launch_bounds__(64) k_conv_cells_f64(const double2 *__restrict__ fh, const double *__restrict__ W,
-                                                       const long long *__restrict__ row_woff,
-                                                       const int4 *__restrict__ items, int n_items,
-                                                       unsigned *__restrict__ counter, double2 *__restrict__ qh,
-                                                       long long part_stride, const unsigned char *__restrict__ skip) {
+__global__ void __launch_bounds__(64) k_conv_cells_f64(const double2 *__restrict__ fh, const int4 *__restrict__ items,
+                                                       int n_items, unsigned *__restrict__ counter,
+                                                       double2 *__restrict__ qh, long long part_stride,
+                                                       const unsigned char *__restrict__ skip, const ConvPasses ps) {
     constexpr int h = N / 2, M = N * N * N, PS = 3 * N * N / 4;
     constexpr int CH = (PS * 8 + 1023) / 1024;
     __shared__ __attribute__((aligned(16))) double wbuf[2][CH * 128];
@@ -306,17 +313,18 @@ __global__ void __launch_bounds__(64) k_conv_cells_f64(const double2 *__restrict
         const int it = pop_item(counter);
         if (it >= n_items) break;
         const int4 item = items[it];
-        const int g = item.x, r = item.y & 0xffff, part = item.y >> 16, s0 = item.z, s1 = item.w;
+        const int g = item.x, r = item.y & 0xffff, part = (item.y >> 16) & 0xf, s0 = item.z, s1 = item.w;
+        const ConvPass cp = pick_pass(ps, item.y >> 20);
         const int k1 = r / N, k2 = r - k1 * N;
+        double2 *const out = qh + cp.out_off + part * part_stride + (size_t)g * M * kWave + (size_t)r * N * kWave + lane;
         if (skip && skip[g]) {
             // every cell of the group is served elsewhere: leave zeros in this item's outputs
-            double2 *o = qh + part * part_stride + (size_t)g * M * kWave + (size_t)r * N * kWave + lane;
 #pragma unroll
-            for (int t = 0; t < N; ++t) o[t * kWave] = make_double2(0.0, 0.0);
+            for (int t = 0; t < N; ++t) out[t * kWave] = make_double2(0.0, 0.0);
             continue;
         }
-        const double *w = W + row_woff[r] + (long long)s0 * PS;
-        const double2 *F = fh + (size_t)g * M * kWave + lane;
+        const double *w = (const double *)cp.w + cp.row_woff[r] + (long long)s0 * PS;
+        const double2 *F = fh + cp.fh_off + (size_t)g * M * kWave + lane;
         double pr[N], pi[N];
 #pragma unroll
         for (int t = 0; t < N; ++t) pr[t] = pi[t] = 0.0;
@@ -341,7 +349,6 @@ __global__ void __launch_bounds__(64) k_conv_cells_f64(const double2 *__restrict
             }
             __builtin_amdgcn_s_waitcnt(0);
         }
-        double2 *out = qh + part * part_stride + (size_t)g * M * kWave + (size_t)r * N * kWave + lane;
 #pragma unroll
         for (int t = 0; t < N; ++t) out[t * kWave] = make_double2(pr[t], pi[t]);
     }
@@ -429,8 +436,8 @@ template <int N>
 hipError_t cells_f32_variant(const CellsLaunch &p, unsigned grid, hipStream_t s) {
 #define BZ_CELLS_F32(F, C, WPV, RPV, SP)                                                                    \
     hipLaunchKernelGGL((k_conv_cells_f32<N, F, C, WPV, RPV, SP>), dim3(grid), dim3(64), 0, s,               \
-                       (const float2 *)p.fh, (const float *)p.w, p.row_woff, p.items, p.n_items, p.counter, \
-                       p.qh, p.part_stride, p.skip)
+                       (const float2 *)p.fh, p.items, p.n_items, p.counter, p.qh, p.part_stride, p.skip,     \
+                       p.passes)
     switch (p.variant) {
     case 1: BZ_CELLS_F32(2, 1, 0, 1, 1); break;
     case 2: BZ_CELLS_F32(2, 0, 0, 0, 1); break;
@@ -453,8 +460,8 @@ hipError_t cells_f32_variant(const CellsLaunch &p, unsigned grid, hipStream_t s)
 
 template <int N>
 hipError_t cells_f64_launch(const CellsLaunch &p, unsigned grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_conv_cells_f64<N>), dim3(grid), dim3(64), 0, s, (const double2 *)p.fh,
-                       (const double *)p.w, p.row_woff, p.items, p.n_items, p.counter, p.qh, p.part_stride, p.skip);
+    hipLaunchKernelGGL((k_conv_cells_f64<N>), dim3(grid), dim3(64), 0, s, (const double2 *)p.fh, p.items,
+                       p.n_items, p.counter, p.qh, p.part_stride, p.skip, p.passes);
     return hipGetLastError();
 }
 

@@ -280,10 +280,11 @@ __global__ void __launch_bounds__(256) k_dftg_fwd2(const double2 *__restrict__ S
     line_dft<N>(x, roots, T + off, (size_t)N * kWave, 1.0);
 }
 
-// forward, axis 1: line (k2, k3): T (j1, k2, k3) -> fhat (k1, k2, k3), scaled, in the kernel's precision
+// forward, axis 1: line (k2, k3): T (j1, k2, k3) -> fhat (k1, k2, k3), scaled, in the kernel's precision;
+// with copies = 3 also fhat with the axes ordered (2, 1, 3) and (3, 1, 2), copy_stride elements apart
 template <int N, typename Out>
 __global__ void __launch_bounds__(256) k_dftg_fwd3(const double2 *__restrict__ T, int nc, double scale,
-                                                   Out *__restrict__ fh) {
+                                                   Out *__restrict__ fh, int copies, long long copy_stride) {
     BZ_LINE_SETUP(-1.0)
     const size_t off = (gb + (size_t)line) * kWave + lane;
     double2 x[N];
@@ -308,7 +309,76 @@ __global__ void __launch_bounds__(256) k_dftg_fwd3(const double2 *__restrict__ T
         v.x = live ? re * scale : 0.0;
         v.y = live ? im * scale : 0.0;
         fh[off + (size_t)k * N * N * kWave] = v;
+        if (copies > 1) {
+            const int k2 = line / N, k3 = line - k2 * N;
+            const size_t gl = gb * kWave + lane;
+            fh[copy_stride + gl + ((size_t)(k2 * N + k) * N + k3) * kWave] = v;
+            fh[2 * copy_stride + gl + ((size_t)(k3 * N + k) * N + k2) * kWave] = v;
+        }
     }
+}
+
+// inverse, axis 1, conjugate-symmetric schedule: assemble Qhat(k1, k2, k3) of line (k2, k3) from the
+// passes (qh: nA partial buffers of pass A, then E1, E2, E3, then nA partial buffers of Z), then
+// transform -> S (j1, k2, k3).
+//   direct row (k1, k2):        Qhat = A(k)
+//   derived row, k3 = 0:        Qhat = Z at (0, k1, k2) of the (3, 1, 2) order
+//   derived row, k3 >= 1:       Qhat = conj(A(k') - E(k')) + E(k),   k' = N - k
+// E(k) is the edge sum: E1 at (k1, k2, k3) if k1 < N/2, E2 at (k2, k1, k3) if k2 < N/2,
+// E3 at (k3, k1, k2) if k3 < N/2.
+template <int N>
+__global__ void __launch_bounds__(256) k_dftg_inv1_herm(const double2 *__restrict__ qh, int nA, long long pstride,
+                                                        double2 *__restrict__ S) {
+    BZ_LINE_SETUP(+1.0)
+    constexpr int h = N / 2;
+    const int k2 = line / N, k3 = line - k2 * N;
+    const size_t gl = gb * kWave + lane;
+    const double2 *E1 = qh + (size_t)nA * pstride;
+    const double2 *E2 = E1 + pstride, *E3 = E2 + pstride, *Z = E3 + pstride;  // Z: nA partial buffers
+    auto at = [](int a, int b, int c) { return ((size_t)(a * N + b) * N + c) * kWave; };
+    auto sum_parts = [&](const double2 *base, size_t o) {
+        double2 a = base[gl + o];
+        for (int p = 1; p < nA; ++p) {
+            const double2 b = base[gl + o + (size_t)p * pstride];
+            a.x += b.x;
+            a.y += b.y;
+        }
+        return a;
+    };
+    auto edge = [&](int a, int b, int c) {
+        double2 e = make_double2(0.0, 0.0);
+        if (a < h) {
+            const double2 t = E1[gl + at(a, b, c)];
+            e.x += t.x;
+            e.y += t.y;
+        }
+        if (b < h) {
+            const double2 t = E2[gl + at(b, a, c)];
+            e.x += t.x;
+            e.y += t.y;
+        }
+        if (c < h) {
+            const double2 t = E3[gl + at(c, a, b)];
+            e.x += t.x;
+            e.y += t.y;
+        }
+        return e;
+    };
+    double2 x[N];
+#pragma unroll
+    for (int k1 = 0; k1 < N; ++k1) {
+        if (!herm_derived_row(N, k1, k2)) {
+            x[k1] = sum_parts(qh, at(k1, k2, k3));
+        } else if (k3 == 0) {
+            x[k1] = sum_parts(Z, at(0, k1, k2));
+        } else {
+            const int a = N - k1, b = N - k2, c = N - k3;
+            const double2 m = sum_parts(qh, at(a, b, c));
+            const double2 em = edge(a, b, c), ek = edge(k1, k2, k3);
+            x[k1] = make_double2((m.x - em.x) + ek.x, (em.y - m.y) + ek.y);
+        }
+    }
+    line_dft<N>(x, roots, S + gl + (size_t)line * kWave, (size_t)N * N * kWave, 1.0);
 }
 
 // inverse, axis 1: line (k2, k3): sum of the partial buffers (k1, k2, k3) -> S (j1, k2, k3)
@@ -374,28 +444,35 @@ __global__ void __launch_bounds__(256) k_dftg_inv3(const double2 *__restrict__ T
 
 template <int N>
 hipError_t grouped_forward(double L, int nc, const double *f, const long long *f_off, double2 *S, double2 *T,
-                           void *fh, bool f32, hipStream_t s) {
+                           void *fh, bool f32, int copies, hipStream_t s) {
     const int groups = (nc + kWave - 1) / kWave;
     const dim3 grid(N * N / 4, groups);
     const double dv = 2.0 * L / N;
     const double scale = pow(2.0 * kPi, -1.5) * dv * dv * dv;
+    const long long cstride = (long long)groups * N * N * N * kWave;
     hipLaunchKernelGGL(k_dftg_fwd1<N>, grid, dim3(256), 0, s, f, f_off, nc, S);
     hipLaunchKernelGGL(k_dftg_fwd2<N>, grid, dim3(256), 0, s, S, T);
     if (f32)
-        hipLaunchKernelGGL((k_dftg_fwd3<N, float2>), grid, dim3(256), 0, s, T, nc, scale, (float2 *)fh);
+        hipLaunchKernelGGL((k_dftg_fwd3<N, float2>), grid, dim3(256), 0, s, T, nc, scale, (float2 *)fh, copies,
+                           cstride);
     else
-        hipLaunchKernelGGL((k_dftg_fwd3<N, double2>), grid, dim3(256), 0, s, T, nc, scale, (double2 *)fh);
+        hipLaunchKernelGGL((k_dftg_fwd3<N, double2>), grid, dim3(256), 0, s, T, nc, scale, (double2 *)fh, copies,
+                           cstride);
     return hipGetLastError();
 }
 
 template <int N>
-hipError_t grouped_inverse(double L, int nc, const double2 *qh, int nparts, long long pstride, double2 *S,
-                           double2 *T, double *qt, const long long *q_off, hipStream_t s) {
+hipError_t grouped_inverse(double L, int nc, const double2 *qh, int nparts, long long pstride,
+                           const HermAssembly &herm, double2 *S, double2 *T, double *qt, const long long *q_off,
+                           hipStream_t s) {
     const int groups = (nc + kWave - 1) / kWave;
     const dim3 grid(N * N / 4, groups);
     const double dz = kPi / L;
     const double scale = pow(2.0 * kPi, -1.5) * dz * dz * dz;
-    hipLaunchKernelGGL(k_dftg_inv1<N>, grid, dim3(256), 0, s, qh, nparts, pstride, S);
+    if (herm.on)
+        hipLaunchKernelGGL(k_dftg_inv1_herm<N>, grid, dim3(256), 0, s, qh, herm.nA, pstride, S);
+    else
+        hipLaunchKernelGGL(k_dftg_inv1<N>, grid, dim3(256), 0, s, qh, nparts, pstride, S);
     hipLaunchKernelGGL(k_dftg_inv2<N>, grid, dim3(256), 0, s, S, T);
     hipLaunchKernelGGL(k_dftg_inv3<N>, grid, dim3(256), 0, s, T, nc, scale, qt, q_off);
     return hipGetLastError();
@@ -406,10 +483,11 @@ hipError_t grouped_inverse(double L, int nc, const double2 *qh, int nparts, long
 #define BZ_FOR_EACH_N(X) X(8) X(12) X(16) X(20) X(24) X(28) X(32)
 
 hipError_t launch_dft_forward_grouped(int N, double L, int ncells, const double *f, const long long *d_f_off,
-                                      double2 *S, double2 *T, void *fh, bool out_f32, hipStream_t s) {
+                                      double2 *S, double2 *T, void *fh, bool out_f32, int copies, hipStream_t s) {
     if (ncells <= 0) return hipSuccess;
+    if (copies != 1 && copies != 3) return hipErrorInvalidValue;
 #define CASE(NN) \
-    case NN: return grouped_forward<NN>(L, ncells, f, d_f_off, S, T, fh, out_f32, s);
+    case NN: return grouped_forward<NN>(L, ncells, f, d_f_off, S, T, fh, out_f32, copies, s);
     switch (N) {
         BZ_FOR_EACH_N(CASE)
     default:
@@ -419,10 +497,11 @@ hipError_t launch_dft_forward_grouped(int N, double L, int ncells, const double 
 }
 
 hipError_t launch_dft_inverse_grouped(int N, double L, int ncells, const double2 *qh, int nparts, long long pstride,
-                                      double2 *S, double2 *T, double *qt, const long long *d_q_off, hipStream_t s) {
+                                      const HermAssembly &herm, double2 *S, double2 *T, double *qt,
+                                      const long long *d_q_off, hipStream_t s) {
     if (ncells <= 0) return hipSuccess;
 #define CASE(NN) \
-    case NN: return grouped_inverse<NN>(L, ncells, qh, nparts, pstride, S, T, qt, d_q_off, s);
+    case NN: return grouped_inverse<NN>(L, ncells, qh, nparts, pstride, herm, S, T, qt, d_q_off, s);
     switch (N) {
         BZ_FOR_EACH_N(CASE)
     default:

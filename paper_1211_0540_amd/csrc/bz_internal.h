@@ -75,6 +75,48 @@ __host__ __device__ inline int cells_steps(int N, int k1, int k2) {
 }
 
 // ---------------------------------------------------------------------------
+// Conjugate-symmetric ("halved") batched schedule.
+//
+// f is real, so fhat(-zeta) = conj fhat(zeta): on the mesh, index k maps to
+// N - k on every axis, except the planes k_d = 0 (zeta_d = -N dzeta / 2),
+// whose mirror lies off the mesh.  Split the sum of an output k into interior
+// pairs (every coordinate of m and j in [1, N)) and edge pairs (some
+// coordinate of m or j equal to 0).  The weight is invariant under
+// (k, m) -> (N - k, N - m), so the interior sum I satisfies
+// I(N - k) = conj I(k) whenever every k_d >= 1, and
+//   Qhat(N - k) = conj(Qhat(k) - E(k)) + E(N - k)
+// with E the edge sum.  The library therefore evaluates
+//   pass A : whole rows (k1, k2) of the "direct" half, every step;
+//   pass E1: edge pairs with m1 = 0 or j1 = 0 (in the schedule, the steps
+//            with m1 = 0 of the rows with k1 < N/2), every row;
+//   pass E2: edge pairs with m2 = 0 or j2 = 0 and no axis-1 edge: the same
+//            step block on a copy of fhat with axes 1 and 2 exchanged, minus
+//            its first and last step (m1 = 0, j1 = 0);
+//   pass E3: edge pairs with m3 = 0 or j3 = 0 and no axis-1 or axis-2 edge:
+//            the block on a copy with axes ordered (3, 1, 2), minus its end
+//            steps, with the weights of the inner-axis edge terms set to 0
+//            (a separate weight stream);
+//   pass Z : the outputs k3 = 0 of the "derived" rows (no mirror), as whole
+//            rows (0, k1) of the (3, 1, 2) copy;
+// and the first inverse-transform pass assembles Qhat.  The weight stream of
+// a row serves every axis order because W depends on k and m only through
+// |k - N/2|^2, |2m - k - N/2|^2 and |m - N/2|^2.
+// ---------------------------------------------------------------------------
+// rows (k1, k2) whose outputs with k3 >= 1 are mirrors of the direct rows
+__host__ __device__ inline bool herm_derived_row(int N, int k1, int k2) {
+    const int h = N / 2;
+    return k1 >= 1 && k2 >= 1 && (k1 > h || (k1 == h && k2 > h));
+}
+enum ConvPassId { kPassA = 0, kPassE1 = 1, kPassE2 = 2, kPassE3 = 3, kPassZ = 4, kPasses = 5 };
+// Assembly of Qhat from the passes of the conjugate-symmetric schedule, done by
+// the first inverse-transform pass: buffers [0, nA) hold pass A's partial sums,
+// then E1, E2, E3, then nA partial sums of pass Z, each part_stride apart.
+struct HermAssembly {
+    bool on;
+    int nA;
+};
+
+// ---------------------------------------------------------------------------
 // Plain ("lane = output") schedule, one cell at a time.
 //
 // A block holds R consecutive rows k2 = kb R .. kb R + R - 1 of one k1 plane,
@@ -101,6 +143,10 @@ struct Schedule {
     std::vector<long long> row_woff;
     std::vector<int> row_steps;
     long long cells_weights = 0;
+    // edge-pass weights of pass E3 (rows a < N/2: the m1 = 0 block of row (a, b),
+    // inner edge terms zeroed), offsets relative to the start of that stream
+    std::vector<long long> e3_woff;
+    long long e3_weights = 0;
     // plain: N * (N / R) blocks
     std::vector<long long> blk_woff;
     long long plain_weights = 0;
@@ -143,10 +189,13 @@ hipError_t launch_expand_plain(int N, const double *dT, int qstride, double scal
 // batched paths: cell-interleaved groups of 64; S and T are scratch buffers of
 // groups * N^3 * 64 double2 each (T may be the first partial buffer of qh for
 // the inverse, which reads qh only in its first pass)
+// With `copies` = 3 the last pass also writes fhat with the axes ordered
+// (2, 1, 3) and (3, 1, 2) after the first copy, G * N^3 * 64 elements apart.
 hipError_t launch_dft_forward_grouped(int N, double L, int ncells, const double *f, const long long *d_f_off,
-                                      double2 *S, double2 *T, void *fh, bool out_f32, hipStream_t s);
+                                      double2 *S, double2 *T, void *fh, bool out_f32, int copies, hipStream_t s);
 hipError_t launch_dft_inverse_grouped(int N, double L, int ncells, const double2 *qh, int nparts, long long pstride,
-                                      double2 *S, double2 *T, double *qt, const long long *d_q_off, hipStream_t s);
+                                      const HermAssembly &herm, double2 *S, double2 *T, double *qt,
+                                      const long long *d_q_off, hipStream_t s);
 hipError_t launch_dft_forward(int N, double L, int ncells, const double *f, const long long *d_f_off,
                               double2 *scratch, void *out, bool out_f32, const long long *d_o_base,
                               long long o_stride, hipStream_t s);
@@ -160,20 +209,34 @@ hipError_t launch_dft_inverse(int N, double L, int ncells, const double2 *in, co
 // step (1 KiB granules) stays inside the buffer.
 constexpr size_t kWeightPadBytes = 16384;
 
-// Batched convolution over the (group, row, step range) items of one mesh.
+// One pass of the batched convolution: where its fhat copy, weights and
+// output buffer are.  Offsets are in complex elements from fh and qh.
+struct ConvPass {
+    long long fh_off;            // fhat copy read by the pass
+    long long out_off;           // first output buffer written by the pass
+    const void *w;               // weight stream
+    const long long *row_woff;   // device, N*N offsets of the rows in w (elements)
+};
+struct ConvPasses {
+    ConvPass p[kPasses];
+};
+
+// Batched convolution over the (group, row | part << 16 | pass << 20, first
+// step, end step) items of one mesh.
 struct CellsLaunch {
     int N;
-    const void *fh;              // [G][N^3][64] float2 or double2
-    const void *w;               // batched schedule weights
-    const long long *row_woff;   // device, N*N
-    const int4 *items;           // device, (group, row | part << 16, first step, end step), longest first
+    const void *fh;              // [copies][G][N^3][64] float2 or double2
+    const int4 *items;           // device, longest first
     int n_items;
     unsigned *counter;           // device, zeroed by the launcher's fill kernel
-    double2 *qh;                 // [parts][G][N^3][64]
-    long long part_stride;       // complex elements between partial-sum buffers
+    double2 *qh;                 // [buffers][G][N^3][64]
+    long long part_stride;       // complex elements between output buffers
     int variant;                 // tuning variant
     const unsigned char *skip;   // device, per group: 1 = outputs not needed (may be NULL)
+    ConvPasses passes;
 };
+hipError_t launch_build_e3(int N, const long long *d_row_woff, const long long *d_e3_woff, const void *w_main,
+                           void *w_e3, bool f64, hipStream_t s);
 // batched FP32 variants: count, and a rank that grows with the accuracy of the
 // accumulation (more interleaved partials, then shorter fold interval)
 int conv_variant_count();

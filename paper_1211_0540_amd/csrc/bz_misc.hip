@@ -219,6 +219,47 @@ hipError_t launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Weights of edge pass E3 of the conjugate-symmetric schedule: for each row
+// (a, b) with a < N/2, the block of steps with m1 = 0 copied from the main
+// stream, with the terms whose inner partner sits on an edge plane (k3 < N/2
+// and m3 = 0 or j3 = 0, i.e. m3 = k3 + N/2) set to zero.
+template <typename W>
+__global__ void __launch_bounds__(256) k_build_e3(int N, const long long *__restrict__ row_woff,
+                                                  const long long *__restrict__ e3_woff, const W *__restrict__ w,
+                                                  W *__restrict__ e3) {
+    const int h = N / 2;
+    const int r = blockIdx.x;  // a * N + b, a < N/2
+    const int b = r % N;
+    const int PS = pairs_per_step(N);
+    const long long n = (long long)axis_cnt(N, b) * PS;
+    const W *src = w + row_woff[r];
+    W *dst = e3 + e3_woff[r];
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+        const int t = (int)(i % PS);
+        int k3 = 0, base = 0;
+        for (;; ++k3) {
+            const int cnt = axis_cnt(N, k3);
+            if (t < base + cnt) break;
+            base += cnt;
+        }
+        const int m3 = axis_lo(N, k3) + (t - base);
+        const bool edge = k3 < h && (m3 == 0 || m3 == k3 + h);
+        dst[i] = edge ? (W)0 : src[i];
+    }
+}
+
+hipError_t launch_build_e3(int N, const long long *d_row_woff, const long long *d_e3_woff, const void *w_main,
+                           void *w_e3, bool f64, hipStream_t s) {
+    const dim3 grid(N / 2 * N);
+    if (f64)
+        hipLaunchKernelGGL(k_build_e3<double>, grid, dim3(256), 0, s, N, d_row_woff, d_e3_woff,
+                           (const double *)w_main, (double *)w_e3);
+    else
+        hipLaunchKernelGGL(k_build_e3<float>, grid, dim3(256), 0, s, N, d_row_woff, d_e3_woff,
+                           (const float *)w_main, (float *)w_e3);
+    return hipGetLastError();
+}
+
 hipError_t launch_expand_cells(int N, const double *dT, int qstride, double scale, const long long *d_row_woff,
                                void *d_w, bool f64, hipStream_t s) {
     if (f64)

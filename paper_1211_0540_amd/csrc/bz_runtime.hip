@@ -158,6 +158,14 @@ static void build_schedules(bz_grid_s *g) {
         off += (long long)s.row_steps[r] * pairs_per_step(N);
     }
     s.cells_weights = off;
+    // pass E3 of the conjugate-symmetric schedule: the m1 = 0 block of rows (a < N/2, b)
+    s.e3_woff.assign(N * N, 0);
+    off = 0;
+    for (int r = 0; r < N / 2 * N; ++r) {
+        s.e3_woff[r] = off;
+        off += (long long)axis_cnt(N, r % N) * pairs_per_step(N);
+    }
+    s.e3_weights = off;
     const int R = plain_rows(N), NB = N / R, LN = R * N;
     s.blk_woff.resize(N * NB);
     off = 0;
@@ -170,6 +178,11 @@ static void build_schedules(bz_grid_s *g) {
 
 static size_t kind_elem(int kind) {
     return (kind == BZ_W_BATCHED_F64 || kind == BZ_W_PLAIN_F64) ? 8 : 4;
+}
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+// byte offset of the pass-E3 stream in a batched weight buffer (after the main stream and its pad)
+static size_t e3_base_bytes(const bz_grid_s *g, size_t elem) {
+    return align256((size_t)g->sched.cells_weights * elem + kWeightPadBytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -188,9 +201,12 @@ struct Part {
     long long *d_row_woff = nullptr;
     long long *d_blk_woff = nullptr;
     long long *d_zero = nullptr;     // single 0 (plain: base of the one cell)
+    long long *d_e3_woff = nullptr;  // pass-E3 row offsets (conjugate-symmetric schedule)
     int4 *d_items = nullptr;
     int n_items = 0;
-    int parts = 1;                   // partial-sum buffers of the batched schedule
+    bool herm = false;               // conjugate-symmetric (halved) batched schedule
+    int parts = 1;                   // partial-sum buffers of pass A (and of pass Z) of the batched schedule
+    int qbufs = 1;                   // output buffers in qh
     int variant = 0;                 // convolution kernel variant
     std::vector<long long> f_off;    // host copy
     // workspace offsets (bytes)
@@ -228,8 +244,6 @@ static int mode_wkind(int mode) {
     default: return BZ_W_PLAIN_F64;
     }
 }
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
 static int plain_split_for(int N) {
     // enough partial sums to give >= ~2048 single-wave blocks, bounded by the m1 band
     const int nb = N * (N / plain_rows(N));
@@ -336,7 +350,8 @@ size_t bz_weights_bytes(bz_grid g, int kind) {
     if (!g) return 0;
     switch (kind) {
     case BZ_W_BATCHED_F32:
-    case BZ_W_BATCHED_F64: return (size_t)g->sched.cells_weights * kind_elem(kind) + kWeightPadBytes;
+    case BZ_W_BATCHED_F64:
+        return e3_base_bytes(g, kind_elem(kind)) + (size_t)g->sched.e3_weights * kind_elem(kind) + kWeightPadBytes;
     case BZ_W_PLAIN_F32:
     case BZ_W_PLAIN_F64: return (size_t)g->sched.plain_weights * kind_elem(kind);
     default: return 0;
@@ -356,18 +371,26 @@ bz_status bz_weights(bz_grid g, int kind, void *d_w, size_t bytes, void *stream)
     const std::vector<long long> &off = cells ? g->sched.row_woff : g->sched.blk_woff;
     double *dT = nullptr;
     long long *dOff = nullptr;
+    const size_t noff = off.size() + (cells ? g->sched.e3_woff.size() : 0);
     BZ_HIP(hipMalloc(&dT, T.size() * sizeof(double)), "bz_weights: hipMalloc table");
-    hipError_t e = hipMalloc(&dOff, off.size() * sizeof(long long));
+    hipError_t e = hipMalloc(&dOff, noff * sizeof(long long));
     if (e != hipSuccess) {
         (void)hipFree(dT);
         return hip_fail(e, "bz_weights: hipMalloc offsets");
     }
     e = hipMemcpyAsync(dT, T.data(), T.size() * sizeof(double), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dOff, off.data(), off.size() * sizeof(long long), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && cells)
+        e = hipMemcpyAsync(dOff + off.size(), g->sched.e3_woff.data(), g->sched.e3_woff.size() * sizeof(long long),
+                           hipMemcpyHostToDevice, s);
     const bool f64 = kind_elem(kind) == 8;
     if (e == hipSuccess)
         e = cells ? launch_expand_cells(g->N, dT, qs, weight_scale(g), dOff, d_w, f64, s)
                   : launch_expand_plain(g->N, dT, qs, weight_scale(g), dOff, d_w, f64, s);
+    // the pass-E3 stream is derived from the main stream
+    if (e == hipSuccess && cells)
+        e = launch_build_e3(g->N, dOff, dOff + off.size(), d_w, (char *)d_w + e3_base_bytes(g, kind_elem(kind)), f64,
+                            s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(dT);
     (void)hipFree(dOff);
@@ -377,7 +400,13 @@ bz_status bz_weights(bz_grid g, int kind, void *d_w, size_t bytes, void *stream)
 
 bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids, const bz_grid *grids, int mode,
                           bz_batch *out) {
+    return bz_batch_create_ex(n_cells, grid_of_cell, n_grids, grids, mode, 0, out);
+}
+
+bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_grids, const bz_grid *grids, int mode,
+                             int flags, bz_batch *out) {
     if (!out) return fail(BZ_EINVAL, "bz_batch_create: out is NULL");
+    if (flags & ~BZ_BATCH_FULL_SUM) return fail(BZ_EINVAL, "bz_batch_create: unknown flags");
     *out = nullptr;
     if (n_cells < 1 || !grid_of_cell || n_grids < 1 || !grids)
         return fail(BZ_EINVAL, "bz_batch_create: empty batch or NULL argument");
@@ -427,7 +456,7 @@ bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids,
         std::memcpy(host.data() + o, src, bytes);
         return o;
     };
-    struct Offs { size_t f_off, fh_base, row, blk, zero, items; };
+    struct Offs { size_t f_off, fh_base, row, blk, zero, items, e3; };
     std::vector<Offs> offs;
     size_t ws = 0, scratch = 0;
     for (Part &p : b->parts) {
@@ -449,32 +478,54 @@ bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids,
         if (bat) {
             // split every row's steps into `parts` contiguous ranges so that there are
             // enough work items to fill the chip; order longest first
-            const long long rows = (long long)p.groups * N * N;
-            int parts = (int)((8192 + rows - 1) / rows);
+            const int h = N / 2;
+            p.herm = !(flags & BZ_BATCH_FULL_SUM);
+            long long rows = 0;
+            for (int r = 0; r < N * N; ++r)
+                if (!p.herm || !herm_derived_row(N, r / N, r % N)) rows += p.groups;
+            int parts = (int)(((p.herm ? 4096 : 8192) + rows - 1) / rows);
             parts = std::max(1, std::min(parts, 8));
             p.parts = parts;
+            p.qbufs = p.herm ? 2 * parts + 3 : parts;
             std::vector<int4> items;
-            items.reserve((size_t)rows * parts);
             const std::vector<int> &st = p.g->sched.row_steps;
-            for (int gq = 0; gq < p.groups; ++gq)
+            // every item writes its whole output slot, so an empty step range still
+            // leaves zeros where the assembly reads
+            auto item = [&](int gq, int r, int q, int pass, int a, int e) {
+                items.push_back(make_int4(gq, r | (q << 16) | (pass << 20), a, e));
+            };
+            auto split = [&](int gq, int r, int pass) {
+                for (int q = 0; q < parts; ++q)
+                    item(gq, r, q, pass, (int)((long long)st[r] * q / parts), (int)((long long)st[r] * (q + 1) / parts));
+            };
+            for (int gq = 0; gq < p.groups; ++gq) {
                 for (int r = 0; r < N * N; ++r)
-                    for (int q = 0; q < parts; ++q) {
-                        const int a = (int)((long long)st[r] * q / parts), e = (int)((long long)st[r] * (q + 1) / parts);
-                        items.push_back(make_int4(gq, r | (q << 16), a, e));
+                    if (!p.herm || !herm_derived_row(N, r / N, r % N)) split(gq, r, kPassA);
+                if (!p.herm) continue;
+                for (int a = 0; a < h; ++a)
+                    for (int b = 0; b < N; ++b) {
+                        // the m1 = 0 block of row (a, b) is its first axis_cnt(b) steps
+                        const int c = axis_cnt(N, b), cut = b < h ? 1 : 0;
+                        item(gq, a * N + b, 0, kPassE1, 0, c);
+                        item(gq, a * N + b, 0, kPassE2, cut, c - cut);
+                        item(gq, a * N + b, 0, kPassE3, cut, c - cut);
                     }
+                for (int b = h; b < N; ++b) split(gq, b, kPassZ);
+            }
             std::stable_sort(items.begin(), items.end(),
                              [](const int4 &x, const int4 &y) { return x.w - x.z > y.w - y.z; });
             p.n_items = (int)items.size();
             o.items = put(items.data(), items.size() * sizeof(int4));
+            o.e3 = put(p.g->sched.e3_woff.data(), p.g->sched.e3_woff.size() * sizeof(long long));
         }
         offs.push_back(o);
         // workspace: fhat, qhat, counter
         const size_t cs = f64 ? 16 : 8;
         if (bat) {
             p.ws_fh = ws;
-            ws = align256(ws + (size_t)p.groups * M * kWave * cs);
+            ws = align256(ws + (size_t)(p.herm ? 3 : 1) * p.groups * M * kWave * cs);
             p.ws_qh = ws;
-            ws = align256(ws + (size_t)p.parts * p.groups * M * kWave * 16);
+            ws = align256(ws + (size_t)p.qbufs * p.groups * M * kWave * 16);
         } else {
             const int sp = plain_split_for(N);
             p.ws_fh = ws;
@@ -510,6 +561,7 @@ bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids,
         p.d_row_woff = (long long *)(base + offs[i].row);
         p.d_blk_woff = (long long *)(base + offs[i].blk);
         p.d_items = bat ? (int4 *)(base + offs[i].items) : nullptr;
+        p.d_e3_woff = bat ? (long long *)(base + offs[i].e3) : nullptr;
     }
     *out = b.release();
     return BZ_OK;
@@ -683,11 +735,17 @@ static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void 
         if (batched(b->mode)) {
             const int nc = (int)p.cells.size();
             // the first partial buffer of qh serves as the second scratch buffer of the transforms
-            BZ_HIP(launch_dft_forward_grouped(N, p.g->L, nc, d_f, p.d_f_off, scratch, qh, fh, !f64, s),
+            BZ_HIP(launch_dft_forward_grouped(N, p.g->L, nc, d_f, p.d_f_off, scratch, qh, fh, !f64, p.herm ? 3 : 1, s),
                    "forward transform");
-            const long long pstride = (long long)p.groups * M * kWave;
-            CellsLaunch cl{N, fh, p.w, p.d_row_woff, p.d_items, p.n_items, (unsigned *)(ws + p.ws_counter), qh,
-                           pstride, 0, skip};
+            const long long pstride = (long long)p.groups * M * kWave;  // one copy of fhat, one output buffer
+            CellsLaunch cl{N, fh, p.d_items, p.n_items, (unsigned *)(ws + p.ws_counter), qh, pstride, 0, skip, {}};
+            const void *w_e3 = (const char *)p.w + e3_base_bytes(p.g, f64 ? 8 : 4);
+            const long long P = p.parts;
+            cl.passes.p[kPassA] = ConvPass{0, 0, p.w, p.d_row_woff};
+            cl.passes.p[kPassE1] = ConvPass{0, P * pstride, p.w, p.d_row_woff};
+            cl.passes.p[kPassE2] = ConvPass{pstride, (P + 1) * pstride, p.w, p.d_row_woff};
+            cl.passes.p[kPassE3] = ConvPass{2 * pstride, (P + 2) * pstride, w_e3, p.d_e3_woff};
+            cl.passes.p[kPassZ] = ConvPass{2 * pstride, (P + 3) * pstride, p.w, p.d_row_woff};
             std::pair<hipEvent_t, hipEvent_t> ev{};
             if (b->timing) {
                 if (!timer_pair(b, ev)) return fail(BZ_EDEVICE, "bz_collide_batch: hipEventCreate failed");
@@ -696,7 +754,9 @@ static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void 
             cl.variant = p.variant;
             BZ_HIP(launch_conv_cells(cl, f64, s), "batched convolution");
             if (b->timing) BZ_HIP(hipEventRecord(ev.second, s), "timer stop");
-            BZ_HIP(launch_dft_inverse_grouped(N, p.g->L, nc, qh, p.parts, pstride, scratch, qh, d_Qt, p.d_f_off, s),
+            const HermAssembly herm{p.herm, p.parts};
+            BZ_HIP(launch_dft_inverse_grouped(N, p.g->L, nc, qh, p.parts, pstride, herm, scratch, qh, d_Qt, p.d_f_off,
+                                              s),
                    "inverse transform");
         } else {
             const int sp = plain_split_for(N);

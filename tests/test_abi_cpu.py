@@ -68,10 +68,15 @@ def test_batched_schedule_visits_each_unordered_pair_once(N):
                 for m2 in range(lo2, hi2 + 1):
                     if (m1, m2) <= (k1 + h - m1, k2 + h - m2):
                         steps += 1
+    # the buffer also holds the edge-pass stream of the conjugate-symmetric schedule:
+    # the m1 = 0 block (one step per m2 of the band) of every row (k1 < N/2, k2)
+    e3_steps = h * sum(_axis_range(N, k)[1] - _axis_range(N, k)[0] + 1 for k in range(N))
+    up = lambda x: (x + 255) // 256 * 256
     g = bz.bz_grid_init(N, 6.0, 1.0)
     try:
-        assert bz.bz_weights_bytes(g, bz.BZ_W_BATCHED_F32) == steps * (3 * N * N // 4) * 4 + 16384
-        assert bz.bz_weights_bytes(g, bz.BZ_W_BATCHED_F64) == steps * (3 * N * N // 4) * 8 + 16384
+        for kind, el in ((bz.BZ_W_BATCHED_F32, 4), (bz.BZ_W_BATCHED_F64, 8)):
+            main = up(steps * (3 * N * N // 4) * el + 16384)
+            assert bz.bz_weights_bytes(g, kind) == main + e3_steps * (3 * N * N // 4) * el + 16384
         # the visited slots cover every unordered pair: (P + D) / 2 <= slots
         P = (3 * N * N // 4) ** 3
         assert 2 * steps * (3 * N * N // 4) >= P
@@ -106,6 +111,16 @@ def test_batch_validation_errors_before_device_work():
             with pytest.raises(bz.BzError) as e:
                 bz.bz_batch_create(goc, [g], mode)
             assert e.value.status == bz.BZ_EINVAL
+    finally:
+        bz.bz_grid_free(g)
+
+
+def test_batch_flags_are_validated():
+    g = bz.bz_grid_init(8, 4.0, 1.0)
+    try:
+        with pytest.raises(bz.BzError) as e:
+            bz.bz_batch_create_ex([0], [g], bz.BZ_MODE_BATCHED_F32, 6)
+        assert e.value.status == bz.BZ_EINVAL
     finally:
         bz.bz_grid_free(g)
 

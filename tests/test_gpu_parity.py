@@ -42,8 +42,8 @@ def oracle_for(N, L, lam):
 _WCACHE = {}
 
 
-def run(meshes, goc, cells, mode, dev, project=True):
-    c = bz.Collision(meshes, goc, mode, weights_cache=_WCACHE)
+def run(meshes, goc, cells, mode, dev, project=True, schedule="symmetric"):
+    c = bz.Collision(meshes, goc, mode, weights_cache=_WCACHE, schedule=schedule)
     f = torch.from_numpy(c.pack(cells)).to(dev)
     qt = c.collide(f)
     q = qt.clone()
@@ -90,13 +90,14 @@ def test_mixture_cell_fp64(dev, mode):
     assert_conserved(q, N, L)
 
 
-@pytest.mark.parametrize("mode", ["plain_f64", "batched_f64"])
-def test_ragged_batch_fp64_hard_spheres(dev, mode):
+@pytest.mark.parametrize("mode,schedule", [("plain_f64", "full"), ("batched_f64", "symmetric"),
+                                           ("batched_f64", "full")])
+def test_ragged_batch_fp64_hard_spheres(dev, mode, schedule):
     """70 cells on N=12 (one full wavefront group and a ragged tail of 6)."""
     N, L, lam = 12, 5.0, 1.0
     n = 70 if mode == "batched_f64" else 5
     cells = list(W.random_smooth_cells(n, N, L, seed=3, umax=0.7))
-    qts, qs = run([(N, L, lam)], [0] * n, cells, mode, dev)
+    qts, qs = run([(N, L, lam)], [0] * n, cells, mode, dev, schedule=schedule)
     o = oracle_for(N, L, lam)
     for i in range(n):
         qt_o, q_o, _, _ = o.collide(cells[i])
@@ -107,11 +108,12 @@ def test_ragged_batch_fp64_hard_spheres(dev, mode):
 # ---------------------------------------------------------------------------
 # FP32 batched path with compensated accumulation
 # ---------------------------------------------------------------------------
-def test_mixture_cell_fp32_batched(dev):
+@pytest.mark.parametrize("schedule", ["symmetric", "full"])
+def test_mixture_cell_fp32_batched(dev, schedule):
     N, L, lam = 16, 6.0, 0.0
     f = W.single_cell_mixture(N, L)
     _, q_o, _, _ = oracle_for(N, L, lam).collide(f)
-    _, (q,) = run([(N, L, lam)], [0], [f], "batched_f32", dev)
+    _, (q,) = run([(N, L, lam)], [0], [f], "batched_f32", dev, schedule=schedule)
     assert rel_l2(q, q_o) < 1e-5
     assert_conserved(q, N, L)
 
@@ -134,6 +136,40 @@ def test_relaxation_cell_n32_fp64_plain(dev):
     (qt,), (q,) = run([(N, L, lam)], [0], [f], "plain_f64", dev)
     assert max_rel(qt, qt_o) < 1e-12
     assert max_rel(q, q_o) < 1e-12
+
+
+@pytest.mark.parametrize("N,L,n", [(8, 4.0, 3), (12, 5.0, 70), (16, 6.0, 65), (20, 6.0, 2)])
+def test_symmetric_schedule_equals_full_sum_fp64(dev, N, L, n):
+    """The conjugate-symmetric schedule (half the rows, edge passes, mirrored assembly)
+    gives the full FP64 sum to rounding, for every cell and output, on several meshes and
+    ragged groups; sampled cells also against the oracle."""
+    lam = 1.0
+    cells = list(W.random_smooth_cells(n, N, L, seed=N, umax=1.0))
+    full, _ = run([(N, L, lam)], [0] * n, cells, "batched_f64", dev, project=False, schedule="full")
+    sym, _ = run([(N, L, lam)], [0] * n, cells, "batched_f64", dev, project=False, schedule="symmetric")
+    for i in range(n):
+        assert max_rel(sym[i], full[i]) < 1e-12, i
+    o = oracle_for(N, L, lam)
+    for i in sorted({0, n // 2, n - 1}):
+        qt_o, _, _, _ = o.collide(cells[i])
+        assert max_rel(sym[i], qt_o) < 1e-12, i
+
+
+def test_symmetric_schedule_fp32_mixed_meshes(dev):
+    """FP32, two meshes in one batch (N=16 ragged, N=24): both schedules against the oracle."""
+    meshes = [(16, 6.0, 1.0), (24, 7.0, 1.0)]
+    c16 = list(W.random_smooth_cells(67, 16, 6.0, seed=4, umax=1.2))
+    c24 = list(W.random_smooth_cells(3, 24, 7.0, seed=5, umax=1.2))
+    cells, goc = c16 + c24, [0] * 67 + [1] * 3
+    _, q_full = run(meshes, goc, cells, "batched_f32", dev, schedule="full")
+    _, q_sym = run(meshes, goc, cells, "batched_f32", dev, schedule="symmetric")
+    for i in (0, 40, 64, 66, 67, 69):
+        N, L = (16, 6.0) if i < 67 else (24, 7.0)
+        _, q_o, _, _ = oracle_for(N, L, 1.0).collide(cells[i])
+        tol = max(1e-5, 8 * U32 * _kappa(cells[i], N, L, 1.0))
+        assert rel_l2(q_sym[i], q_o) < tol, i
+        assert rel_l2(q_full[i], q_o) < tol, i
+        assert_conserved(q_sym[i], N, L)
 
 
 def _kappa(f, N, L, lam):
