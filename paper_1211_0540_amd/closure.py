@@ -50,6 +50,7 @@ class ClosureModel:
         self.xs, self.ys = [], []
         self.step = 0
         self.history = []
+        self.val_idx = torch.zeros(0, dtype=torch.long)
         self.wcache = {}
 
     # ----------------------------------------------------------------- data
@@ -135,23 +136,30 @@ class ClosureModel:
         return sum(int(a.shape[0]) for a in self.xs)
 
     # ---------------------------------------------------------------- train
-    def fit(self, steps=1000, batch=256, lr=1e-3, seed=0, lr_min_frac=0.05, calibrate=True):
+    def fit(self, steps=1000, batch=256, lr=1e-3, seed=0, lr_min_frac=0.05, calibrate=True, holdout=0.1):
+        """Adam on the MSE of the normalised targets, cosine learning-rate decay.  A
+        random `holdout` fraction of the rows is kept out of training for
+        `validation_error`."""
         X = torch.cat(self.xs) if len(self.xs) > 1 else self.xs[0]
         Y = torch.cat(self.ys) if len(self.ys) > 1 else self.ys[0]
         self.xs, self.ys = [X], [Y]
-        S = X.shape[0]
+        gen = torch.Generator(device="cpu").manual_seed(seed)
+        order = torch.randperm(X.shape[0], generator=gen)
+        nval = int(X.shape[0] * holdout) if holdout > 0 else 0
+        self.val_idx = order[:nval].to(self.dev)
+        train_idx = order[nval:]
+        S = train_idx.numel()
         batch = max(32, min(batch, (S // 32) * 32))
         work = torch.zeros(bz.bz_mlp_workspace_bytes(self.net, batch), dtype=torch.uint8, device=self.dev)
         grad = torch.zeros(bz.bz_mlp_param_count(self.net), dtype=torch.float32, device=self.dev)
         loss = torch.zeros(1, dtype=torch.float32, device=self.dev)
-        gen = torch.Generator(device="cpu").manual_seed(seed)
         perm = torch.randperm(S, generator=gen)
         pos = 0
         for i in range(steps):
             if pos + batch > S:
                 perm = torch.randperm(S, generator=gen)
                 pos = 0
-            idx = perm[pos:pos + batch].to(self.dev)
+            idx = train_idx[perm[pos:pos + batch]].to(self.dev)
             pos += batch
             xb = X[idx].contiguous()
             yb = Y[idx].contiguous()
@@ -181,14 +189,28 @@ class ClosureModel:
         master[-self.M:] -= y[0].cpu().numpy()
         bz.bz_mlp_set_params(self.net, self.params, master)
 
-    def validation_error(self, rows=512):
-        """Relative L2 error of the network on the last `rows` training rows."""
-        X, Y = self.xs[0][-rows:].contiguous(), self.ys[0][-rows:].contiguous()
-        n = X.shape[0]
-        work = torch.zeros(bz.bz_mlp_workspace_bytes(self.net, n), dtype=torch.uint8, device=self.dev)
-        out = torch.zeros(n, self.M, dtype=torch.float32, device=self.dev)
-        bz.bz_mlp_forward(self.net, self.params, X, n, out, work)
-        return float((out - Y).norm() / Y.norm())
+    def validation_error(self, rows=4096):
+        """Relative L2 error of the network on up to `rows` held-out rows (kept out of
+        training by `fit`): (overall |Yhat - Y| / |Y|, median over rows of the per-row
+        relative error)."""
+        idx = self.val_idx[:rows]
+        n_all = idx.numel()
+        if n_all == 0:
+            raise RuntimeError("no held-out rows: fit with holdout > 0")
+        num = den = 0.0
+        per_row = []
+        for a in range(0, n_all, 1024):
+            X = self.xs[0][idx[a:a + 1024]].contiguous()
+            Y = self.ys[0][idx[a:a + 1024]]
+            n = X.shape[0]
+            work = torch.zeros(bz.bz_mlp_workspace_bytes(self.net, n), dtype=torch.uint8, device=self.dev)
+            out = torch.zeros(n, self.M, dtype=torch.float32, device=self.dev)
+            bz.bz_mlp_forward(self.net, self.params, X, n, out, work)
+            d, r = (out - Y).norm(dim=1), Y.norm(dim=1)
+            num += float((d ** 2).sum())
+            den += float((r ** 2).sum())
+            per_row.append((d / r).cpu())
+        return math.sqrt(num / den), float(torch.cat(per_row).median())
 
     def desc(self, gate=0.05, judge_every=16, judge_tol=1e-2, judge_floor=1e-3):
         return bz.closure_desc(self.net, self.params, gate, self.s_in, self.s_out, judge_every, judge_tol,
