@@ -62,7 +62,8 @@ def measured_traffic(cells, variant):
 def schedule_slots(N, symmetric):
     """Weight slots (unordered pairs incl. the zero-weight half of diagonal steps) one
     64-cell group processes: every row's steps in the full-sum schedule; in the
-    conjugate-symmetric one, the direct rows, the three edge passes and pass Z."""
+    conjugate-symmetric one, the direct rows less their m1 = 0 block, the three edge
+    passes and pass Z."""
     h = N // 2
     lo = lambda k: max(0, k - h + 1)
     hi = lambda k: min(N - 1, k + h)
@@ -78,6 +79,8 @@ def schedule_slots(N, symmetric):
     derived = lambda a, b: a >= 1 and b >= 1 and (a > h or (a == h and b > h))
     rows = sum(steps(a, b) for a in range(N) for b in range(N) if not (symmetric and derived(a, b)))
     if symmetric:
+        # pass A skips the m1 = 0 block of its rows (zero on the plane-zeroed copy)
+        rows -= sum(cnt(b) for a in range(h) for b in range(N) if not derived(a, b))
         rows += sum(cnt(b) + 2 * (cnt(b) - (2 if b < h else 0)) for a in range(h) for b in range(N))
         rows += sum(steps(0, b) for b in range(h, N))
     return rows * 3 * N * N // 4

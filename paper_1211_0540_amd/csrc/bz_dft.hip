@@ -281,7 +281,8 @@ __global__ void __launch_bounds__(256) k_dftg_fwd2(const double2 *__restrict__ S
 }
 
 // forward, axis 1: line (k2, k3): T (j1, k2, k3) -> fhat (k1, k2, k3), scaled, in the kernel's precision;
-// with copies = 3 also fhat with the axes ordered (2, 1, 3) and (3, 1, 2), copy_stride elements apart
+// with copies = 4 also fhat with the axes ordered (2, 1, 3) and (3, 1, 2), and fhat with every k_d = 0
+// plane set to zero (axes in order), copy_stride elements apart
 template <int N, typename Out>
 __global__ void __launch_bounds__(256) k_dftg_fwd3(const double2 *__restrict__ T, int nc, double scale,
                                                    Out *__restrict__ fh, int copies, long long copy_stride) {
@@ -314,16 +315,19 @@ __global__ void __launch_bounds__(256) k_dftg_fwd3(const double2 *__restrict__ T
             const size_t gl = gb * kWave + lane;
             fh[copy_stride + gl + ((size_t)(k2 * N + k) * N + k3) * kWave] = v;
             fh[2 * copy_stride + gl + ((size_t)(k3 * N + k) * N + k2) * kWave] = v;
+            Out z = v;
+            if (k == 0 || k2 == 0 || k3 == 0) z.x = z.y = 0.0;
+            fh[3 * copy_stride + off + (size_t)k * N * N * kWave] = z;
         }
     }
 }
 
 // inverse, axis 1, conjugate-symmetric schedule: assemble Qhat(k1, k2, k3) of line (k2, k3) from the
 // passes (qh: nA partial buffers of pass A, then E1, E2, E3, then nA partial buffers of Z), then
-// transform -> S (j1, k2, k3).
-//   direct row (k1, k2):        Qhat = A(k)
+// transform -> S (j1, k2, k3).  Pass A holds the interior sums I of the direct rows.
+//   direct row (k1, k2):        Qhat = I(k) + E(k)
 //   derived row, k3 = 0:        Qhat = Z at (0, k1, k2) of the (3, 1, 2) order
-//   derived row, k3 >= 1:       Qhat = conj(A(k') - E(k')) + E(k),   k' = N - k
+//   derived row, k3 >= 1:       Qhat = conj I(k') + E(k),   k' = N - k
 // E(k) is the edge sum: E1 at (k1, k2, k3) if k1 < N/2, E2 at (k2, k1, k3) if k2 < N/2,
 // E3 at (k3, k1, k2) if k3 < N/2.
 template <int N>
@@ -368,14 +372,13 @@ __global__ void __launch_bounds__(256) k_dftg_inv1_herm(const double2 *__restric
 #pragma unroll
     for (int k1 = 0; k1 < N; ++k1) {
         if (!herm_derived_row(N, k1, k2)) {
-            x[k1] = sum_parts(qh, at(k1, k2, k3));
+            const double2 i = sum_parts(qh, at(k1, k2, k3)), e = edge(k1, k2, k3);
+            x[k1] = make_double2(i.x + e.x, i.y + e.y);
         } else if (k3 == 0) {
             x[k1] = sum_parts(Z, at(0, k1, k2));
         } else {
-            const int a = N - k1, b = N - k2, c = N - k3;
-            const double2 m = sum_parts(qh, at(a, b, c));
-            const double2 em = edge(a, b, c), ek = edge(k1, k2, k3);
-            x[k1] = make_double2((m.x - em.x) + ek.x, (em.y - m.y) + ek.y);
+            const double2 i = sum_parts(qh, at(N - k1, N - k2, N - k3)), e = edge(k1, k2, k3);
+            x[k1] = make_double2(i.x + e.x, e.y - i.y);
         }
     }
     line_dft<N>(x, roots, S + gl + (size_t)line * kWave, (size_t)N * N * kWave, 1.0);
@@ -485,7 +488,7 @@ hipError_t grouped_inverse(double L, int nc, const double2 *qh, int nparts, long
 hipError_t launch_dft_forward_grouped(int N, double L, int ncells, const double *f, const long long *d_f_off,
                                       double2 *S, double2 *T, void *fh, bool out_f32, int copies, hipStream_t s) {
     if (ncells <= 0) return hipSuccess;
-    if (copies != 1 && copies != 3) return hipErrorInvalidValue;
+    if (copies != 1 && copies != 4) return hipErrorInvalidValue;
 #define CASE(NN) \
     case NN: return grouped_forward<NN>(L, ncells, f, d_f_off, S, T, fh, out_f32, copies, s);
     switch (N) {

@@ -83,10 +83,13 @@ __host__ __device__ inline int cells_steps(int N, int k1, int k2) {
 // pairs (every coordinate of m and j in [1, N)) and edge pairs (some
 // coordinate of m or j equal to 0).  The weight is invariant under
 // (k, m) -> (N - k, N - m), so the interior sum I satisfies
-// I(N - k) = conj I(k) whenever every k_d >= 1, and
-//   Qhat(N - k) = conj(Qhat(k) - E(k)) + E(N - k)
-// with E the edge sum.  The library therefore evaluates
-//   pass A : whole rows (k1, k2) of the "direct" half, every step;
+// I(N - k) = conj I(k) whenever every k_d >= 1, and with E the edge sum
+//   Qhat(k) = I(k) + E(k),   Qhat(N - k) = conj I(k) + E(N - k).
+// The library therefore evaluates
+//   pass A : the interior sums of the rows (k1, k2) of the "direct" half, as
+//            whole rows on a copy of fhat whose k_d = 0 planes are zeroed
+//            (edge pairs then contribute nothing; the steps with m1 = 0 are
+//            skipped);
 //   pass E1: edge pairs with m1 = 0 or j1 = 0 (in the schedule, the steps
 //            with m1 = 0 of the rows with k1 < N/2), every row;
 //   pass E2: edge pairs with m2 = 0 or j2 = 0 and no axis-1 edge: the same
@@ -189,8 +192,9 @@ hipError_t launch_expand_plain(int N, const double *dT, int qstride, double scal
 // batched paths: cell-interleaved groups of 64; S and T are scratch buffers of
 // groups * N^3 * 64 double2 each (T may be the first partial buffer of qh for
 // the inverse, which reads qh only in its first pass)
-// With `copies` = 3 the last pass also writes fhat with the axes ordered
-// (2, 1, 3) and (3, 1, 2) after the first copy, G * N^3 * 64 elements apart.
+// With `copies` = 4 the last pass also writes fhat with the axes ordered
+// (2, 1, 3) and (3, 1, 2), and fhat with its k_d = 0 planes zeroed, after the
+// first copy, G * N^3 * 64 elements apart.
 hipError_t launch_dft_forward_grouped(int N, double L, int ncells, const double *f, const long long *d_f_off,
                                       double2 *S, double2 *T, void *fh, bool out_f32, int copies, hipStream_t s);
 hipError_t launch_dft_inverse_grouped(int N, double L, int ncells, const double2 *qh, int nparts, long long pstride,

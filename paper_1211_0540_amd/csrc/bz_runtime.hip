@@ -494,13 +494,20 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
             auto item = [&](int gq, int r, int q, int pass, int a, int e) {
                 items.push_back(make_int4(gq, r | (q << 16) | (pass << 20), a, e));
             };
-            auto split = [&](int gq, int r, int pass) {
+            // steps [s0, st[r]) of row r in `parts` contiguous ranges
+            auto split = [&](int gq, int r, int pass, int s0) {
+                const long long n = st[r] - s0;
                 for (int q = 0; q < parts; ++q)
-                    item(gq, r, q, pass, (int)((long long)st[r] * q / parts), (int)((long long)st[r] * (q + 1) / parts));
+                    item(gq, r, q, pass, s0 + (int)(n * q / parts), s0 + (int)(n * (q + 1) / parts));
             };
             for (int gq = 0; gq < p.groups; ++gq) {
-                for (int r = 0; r < N * N; ++r)
-                    if (!p.herm || !herm_derived_row(N, r / N, r % N)) split(gq, r, kPassA);
+                // pass A runs on fhat with its k_d = 0 planes zeroed, so the steps with
+                // m1 = 0 (the first axis_cnt(k2) steps of rows k1 < N/2) add nothing
+                for (int r = 0; r < N * N; ++r) {
+                    const int k1 = r / N, k2 = r % N;
+                    if (!p.herm) split(gq, r, kPassA, 0);
+                    else if (!herm_derived_row(N, k1, k2)) split(gq, r, kPassA, k1 < h ? axis_cnt(N, k2) : 0);
+                }
                 if (!p.herm) continue;
                 for (int a = 0; a < h; ++a)
                     for (int b = 0; b < N; ++b) {
@@ -510,7 +517,7 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
                         item(gq, a * N + b, 0, kPassE2, cut, c - cut);
                         item(gq, a * N + b, 0, kPassE3, cut, c - cut);
                     }
-                for (int b = h; b < N; ++b) split(gq, b, kPassZ);
+                for (int b = h; b < N; ++b) split(gq, b, kPassZ, 0);
             }
             std::stable_sort(items.begin(), items.end(),
                              [](const int4 &x, const int4 &y) { return x.w - x.z > y.w - y.z; });
@@ -523,7 +530,7 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
         const size_t cs = f64 ? 16 : 8;
         if (bat) {
             p.ws_fh = ws;
-            ws = align256(ws + (size_t)(p.herm ? 3 : 1) * p.groups * M * kWave * cs);
+            ws = align256(ws + (size_t)(p.herm ? 4 : 1) * p.groups * M * kWave * cs);
             p.ws_qh = ws;
             ws = align256(ws + (size_t)p.qbufs * p.groups * M * kWave * 16);
         } else {
@@ -735,13 +742,13 @@ static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void 
         if (batched(b->mode)) {
             const int nc = (int)p.cells.size();
             // the first partial buffer of qh serves as the second scratch buffer of the transforms
-            BZ_HIP(launch_dft_forward_grouped(N, p.g->L, nc, d_f, p.d_f_off, scratch, qh, fh, !f64, p.herm ? 3 : 1, s),
+            BZ_HIP(launch_dft_forward_grouped(N, p.g->L, nc, d_f, p.d_f_off, scratch, qh, fh, !f64, p.herm ? 4 : 1, s),
                    "forward transform");
             const long long pstride = (long long)p.groups * M * kWave;  // one copy of fhat, one output buffer
             CellsLaunch cl{N, fh, p.d_items, p.n_items, (unsigned *)(ws + p.ws_counter), qh, pstride, 0, skip, {}};
             const void *w_e3 = (const char *)p.w + e3_base_bytes(p.g, f64 ? 8 : 4);
             const long long P = p.parts;
-            cl.passes.p[kPassA] = ConvPass{0, 0, p.w, p.d_row_woff};
+            cl.passes.p[kPassA] = ConvPass{p.herm ? 3 * pstride : 0, 0, p.w, p.d_row_woff};
             cl.passes.p[kPassE1] = ConvPass{0, P * pstride, p.w, p.d_row_woff};
             cl.passes.p[kPassE2] = ConvPass{pstride, (P + 1) * pstride, p.w, p.d_row_woff};
             cl.passes.p[kPassE3] = ConvPass{2 * pstride, (P + 2) * pstride, w_e3, p.d_e3_woff};
