@@ -41,8 +41,13 @@ def log(msg):
 
 
 def conv_source_sha():
-    with open(os.path.join(ROOT, "paper_1211_0540_amd", "csrc", "bz_conv.hip"), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Digest of the sources that fix what one convolution launch reads and writes:
+    the kernel and the schedule that builds its work items."""
+    h = hashlib.sha256()
+    for name in ("bz_conv.hip", "bz_runtime.hip", "bz_internal.h"):
+        with open(os.path.join(ROOT, "paper_1211_0540_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(cells, variant):
