@@ -424,13 +424,16 @@ __global__ void __launch_bounds__(64) k_conv_plain(const typename cplx<T>::t *__
 //  11: as 10 with FOLD 8
 //  12: as 10 with two interleaved partials
 //  13: as 5 with four interleaved partials
+//  14: as 10 with FOLD 4
+//  15: as 10 with FOLD 2
 // Accumulation parameters of each variant (must match the switch below): the
 // autotuner prefers more interleaved partials, then a shorter fold interval.
 struct VariantAcc {
     int fold, split;
 };
 constexpr VariantAcc kVariantAcc[] = {{2, 1}, {2, 1}, {2, 1}, {2, 1}, {2, 1},  {4, 1},  {2, 1},
-                                      {4, 1}, {8, 1}, {16, 1}, {16, 4}, {8, 4}, {16, 2}, {4, 4}};
+                                      {4, 1}, {8, 1}, {16, 1}, {16, 4}, {8, 4}, {16, 2}, {4, 4},
+                                      {4, 4}, {2, 4}};
 
 template <int N>
 hipError_t cells_f32_variant(const CellsLaunch &p, unsigned grid, hipStream_t s) {
@@ -452,6 +455,8 @@ hipError_t cells_f32_variant(const CellsLaunch &p, unsigned grid, hipStream_t s)
     case 11: BZ_CELLS_F32(8, 2, 0, 0, 4); break;
     case 12: BZ_CELLS_F32(16, 2, 0, 0, 2); break;
     case 13: BZ_CELLS_F32(4, 0, 0, 1, 4); break;
+    case 14: BZ_CELLS_F32(4, 2, 0, 0, 4); break;
+    case 15: BZ_CELLS_F32(2, 2, 0, 0, 4); break;
     default: BZ_CELLS_F32(2, 0, 0, 1, 1); break;
     }
 #undef BZ_CELLS_F32

@@ -39,9 +39,11 @@ __device__ inline double wave_sum(double x) {
     return x;
 }
 
-__global__ void __launch_bounds__(256) k_project(int N, double dv, Linv li, double *__restrict__ q,
-                                                 const long long *__restrict__ off) {
-    __shared__ double red[4][5];
+// One block of kProjThreads threads per cell.
+constexpr int kProjThreads = 1024;
+__global__ void __launch_bounds__(kProjThreads) k_project(int N, double dv, Linv li, double *__restrict__ q,
+                                                          const long long *__restrict__ off) {
+    __shared__ double red[kProjThreads / 64][5];
     __shared__ double mu[5];
     const int M = N * N * N;
     double *Q = q + off[blockIdx.x];
@@ -193,7 +195,7 @@ hipError_t launch_project(int N, double dv, const double *linv, int ncells, doub
     if (ncells <= 0) return hipSuccess;
     Linv li;
     for (int i = 0; i < 25; ++i) li.a[i] = linv[i];
-    hipLaunchKernelGGL(k_project, dim3(ncells), dim3(256), 0, s, N, dv, li, q, d_off);
+    hipLaunchKernelGGL(k_project, dim3(ncells), dim3(kProjThreads), 0, s, N, dv, li, q, d_off);
     return hipGetLastError();
 }
 

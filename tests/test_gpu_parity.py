@@ -287,7 +287,7 @@ def test_unbound_weights_and_short_workspace(dev):
     bz.bz_grid_free(g)
 
 
-@pytest.mark.parametrize("variant", range(14))
+@pytest.mark.parametrize("variant", range(16))
 def test_every_batched_fp32_variant_matches_oracle(dev, variant):
     """Each tuning variant computes the same sums: 70 cells on N=24 (a ragged second group)."""
     N, L, lam = 24, 7.0, 1.0
