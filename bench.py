@@ -84,8 +84,18 @@ def schedule_slots(N, symmetric):
     derived = lambda a, b: a >= 1 and b >= 1 and (a > h or (a == h and b > h))
     rows = sum(steps(a, b) for a in range(N) for b in range(N) if not (symmetric and derived(a, b)))
     if symmetric:
-        # pass A skips the m1 = 0 block of its rows (zero on the plane-zeroed copy)
-        rows -= sum(cnt(b) for a in range(h) for b in range(N) if not derived(a, b))
+        # pass A skips the steps that only meet zeroed planes of its fhat copy: the
+        # m1 = 0 block of rows k1 < N/2, and the steps with m2 = 0 or j2 = 0
+        for a in range(N):
+            for b in range(N):
+                if derived(a, b):
+                    continue
+                if a < h:
+                    rows -= cnt(b)
+                if b < h:
+                    for m1 in range(max(lo(a), 1), min((a + h) // 2, hi(a)) + 1):
+                        last = hi(b) if 2 * m1 < a + h else min((b + h) // 2, hi(b))
+                        rows -= 1 + (1 if last == b + h else 0)
         rows += sum(cnt(b) + 2 * (cnt(b) - (2 if b < h else 0)) for a in range(h) for b in range(N))
         rows += sum(steps(0, b) for b in range(h, N))
     return rows * 3 * N * N // 4

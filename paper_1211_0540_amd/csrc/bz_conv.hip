@@ -241,6 +241,8 @@ k_conv_cells_f32(const float2 *__restrict__ fh, const int4 *__restrict__ items, 
         int buf = 0, nst = 0;
         for (int s = s0; s < s1; ++s) {
             const int j1 = k1 + h - m1, j2 = k2 + h - m2;
+            // on a plane-zeroed copy a step with m2 = 0 or j2 = 0 has only zero products
+            const bool live = !cp.zero_planes || (m2 != 0 && j2 != 0);
             // (m1, m2) of the next step in the row's order
             int n1 = m1, n2 = m2 + 1;
             if (n2 > cells_m2_last(N, k1, k2, m1)) {
@@ -263,16 +265,17 @@ k_conv_cells_f32(const float2 *__restrict__ fh, const int4 *__restrict__ items, 
             if (WP == 0) {
                 // next step's weights into the other LDS half; this step reads its half
                 prefetch_weights<CH>(w + PS, wl + (buf ^ 1) * CH * 1024);
-                cells_step<float, N, SPLIT>(mv, jv, (const float *)wbuf[buf], pr, pi);
+                if (live) cells_step<float, N, SPLIT>(mv, jv, (const float *)wbuf[buf], pr, pi);
             } else if (WP == 1) {
                 // next step's weights pulled into L2 (the LDS copy is discarded); this
                 // step's weights, pulled last step, are read through the scalar cache
                 prefetch_weights<CH>(w + PS, wl + CH * 1024);
-                cells_step<float, N, SPLIT>(mv, jv, (const __attribute__((address_space(4))) float *)w, pr, pi);
+                if (live)
+                    cells_step<float, N, SPLIT>(mv, jv, (const __attribute__((address_space(4))) float *)w, pr, pi);
             } else {
                 // as 1, but the weights are read by uniform-address vector loads
                 prefetch_weights<CH>(w + PS, wl + CH * 1024);
-                cells_step<float, N, SPLIT>(mv, jv, w, pr, pi);
+                if (live) cells_step<float, N, SPLIT>(mv, jv, w, pr, pi);
             }
             w += PS;
             buf ^= 1;
@@ -340,7 +343,8 @@ __global__ void __launch_bounds__(64) k_conv_cells_f64(const double2 *__restrict
             double2 mv[N], jv[N];
             load_row<double, N>(F + (size_t)((m1 * N + m2) * N) * kWave, mv);
             load_row<double, N>(F + (size_t)((j1 * N + j2) * N) * kWave, jv);
-            cells_step<double, N, 1>(mv, jv, (const double *)wbuf[buf], pr, pi);
+            if (!cp.zero_planes || (m2 != 0 && j2 != 0))
+                cells_step<double, N, 1>(mv, jv, (const double *)wbuf[buf], pr, pi);
             w += PS;
             buf ^= 1;
             if (++m2 > cells_m2_last(N, k1, k2, m1)) {

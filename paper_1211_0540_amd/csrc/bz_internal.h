@@ -220,6 +220,7 @@ struct ConvPass {
     long long out_off;           // first output buffer written by the pass
     const void *w;               // weight stream
     const long long *row_woff;   // device, N*N offsets of the rows in w (elements)
+    int zero_planes;             // fhat copy has its k_d = 0 planes zeroed: skip steps with m2 = 0 or j2 = 0
 };
 struct ConvPasses {
     ConvPass p[kPasses];

@@ -748,11 +748,11 @@ static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void 
             CellsLaunch cl{N, fh, p.d_items, p.n_items, (unsigned *)(ws + p.ws_counter), qh, pstride, 0, skip, {}};
             const void *w_e3 = (const char *)p.w + e3_base_bytes(p.g, f64 ? 8 : 4);
             const long long P = p.parts;
-            cl.passes.p[kPassA] = ConvPass{p.herm ? 3 * pstride : 0, 0, p.w, p.d_row_woff};
-            cl.passes.p[kPassE1] = ConvPass{0, P * pstride, p.w, p.d_row_woff};
-            cl.passes.p[kPassE2] = ConvPass{pstride, (P + 1) * pstride, p.w, p.d_row_woff};
-            cl.passes.p[kPassE3] = ConvPass{2 * pstride, (P + 2) * pstride, w_e3, p.d_e3_woff};
-            cl.passes.p[kPassZ] = ConvPass{2 * pstride, (P + 3) * pstride, p.w, p.d_row_woff};
+            cl.passes.p[kPassA] = ConvPass{p.herm ? 3 * pstride : 0, 0, p.w, p.d_row_woff, p.herm ? 1 : 0};
+            cl.passes.p[kPassE1] = ConvPass{0, P * pstride, p.w, p.d_row_woff, 0};
+            cl.passes.p[kPassE2] = ConvPass{pstride, (P + 1) * pstride, p.w, p.d_row_woff, 0};
+            cl.passes.p[kPassE3] = ConvPass{2 * pstride, (P + 2) * pstride, w_e3, p.d_e3_woff, 0};
+            cl.passes.p[kPassZ] = ConvPass{2 * pstride, (P + 3) * pstride, p.w, p.d_row_woff, 0};
             std::pair<hipEvent_t, hipEvent_t> ev{};
             if (b->timing) {
                 if (!timer_pair(b, ev)) return fail(BZ_EDEVICE, "bz_collide_batch: hipEventCreate failed");
