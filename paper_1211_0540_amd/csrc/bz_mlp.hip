@@ -43,12 +43,15 @@ __device__ inline float gelu_prime(float z) {
     return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.3989422804014327f;
 }
 
-enum { EPI_F32 = 0, EPI_GELU = 1 };
+enum { EPI_F32 = 0, EPI_GELU = 1, EPI_PARTIAL = 2 };
 
 constexpr int TBM = 128, TBN = 128, TBK = 32, LDSK = TBK + 8;
 
 // EPI_F32:  C32[m][n] = alpha * acc + (bias ? bias[n] : 0)
 // EPI_GELU: Z = acc + bias[n]; C32 = Z; Cbf = bf16(gelu(Z))
+// EPI_PARTIAL (split K): workgroup z of gridDim.z sums the k tiles
+//           [z nk / Z, (z + 1) nk / Z) and writes its raw sums to C32 + z M ldc;
+//           k_splitk_reduce then adds the Z slices in order and applies the epilogue.
 template <int EPI>
 __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const unsigned short *__restrict__ A, int lda,
                                                  const unsigned short *__restrict__ B, int ldb, float alpha,
@@ -66,15 +69,18 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const unsi
     const uint4 *ap = (const uint4 *)(A + (size_t)(aok ? am : 0) * lda + lk);
     const uint4 *bp = (const uint4 *)(B + (size_t)(bok ? bn : 0) * ldb + lk);
     const uint4 z4 = make_uint4(0, 0, 0, 0);
-    uint4 ra0 = aok ? ap[0] : z4, ra1 = aok ? ap[1] : z4;
-    uint4 rb0 = bok ? bp[0] : z4, rb1 = bok ? bp[1] : z4;
+    const int nk_all = K / TBK;
+    const int kt0 = (int)((long long)nk_all * blockIdx.z / gridDim.z);
+    const int nk = (int)((long long)nk_all * (blockIdx.z + 1) / gridDim.z);
+    const int o0 = kt0 * TBK / 8;  // first k tile of this workgroup, in uint4 units
+    uint4 ra0 = aok ? ap[o0] : z4, ra1 = aok ? ap[o0 + 1] : z4;
+    uint4 rb0 = bok ? bp[o0] : z4, rb1 = bok ? bp[o0 + 1] : z4;
     f32x4 acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int nk = K / TBK;
-    for (int kt = 0; kt < nk; ++kt) {
+    for (int kt = kt0; kt < nk; ++kt) {
         __syncthreads();
         *(uint4 *)(As + lr * LDSK + lk) = ra0;
         *(uint4 *)(As + lr * LDSK + lk + 8) = ra1;
@@ -112,6 +118,10 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const unsi
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + r;
                 if (row >= M) continue;
+                if (EPI == EPI_PARTIAL) {
+                    C32[((size_t)blockIdx.z * M + row) * ldc + col] = acc[i][j][r];
+                    continue;
+                }
                 const float z = alpha * acc[i][j][r] + bcol;
                 if (EPI == EPI_GELU) {
                     C32[(size_t)row * ldc + col] = z;
@@ -121,6 +131,22 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const unsi
                 }
             }
         }
+}
+
+// Sum of the Z split-K slices P[z][M][N] in order z = 0, 1, ..., then the epilogue of EPI.
+template <int EPI>
+__global__ void __launch_bounds__(256) k_splitk_reduce(int M, int N, int Z, const float *__restrict__ P, float alpha,
+                                                       const float *__restrict__ bias, float *__restrict__ C32,
+                                                       int ldc, unsigned short *__restrict__ Cbf, int ldcb) {
+    const size_t MN = (size_t)M * N;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < MN; i += (size_t)gridDim.x * blockDim.x) {
+        const int row = (int)(i / N), col = (int)(i - (size_t)row * N);
+        float acc = 0.f;
+        for (int z = 0; z < Z; ++z) acc += P[z * MN + i];
+        const float v = alpha * acc + (bias ? bias[col] : 0.f);
+        C32[(size_t)row * ldc + col] = v;
+        if (EPI == EPI_GELU) Cbf[(size_t)row * ldcb + col] = f2bf(gelu(v));
+    }
 }
 
 // out[c][r] = in[r][c] for an R x C BF16 matrix (32 x 32 tiles through LDS).
@@ -249,7 +275,12 @@ static size_t param_bytes(const bz_mlp_s *n) {
            2 * a256((size_t)n->n_out * n->n_hid * 2);
 }
 
+// split-K slices: up to kMaxSplit x batch x n_hid FP32 values
+constexpr int kMaxSplit = 16;
+
 struct WorkView {
+    float *split;                // split-K slices
+    size_t split_floats;
     float *Z1, *Z2, *Y, *dA;     // FP32
     unsigned short *A1, *A2;     // BF16 activations
     unsigned short *dY, *dZ;     // BF16 gradients (dZ reused for layers 2 and 1)
@@ -267,6 +298,8 @@ static WorkView work_view(const bz_mlp_s *n, int B, void *w) {
         return p;
     };
     const size_t H = n->n_hid, O = n->n_out, I = n->n_in;
+    v.split_floats = (size_t)kMaxSplit * B * H;
+    v.split = (float *)take(v.split_floats * 4);
     v.Z1 = (float *)take((size_t)B * H * 4);
     v.Z2 = (float *)take((size_t)B * H * 4);
     v.Y = (float *)take((size_t)B * O * 4);
@@ -285,13 +318,39 @@ static WorkView work_view(const bz_mlp_s *n, int B, void *w) {
 
 static size_t work_bytes(const bz_mlp_s *n, int B) {
     const size_t H = n->n_hid, O = n->n_out, I = n->n_in;
-    return a256((size_t)B * H * 4) * 3 + a256((size_t)B * O * 4) + a256((size_t)B * H * 2) * 3 +
+    return a256((size_t)kMaxSplit * B * H * 4) + a256((size_t)B * H * 4) * 3 + a256((size_t)B * O * 4) +
+           a256((size_t)B * H * 2) * 3 +
            a256((size_t)B * O * 2) + 2 * a256(std::max(std::max(O, I), H) * (size_t)B * 2) + a256(16384 * 8) + 256;
 }
 
+// C = alpha A B^T (+ bias, epilogue).  A product with fewer output tiles than
+// there are compute units and a long K is split over K into up to kMaxSplit
+// slices (at least 8 k tiles each) when the workspace slice buffer holds them.
 static hipError_t gemm(int epi, int M, int N, int K, const unsigned short *A, int lda, const unsigned short *B, int ldb,
-                       float alpha, const float *bias, float *C32, int ldc, unsigned short *Cbf, int ldcb, hipStream_t s) {
+                       float alpha, const float *bias, float *C32, int ldc, unsigned short *Cbf, int ldcb,
+                       const WorkView &wv, hipStream_t s) {
     dim3 grid((N + TBN - 1) / TBN, (M + TBM - 1) / TBM);
+    const int tiles = (int)(grid.x * grid.y), nk = K / TBK;
+    int split = 1;
+    if (tiles < 128) {
+        split = std::min(std::min(kMaxSplit, nk / 8), (256 + tiles - 1) / tiles);
+        const size_t cap = wv.split_floats / ((size_t)M * N);
+        if ((size_t)split > cap) split = (int)cap;
+    }
+    if (split >= 2) {
+        grid.z = split;
+        hipLaunchKernelGGL(k_gemm_nt<EPI_PARTIAL>, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, 1.f, nullptr,
+                           wv.split, N, nullptr, 0);
+        const size_t mn = (size_t)M * N;
+        const unsigned rg = (unsigned)std::min<size_t>((mn + 255) / 256, 4096);
+        if (epi == EPI_GELU)
+            hipLaunchKernelGGL(k_splitk_reduce<EPI_GELU>, dim3(rg), dim3(256), 0, s, M, N, split, wv.split, alpha, bias,
+                               C32, ldc, Cbf, ldcb);
+        else
+            hipLaunchKernelGGL(k_splitk_reduce<EPI_F32>, dim3(rg), dim3(256), 0, s, M, N, split, wv.split, alpha, bias,
+                               C32, ldc, Cbf, ldcb);
+        return hipGetLastError();
+    }
     if (epi == EPI_GELU)
         hipLaunchKernelGGL(k_gemm_nt<EPI_GELU>, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, alpha, bias, C32, ldc,
                            Cbf, ldcb);
@@ -319,9 +378,9 @@ static hipError_t refresh_bf16(const bz_mlp_s *n, const ParamView &pv, hipStream
 static hipError_t forward(const bz_mlp_s *n, const ParamView &pv, const unsigned short *X, int B, const WorkView &wv,
                           float *Y, hipStream_t s) {
     const int H = n->n_hid, O = n->n_out, I = n->n_in;
-    hipError_t e = gemm(EPI_GELU, B, H, I, X, I, pv.W1, I, 1.f, pv.master + n->ob1, wv.Z1, H, wv.A1, H, s);
-    if (e == hipSuccess) e = gemm(EPI_GELU, B, H, H, wv.A1, H, pv.W2, H, 1.f, pv.master + n->ob2, wv.Z2, H, wv.A2, H, s);
-    if (e == hipSuccess) e = gemm(EPI_F32, B, O, H, wv.A2, H, pv.W3, H, 1.f, pv.master + n->ob3, Y, O, nullptr, 0, s);
+    hipError_t e = gemm(EPI_GELU, B, H, I, X, I, pv.W1, I, 1.f, pv.master + n->ob1, wv.Z1, H, wv.A1, H, wv, s);
+    if (e == hipSuccess) e = gemm(EPI_GELU, B, H, H, wv.A1, H, pv.W2, H, 1.f, pv.master + n->ob2, wv.Z2, H, wv.A2, H, wv, s);
+    if (e == hipSuccess) e = gemm(EPI_F32, B, O, H, wv.A2, H, pv.W3, H, 1.f, pv.master + n->ob3, Y, O, nullptr, 0, wv, s);
     return e;
 }
 
@@ -339,21 +398,21 @@ static hipError_t backward(const bz_mlp_s *n, const ParamView &pv, const unsigne
     // layer 3: dW3 = gs dY^T A2 ([O x B] x [H x B]^T), db3 = gs colsum(dY), dA2 = dY W3 (via W3t [H x O])
     hipError_t e = transpose(B, O, wv.dY, wv.tA, s);
     if (e == hipSuccess) e = transpose(B, H, wv.A2, wv.tB, s);
-    if (e == hipSuccess) e = gemm(EPI_F32, O, H, B, wv.tA, B, wv.tB, B, gs, nullptr, g + n->oW3, H, nullptr, 0, s);
+    if (e == hipSuccess) e = gemm(EPI_F32, O, H, B, wv.tA, B, wv.tB, B, gs, nullptr, g + n->oW3, H, nullptr, 0, wv, s);
     hipLaunchKernelGGL(k_col_sums, dim3((O + 255) / 256), dim3(256), 0, s, B, O, wv.dY, gs, g + n->ob3);
-    if (e == hipSuccess) e = gemm(EPI_F32, B, H, O, wv.dY, O, pv.W3t, O, gs, nullptr, wv.dA, H, nullptr, 0, s);
+    if (e == hipSuccess) e = gemm(EPI_F32, B, H, O, wv.dY, O, pv.W3t, O, gs, nullptr, wv.dA, H, nullptr, 0, wv, s);
     hipLaunchKernelGGL(k_gelu_bwd, dim3(grid1((size_t)B * H)), dim3(256), 0, s, (size_t)B * H, wv.dA, wv.Z2, wv.dZ);
     // layer 2 (dZ holds the true gradient dL/dZ2)
     if (e == hipSuccess) e = transpose(B, H, wv.dZ, wv.tA, s);
     if (e == hipSuccess) e = transpose(B, H, wv.A1, wv.tB, s);
-    if (e == hipSuccess) e = gemm(EPI_F32, H, H, B, wv.tA, B, wv.tB, B, 1.f, nullptr, g + n->oW2, H, nullptr, 0, s);
+    if (e == hipSuccess) e = gemm(EPI_F32, H, H, B, wv.tA, B, wv.tB, B, 1.f, nullptr, g + n->oW2, H, nullptr, 0, wv, s);
     hipLaunchKernelGGL(k_col_sums, dim3((H + 255) / 256), dim3(256), 0, s, B, H, wv.dZ, 1.f, g + n->ob2);
-    if (e == hipSuccess) e = gemm(EPI_F32, B, H, H, wv.dZ, H, pv.W2t, H, 1.f, nullptr, wv.dA, H, nullptr, 0, s);
+    if (e == hipSuccess) e = gemm(EPI_F32, B, H, H, wv.dZ, H, pv.W2t, H, 1.f, nullptr, wv.dA, H, nullptr, 0, wv, s);
     hipLaunchKernelGGL(k_gelu_bwd, dim3(grid1((size_t)B * H)), dim3(256), 0, s, (size_t)B * H, wv.dA, wv.Z1, wv.dZ);
     // layer 1
     if (e == hipSuccess) e = transpose(B, H, wv.dZ, wv.tA, s);
     if (e == hipSuccess) e = transpose(B, I, X, wv.tB, s);
-    if (e == hipSuccess) e = gemm(EPI_F32, H, I, B, wv.tA, B, wv.tB, B, 1.f, nullptr, g + n->oW1, I, nullptr, 0, s);
+    if (e == hipSuccess) e = gemm(EPI_F32, H, I, B, wv.tA, B, wv.tB, B, 1.f, nullptr, g + n->oW1, I, nullptr, 0, wv, s);
     hipLaunchKernelGGL(k_col_sums, dim3((H + 255) / 256), dim3(256), 0, s, B, H, wv.dZ, 1.f, g + n->ob1);
     return e == hipSuccess ? hipGetLastError() : e;
 }

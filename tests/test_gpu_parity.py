@@ -208,6 +208,37 @@ def test_shock_cells_fp32_full_size(dev):
         assert rel_l2(qs[i], q_o) < max(1e-5, 8 * U32 * kap)
 
 
+def test_bench_workload_n32_full_batch(dev):
+    """The benchmark's launch: the 190 N=32 cells of the 1024-cell uneven draw in one
+    batched FP32 launch (default schedule, autotuned variant).  Every cell against the
+    batched FP64 result of the full-sum schedule, which is checked against the oracle on
+    sampled cells; three cells also directly against the oracle; conservation everywhere."""
+    N, L, lam = 32, 8.0, 1.0
+    batch = W.uneven_batch(n_cells=1024, only_N=32)
+    cells, n = batch.cells, len(batch.cells)
+    assert n == 190
+    c = bz.Collision([(N, L, lam)], [0] * n, "batched_f32", weights_cache=_WCACHE)
+    f = torch.from_numpy(c.pack(cells)).to(dev)
+    c.autotune(f, reps=1)
+    q32 = c.unpack(c.project(c.collide(f)).cpu().numpy())
+    c.close()
+    c64 = bz.Collision([(N, L, lam)], [0] * n, "batched_f64", weights_cache=_WCACHE, schedule="full")
+    q64 = c64.unpack(c64.project(c64.collide(f)).cpu().numpy())
+    c64.close()
+    o = oracle_for(N, L, lam)
+    for i in (0, 95, 189):
+        _, q_o, _, _ = o.collide(cells[i])
+        assert max_rel(q64[i], q_o) < 1e-12, i
+        assert rel_l2(q32[i], q_o) < max(1e-5, 8 * U32 * _kappa(cells[i], N, L, lam)), i
+    errs = np.array([rel_l2(q32[i], q64[i]) for i in range(n)])
+    for i in range(n):
+        assert_conserved(q32[i], N, L)
+    # kappa of these perturbed Maxwellians stays below ~2000 (8 u32 kappa < 1e-3)
+    assert errs.max() < 1e-3
+    print("bench workload FP32 vs FP64: median %.2e max %.2e, %.0f%% <= 1e-5"
+          % (np.median(errs), errs.max(), 100 * np.mean(errs <= 1e-5)))
+
+
 def test_batched_fp32_is_deterministic(dev):
     N, L, lam = 16, 6.0, 1.0
     cells = list(W.random_smooth_cells(80, N, L, seed=9))
