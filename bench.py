@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-collision evals/s at N=32: FP32 batched & surrogate vs FP64 plain; rel L2 err"
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector, published
-TRAIN_STEPS = 12000        # closure training: Adam steps of 512 rows
+TRAIN_STEPS = 30000        # closure training: Adam steps of 512 rows
 HBM_TBPS = 8.0
 
 

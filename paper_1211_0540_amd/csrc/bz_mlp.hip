@@ -189,12 +189,17 @@ __global__ void __launch_bounds__(256) k_mse_grad(size_t n, const float *__restr
     if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-__global__ void k_sum_parts(int n, const double *__restrict__ part, double inv_n, float *__restrict__ loss) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += part[i];
-        loss[0] = (float)(s * inv_n);
-    }
+// loss = inv_n * sum of the n block partials (one 256-thread block, fixed order)
+__global__ void __launch_bounds__(256) k_sum_parts(int n, const double *__restrict__ part, double inv_n,
+                                                   float *__restrict__ loss) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) loss[0] = (float)((red[0] + red[1] + red[2] + red[3]) * inv_n);
 }
 
 // dZ = bf16(dA * gelu'(Z))
@@ -204,13 +209,25 @@ __global__ void k_gelu_bwd(size_t n, const float *__restrict__ dA, const float *
         dZ[i] = f2bf(dA[i] * gelu_prime(Z[i]));
 }
 
-// db[n] = alpha * sum_m bf2f(D[m][n])  (D is rows x cols BF16)
-__global__ void k_col_sums(int rows, int cols, const unsigned short *__restrict__ D, float alpha, float *__restrict__ db) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
+// db[n] = alpha * sum_m bf2f(D[m][n])  (D is rows x cols BF16).  A block of 64 x 16
+// threads owns 64 columns; thread (c, t) sums the rows r = t (mod 16) of its column,
+// then the 16 partial sums are added in order.
+__global__ void __launch_bounds__(1024) k_col_sums(int rows, int cols, const unsigned short *__restrict__ D,
+                                                   float alpha, float *__restrict__ db) {
+    __shared__ float part[16][64];
+    const int tc = threadIdx.x & 63, tr = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + tc;
     float s = 0.f;
-    for (int r = 0; r < rows; ++r) s += bf2f(D[(size_t)r * cols + c]);
-    db[c] = alpha * s;
+    if (c < cols)
+        for (int r = tr; r < rows; r += 16) s += bf2f(D[(size_t)r * cols + c]);
+    part[tr][tc] = s;
+    __syncthreads();
+    if (tr == 0 && c < cols) {
+        float t = 0.f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) t += part[i][tc];
+        db[c] = alpha * t;
+    }
 }
 
 __global__ void k_adam(size_t n, float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
@@ -394,26 +411,26 @@ static hipError_t backward(const bz_mlp_s *n, const ParamView &pv, const unsigne
     hipLaunchKernelGGL(k_mse_grad, dim3(grid1(nY) > 4096 ? 4096 : grid1(nY)), dim3(256), 0, s, nY, wv.Y, T, 1.0f,
                        wv.dY, wv.part);
     const int nparts = grid1(nY) > 4096 ? 4096 : (int)grid1(nY);
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, nparts, wv.part, 1.0 / (double)nY, wv.loss);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, nparts, wv.part, 1.0 / (double)nY, wv.loss);
     // layer 3: dW3 = gs dY^T A2 ([O x B] x [H x B]^T), db3 = gs colsum(dY), dA2 = dY W3 (via W3t [H x O])
     hipError_t e = transpose(B, O, wv.dY, wv.tA, s);
     if (e == hipSuccess) e = transpose(B, H, wv.A2, wv.tB, s);
     if (e == hipSuccess) e = gemm(EPI_F32, O, H, B, wv.tA, B, wv.tB, B, gs, nullptr, g + n->oW3, H, nullptr, 0, wv, s);
-    hipLaunchKernelGGL(k_col_sums, dim3((O + 255) / 256), dim3(256), 0, s, B, O, wv.dY, gs, g + n->ob3);
+    hipLaunchKernelGGL(k_col_sums, dim3((O + 63) / 64), dim3(1024), 0, s, B, O, wv.dY, gs, g + n->ob3);
     if (e == hipSuccess) e = gemm(EPI_F32, B, H, O, wv.dY, O, pv.W3t, O, gs, nullptr, wv.dA, H, nullptr, 0, wv, s);
     hipLaunchKernelGGL(k_gelu_bwd, dim3(grid1((size_t)B * H)), dim3(256), 0, s, (size_t)B * H, wv.dA, wv.Z2, wv.dZ);
     // layer 2 (dZ holds the true gradient dL/dZ2)
     if (e == hipSuccess) e = transpose(B, H, wv.dZ, wv.tA, s);
     if (e == hipSuccess) e = transpose(B, H, wv.A1, wv.tB, s);
     if (e == hipSuccess) e = gemm(EPI_F32, H, H, B, wv.tA, B, wv.tB, B, 1.f, nullptr, g + n->oW2, H, nullptr, 0, wv, s);
-    hipLaunchKernelGGL(k_col_sums, dim3((H + 255) / 256), dim3(256), 0, s, B, H, wv.dZ, 1.f, g + n->ob2);
+    hipLaunchKernelGGL(k_col_sums, dim3((H + 63) / 64), dim3(1024), 0, s, B, H, wv.dZ, 1.f, g + n->ob2);
     if (e == hipSuccess) e = gemm(EPI_F32, B, H, H, wv.dZ, H, pv.W2t, H, 1.f, nullptr, wv.dA, H, nullptr, 0, wv, s);
     hipLaunchKernelGGL(k_gelu_bwd, dim3(grid1((size_t)B * H)), dim3(256), 0, s, (size_t)B * H, wv.dA, wv.Z1, wv.dZ);
     // layer 1
     if (e == hipSuccess) e = transpose(B, H, wv.dZ, wv.tA, s);
     if (e == hipSuccess) e = transpose(B, I, X, wv.tB, s);
     if (e == hipSuccess) e = gemm(EPI_F32, H, I, B, wv.tA, B, wv.tB, B, 1.f, nullptr, g + n->oW1, I, nullptr, 0, wv, s);
-    hipLaunchKernelGGL(k_col_sums, dim3((H + 255) / 256), dim3(256), 0, s, B, H, wv.dZ, 1.f, g + n->ob1);
+    hipLaunchKernelGGL(k_col_sums, dim3((H + 63) / 64), dim3(1024), 0, s, B, H, wv.dZ, 1.f, g + n->ob1);
     return e == hipSuccess ? hipGetLastError() : e;
 }
 
