@@ -294,7 +294,7 @@ def main():
     elif args.profile_run:
         variant = bz.bz_batch_get_variant(col.batch, 0)
     else:
-        variant = col.autotune(f0, reps=1)[0]
+        variant = col.autotune(f0, reps=3)[0]
     log(f"convolution variant {variant}")
 
     # FP32 result of one evaluation (kept for the error report)
