@@ -250,10 +250,14 @@ bz_status bz_mlp_adam(bz_mlp n, void *d_params, const float *d_grad, int step, f
 /* Gated learned closure around the collision step.                      */
 /* ------------------------------------------------------------------ */
 /* Per cell: rho, u, T (FP64 moments), the local Maxwellian M, the deviation
- * d = |f - M|_2 / |M|_2.  Cells with d < gate are served by the network:
- * x = (f - M) / (rho s_in) in BF16, Q_s = rho^2 s_out net(x) (the density
- * scales out of the bilinear Q exactly).  The others take the weighted
- * convolution.  The gated cells of the 64-cell groups g with
+ * d = |f - M|_2 / |M|_2.  Cells with d < gate are served by the network.  Its
+ * BF16 input x is the direction of f - M scaled to unit RMS,
+ *   x_j = (f_j - M_j) sqrt(N^3) / |f - M|_2   (j > 0),
+ * with the amplitude x_0 = d / s_in in the corner entry v = (-L, -L, -L),
+ * where f - M is negligible; the closure is Q_s = rho |f - M|_2 s_out net(x)
+ * (near equilibrium Q is linear in f - M with a coefficient proportional to
+ * rho, so the network sees the direction and a bounded amplitude, and Q_s
+ * vanishes with f - M).  The others take the weighted convolution.  The gated cells of the 64-cell groups g with
  * g mod judge_every = (evaluation count) mod judge_every are also convolved
  * ("judged"), compared after projection,
  *   err = |P(Q_s - Q_c)|_2 / (|P Q_c|_2 + judge_floor rho |M|_2)
@@ -288,7 +292,8 @@ size_t bz_closure_workspace_bytes(bz_batch b, const bz_closure *c);
  * d_x[n_cells][N^3] BF16. */
 bz_status bz_closure_prepare(bz_batch b, const double *d_f, double gate, double s_in, double *d_state,
                              uint16_t *d_x, void *stream);
-/* Training targets d_y[n_cells][N^3] = Q / (rho^2 s_out) from a projected Q. */
+/* Training targets d_y[n_cells][N^3] = Q / (rho |f - M|_2 s_out) from a
+ * projected Q (0 for a cell with f = M). */
 bz_status bz_closure_targets(bz_batch b, const double *d_state, const double *d_Q, double s_out, float *d_y,
                              void *stream);
 /* Qt of every cell with the gate applied (unprojected, like bz_collide_batch). */

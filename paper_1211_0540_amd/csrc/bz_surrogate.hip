@@ -2,9 +2,13 @@
 //
 // For every cell:  rho, u, T (FP64 moments on the mesh), the local Maxwellian
 // M = rho (2 pi T)^{-3/2} exp(-|v-u|^2 / 2T), the deviation d = |f - M|_2 / |M|_2
-// and the gate d < gate.  The network maps x = (f - M) / (rho s_in) (BF16) to
-// y (FP32); the closure is Q_s = rho^2 s_out y (Q is bilinear, so the density
-// scales out exactly).  Gated cells take Q_s, the others the weighted
+// and the gate d < gate.  The network input x (BF16) is the direction of f - M,
+// scaled to unit RMS, with the amplitude d / s_in in the corner entry
+// v = (-L, -L, -L); its output y (FP32) gives the closure
+// Q_s = rho |f - M|_2 s_out y.  Near equilibrium Q is linear in f - M with a
+// coefficient proportional to rho, so y depends on the direction, on d only
+// through the quadratic part, and vanishes with f - M.  Gated cells take Q_s,
+// the others the weighted
 // convolution; the gated cells of one 64-cell group in judge_every (rotating
 // over evaluations, "judged" cells) are also convolved and compared after
 // projection,
@@ -66,19 +70,26 @@ __global__ void __launch_bounds__(256) k_prepare(int N, double dv, const double 
     const double e = block_sum(s4, red) * w / rho;
     const double T = (e - (u1 * u1 + u2 * u2 + u3 * u3)) / 3.0;
     const double nrm = rho * pow(2.0 * M_PI * T, -1.5);
-    double dd = 0, mm = 0;
-    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+    auto maxwell = [&](int j) {
         const double a = dv * (j / (N * N) - N / 2) - u1, b = dv * ((j / N) % N - N / 2) - u2,
                      cc = dv * (j % N - N / 2) - u3;
-        const double Mj = nrm * exp(-(a * a + b * b + cc * cc) / (2.0 * T));
+        return nrm * exp(-(a * a + b * b + cc * cc) / (2.0 * T));
+    };
+    double dd = 0, mm = 0;
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        const double Mj = maxwell(j);
         const double dj = F[j] - Mj;
         dd += dj * dj;
         mm += Mj * Mj;
-        x[(size_t)c * M + j] = f2bf((float)(dj / rho * inv_s_in));
     }
     const double D2 = block_sum(dd, red), M2 = block_sum(mm, red);
+    const double d = sqrt(D2 / M2);
+    // network input: the direction of f - M scaled to unit RMS, and in the corner entry
+    // (v = (-L, -L, -L), where f - M is negligible) the amplitude d / s_in
+    const double sx = D2 > 0 ? sqrt((double)M / D2) : 0.0;
+    for (int j = threadIdx.x; j < M; j += blockDim.x)
+        x[(size_t)c * M + j] = f2bf((float)(j == 0 ? d * inv_s_in : (F[j] - maxwell(j)) * sx));
     if (threadIdx.x == 0) {
-        const double d = sqrt(D2 / M2);
         const bool gated = d < gate && rho > 0 && T > 0;
         // judge whole wavefront groups (one group in judge_every per evaluation, rotating) so
         // that the groups that are not judged can skip the convolution
@@ -137,7 +148,7 @@ __global__ void __launch_bounds__(256) k_finish(int N, double dv, Basis li, cons
     const bool gated = st[6] != 0.0, judged = st[7] != 0.0;
     if (!gated) return;
     double *Q = q + q_off[c];
-    const double sc = st[0] * st[0] * s_out;
+    const double sc = st[0] * st[5] * st[8] * s_out;   // rho |f - M|_2 s_out
     const float *Y = y + (size_t)c * M;
     if (!judged) {
         for (int j = threadIdx.x; j < M; j += blockDim.x) Q[j] = sc * (double)Y[j];
@@ -173,12 +184,13 @@ __global__ void __launch_bounds__(256) k_finish(int N, double dv, Basis li, cons
     // the judged cell keeps the convolution result (fallback)
 }
 
-// y = Q / (rho^2 s_out) for harvesting training targets
+// y = Q / (rho |f - M|_2 s_out) for harvesting training targets (0 where f = M)
 __global__ void k_targets(int N, const double *__restrict__ state, const double *__restrict__ q,
                           const long long *__restrict__ q_off, double inv_s_out, float *__restrict__ y) {
     const int c = blockIdx.y, M = N * N * N;
-    const double r = state[(size_t)c * kState];
-    const double sc = inv_s_out / (r * r);
+    const double *st = state + (size_t)c * kState;
+    const double a = st[0] * st[5] * st[8];
+    const double sc = a > 0 ? inv_s_out / a : 0.0;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < M; j += gridDim.x * blockDim.x)
         y[(size_t)c * M + j] = (float)(q[q_off[c] + j] * sc);
 }

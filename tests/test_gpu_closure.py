@@ -1,6 +1,7 @@
-"""Gated learned closure on the GPU: gate and inputs against the oracle's
-moments, the exact fallbacks (gate closed; judge failing on every cell), and
-a small harvest -> train -> serve run on the wall-heating shock problem."""
+"""Gated learned closure on the GPU: gate and network input against the
+oracle's moments, the exact fallbacks (gate closed; judge failing on every
+cell), and a small harvest -> train -> serve run on the wall-heating shock
+problem."""
 import numpy as np
 import pytest
 import torch
@@ -36,16 +37,25 @@ def test_prepare_matches_oracle_moments(dev):
     f = torch.from_numpy(c.pack(cells)).to(dev)
     state = torch.zeros(70 * 10, dtype=torch.float64, device=dev)
     x = torch.zeros(70 * N ** 3, dtype=torch.int16, device=dev)
-    bz.bz_closure_prepare(c.batch, f, 0.05, 2.0 ** -9, state, x)
+    s_in = 0.05
+    bz.bz_closure_prepare(c.batch, f, 0.05, s_in, state, x)
     st = state.view(70, 10).cpu().numpy()
+    xs = (x.view(torch.int16).to(torch.int32) << 16).view(torch.float32).view(70, -1).cpu().numpy()
     for i in (0, 31, 69):
         rho, u, T, _ = O.moments(cells[i], L)
         assert st[i, 0] == pytest.approx(rho, rel=1e-12)
         assert np.allclose(st[i, 1:4], u, atol=1e-12)
         assert st[i, 4] == pytest.approx(T, rel=1e-12)
         M = W.maxwellian(N, L, rho, u, T)
-        assert st[i, 5] == pytest.approx(np.linalg.norm(cells[i] - M) / np.linalg.norm(M), rel=1e-9)
+        g = (cells[i] - M).ravel()
+        d = np.linalg.norm(g) / np.linalg.norm(M)
+        assert st[i, 5] == pytest.approx(d, rel=1e-9)
         assert st[i, 6] == float(st[i, 5] < 0.05)
+        assert st[i, 8] == pytest.approx(np.linalg.norm(M), rel=1e-9)
+        # network input: direction of f - M at unit RMS, amplitude d / s_in in the corner entry
+        want = g * np.sqrt(g.size) / np.linalg.norm(g)
+        want[0] = d / s_in
+        assert np.allclose(xs[i], want, rtol=2.0 ** -8, atol=2.0 ** -8 * np.abs(want).max())
     c.close()
 
 
@@ -86,32 +96,6 @@ def test_open_gate_serves_the_network(dev, model):
     q, ref, st = _closure_run(dev, model, _cells(64, 4), gate=1e30, judge_every=0)
     assert st["served"] == 64 and st["judged"] == 0
     assert np.all(q == 0.0)          # the untrained closure predicts zero
-
-
-def test_zero_input_calibration(dev):
-    """After calibration the network maps the equilibrium input x = 0 to 0 (FP32 rounding of
-    the bias shift), and inputs away from 0 still reach the trained layers."""
-    M = N ** 3
-    m = ClosureModel(N, L, LAM, hidden=1024, seed=12)
-    master = bz.bz_mlp_get_params(m.net, m.params)
-    rng = np.random.default_rng(3)
-    # give the output layer (W3 [M, 1024], then b3 [M], last in the layout) non-zero
-    # weights and biases so that MLP(0) != 0
-    w3 = slice(len(master) - M - M * 1024, len(master) - M)
-    master[w3] = rng.uniform(-1e-2, 1e-2, M * 1024).astype(np.float32)
-    master[-M:] = rng.uniform(-0.5, 0.5, M).astype(np.float32)
-    bz.bz_mlp_set_params(m.net, m.params, master)
-    n = 32
-    work = torch.zeros(bz.bz_mlp_workspace_bytes(m.net, n), dtype=torch.uint8, device=dev)
-    x0 = torch.zeros(n * M, dtype=torch.int16, device=dev)
-    y = torch.zeros(n, M, dtype=torch.float32, device=dev)
-    bz.bz_mlp_forward(m.net, m.params, x0, n, y, work)
-    before = float(y[0].abs().max())
-    assert before > 0.1
-    m.calibrate_zero()
-    bz.bz_mlp_forward(m.net, m.params, x0, n, y, work)
-    assert float(y.abs().max()) <= 1e-6 * before
-    bz.bz_mlp_free(m.net)
 
 
 def test_harvest_train_serve_shock(dev):
