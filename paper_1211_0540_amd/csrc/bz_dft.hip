@@ -204,6 +204,7 @@ __device__ __forceinline__ void tw_next(int &t, int step) {
 
 // line index of this wavefront (4 per block) and its lane
 #define BZ_LINE_SETUP(SIGN)                                   \
+    if (skip && skip[blockIdx.y]) return;                     \
     __shared__ double2 roots[N];                              \
     load_roots(roots, N, SIGN);                               \
     __syncthreads();                                          \
@@ -217,7 +218,8 @@ __device__ __forceinline__ void tw_next(int &t, int step) {
 // forward, axis 3: real f of cell g*64 + lane, line (j1, j2) -> S (j1, j2, k3)
 template <int N>
 __global__ void __launch_bounds__(256) k_dftg_fwd1(const double *__restrict__ f, const long long *__restrict__ f_off,
-                                                   int nc, double2 *__restrict__ S) {
+                                                   int nc, double2 *__restrict__ S,
+    const unsigned char *__restrict__ skip) {
     BZ_LINE_SETUP(-1.0)
     const int i = g * kWave + lane;
     double x[N];
@@ -270,7 +272,8 @@ __device__ __forceinline__ void line_dft(const double2 (&x)[N], const double2 *r
 
 // forward, axis 2: line (j1, k3): S (j1, j2, k3) -> T (j1, k2, k3)
 template <int N>
-__global__ void __launch_bounds__(256) k_dftg_fwd2(const double2 *__restrict__ S, double2 *__restrict__ T) {
+__global__ void __launch_bounds__(256) k_dftg_fwd2(const double2 *__restrict__ S, double2 *__restrict__ T,
+    const unsigned char *__restrict__ skip) {
     BZ_LINE_SETUP(-1.0)
     const int j1 = line / N, k3 = line - j1 * N;
     const size_t off = (gb + (size_t)j1 * N * N + k3) * kWave + lane;
@@ -285,7 +288,8 @@ __global__ void __launch_bounds__(256) k_dftg_fwd2(const double2 *__restrict__ S
 // plane set to zero (axes in order), copy_stride elements apart
 template <int N, typename Out>
 __global__ void __launch_bounds__(256) k_dftg_fwd3(const double2 *__restrict__ T, int nc, double scale,
-                                                   Out *__restrict__ fh, int copies, long long copy_stride) {
+                                                   Out *__restrict__ fh, int copies, long long copy_stride,
+    const unsigned char *__restrict__ skip) {
     BZ_LINE_SETUP(-1.0)
     const size_t off = (gb + (size_t)line) * kWave + lane;
     double2 x[N];
@@ -332,7 +336,8 @@ __global__ void __launch_bounds__(256) k_dftg_fwd3(const double2 *__restrict__ T
 // E3 at (k3, k1, k2) if k3 < N/2.
 template <int N>
 __global__ void __launch_bounds__(256) k_dftg_inv1_herm(const double2 *__restrict__ qh, int nA, long long pstride,
-                                                        double2 *__restrict__ S) {
+                                                        double2 *__restrict__ S,
+    const unsigned char *__restrict__ skip) {
     BZ_LINE_SETUP(+1.0)
     constexpr int h = N / 2;
     const int k2 = line / N, k3 = line - k2 * N;
@@ -387,7 +392,8 @@ __global__ void __launch_bounds__(256) k_dftg_inv1_herm(const double2 *__restric
 // inverse, axis 1: line (k2, k3): sum of the partial buffers (k1, k2, k3) -> S (j1, k2, k3)
 template <int N>
 __global__ void __launch_bounds__(256) k_dftg_inv1(const double2 *__restrict__ qh, int nparts, long long pstride,
-                                                   double2 *__restrict__ S) {
+                                                   double2 *__restrict__ S,
+    const unsigned char *__restrict__ skip) {
     BZ_LINE_SETUP(+1.0)
     const size_t off = (gb + (size_t)line) * kWave + lane;
     double2 x[N];
@@ -406,7 +412,8 @@ __global__ void __launch_bounds__(256) k_dftg_inv1(const double2 *__restrict__ q
 
 // inverse, axis 2: line (j1, k3): S (j1, k2, k3) -> T (j1, j2, k3)
 template <int N>
-__global__ void __launch_bounds__(256) k_dftg_inv2(const double2 *__restrict__ S, double2 *__restrict__ T) {
+__global__ void __launch_bounds__(256) k_dftg_inv2(const double2 *__restrict__ S, double2 *__restrict__ T,
+    const unsigned char *__restrict__ skip) {
     BZ_LINE_SETUP(+1.0)
     const int j1 = line / N, k3 = line - j1 * N;
     const size_t off = (gb + (size_t)j1 * N * N + k3) * kWave + lane;
@@ -419,7 +426,8 @@ __global__ void __launch_bounds__(256) k_dftg_inv2(const double2 *__restrict__ S
 // inverse, axis 3: line (j1, j2): T (j1, j2, k3) -> Qt (j1, j2, j3) = scale Re(...) of cell g*64 + lane
 template <int N>
 __global__ void __launch_bounds__(256) k_dftg_inv3(const double2 *__restrict__ T, int nc, double scale,
-                                                   double *__restrict__ qt, const long long *__restrict__ q_off) {
+                                                   double *__restrict__ qt, const long long *__restrict__ q_off,
+    const unsigned char *__restrict__ skip) {
     BZ_LINE_SETUP(+1.0)
     const int i = g * kWave + lane;
     const size_t off = (gb + (size_t)line * N) * kWave + lane;
@@ -447,37 +455,37 @@ __global__ void __launch_bounds__(256) k_dftg_inv3(const double2 *__restrict__ T
 
 template <int N>
 hipError_t grouped_forward(double L, int nc, const double *f, const long long *f_off, double2 *S, double2 *T,
-                           void *fh, bool f32, int copies, hipStream_t s) {
+                           void *fh, bool f32, int copies, const unsigned char *skip, hipStream_t s) {
     const int groups = (nc + kWave - 1) / kWave;
     const dim3 grid(N * N / 4, groups);
     const double dv = 2.0 * L / N;
     const double scale = pow(2.0 * kPi, -1.5) * dv * dv * dv;
     const long long cstride = (long long)groups * N * N * N * kWave;
-    hipLaunchKernelGGL(k_dftg_fwd1<N>, grid, dim3(256), 0, s, f, f_off, nc, S);
-    hipLaunchKernelGGL(k_dftg_fwd2<N>, grid, dim3(256), 0, s, S, T);
+    hipLaunchKernelGGL(k_dftg_fwd1<N>, grid, dim3(256), 0, s, f, f_off, nc, S, skip);
+    hipLaunchKernelGGL(k_dftg_fwd2<N>, grid, dim3(256), 0, s, S, T, skip);
     if (f32)
         hipLaunchKernelGGL((k_dftg_fwd3<N, float2>), grid, dim3(256), 0, s, T, nc, scale, (float2 *)fh, copies,
-                           cstride);
+                           cstride, skip);
     else
         hipLaunchKernelGGL((k_dftg_fwd3<N, double2>), grid, dim3(256), 0, s, T, nc, scale, (double2 *)fh, copies,
-                           cstride);
+                           cstride, skip);
     return hipGetLastError();
 }
 
 template <int N>
 hipError_t grouped_inverse(double L, int nc, const double2 *qh, int nparts, long long pstride,
                            const HermAssembly &herm, double2 *S, double2 *T, double *qt, const long long *q_off,
-                           hipStream_t s) {
+                           const unsigned char *skip, hipStream_t s) {
     const int groups = (nc + kWave - 1) / kWave;
     const dim3 grid(N * N / 4, groups);
     const double dz = kPi / L;
     const double scale = pow(2.0 * kPi, -1.5) * dz * dz * dz;
     if (herm.on)
-        hipLaunchKernelGGL(k_dftg_inv1_herm<N>, grid, dim3(256), 0, s, qh, herm.nA, pstride, S);
+        hipLaunchKernelGGL(k_dftg_inv1_herm<N>, grid, dim3(256), 0, s, qh, herm.nA, pstride, S, skip);
     else
-        hipLaunchKernelGGL(k_dftg_inv1<N>, grid, dim3(256), 0, s, qh, nparts, pstride, S);
-    hipLaunchKernelGGL(k_dftg_inv2<N>, grid, dim3(256), 0, s, S, T);
-    hipLaunchKernelGGL(k_dftg_inv3<N>, grid, dim3(256), 0, s, T, nc, scale, qt, q_off);
+        hipLaunchKernelGGL(k_dftg_inv1<N>, grid, dim3(256), 0, s, qh, nparts, pstride, S, skip);
+    hipLaunchKernelGGL(k_dftg_inv2<N>, grid, dim3(256), 0, s, S, T, skip);
+    hipLaunchKernelGGL(k_dftg_inv3<N>, grid, dim3(256), 0, s, T, nc, scale, qt, q_off, skip);
     return hipGetLastError();
 }
 
@@ -486,11 +494,12 @@ hipError_t grouped_inverse(double L, int nc, const double2 *qh, int nparts, long
 #define BZ_FOR_EACH_N(X) X(8) X(12) X(16) X(20) X(24) X(28) X(32)
 
 hipError_t launch_dft_forward_grouped(int N, double L, int ncells, const double *f, const long long *d_f_off,
-                                      double2 *S, double2 *T, void *fh, bool out_f32, int copies, hipStream_t s) {
+                                      double2 *S, double2 *T, void *fh, bool out_f32, int copies,
+                                      const unsigned char *skip, hipStream_t s) {
     if (ncells <= 0) return hipSuccess;
     if (copies != 1 && copies != 4) return hipErrorInvalidValue;
 #define CASE(NN) \
-    case NN: return grouped_forward<NN>(L, ncells, f, d_f_off, S, T, fh, out_f32, copies, s);
+    case NN: return grouped_forward<NN>(L, ncells, f, d_f_off, S, T, fh, out_f32, copies, skip, s);
     switch (N) {
         BZ_FOR_EACH_N(CASE)
     default:
@@ -501,10 +510,10 @@ hipError_t launch_dft_forward_grouped(int N, double L, int ncells, const double 
 
 hipError_t launch_dft_inverse_grouped(int N, double L, int ncells, const double2 *qh, int nparts, long long pstride,
                                       const HermAssembly &herm, double2 *S, double2 *T, double *qt,
-                                      const long long *d_q_off, hipStream_t s) {
+                                      const long long *d_q_off, const unsigned char *skip, hipStream_t s) {
     if (ncells <= 0) return hipSuccess;
 #define CASE(NN) \
-    case NN: return grouped_inverse<NN>(L, ncells, qh, nparts, pstride, herm, S, T, qt, d_q_off, s);
+    case NN: return grouped_inverse<NN>(L, ncells, qh, nparts, pstride, herm, S, T, qt, d_q_off, skip, s);
     switch (N) {
         BZ_FOR_EACH_N(CASE)
     default:

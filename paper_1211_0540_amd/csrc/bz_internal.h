@@ -194,12 +194,14 @@ hipError_t launch_expand_plain(int N, const double *dT, int qstride, double scal
 // the inverse, which reads qh only in its first pass)
 // With `copies` = 4 the last pass also writes fhat with the axes ordered
 // (2, 1, 3) and (3, 1, 2), and fhat with its k_d = 0 planes zeroed, after the
-// first copy, G * N^3 * 64 elements apart.
+// first copy, G * N^3 * 64 elements apart.  Groups g with skip[g] != 0 (skip
+// may be NULL) are left untouched by both directions.
 hipError_t launch_dft_forward_grouped(int N, double L, int ncells, const double *f, const long long *d_f_off,
-                                      double2 *S, double2 *T, void *fh, bool out_f32, int copies, hipStream_t s);
+                                      double2 *S, double2 *T, void *fh, bool out_f32, int copies,
+                                      const unsigned char *skip, hipStream_t s);
 hipError_t launch_dft_inverse_grouped(int N, double L, int ncells, const double2 *qh, int nparts, long long pstride,
                                       const HermAssembly &herm, double2 *S, double2 *T, double *qt,
-                                      const long long *d_q_off, hipStream_t s);
+                                      const long long *d_q_off, const unsigned char *skip, hipStream_t s);
 hipError_t launch_dft_forward(int N, double L, int ncells, const double *f, const long long *d_f_off,
                               double2 *scratch, void *out, bool out_f32, const long long *d_o_base,
                               long long o_stride, hipStream_t s);

@@ -442,6 +442,9 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
             if (grid_of_cell[c] == gi) p.cells.push_back(c);
         if (p.cells.empty()) continue;
         p.groups = (int)((p.cells.size() + kWave - 1) / kWave);
+        // untuned default: the output-slot variant with interleaved partials from N = 24 on,
+        // the in-register FP64 total with interleaved partials below (measured on MI355X)
+        p.variant = p.g->N >= 24 ? 10 : 13;
         for (auto &kv : g_tuned)
             if (kv.first == tune_key(p.g->N, p.groups, mode)) p.variant = kv.second;
         b->parts.push_back(std::move(p));
@@ -742,7 +745,8 @@ static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void 
         if (batched(b->mode)) {
             const int nc = (int)p.cells.size();
             // the first partial buffer of qh serves as the second scratch buffer of the transforms
-            BZ_HIP(launch_dft_forward_grouped(N, p.g->L, nc, d_f, p.d_f_off, scratch, qh, fh, !f64, p.herm ? 4 : 1, s),
+            BZ_HIP(launch_dft_forward_grouped(N, p.g->L, nc, d_f, p.d_f_off, scratch, qh, fh, !f64, p.herm ? 4 : 1, skip,
+                                              s),
                    "forward transform");
             const long long pstride = (long long)p.groups * M * kWave;  // one copy of fhat, one output buffer
             CellsLaunch cl{N, fh, p.d_items, p.n_items, (unsigned *)(ws + p.ws_counter), qh, pstride, 0, skip, {}};
@@ -762,8 +766,10 @@ static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void 
             BZ_HIP(launch_conv_cells(cl, f64, s), "batched convolution");
             if (b->timing) BZ_HIP(hipEventRecord(ev.second, s), "timer stop");
             const HermAssembly herm{p.herm, p.parts};
+            // groups whose cells are all served by the closure (skip) need no transforms: the
+            // closure writes their outputs
             BZ_HIP(launch_dft_inverse_grouped(N, p.g->L, nc, qh, p.parts, pstride, herm, scratch, qh, d_Qt, p.d_f_off,
-                                              s),
+                                              skip, s),
                    "inverse transform");
         } else {
             const int sp = plain_split_for(N);

@@ -108,17 +108,18 @@ __global__ void __launch_bounds__(256) k_prepare(int N, double dv, const double 
     }
 }
 
-// skip[g] = every live cell of group g gated and not judged
-__global__ void k_group_skip(int n_cells, const double *__restrict__ state, unsigned char *__restrict__ skip) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    const int groups = (n_cells + kWave - 1) / kWave;
-    if (g >= groups) return;
-    bool s = true;
-    for (int c = g * kWave; c < n_cells && c < (g + 1) * kWave; ++c) {
+// skip[g] = every live cell of group g gated and not judged (one wavefront per group,
+// lane = cell)
+__global__ void __launch_bounds__(64) k_group_skip(int n_cells, const double *__restrict__ state,
+                                                   unsigned char *__restrict__ skip) {
+    const int g = blockIdx.x, c = g * kWave + threadIdx.x;
+    bool served = true;
+    if (c < n_cells) {
         const double *st = state + (size_t)c * kState;
-        s = s && st[6] != 0.0 && st[7] == 0.0;
+        served = st[6] != 0.0 && st[7] == 0.0;
     }
-    skip[g] = s ? 1 : 0;
+    const bool all = __all(served);
+    if (threadIdx.x == 0) skip[g] = all ? 1 : 0;
 }
 
 struct Basis {
@@ -207,7 +208,7 @@ hipError_t launch_sur_prepare(int N, double dv, int n, const double *f, const lo
 
 hipError_t launch_group_skip(int n, const double *state, unsigned char *skip, hipStream_t s) {
     const int groups = (n + kWave - 1) / kWave;
-    hipLaunchKernelGGL(k_group_skip, dim3((groups + 63) / 64), dim3(64), 0, s, n, state, skip);
+    hipLaunchKernelGGL(k_group_skip, dim3(groups), dim3(kWave), 0, s, n, state, skip);
     return hipGetLastError();
 }
 
