@@ -382,7 +382,35 @@ def main():
     b64 = q64.cpu().numpy()
     errs = [float(np.linalg.norm(x - y) / np.linalg.norm(y)) for x, y in zip(col.unpack(a), plain.unpack(b64))]
     comp["rel_l2_fp32_batched_vs_fp64_plain"] = {"median": float(np.median(errs)), "max": float(np.max(errs)),
+                                                 "frac_le_1e-5": float(np.mean(np.array(errs) <= 1e-5)),
                                                  "cells": nc}
+    # the accumulation variants that fold into the FP64 total more often: accuracy against speed
+    acc = {}
+    for v in (14, 15):
+        try:
+            col.set_variant(v)
+            qv = col.project(col.collide(f0))
+            fv = f0.clone()
+            col.step(fv, dt_over_eps)
+            torch.cuda.synchronize()
+            bz.bz_batch_timer_read(col.batch)
+            bz.bz_batch_timer(col.batch, True)
+            t0 = time.perf_counter()
+            for _ in range(3):
+                col.step(fv, dt_over_eps)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / 3 * 1e3
+            bz.bz_batch_timer(col.batch, False)
+            cms, k = bz.bz_batch_timer_read(col.batch)
+            ev = np.array([np.linalg.norm(x - y) / np.linalg.norm(y)
+                           for x, y in zip(col.unpack(qv.cpu().numpy()), plain.unpack(b64))])
+            acc[str(v)] = {"ms_per_step": ms, "cell_evals_per_s": 2 * nc / ms * 1e3, "conv_avg_ms": cms / max(k, 1),
+                           "rel_l2_vs_fp64": {"median": float(np.median(ev)), "max": float(ev.max()),
+                                              "frac_le_1e-5": float(np.mean(ev <= 1e-5))}}
+        except Exception as exc:
+            acc[str(v)] = {"error": str(exc)}
+    col.set_variant(variant)
+    comp["accuracy_variants"] = acc
     plain.close()
     # batched FP64
     b64c = bz.Collision([(N, L, lam)], [0] * nc, "batched_f64", weights_cache=wcache)

@@ -138,7 +138,8 @@ def test_relaxation_cell_n32_fp64_plain(dev):
     assert max_rel(q, q_o) < 1e-12
 
 
-@pytest.mark.parametrize("N,L,n", [(8, 4.0, 3), (12, 5.0, 70), (16, 6.0, 65), (20, 6.0, 2)])
+@pytest.mark.parametrize("N,L,n", [(8, 4.0, 3), (12, 5.0, 70), (16, 6.0, 65), (20, 6.0, 2), (24, 7.0, 2),
+                                   (28, 7.0, 1), (32, 8.0, 2)])
 def test_symmetric_schedule_equals_full_sum_fp64(dev, N, L, n):
     """The conjugate-symmetric schedule (half the rows, edge passes, mirrored assembly)
     gives the full FP64 sum to rounding, for every cell and output, on several meshes and
