@@ -15,7 +15,7 @@
  * elastic collisions beta = 1, radial cut-off r0 = L).
  *
  * Conventions for every entry point:
- *   - Mesh (Sec. 3.1): N even, 8 <= N <= 32, half-width L > 0;
+ *   - Mesh (Sec. 3.1): N a multiple of 4, 8 <= N <= 32, half-width L > 0;
  *     v_k = (2L/N)(k - N/2), zeta_k = (pi/L)(k - N/2), k = 0..N-1.
  *   - A cell is N^3 FP64 values, C-contiguous, flat index (k1*N + k2)*N + k3;
  *     axis 1 is the transport direction v1.  The cells of a batch are stored
@@ -86,10 +86,11 @@ typedef struct {
     long long pairs;     /* valid (zeta_k, xi_m) pairs of the convolution: (3N^2/4)^3 */
 } bz_grid_info;
 
-/* Create a mesh handle.  Host only, no device work.  Errors: BZ_EINVAL for
- * odd N, N outside [8, 32], L <= 0 or non-finite; BZ_EUNSUPPORTED for lambda
- * outside [0, 1] (integer lambda uses the closed form of eq. GHat_calc, other
- * values a 64-point Gauss-Legendre rule). */
+/* Create a mesh handle.  Host only, no device work.  Errors: BZ_EINVAL for N
+ * not a multiple of 4, N outside [8, 32], L <= 0 or non-finite;
+ * BZ_EUNSUPPORTED for lambda other than 0 (Maxwell molecules) or 1 (hard
+ * spheres), the two exponents whose weight integral the library evaluates in
+ * closed form. */
 bz_status bz_grid_init(int N, double L, double lambda, bz_grid *out);
 void bz_grid_free(bz_grid g);
 bz_status bz_grid_query(bz_grid g, bz_grid_info *info);
@@ -105,7 +106,10 @@ bz_status bz_grid_coords(bz_grid g, double *v, double *zeta);
 /* and are expanded into the caller's buffer in the order the chosen      */
 /* schedule reads them (dzeta^3 folded in).                               */
 /* ------------------------------------------------------------------ */
-/* Bytes needed for a weight buffer of the given kind (0 for an unknown kind). */
+/* Bytes needed for a weight buffer of the given kind (0 for an unknown kind).
+ * A batched buffer holds the weight stream of every output row in schedule
+ * order and, after it, the stream of the edge pass of the conjugate-symmetric
+ * schedule (bz_batch_create_ex). */
 size_t bz_weights_bytes(bz_grid g, int kind);
 /* Fill d_w (bytes >= bz_weights_bytes) on `stream`.  Synchronises the stream
  * before returning (it uploads a host-built table).  Errors: BZ_EINVAL for a
