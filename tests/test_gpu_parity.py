@@ -240,6 +240,27 @@ def test_bench_workload_n32_full_batch(dev):
           % (np.median(errs), errs.max(), 100 * np.mean(errs <= 1e-5)))
 
 
+@pytest.mark.parametrize("mode", ["batched_f64", "batched_f32"])
+def test_degenerate_cells_zero_and_maxwellian(dev, mode):
+    """Degenerate inputs in one ragged batch: f = 0 gives Q = 0 exactly; an exact discrete
+    Maxwellian gives only the discretisation residual, matched to the oracle within the
+    rounding bound of its cancellation (kappa ~ 1e4); the neighbouring cells are unaffected."""
+    N, L, lam = 16, 6.0, 1.0
+    smooth = list(W.random_smooth_cells(3, N, L, seed=6))
+    maxw = W.maxwellian(N, L, 1.3, (0.4, -0.2, 0.1), 0.9)
+    cells = [np.zeros((N, N, N)), smooth[0], maxw, smooth[1], np.zeros((N, N, N)), smooth[2]]
+    _, qs = run([(N, L, lam)], [0] * len(cells), cells, mode, dev)
+    assert not np.any(qs[0]) and not np.any(qs[4])
+    o = oracle_for(N, L, lam)
+    u = 2.0 ** -52 if mode == "batched_f64" else U32
+    floor = 1e-12 if mode == "batched_f64" else 1e-5
+    for i in (1, 2, 3, 5):
+        _, q_o, _, _ = o.collide(cells[i])
+        kap = _kappa(cells[i], N, L, lam)
+        assert rel_l2(qs[i], q_o) < max(floor, 8 * u * kap), (i, kap)
+        assert_conserved(qs[i], N, L)
+
+
 def test_batched_fp32_is_deterministic(dev):
     N, L, lam = 16, 6.0, 1.0
     cells = list(W.random_smooth_cells(80, N, L, seed=9))
