@@ -167,7 +167,7 @@ def uneven_leg(torch, np, bz, W, steps=5):
     gidx = [{16: 0, 24: 1, 32: 2}[int(n)] for n in batch.Ns]
     c32 = bz.Collision(meshes, gidx, "batched_f32")
     f0 = torch.from_numpy(c32.pack(batch.cells)).cuda()
-    variants = c32.autotune(f0, reps=1)
+    variants = c32.autotune(f0, reps=2)
     q32 = c32.project(c32.collide(f0)).cpu().numpy()
     c64 = bz.Collision(meshes, gidx, "batched_f64")
     q64 = c64.project(c64.collide(f0)).cpu().numpy()
@@ -184,9 +184,30 @@ def uneven_leg(torch, np, bz, W, steps=5):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - a) / steps * 1e3
     c32.check()
+    # the same step captured as one HIP graph (three meshes, all their launches) and replayed
+    graph = None
+    try:
+        gs = torch.cuda.Stream()
+        fg = f.clone()
+        wg = torch.zeros_like(c32.work)
+        with torch.cuda.stream(gs):
+            gh = bz.bz_graph_capture_step(c32.batch, fg, 0.01, wg, gs)
+        torch.cuda.synchronize()
+        bz.bz_graph_launch(gh, gs)
+        gs.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(gs)
+        for _ in range(steps):
+            bz.bz_graph_launch(gh, gs)
+        e1.record(gs)
+        gs.synchronize()
+        graph = {"ms_per_step": e0.elapsed_time(e1) / steps}
+        bz.bz_graph_free(gh)
+    except Exception as exc:
+        graph = {"error": str(exc)}
     c32.close()
     return {"workload": "1024 cells of the seeded uneven draw (521 N=16, 313 N=24, 190 N=32), one batch",
-            "ms_per_step": ms, "cell_evals_per_s": 2 * len(batch.Ns) / ms * 1e3,
+            "ms_per_step": ms, "cell_evals_per_s": 2 * len(batch.Ns) / ms * 1e3, "graph_replay": graph,
             "variants_N16_N24_N32": variants,
             "rel_l2_fp32_vs_fp64": {str(k): {"median": float(np.median(v)), "max": float(np.max(v)),
                                              "frac_le_1e-5": float(np.mean(np.array(v) <= 1e-5))}
