@@ -17,8 +17,11 @@ The JSON line also carries:
                 processed is also given.
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same cells
   comparisons   the plain unbatched FP64 path on the same GPU, the batched
-                FP64 path, and the relative L2 error of the FP32 result
-                against the FP64 plain result for every cell
+                FP64 path, the relative L2 error of the FP32 result against
+                the FP64 plain result for every cell, the accuracy-oriented
+                accumulation variants, graph replay, the full-sum schedule,
+                the N=32 relaxation, the whole uneven batch, and the gated
+                closure on the shock problem at N=24 and N=32
 """
 import argparse
 import hashlib
@@ -214,17 +217,18 @@ def uneven_leg(torch, np, bz, W, steps=5):
                                     for k, v in errs.items()}}
 
 
-def closure_leg(args, torch, np, bz, W):
-    """Harvest (f, Q) pairs on the N=24 shock problem and homogeneous relaxations,
-    train the 13824-1024-1024-13824 network with the library's kernels, then time
-    Strang steps of the 256-cell shock problem with and without the gated closure
+def closure_leg(args, torch, np, bz, W, N=24, L=7.0, snapshots=600, relax_cells=512):
+    """Harvest (f, Q) pairs on the shock problem and homogeneous relaxations on the
+    N^3 mesh, train the N^3-1024-1024-N^3 network with the library's kernels, then
+    time Strang steps of the 256-cell shock problem with and without the gated closure
     (gate 0.05, one group in 16 judged) and compare the temperature profiles."""
     import oracle as O
     from paper_1211_0540_amd.closure import ClosureModel
-    N, L, lam, nx, eps = 24, 7.0, 1.0, 256, 0.1
+    lam, nx, eps = 1.0, 256, 0.1
     t0 = time.perf_counter()
     m = ClosureModel(N, L, lam, hidden=1024, seed=1211)
-    rows = m.harvest_shock(snapshots=600, every=1, keep=0.1) + m.harvest_relaxation(cells=512, steps=40, keep=0.1)
+    rows = (m.harvest_shock(snapshots=snapshots, every=1, keep=0.1)
+            + m.harvest_relaxation(cells=relax_cells, steps=40, keep=0.1))
     torch.cuda.synchronize()
     t_harvest = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -261,7 +265,7 @@ def closure_leg(args, torch, np, bz, W):
     bz.bz_transport_free(t)
     c.close()
     evals = 2 * nx * K
-    return {"workload": "256-cell N=24 shock problem (wall T=2, Kn 0.1), 300 Strang steps",
+    return {"workload": f"256-cell N={N} shock problem (wall T=2, Kn 0.1), 300 Strang steps",
             "training_rows": rows, "harvest_s": t_harvest, "train_steps": TRAIN_STEPS,
             "train_s": t_train,
             "loss_first_last": [hist[0][1], hist[-1][1]], "heldout_rel_l2": val, "heldout_median_row_rel_l2": val_median,
@@ -463,12 +467,15 @@ def main():
             comp[key] = {"error": str(exc)}
         torch.cuda.empty_cache()
 
-    # ---- learned closure on the N=24 shock problem ----------------------
+    # ---- learned closure on the N=24 shock problem, and on the N=32 mesh of the metric
     if not args.no_closure:
-        try:
-            comp["closure_shock_n24"] = closure_leg(args, torch, np, bz, W)
-        except Exception as exc:
-            comp["closure_shock_n24"] = {"error": str(exc)}
+        for key, kw in (("closure_shock_n24", {}),
+                        ("closure_shock_n32", dict(N=32, L=8.0, snapshots=400, relax_cells=256))):
+            try:
+                comp[key] = closure_leg(args, torch, np, bz, W, **kw)
+            except Exception as exc:
+                comp[key] = {"error": str(exc)}
+            torch.cuda.empty_cache()
 
     # ---- CPU oracle baseline ------------------------------------------
     cpu = None
