@@ -514,6 +514,8 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "kernel": "k_conv_cells_f32<32>", "flops_per_launch": 10.0 * P * nc,
                      "avg_launch_ms": conv_avg_ms, "launches": conv_launches,
+                     "traffic_gb_per_s": (traffic / (conv_avg_ms * 1e-3) / 1e9) if traffic else None,
+                     "hbm_peak_gb_per_s": HBM_TBPS * 1e3,
                      "schedule": "conjugate-symmetric",
                      "slots_vs_full_sum": slot_frac,
                      "achieved_on_processed_slots": achieved * slot_frac,
