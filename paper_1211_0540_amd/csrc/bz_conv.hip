@@ -20,7 +20,11 @@
 //   operations per visited pair: 4 for the complex product fhat_m fhat_j and 2
 //   FMAs that add its weighted parts to a fresh per-output partial of the step,
 //   plus 2 additions per output and step into the running sums.  Work items are popped from an atomic
-//   queue ordered longest first, so the launch is persistent.
+//   queue ordered longest first, so the launch is persistent.  Every item names
+//   its pass of the conjugate-symmetric schedule (bz_internal.h): which fhat
+//   copy it reads, which weight stream and which output buffer it writes; the
+//   full-sum schedule uses pass A only.  Steps of pass A whose rows lie on a
+//   zeroed plane of its fhat copy are skipped.
 //
 //   FP32 variant: products, per-step partials and a running sum over FOLD
 //   steps in FP32 (the running sum takes one rounding per output and step);
