@@ -165,7 +165,7 @@ __device__ inline int pop_item(unsigned *counter) {
 template <int N, int FOLD, int COMP, int WP, int RP, int SPLIT>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(COMP == 2 ? 2 : 1)))
 k_conv_cells_f32(const float2 *__restrict__ fh, const int4 *__restrict__ items, int n_items,
-                 unsigned *__restrict__ counter, double2 *__restrict__ qh, long long part_stride,
+                 unsigned *__restrict__ counter, double2 *__restrict__ qh,
                  const unsigned char *__restrict__ skip, const ConvPasses ps) {
     constexpr int h = N / 2, M = N * N * N, PS = 3 * N * N / 4;
     constexpr int CH = (PS * 4 + 1023) / 1024;       // KiB per step of weights
@@ -182,7 +182,7 @@ k_conv_cells_f32(const float2 *__restrict__ fh, const int4 *__restrict__ items, 
         const int g = item.x, r = item.y & 0xffff, part = (item.y >> 16) & 0xf, s0 = item.z, s1 = item.w;
         const ConvPass cp = pick_pass(ps, item.y >> 20);
         const int k1 = r / N, k2 = r - k1 * N;
-        double2 *const out = qh + cp.out_off + part * part_stride + (size_t)g * M * kWave + (size_t)r * N * kWave + lane;
+        double2 *const out = qh + cp.out_off + part * cp.pstride + g * cp.gstride + (size_t)(r - cp.row0) * N * kWave + lane;
         if (skip && skip[g]) {
             // every cell of the group is served elsewhere: leave zeros in this item's outputs
 #pragma unroll
@@ -309,7 +309,7 @@ k_conv_cells_f32(const float2 *__restrict__ fh, const int4 *__restrict__ items, 
 template <int N>
 __global__ void __launch_bounds__(64) k_conv_cells_f64(const double2 *__restrict__ fh, const int4 *__restrict__ items,
                                                        int n_items, unsigned *__restrict__ counter,
-                                                       double2 *__restrict__ qh, long long part_stride,
+                                                       double2 *__restrict__ qh,
                                                        const unsigned char *__restrict__ skip, const ConvPasses ps) {
     constexpr int h = N / 2, M = N * N * N, PS = 3 * N * N / 4;
     constexpr int CH = (PS * 8 + 1023) / 1024;
@@ -323,7 +323,7 @@ __global__ void __launch_bounds__(64) k_conv_cells_f64(const double2 *__restrict
         const int g = item.x, r = item.y & 0xffff, part = (item.y >> 16) & 0xf, s0 = item.z, s1 = item.w;
         const ConvPass cp = pick_pass(ps, item.y >> 20);
         const int k1 = r / N, k2 = r - k1 * N;
-        double2 *const out = qh + cp.out_off + part * part_stride + (size_t)g * M * kWave + (size_t)r * N * kWave + lane;
+        double2 *const out = qh + cp.out_off + part * cp.pstride + g * cp.gstride + (size_t)(r - cp.row0) * N * kWave + lane;
         if (skip && skip[g]) {
             // every cell of the group is served elsewhere: leave zeros in this item's outputs
 #pragma unroll
@@ -447,8 +447,7 @@ template <int N>
 hipError_t cells_f32_variant(const CellsLaunch &p, unsigned grid, hipStream_t s) {
 #define BZ_CELLS_F32(F, C, WPV, RPV, SP)                                                                    \
     hipLaunchKernelGGL((k_conv_cells_f32<N, F, C, WPV, RPV, SP>), dim3(grid), dim3(64), 0, s,               \
-                       (const float2 *)p.fh, p.items, p.n_items, p.counter, p.qh, p.part_stride, p.skip,     \
-                       p.passes)
+                       (const float2 *)p.fh, p.items, p.n_items, p.counter, p.qh, p.skip, p.passes)
     switch (p.variant) {
     case 1: BZ_CELLS_F32(2, 1, 0, 1, 1); break;
     case 2: BZ_CELLS_F32(2, 0, 0, 0, 1); break;
@@ -474,7 +473,7 @@ hipError_t cells_f32_variant(const CellsLaunch &p, unsigned grid, hipStream_t s)
 template <int N>
 hipError_t cells_f64_launch(const CellsLaunch &p, unsigned grid, hipStream_t s) {
     hipLaunchKernelGGL((k_conv_cells_f64<N>), dim3(grid), dim3(64), 0, s, (const double2 *)p.fh, p.items,
-                       p.n_items, p.counter, p.qh, p.part_stride, p.skip, p.passes);
+                       p.n_items, p.counter, p.qh, p.skip, p.passes);
     return hipGetLastError();
 }
 

@@ -327,8 +327,8 @@ __global__ void __launch_bounds__(256) k_dftg_fwd3(const double2 *__restrict__ T
 }
 
 // inverse, axis 1, conjugate-symmetric schedule: assemble Qhat(k1, k2, k3) of line (k2, k3) from the
-// passes (qh: nA partial buffers of pass A, then E1, E2, E3, then nA partial buffers of Z), then
-// transform -> S (j1, k2, k3).  Pass A holds the interior sums I of the direct rows.
+// passes (qh: nA partial buffers of pass A, then the half-size E1, E2, E3, then nA partial buffers
+// of Z, laid out as HermAssembly describes; pstride = one full buffer), then transform -> S (j1, k2, k3).  Pass A holds the interior sums I of the direct rows.
 //   direct row (k1, k2):        Qhat = I(k) + E(k)
 //   derived row, k3 = 0:        Qhat = Z at (0, k1, k2) of the (3, 1, 2) order
 //   derived row, k3 >= 1:       Qhat = conj I(k') + E(k),   k' = N - k
@@ -341,14 +341,18 @@ __global__ void __launch_bounds__(256) k_dftg_inv1_herm(const double2 *__restric
     BZ_LINE_SETUP(+1.0)
     constexpr int h = N / 2;
     const int k2 = line / N, k3 = line - k2 * N;
+    // pstride = B, one full buffer; group bases of the full, edge (half) and Z buffers
     const size_t gl = gb * kWave + lane;
+    const size_t ge = (size_t)g * (M / 2) * kWave + lane;
+    const size_t gz = (size_t)g * h * N * kWave + lane;
     const double2 *E1 = qh + (size_t)nA * pstride;
-    const double2 *E2 = E1 + pstride, *E3 = E2 + pstride, *Z = E3 + pstride;  // Z: nA partial buffers
+    const double2 *E2 = E1 + pstride / 2, *E3 = E2 + pstride / 2, *Z = E3 + pstride / 2;
+    const size_t zstride = (size_t)pstride / (2 * N);
     auto at = [](int a, int b, int c) { return ((size_t)(a * N + b) * N + c) * kWave; };
-    auto sum_parts = [&](const double2 *base, size_t o) {
-        double2 a = base[gl + o];
+    auto sum_parts = [&](const double2 *base, size_t o, size_t stride) {
+        double2 a = base[o];
         for (int p = 1; p < nA; ++p) {
-            const double2 b = base[gl + o + (size_t)p * pstride];
+            const double2 b = base[o + (size_t)p * stride];
             a.x += b.x;
             a.y += b.y;
         }
@@ -357,17 +361,17 @@ __global__ void __launch_bounds__(256) k_dftg_inv1_herm(const double2 *__restric
     auto edge = [&](int a, int b, int c) {
         double2 e = make_double2(0.0, 0.0);
         if (a < h) {
-            const double2 t = E1[gl + at(a, b, c)];
+            const double2 t = E1[ge + at(a, b, c)];
             e.x += t.x;
             e.y += t.y;
         }
         if (b < h) {
-            const double2 t = E2[gl + at(b, a, c)];
+            const double2 t = E2[ge + at(b, a, c)];
             e.x += t.x;
             e.y += t.y;
         }
         if (c < h) {
-            const double2 t = E3[gl + at(c, a, b)];
+            const double2 t = E3[ge + at(c, a, b)];
             e.x += t.x;
             e.y += t.y;
         }
@@ -377,12 +381,13 @@ __global__ void __launch_bounds__(256) k_dftg_inv1_herm(const double2 *__restric
 #pragma unroll
     for (int k1 = 0; k1 < N; ++k1) {
         if (!herm_derived_row(N, k1, k2)) {
-            const double2 i = sum_parts(qh, at(k1, k2, k3)), e = edge(k1, k2, k3);
+            const double2 i = sum_parts(qh, gl + at(k1, k2, k3), pstride), e = edge(k1, k2, k3);
             x[k1] = make_double2(i.x + e.x, i.y + e.y);
         } else if (k3 == 0) {
-            x[k1] = sum_parts(Z, at(0, k1, k2));
+            // derived rows have k1 >= N/2: Z slot (k1 - N/2, k2) of the k3 = 0 plane
+            x[k1] = sum_parts(Z, gz + ((size_t)(k1 - h) * N + k2) * kWave, zstride);
         } else {
-            const double2 i = sum_parts(qh, at(N - k1, N - k2, N - k3)), e = edge(k1, k2, k3);
+            const double2 i = sum_parts(qh, gl + at(N - k1, N - k2, N - k3), pstride), e = edge(k1, k2, k3);
             x[k1] = make_double2(i.x + e.x, e.y - i.y);
         }
     }

@@ -112,8 +112,10 @@ __host__ __device__ inline bool herm_derived_row(int N, int k1, int k2) {
 }
 enum ConvPassId { kPassA = 0, kPassE1 = 1, kPassE2 = 2, kPassE3 = 3, kPassZ = 4, kPasses = 5 };
 // Assembly of Qhat from the passes of the conjugate-symmetric schedule, done by
-// the first inverse-transform pass: buffers [0, nA) hold pass A's partial sums,
-// then E1, E2, E3, then nA partial sums of pass Z, each part_stride apart.
+// the first inverse-transform pass.  With B = G N^3 64 complex elements (one
+// full buffer): pass A's nA partial sums at [0, nA B); then E1, E2 and E3, B/2
+// each (rows a < N/2 only, N^3/2 64 per group); then nA partial sums of pass Z,
+// B / (2N) each (rows k1 = N/2..N-1 of the k3 = 0 plane, N^2/2 64 per group).
 struct HermAssembly {
     bool on;
     int nA;
@@ -223,6 +225,9 @@ struct ConvPass {
     const void *w;               // weight stream
     const long long *row_woff;   // device, N*N offsets of the rows in w (elements)
     int zero_planes;             // fhat copy has its k_d = 0 planes zeroed: skip steps with m2 = 0 or j2 = 0
+    int row0;                    // first row the pass writes: row r goes to slot r - row0
+    long long gstride;           // complex elements per group in the pass's output buffer
+    long long pstride;           // complex elements between its partial-sum buffers
 };
 struct ConvPasses {
     ConvPass p[kPasses];
@@ -236,8 +241,7 @@ struct CellsLaunch {
     const int4 *items;           // device, longest first
     int n_items;
     unsigned *counter;           // device, zeroed by the launcher's fill kernel
-    double2 *qh;                 // [buffers][G][N^3][64]
-    long long part_stride;       // complex elements between output buffers
+    double2 *qh;                 // output buffers of the passes (ConvPass.out_off, gstride, pstride)
     int variant;                 // tuning variant
     const unsigned char *skip;   // device, per group: 1 = outputs not needed (may be NULL)
     ConvPasses passes;

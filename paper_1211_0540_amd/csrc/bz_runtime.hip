@@ -206,7 +206,6 @@ struct Part {
     int n_items = 0;
     bool herm = false;               // conjugate-symmetric (halved) batched schedule
     int parts = 1;                   // partial-sum buffers of pass A (and of pass Z) of the batched schedule
-    int qbufs = 1;                   // output buffers in qh
     int variant = 0;                 // convolution kernel variant
     std::vector<long long> f_off;    // host copy
     // workspace offsets (bytes)
@@ -489,7 +488,6 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
             int parts = (int)(((p.herm ? 4096 : 8192) + rows - 1) / rows);
             parts = std::max(1, std::min(parts, 8));
             p.parts = parts;
-            p.qbufs = p.herm ? 2 * parts + 3 : parts;
             std::vector<int4> items;
             const std::vector<int> &st = p.g->sched.row_steps;
             // every item writes its whole output slot, so an empty step range still
@@ -534,8 +532,12 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
         if (bat) {
             p.ws_fh = ws;
             ws = align256(ws + (size_t)(p.herm ? 4 : 1) * p.groups * M * kWave * cs);
+            // qhat buffers, in units of B = one full output buffer: pass A's partial sums (B
+            // each), then E1, E2, E3 (rows k_a < N/2: B/2 each) and Z's partial sums (the
+            // rows N/2..N-1 of one plane: B/(2N) each)
+            const size_t B = (size_t)p.groups * M * kWave;
             p.ws_qh = ws;
-            ws = align256(ws + (size_t)p.qbufs * p.groups * M * kWave * 16);
+            ws = align256(ws + (p.parts * B + (p.herm ? 3 * (B / 2) + p.parts * (B / (2 * N)) : 0)) * 16);
         } else {
             const int sp = plain_split_for(N);
             p.ws_fh = ws;
@@ -749,14 +751,16 @@ static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void 
                                               s),
                    "forward transform");
             const long long pstride = (long long)p.groups * M * kWave;  // one copy of fhat, one output buffer
-            CellsLaunch cl{N, fh, p.d_items, p.n_items, (unsigned *)(ws + p.ws_counter), qh, pstride, 0, skip, {}};
+            CellsLaunch cl{N, fh, p.d_items, p.n_items, (unsigned *)(ws + p.ws_counter), qh, 0, skip, {}};
             const void *w_e3 = (const char *)p.w + e3_base_bytes(p.g, f64 ? 8 : 4);
-            const long long P = p.parts;
-            cl.passes.p[kPassA] = ConvPass{p.herm ? 3 * pstride : 0, 0, p.w, p.d_row_woff, p.herm ? 1 : 0};
-            cl.passes.p[kPassE1] = ConvPass{0, P * pstride, p.w, p.d_row_woff, 0};
-            cl.passes.p[kPassE2] = ConvPass{pstride, (P + 1) * pstride, p.w, p.d_row_woff, 0};
-            cl.passes.p[kPassE3] = ConvPass{2 * pstride, (P + 2) * pstride, w_e3, p.d_e3_woff, 0};
-            cl.passes.p[kPassZ] = ConvPass{2 * pstride, (P + 3) * pstride, p.w, p.d_row_woff, 0};
+            // output layout as HermAssembly describes; the full schedule has pass A only
+            const long long P = p.parts, gM = M * kWave, gE = gM / 2, gZ = (long long)(N / 2) * N * kWave;
+            const long long e0 = P * pstride, z0 = e0 + 3 * (pstride / 2);
+            cl.passes.p[kPassA] = ConvPass{p.herm ? 3 * pstride : 0, 0, p.w, p.d_row_woff, p.herm ? 1 : 0, 0, gM, pstride};
+            cl.passes.p[kPassE1] = ConvPass{0, e0, p.w, p.d_row_woff, 0, 0, gE, 0};
+            cl.passes.p[kPassE2] = ConvPass{pstride, e0 + pstride / 2, p.w, p.d_row_woff, 0, 0, gE, 0};
+            cl.passes.p[kPassE3] = ConvPass{2 * pstride, e0 + pstride, w_e3, p.d_e3_woff, 0, 0, gE, 0};
+            cl.passes.p[kPassZ] = ConvPass{2 * pstride, z0, p.w, p.d_row_woff, 0, N / 2, gZ, pstride / (2 * N)};
             std::pair<hipEvent_t, hipEvent_t> ev{};
             if (b->timing) {
                 if (!timer_pair(b, ev)) return fail(BZ_EDEVICE, "bz_collide_batch: hipEventCreate failed");
