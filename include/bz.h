@@ -139,11 +139,19 @@ bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids,
  *                      pairs with a coordinate on a k_d = 0 plane and the outputs
  *                      with no mirror; the other outputs are the conjugates of
  *                      their mirrors corrected by those edge sums.  Same result
- *                      up to rounding as the full sum; about 0.67 / 0.73 / 0.84
+ *                      up to rounding as the full sum; about 0.61 / 0.65 / 0.71
  *                      of its work at N = 32 / 24 / 16.
  *   BZ_BATCH_FULL_SUM  every output row is summed directly.
+ *   BZ_BATCH_FINE_SPLIT  cut the rows into work items small enough for the
+ *                      rows of a single 64-cell group to fill the device (by
+ *                      default the whole batch is counted).  For batches of
+ *                      which only a few groups are usually convolved, as with
+ *                      the gated closure; a full batch takes somewhat longer.
+ *                      The same sum in more partial sums: results agree with
+ *                      the default split to rounding.
  * Errors: as bz_batch_create, and BZ_EINVAL for unknown flags. */
 #define BZ_BATCH_FULL_SUM 1
+#define BZ_BATCH_FINE_SPLIT 2
 bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_grids, const bz_grid *grids,
                              int mode, int flags, bz_batch *out);
 void bz_batch_free(bz_batch b);
@@ -269,8 +277,11 @@ bz_status bz_mlp_adam(bz_mlp n, void *d_params, const float *d_grad, int step, f
  * whose Q is only the discretisation residual, are judged against the
  * collision rate),
  * counted as failed if err > judge_tol, and keeps the convolution result.
- * The FP64 projection of Sec. 3.3 is always applied.  Requires a batch on one
- * mesh with n_in = n_out = N^3. */
+ * The FP64 projection of Sec. 3.3 is always applied.  In the batched modes
+ * the cells that need the convolution (not gated, or judged) are packed into
+ * the first 64-cell groups of the launch, and only those groups are
+ * transformed and convolved; every cell's result is the same as in the
+ * batch's own order.  Requires a batch on one mesh with n_in = n_out = N^3. */
 typedef struct {
     bz_mlp net;
     const void *d_params;   /* network parameters (bz_mlp_set_params / training) */

@@ -19,6 +19,7 @@ BZ_OK, BZ_EINVAL, BZ_EUNSUPPORTED, BZ_EDEVICE, BZ_ENOMEM, BZ_ENONFINITE, BZ_ESTA
 BZ_W_BATCHED_F32, BZ_W_BATCHED_F64, BZ_W_PLAIN_F32, BZ_W_PLAIN_F64 = 1, 2, 3, 4
 BZ_MODE_PLAIN_F64, BZ_MODE_BATCHED_F32, BZ_MODE_BATCHED_F64, BZ_MODE_PLAIN_F32 = 1, 2, 3, 4
 BZ_BATCH_FULL_SUM = 1
+BZ_BATCH_FINE_SPLIT = 2
 SCHEDULES = {"symmetric": 0, "full": BZ_BATCH_FULL_SUM}
 
 MODE_WEIGHTS = {BZ_MODE_PLAIN_F64: BZ_W_PLAIN_F64, BZ_MODE_BATCHED_F32: BZ_W_BATCHED_F32,
@@ -465,12 +466,14 @@ class Collision:
 
     meshes: list of (N, L, lambda); grid_of_cell: mesh index per cell;
     mode: one of MODE_NAMES or BZ_MODE_*; schedule: "symmetric" (conjugate
-    symmetry halves the batched sum, the default) or "full".  Weight buffers
-    may be shared between Collision objects through `weights_cache`.
+    symmetry halves the batched sum, the default) or "full"; fine_split: work
+    items sized for a single 64-cell group to fill the device (for batches of
+    which the gated closure convolves only a few groups).  Weight buffers may be
+    shared between Collision objects through `weights_cache`.
     """
 
     def __init__(self, meshes, grid_of_cell, mode="batched_f32", weights_cache=None, device="cuda",
-                 schedule="symmetric"):
+                 schedule="symmetric", fine_split=False):
         import torch
         self.mode = MODE_NAMES.get(mode, mode)
         self.kind = MODE_WEIGHTS[self.mode]
@@ -478,7 +481,8 @@ class Collision:
         self.grids = [bz_grid_init(*m) for m in self.meshes]
         self.grid_of_cell = np.asarray(grid_of_cell, dtype=np.int32)
         self.schedule = schedule
-        self.batch = bz_batch_create_ex(self.grid_of_cell, self.grids, self.mode, SCHEDULES[schedule])
+        flags = SCHEDULES[schedule] | (BZ_BATCH_FINE_SPLIT if fine_split else 0)
+        self.batch = bz_batch_create_ex(self.grid_of_cell, self.grids, self.mode, flags)
         cache = weights_cache if weights_cache is not None else {}
         self.weights = []
         for gi, (g, m) in enumerate(zip(self.grids, self.meshes)):

@@ -280,7 +280,8 @@ hipError_t launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t s);
 hipError_t launch_sur_prepare(int N, double dv, int n, const double *f, const long long *f_off, double gate,
                               double s_in, int judge_every, int phase, double *state, unsigned short *x,
                               hipStream_t s);
-hipError_t launch_group_skip(int n, const double *state, unsigned char *skip, hipStream_t s);
+hipError_t launch_pack_slots(int n, const double *state, const long long *f_off, long long *slot_off,
+                             unsigned char *skip, hipStream_t s);
 hipError_t launch_sur_finish(int N, double dv, const double *linv, int n, const double *state, const float *y,
                              double s_out, double floor_, double tol, const long long *q_off, double *q,
                              unsigned *stats, hipStream_t s);

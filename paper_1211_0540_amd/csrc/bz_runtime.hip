@@ -405,7 +405,7 @@ bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids,
 bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_grids, const bz_grid *grids, int mode,
                              int flags, bz_batch *out) {
     if (!out) return fail(BZ_EINVAL, "bz_batch_create: out is NULL");
-    if (flags & ~BZ_BATCH_FULL_SUM) return fail(BZ_EINVAL, "bz_batch_create: unknown flags");
+    if (flags & ~(BZ_BATCH_FULL_SUM | BZ_BATCH_FINE_SPLIT)) return fail(BZ_EINVAL, "bz_batch_create: unknown flags");
     *out = nullptr;
     if (n_cells < 1 || !grid_of_cell || n_grids < 1 || !grids)
         return fail(BZ_EINVAL, "bz_batch_create: empty batch or NULL argument");
@@ -479,12 +479,14 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
         o.blk = put(p.g->sched.blk_woff.data(), p.g->sched.blk_woff.size() * sizeof(long long));
         if (bat) {
             // split every row's steps into `parts` contiguous ranges so that there are
-            // enough work items to fill the chip; order longest first
+            // enough work items to fill the chip (with BZ_BATCH_FINE_SPLIT: from the rows of
+            // one group alone); order longest first
             const int h = N / 2;
             p.herm = !(flags & BZ_BATCH_FULL_SUM);
             long long rows = 0;
             for (int r = 0; r < N * N; ++r)
-                if (!p.herm || !herm_derived_row(N, r / N, r % N)) rows += p.groups;
+                if (!p.herm || !herm_derived_row(N, r / N, r % N)) ++rows;
+            if (!(flags & BZ_BATCH_FINE_SPLIT)) rows *= p.groups;
             int parts = (int)(((p.herm ? 4096 : 8192) + rows - 1) / rows);
             parts = std::max(1, std::min(parts, 8));
             p.parts = parts;
@@ -721,15 +723,18 @@ size_t bz_workspace_bytes(bz_batch b) { return b ? b->ws_total : 0; }
 size_t bz_step_workspace_bytes(bz_batch b) { return b ? align256(b->ws_total) + 2 * align256(b->elems * 8) : 0; }
 
 static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void *d_work, size_t work_bytes,
-                              void *stream, const unsigned char *skip);
+                              void *stream, const unsigned char *skip, const long long *slot_off);
 
 bz_status bz_collide_batch(bz_batch b, const double *d_f, double *d_Qt, void *d_work, size_t work_bytes,
                            void *stream) {
-    return collide_impl(b, d_f, d_Qt, d_work, work_bytes, stream, nullptr);
+    return collide_impl(b, d_f, d_Qt, d_work, work_bytes, stream, nullptr, nullptr);
 }
 
+// skip (device, per group of the batched modes, may be NULL): groups whose outputs are not needed.
+// slot_off (device, may be NULL): offsets of f and Qt of the cell in each slot of a one-mesh batch,
+// in place of the batch's own cell order.
 static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void *d_work, size_t work_bytes,
-                              void *stream, const unsigned char *skip) {
+                              void *stream, const unsigned char *skip, const long long *slot_off) {
     if (!b || !d_f || !d_Qt || !d_work) return fail(BZ_EINVAL, "bz_collide_batch: NULL argument");
     if (work_bytes < b->ws_total) return fail(BZ_EINVAL, "bz_collide_batch: workspace too small");
     if ((const void *)d_f == (const void *)d_Qt) return fail(BZ_EINVAL, "bz_collide_batch: f and Qt alias");
@@ -746,8 +751,9 @@ static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void 
         double2 *qh = (double2 *)(ws + p.ws_qh);
         if (batched(b->mode)) {
             const int nc = (int)p.cells.size();
+            const long long *f_off = slot_off ? slot_off : p.d_f_off;
             // the first partial buffer of qh serves as the second scratch buffer of the transforms
-            BZ_HIP(launch_dft_forward_grouped(N, p.g->L, nc, d_f, p.d_f_off, scratch, qh, fh, !f64, p.herm ? 4 : 1, skip,
+            BZ_HIP(launch_dft_forward_grouped(N, p.g->L, nc, d_f, f_off, scratch, qh, fh, !f64, p.herm ? 4 : 1, skip,
                                               s),
                    "forward transform");
             const long long pstride = (long long)p.groups * M * kWave;  // one copy of fhat, one output buffer
@@ -772,7 +778,7 @@ static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void 
             const HermAssembly herm{p.herm, p.parts};
             // groups whose cells are all served by the closure (skip) need no transforms: the
             // closure writes their outputs
-            BZ_HIP(launch_dft_inverse_grouped(N, p.g->L, nc, qh, p.parts, pstride, herm, scratch, qh, d_Qt, p.d_f_off,
+            BZ_HIP(launch_dft_inverse_grouped(N, p.g->L, nc, qh, p.parts, pstride, herm, scratch, qh, d_Qt, f_off,
                                               skip, s),
                    "inverse transform");
         } else {
@@ -840,12 +846,13 @@ bz_status bz_step_check(bz_batch b, void *d_work, void *stream) {
 }
 
 // ---------------------------------------------------------------------------
-// Gated closure.  Workspace: [step workspace][state n*8 doubles][skip groups]
+// Gated closure.  Workspace: [step workspace][state n*10 doubles][skip groups][slot offsets n]
 // [x n*M bf16][y n*M float][stats 4 uint][network workspace for batch n].
 // ---------------------------------------------------------------------------
 struct ClosureView {
     double *state;
     unsigned char *skip;
+    long long *slot_off;
     unsigned short *x;
     float *y;
     unsigned *stats;
@@ -867,6 +874,7 @@ static ClosureView closure_view(bz_batch b, const bz_closure *c, void *d_work) {
     };
     v.state = (double *)take(n * 10 * sizeof(double));
     v.skip = (unsigned char *)take((size_t)p.groups);
+    v.slot_off = (long long *)take(n * sizeof(long long));
     v.x = (unsigned short *)take(n * M * 2);
     v.y = (float *)take(n * M * 4);
     v.stats = (unsigned *)take(256);
@@ -905,11 +913,14 @@ static bz_status closure_collide_impl(bz_batch b, const bz_closure *c, const dou
                               v.state, v.x, s),
            "closure prepare");
     const unsigned char *skip = nullptr;
+    const long long *slot_off = nullptr;
     if (batched(b->mode)) {
-        BZ_HIP(launch_group_skip(n, v.state, v.skip, s), "closure group skip");
+        // the cells that need the convolution go to the first groups; the rest are skipped
+        BZ_HIP(launch_pack_slots(n, v.state, p.d_f_off, v.slot_off, v.skip, s), "closure slot packing");
         skip = v.skip;
+        slot_off = v.slot_off;
     }
-    bz_status st = collide_impl(b, d_f, d_Qt, d_work, b->ws_total, s, skip);
+    bz_status st = collide_impl(b, d_f, d_Qt, d_work, b->ws_total, s, skip, slot_off);
     if (st != BZ_OK) return st;
     st = bz_mlp_forward(c->net, c->d_params, v.x, n, v.y, v.mlp_work, v.mlp_bytes, s);
     if (st != BZ_OK) return st;

@@ -17,8 +17,9 @@
 // equilibrium, whose Q is only the discretisation residual, are judged
 // against the collision rate rather than against that residual)
 // and keeps the convolution result (fallback).  The FP64 projection of
-// Sec. 3.3 is applied to every cell afterwards.  Convolution work groups whose
-// live cells are all gated and unjudged are skipped.
+// Sec. 3.3 is applied to every cell afterwards.  The batched modes pack the
+// cells that need the convolution into the first 64-cell groups of the launch
+// and skip the groups left with served cells only.
 #include <cmath>
 #include <new>
 
@@ -91,8 +92,8 @@ __global__ void __launch_bounds__(256) k_prepare(int N, double dv, const double 
         x[(size_t)c * M + j] = f2bf((float)(j == 0 ? d * inv_s_in : (F[j] - maxwell(j)) * sx));
     if (threadIdx.x == 0) {
         const bool gated = d < gate && rho > 0 && T > 0;
-        // judge whole wavefront groups (one group in judge_every per evaluation, rotating) so
-        // that the groups that are not judged can skip the convolution
+        // judge the gated cells of one 64-cell index range in judge_every per evaluation
+        // (rotating), so that at most 64 served cells per evaluation are also convolved
         const bool judged = gated && judge_every > 0 && ((c / kWave) % judge_every) == (phase % judge_every);
         double *st = state + (size_t)c * kState;
         st[0] = rho;
@@ -108,18 +109,42 @@ __global__ void __launch_bounds__(256) k_prepare(int N, double dv, const double 
     }
 }
 
-// skip[g] = every live cell of group g gated and not judged (one wavefront per group,
-// lane = cell)
-__global__ void __launch_bounds__(64) k_group_skip(int n_cells, const double *__restrict__ state,
-                                                   unsigned char *__restrict__ skip) {
-    const int g = blockIdx.x, c = g * kWave + threadIdx.x;
-    bool served = true;
-    if (c < n_cells) {
+// Slot order of the convolution: the cells that need it (not gated, or judged) first, then the
+// served ones, each in index order.  slot_off[s] = f_off of the cell in slot s; skip[g] = 1 for
+// the groups of 64 slots that hold served cells only.  Every cell keeps its own lane arithmetic,
+// so only the number of convolved groups changes.  One block of kPackThreads; thread t owns a
+// contiguous chunk of cells, and a scan over the chunks gives each its first slot.
+constexpr int kPackThreads = 1024;
+__global__ void __launch_bounds__(kPackThreads) k_pack_slots(int n, const double *__restrict__ state,
+                                                              const long long *__restrict__ f_off,
+                                                              long long *__restrict__ slot_off,
+                                                              unsigned char *__restrict__ skip) {
+    __shared__ int scan[kPackThreads];
+    const int t = threadIdx.x;
+    const int chunk = (n + kPackThreads - 1) / kPackThreads;
+    const int c0 = min(n, t * chunk), c1 = min(n, c0 + chunk);
+    auto needs = [&](int c) {
         const double *st = state + (size_t)c * kState;
-        served = st[6] != 0.0 && st[7] == 0.0;
+        return st[6] == 0.0 || st[7] != 0.0;
+    };
+    int cnt = 0;
+    for (int c = c0; c < c1; ++c) cnt += needs(c) ? 1 : 0;
+    scan[t] = cnt;
+    __syncthreads();
+    for (int o = 1; o < kPackThreads; o <<= 1) {  // inclusive scan of the chunk counts
+        const int v = t >= o ? scan[t - o] : 0;
+        __syncthreads();
+        scan[t] += v;
+        __syncthreads();
     }
-    const bool all = __all(served);
-    if (threadIdx.x == 0) skip[g] = all ? 1 : 0;
+    const int n0 = scan[kPackThreads - 1];  // cells that need the convolution
+    int a = scan[t] - cnt;                   // their slots before this chunk
+    int b = n0 + (c0 - a);                   // served slots: after all of them, in index order
+    for (int c = c0; c < c1; ++c) {
+        if (needs(c)) slot_off[a++] = f_off[c];
+        else slot_off[b++] = f_off[c];
+    }
+    for (int g = t; g * kWave < n; g += kPackThreads) skip[g] = g * kWave >= n0 ? 1 : 0;
 }
 
 struct Basis {
@@ -206,9 +231,9 @@ hipError_t launch_sur_prepare(int N, double dv, int n, const double *f, const lo
     return hipGetLastError();
 }
 
-hipError_t launch_group_skip(int n, const double *state, unsigned char *skip, hipStream_t s) {
-    const int groups = (n + kWave - 1) / kWave;
-    hipLaunchKernelGGL(k_group_skip, dim3(groups), dim3(kWave), 0, s, n, state, skip);
+hipError_t launch_pack_slots(int n, const double *state, const long long *f_off, long long *slot_off,
+                             unsigned char *skip, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_slots, dim3(1), dim3(kPackThreads), 0, s, n, state, f_off, slot_off, skip);
     return hipGetLastError();
 }
 

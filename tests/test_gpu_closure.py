@@ -59,9 +59,9 @@ def test_prepare_matches_oracle_moments(dev):
     c.close()
 
 
-def _closure_run(dev, model, cells, gate, judge_every):
+def _closure_run(dev, model, cells, gate, judge_every, fine_split=False):
     n = len(cells)
-    c = bz.Collision([(N, L, LAM)], [0] * n, "batched_f32", weights_cache=model.wcache)
+    c = bz.Collision([(N, L, LAM)], [0] * n, "batched_f32", weights_cache=model.wcache, fine_split=fine_split)
     f = torch.from_numpy(c.pack(cells)).to(dev)
     model.s_in = model.s_in or 2.0 ** -9
     model.s_out = model.s_out or 2.0 ** -6
@@ -96,6 +96,34 @@ def test_open_gate_serves_the_network(dev, model):
     q, ref, st = _closure_run(dev, model, _cells(64, 4), gate=1e30, judge_every=0)
     assert st["served"] == 64 and st["judged"] == 0
     assert np.all(q == 0.0)          # the untrained closure predicts zero
+
+
+@pytest.mark.parametrize("fine_split", [False, True])
+def test_scattered_gate_packs_the_convolved_cells(dev, model, fine_split):
+    """Gated cells scattered over the 64-cell groups (every third cell an exact
+    Maxwellian, d < 1e-4; the others d > 5e-3; gate 2e-3; three groups, the
+    last ragged): the cells that need the convolution are packed into the first
+    groups of the launch, and each keeps exactly the result of the batch's own
+    order; the served cells take the untrained closure's zero.  With
+    judge_every = 2 the gated cells of the index ranges 0-63 and 128-149 (first
+    evaluation) are judged, fail, and keep the convolution."""
+    n = 150
+    cells = []
+    for i, f in enumerate(_cells(n, 5)):
+        if i % 3 == 0:
+            rho, u, T, _ = O.moments(f, L)
+            f = W.maxwellian(N, L, rho, u, T)
+        cells.append(f)
+    idx = np.arange(n)
+    gated = idx % 3 == 0
+    for judge_every in (0, 2):
+        q, ref, st = _closure_run(dev, model, cells, gate=2e-3, judge_every=judge_every, fine_split=fine_split)
+        q, ref = q.reshape(n, -1), ref.reshape(n, -1)
+        judged = gated & ((idx // 64) % 2 == 0) if judge_every else np.zeros(n, bool)
+        served = gated & ~judged
+        assert st["served"] == served.sum() and st["judged"] == judged.sum()
+        assert np.array_equal(q[~served], ref[~served])
+        assert np.all(q[served] == 0.0)
 
 
 def test_harvest_train_serve_shock(dev):

@@ -42,8 +42,8 @@ def oracle_for(N, L, lam):
 _WCACHE = {}
 
 
-def run(meshes, goc, cells, mode, dev, project=True, schedule="symmetric"):
-    c = bz.Collision(meshes, goc, mode, weights_cache=_WCACHE, schedule=schedule)
+def run(meshes, goc, cells, mode, dev, project=True, schedule="symmetric", fine_split=False):
+    c = bz.Collision(meshes, goc, mode, weights_cache=_WCACHE, schedule=schedule, fine_split=fine_split)
     f = torch.from_numpy(c.pack(cells)).to(dev)
     qt = c.collide(f)
     q = qt.clone()
@@ -154,6 +154,19 @@ def test_symmetric_schedule_equals_full_sum_fp64(dev, N, L, n):
     for i in sorted({0, n // 2, n - 1}):
         qt_o, _, _, _ = o.collide(cells[i])
         assert max_rel(sym[i], qt_o) < 1e-12, i
+
+
+@pytest.mark.parametrize("schedule", ["symmetric", "full"])
+def test_fine_split_equals_default_split_fp64(dev, schedule):
+    """BZ_BATCH_FINE_SPLIT (rows cut into up to 8 partial sums for one group alone) gives the
+    default split's FP64 sums to rounding: 130 N=24 cells in three groups, the last ragged."""
+    N, L, lam, n = 24, 7.0, 1.0, 130
+    cells = list(W.random_smooth_cells(n, N, L, seed=41, umax=1.0))
+    a, _ = run([(N, L, lam)], [0] * n, cells, "batched_f64", dev, project=False, schedule=schedule)
+    b, _ = run([(N, L, lam)], [0] * n, cells, "batched_f64", dev, project=False, schedule=schedule,
+               fine_split=True)
+    for i in range(n):
+        assert max_rel(b[i], a[i]) < 1e-12, i
 
 
 def test_symmetric_schedule_fp32_mixed_meshes(dev):
