@@ -39,23 +39,39 @@ __device__ inline double wave_sum(double x) {
     return x;
 }
 
-// One block of kProjThreads threads per cell.
+// One block of kProjThreads threads per cell.  Thread t owns the values j = t + i kProjThreads,
+// i < PER = ceil(N^3 / kProjThreads), and keeps them in registers through both passes, so the
+// cell is read and written once.  Indices and basis values are recomputed in every loop (the
+// empty asm hides the thread index from common-subexpression elimination, which would otherwise
+// keep PER indices and 5 PER basis values live across the passes and spill them).
 constexpr int kProjThreads = 1024;
-__global__ void __launch_bounds__(kProjThreads) k_project(int N, double dv, Linv li, double *__restrict__ q,
+template <int N>
+__global__ void __launch_bounds__(kProjThreads) k_project(double dv, Linv li, double *__restrict__ q,
                                                           const long long *__restrict__ off) {
+    constexpr int M = N * N * N, PER = (M + kProjThreads - 1) / kProjThreads;
     __shared__ double red[kProjThreads / 64][5];
     __shared__ double mu[5];
-    const int M = N * N * N;
     double *Q = q + off[blockIdx.x];
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double x[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int j = threadIdx.x + i * kProjThreads;
+        x[i] = j < M ? Q[j] : 0.0;
+    }
     for (int pass = 0; pass < 2; ++pass) {
         double s[5] = {0, 0, 0, 0, 0};
-        for (int j = threadIdx.x; j < M; j += blockDim.x) {
-            double e[5];
-            basis(N, dv, li, j, e);
-            const double x = Q[j];
+        int tr = threadIdx.x;
+        asm volatile("" : "+v"(tr));
 #pragma unroll
-            for (int a = 0; a < 5; ++a) s[a] = fma(e[a], x, s[a]);
+        for (int i = 0; i < PER; ++i) {
+            const int j = tr + i * kProjThreads;
+            if (j < M) {
+                double e[5];
+                basis(N, dv, li, j, e);
+#pragma unroll
+                for (int a = 0; a < 5; ++a) s[a] = fma(e[a], x[i], s[a]);
+            }
         }
 #pragma unroll
         for (int a = 0; a < 5; ++a) {
@@ -69,15 +85,28 @@ __global__ void __launch_bounds__(kProjThreads) k_project(int N, double dv, Linv
             mu[threadIdx.x] = t;
         }
         __syncthreads();
-        for (int j = threadIdx.x; j < M; j += blockDim.x) {
-            double e[5];
-            basis(N, dv, li, j, e);
-            double corr = 0.0;
+        int tc = threadIdx.x;
+        asm volatile("" : "+v"(tc));
 #pragma unroll
-            for (int a = 0; a < 5; ++a) corr = fma(e[a], mu[a], corr);
-            Q[j] -= corr;
+        for (int i = 0; i < PER; ++i) {
+            const int j = tc + i * kProjThreads;
+            if (j < M) {
+                double e[5];
+                basis(N, dv, li, j, e);
+                double corr = 0.0;
+#pragma unroll
+                for (int a = 0; a < 5; ++a) corr = fma(e[a], mu[a], corr);
+                x[i] -= corr;
+            }
         }
         __syncthreads();
+    }
+    int ts = threadIdx.x;
+    asm volatile("" : "+v"(ts));
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int j = ts + i * kProjThreads;
+        if (j < M) Q[j] = x[i];
     }
 }
 
@@ -195,7 +224,13 @@ hipError_t launch_project(int N, double dv, const double *linv, int ncells, doub
     if (ncells <= 0) return hipSuccess;
     Linv li;
     for (int i = 0; i < 25; ++i) li.a[i] = linv[i];
-    hipLaunchKernelGGL(k_project, dim3(ncells), dim3(kProjThreads), 0, s, N, dv, li, q, d_off);
+    switch (N) {
+#define BZ_PROJ(n) \
+    case n: hipLaunchKernelGGL(k_project<n>, dim3(ncells), dim3(kProjThreads), 0, s, dv, li, q, d_off); break;
+        BZ_PROJ(8) BZ_PROJ(12) BZ_PROJ(16) BZ_PROJ(20) BZ_PROJ(24) BZ_PROJ(28) BZ_PROJ(32)
+#undef BZ_PROJ
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
