@@ -16,7 +16,7 @@ ARCH = os.environ.get("BZ_OFFLOAD_ARCH", "gfx950")
 
 
 def hipcc_flags():
-    return ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+    return ["-O3", "-std=c++20", f"--offload-arch={ARCH}", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wno-unused-command-line-argument", "-I", os.path.join(HERE, "..", "include")]
 

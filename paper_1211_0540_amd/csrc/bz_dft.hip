@@ -3,8 +3,9 @@
 //   Qt_j   = (2pi)^{-3/2} dzeta^3 Re sum_k Qhat_k exp(+i zeta_k . v_j)
 // On the mesh zeta_k . v_j = (2pi/N) sum_d (k_d - N/2)(j_d - N/2), so each
 // axis is an N-point DFT with the twiddle w^{((k-N/2)(j-N/2)) mod N},
-// w = exp(-2 pi i / N).  N <= 32 is small, so each axis is a direct sum.
-// FP64 throughout; the cost is O(N^4) per cell, about 1% of the convolution.
+// w = exp(-2 pi i / N).  The plain path sums each axis directly (O(N^4) per
+// cell); the batched paths use an in-register FFT per line (O(N^3 log N), the
+// cost the method states for this step).  FP64 throughout.
 //
 // Two organisations:
 // * one cell at a time (plain path): pass A transforms the two fast axes of
@@ -14,6 +15,8 @@
 //   along one axis, lane = cell, so every read and write of the
 //   intermediate and spectral buffers is a whole 1 KiB line; three passes,
 //   one per axis.
+#include <utility>
+
 #include "bz_internal.h"
 
 namespace bz {
@@ -184,30 +187,110 @@ __global__ void __launch_bounds__(256) k_dft_inv_b(int N, double scale, const do
 }
 
 // ---------------------------------------------------------------------------
-// Cell-interleaved groups (batched paths).  The loop over outputs k is kept
-// rolled; along the inputs j the twiddle index ((k - N/2)(j - N/2)) mod N
-// advances by (k - N/2) mod N, a wavefront-uniform add and wrap.
+// Cell-interleaved groups (batched paths).  Each lane transforms its cell's
+// line in registers with an FFT: Cooley-Tukey decimation in time, radix 2 down
+// to an odd length (1, 3, 5 or 7 for the meshes here) done as a direct sum.
+// N and the sign are compile-time, so every twiddle is a constant.
 // ---------------------------------------------------------------------------
-template <int N>
-__device__ __forceinline__ int tw_first(int k) {  // index for j = 0
-    return (((k - N / 2) * (-N / 2)) % N + N) % N;
+struct Twiddle {
+    double c, s;
+};
+// sin and cos on [0, pi/4] by their Taylor series (the omitted terms are below 1e-30)
+constexpr double tw_sin(double x) {
+    double t = x, s = x;
+    for (int i = 1; i < 13; ++i) {
+        t *= -x * x / ((2.0 * i) * (2.0 * i + 1.0));
+        s += t;
+    }
+    return s;
 }
-template <int N>
-__device__ __forceinline__ int tw_step(int k) {
-    return (k - N / 2 + N) % N;
+constexpr double tw_cos(double x) {
+    double t = 1.0, s = 1.0;
+    for (int i = 1; i < 13; ++i) {
+        t *= -x * x / ((2.0 * i - 1.0) * (2.0 * i));
+        s += t;
+    }
+    return s;
 }
-template <int N>
-__device__ __forceinline__ void tw_next(int &t, int step) {
-    t += step;
-    t = t >= N ? t - N : t;
+// exp(sign 2 pi i k / n), 0 <= k < n: the angle is (pi/4)(o + r/n) with octant o = 8k div n and
+// r = 8k mod n; reduced to [0, pi/4] by the octant symmetries, exact at multiples of pi/2
+constexpr Twiddle twiddle(int sign, int k, int n) {
+    constexpr double q = 3.14159265358979323846 / 4.0;
+    const int o = (8 * k) / n, r = 8 * k - o * n;
+    double c = 0.0, s = 0.0;
+    if (o % 2 == 0) {
+        c = tw_cos(q * r / n);
+        s = tw_sin(q * r / n);
+    } else {
+        c = tw_sin(q * (n - r) / n);
+        s = tw_cos(q * (n - r) / n);
+    }
+    double cc = c, ss = s;  // rotate by the quadrant o / 2
+    if (o / 2 == 1) cc = -s, ss = c;
+    if (o / 2 == 2) cc = -c, ss = -s;
+    if (o / 2 == 3) cc = s, ss = -c;
+    return Twiddle{cc, sign * ss};
+}
+
+// output K of a direct transform of odd length n: x_0 + sum_{j >= 1} x_j exp(SIGN 2 pi i K j / n)
+template <int n, int SIGN, int K, int... J>
+__device__ __forceinline__ double2 odd_dft_term(const double2 (&x)[n], std::integer_sequence<int, J...>) {
+    double re = x[0].x, im = x[0].y;
+    ((void)[&] {
+        constexpr Twiddle w = twiddle(SIGN, (K * (J + 1)) % n, n);
+        re = fma(x[J + 1].x, w.c, fma(-x[J + 1].y, w.s, re));
+        im = fma(x[J + 1].x, w.s, fma(x[J + 1].y, w.c, im));
+    }(), ...);
+    return make_double2(re, im);
+}
+
+template <int n, int SIGN>
+__device__ __forceinline__ void fft_rec(double2 (&x)[n]) {
+    if constexpr (n % 2 == 0) {
+        constexpr int m = n / 2;
+        double2 e[m], o[m];
+#pragma unroll
+        for (int i = 0; i < m; ++i) {
+            e[i] = x[2 * i];
+            o[i] = x[2 * i + 1];
+        }
+        fft_rec<m, SIGN>(e);
+        fft_rec<m, SIGN>(o);
+        [&]<int... K>(std::integer_sequence<int, K...>) {
+            ((void)[&] {
+                constexpr Twiddle w = twiddle(SIGN, K, n);
+                double2 t = o[K];
+                if constexpr (K > 0) t = make_double2(fma(w.c, o[K].x, -w.s * o[K].y), fma(w.c, o[K].y, w.s * o[K].x));
+                x[K] = make_double2(e[K].x + t.x, e[K].y + t.y);
+                x[K + m] = make_double2(e[K].x - t.x, e[K].y - t.y);
+            }(), ...);
+        }(std::make_integer_sequence<int, m>{});
+    } else if constexpr (n > 1) {
+        double2 y[n];
+        [&]<int... K>(std::integer_sequence<int, K...>) {
+            ((y[K] = odd_dft_term<n, SIGN, K>(x, std::make_integer_sequence<int, n - 1>{})), ...);
+        }(std::make_integer_sequence<int, n>{});
+#pragma unroll
+        for (int k = 0; k < n; ++k) x[k] = y[k];
+    }
+}
+
+// Centred transform of one line, x_k <- sum_j x_j w^((k - N/2)(j - N/2)), w = exp(SIGN 2 pi i / N).
+// For N a multiple of 4, (k - N/2)(j - N/2) = k j - (N/2)(k + j) + N^2/4 with w^(N/2) = -1 and
+// w^(N^2/4) = 1: the plain transform of (-1)^j x_j, times (-1)^k.
+template <int N, int SIGN>
+__device__ __forceinline__ void centred_dft(double2 (&x)[N]) {
+    static_assert(N % 4 == 0, "mesh sizes are multiples of 4");
+#pragma unroll
+    for (int j = 1; j < N; j += 2) x[j] = make_double2(-x[j].x, -x[j].y);
+    fft_rec<N, SIGN>(x);
+#pragma unroll
+    for (int k = 1; k < N; k += 2) x[k] = make_double2(-x[k].x, -x[k].y);
 }
 
 // line index of this wavefront (4 per block) and its lane
-#define BZ_LINE_SETUP(SIGN)                                   \
+#define BZ_LINE_SETUP                                         \
     if (skip && skip[blockIdx.y]) return;                     \
-    __shared__ double2 roots[N];                              \
-    load_roots(roots, N, SIGN);                               \
-    __syncthreads();                                          \
     constexpr int M = N * N * N;                              \
     const int lane = threadIdx.x & (kWave - 1);               \
     const int line = blockIdx.x * 4 + (threadIdx.x >> 6);     \
@@ -220,7 +303,7 @@ template <int N>
 __global__ void __launch_bounds__(256) k_dftg_fwd1(const double *__restrict__ f, const long long *__restrict__ f_off,
                                                    int nc, double2 *__restrict__ S,
     const unsigned char *__restrict__ skip) {
-    BZ_LINE_SETUP(-1.0)
+    BZ_LINE_SETUP
     const int i = g * kWave + lane;
     double x[N];
     if (i < nc) {
@@ -232,55 +315,33 @@ __global__ void __launch_bounds__(256) k_dftg_fwd1(const double *__restrict__ f,
         for (int j = 0; j < N; ++j) x[j] = 0.0;
     }
     double2 *dst = S + (gb + (size_t)line * N) * kWave + lane;
-#pragma unroll 1
-    for (int k = 0; k < N; ++k) {
-        double re = 0.0, im = 0.0;
-        int t = tw_first<N>(k);
-        const int st = tw_step<N>(k);
+    double2 y[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            const double2 w = roots[t];
-            re = fma(x[j], w.x, re);
-            im = fma(x[j], w.y, im);
-            tw_next<N>(t, st);
-        }
-        dst[(size_t)k * kWave] = make_double2(re, im);
-    }
+    for (int j = 0; j < N; ++j) y[j] = make_double2(x[j], 0.0);
+    centred_dft<N, -1>(y);
+#pragma unroll
+    for (int k = 0; k < N; ++k) dst[(size_t)k * kWave] = y[k];
 }
 
-// one complex line: out_k = sum_j in_j w^{twi(k, j)}; in/out strided by `stride` elements
-template <int N>
-__device__ __forceinline__ void line_dft(const double2 (&x)[N], const double2 *roots, double2 *dst, size_t stride,
-                                         double scale) {
-#pragma unroll 1
-    for (int k = 0; k < N; ++k) {
-        double re = 0.0, im = 0.0;
-        int t = tw_first<N>(k);
-        const int st = tw_step<N>(k);
+// one complex line: out_k = scale sum_j in_j w^((k - N/2)(j - N/2)); out strided by `stride` elements
+template <int N, int SIGN>
+__device__ __forceinline__ void line_dft(double2 (&x)[N], double2 *dst, size_t stride, double scale) {
+    centred_dft<N, SIGN>(x);
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            const double2 w = roots[t];
-            re = fma(x[j].x, w.x, re);
-            re = fma(-x[j].y, w.y, re);
-            im = fma(x[j].x, w.y, im);
-            im = fma(x[j].y, w.x, im);
-            tw_next<N>(t, st);
-        }
-        dst[k * stride] = make_double2(re * scale, im * scale);
-    }
+    for (int k = 0; k < N; ++k) dst[k * stride] = make_double2(x[k].x * scale, x[k].y * scale);
 }
 
 // forward, axis 2: line (j1, k3): S (j1, j2, k3) -> T (j1, k2, k3)
 template <int N>
 __global__ void __launch_bounds__(256) k_dftg_fwd2(const double2 *__restrict__ S, double2 *__restrict__ T,
     const unsigned char *__restrict__ skip) {
-    BZ_LINE_SETUP(-1.0)
+    BZ_LINE_SETUP
     const int j1 = line / N, k3 = line - j1 * N;
     const size_t off = (gb + (size_t)j1 * N * N + k3) * kWave + lane;
     double2 x[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) x[j] = S[off + (size_t)j * N * kWave];
-    line_dft<N>(x, roots, T + off, (size_t)N * kWave, 1.0);
+    line_dft<N, -1>(x, T + off, (size_t)N * kWave, 1.0);
 }
 
 // forward, axis 1: line (k2, k3): T (j1, k2, k3) -> fhat (k1, k2, k3), scaled, in the kernel's precision;
@@ -290,29 +351,18 @@ template <int N, typename Out>
 __global__ void __launch_bounds__(256) k_dftg_fwd3(const double2 *__restrict__ T, int nc, double scale,
                                                    Out *__restrict__ fh, int copies, long long copy_stride,
     const unsigned char *__restrict__ skip) {
-    BZ_LINE_SETUP(-1.0)
+    BZ_LINE_SETUP
     const size_t off = (gb + (size_t)line) * kWave + lane;
     double2 x[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) x[j] = T[off + (size_t)j * N * N * kWave];
     const bool live = g * kWave + lane < nc;
-#pragma unroll 1
-    for (int k = 0; k < N; ++k) {
-        double re = 0.0, im = 0.0;
-        int t = tw_first<N>(k);
-        const int st = tw_step<N>(k);
+    centred_dft<N, -1>(x);
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            const double2 w = roots[t];
-            re = fma(x[j].x, w.x, re);
-            re = fma(-x[j].y, w.y, re);
-            im = fma(x[j].x, w.y, im);
-            im = fma(x[j].y, w.x, im);
-            tw_next<N>(t, st);
-        }
+    for (int k = 0; k < N; ++k) {
         Out v;
-        v.x = live ? re * scale : 0.0;
-        v.y = live ? im * scale : 0.0;
+        v.x = live ? x[k].x * scale : 0.0;
+        v.y = live ? x[k].y * scale : 0.0;
         fh[off + (size_t)k * N * N * kWave] = v;
         if (copies > 1) {
             const int k2 = line / N, k3 = line - k2 * N;
@@ -338,7 +388,7 @@ template <int N>
 __global__ void __launch_bounds__(256) k_dftg_inv1_herm(const double2 *__restrict__ qh, int nA, long long pstride,
                                                         double2 *__restrict__ S,
     const unsigned char *__restrict__ skip) {
-    BZ_LINE_SETUP(+1.0)
+    BZ_LINE_SETUP
     constexpr int h = N / 2;
     const int k2 = line / N, k3 = line - k2 * N;
     // pstride = B, one full buffer; group bases of the full, edge (half) and Z buffers
@@ -391,7 +441,7 @@ __global__ void __launch_bounds__(256) k_dftg_inv1_herm(const double2 *__restric
             x[k1] = make_double2(i.x + e.x, e.y - i.y);
         }
     }
-    line_dft<N>(x, roots, S + gl + (size_t)line * kWave, (size_t)N * N * kWave, 1.0);
+    line_dft<N, +1>(x, S + gl + (size_t)line * kWave, (size_t)N * N * kWave, 1.0);
 }
 
 // inverse, axis 1: line (k2, k3): sum of the partial buffers (k1, k2, k3) -> S (j1, k2, k3)
@@ -399,7 +449,7 @@ template <int N>
 __global__ void __launch_bounds__(256) k_dftg_inv1(const double2 *__restrict__ qh, int nparts, long long pstride,
                                                    double2 *__restrict__ S,
     const unsigned char *__restrict__ skip) {
-    BZ_LINE_SETUP(+1.0)
+    BZ_LINE_SETUP
     const size_t off = (gb + (size_t)line) * kWave + lane;
     double2 x[N];
 #pragma unroll
@@ -412,20 +462,20 @@ __global__ void __launch_bounds__(256) k_dftg_inv1(const double2 *__restrict__ q
         }
         x[j] = a;
     }
-    line_dft<N>(x, roots, S + off, (size_t)N * N * kWave, 1.0);
+    line_dft<N, +1>(x, S + off, (size_t)N * N * kWave, 1.0);
 }
 
 // inverse, axis 2: line (j1, k3): S (j1, k2, k3) -> T (j1, j2, k3)
 template <int N>
 __global__ void __launch_bounds__(256) k_dftg_inv2(const double2 *__restrict__ S, double2 *__restrict__ T,
     const unsigned char *__restrict__ skip) {
-    BZ_LINE_SETUP(+1.0)
+    BZ_LINE_SETUP
     const int j1 = line / N, k3 = line - j1 * N;
     const size_t off = (gb + (size_t)j1 * N * N + k3) * kWave + lane;
     double2 x[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) x[j] = S[off + (size_t)j * N * kWave];
-    line_dft<N>(x, roots, T + off, (size_t)N * kWave, 1.0);
+    line_dft<N, +1>(x, T + off, (size_t)N * kWave, 1.0);
 }
 
 // inverse, axis 3: line (j1, j2): T (j1, j2, k3) -> Qt (j1, j2, j3) = scale Re(...) of cell g*64 + lane
@@ -433,7 +483,7 @@ template <int N>
 __global__ void __launch_bounds__(256) k_dftg_inv3(const double2 *__restrict__ T, int nc, double scale,
                                                    double *__restrict__ qt, const long long *__restrict__ q_off,
     const unsigned char *__restrict__ skip) {
-    BZ_LINE_SETUP(+1.0)
+    BZ_LINE_SETUP
     const int i = g * kWave + lane;
     const size_t off = (gb + (size_t)line * N) * kWave + lane;
     double2 x[N];
@@ -441,20 +491,9 @@ __global__ void __launch_bounds__(256) k_dftg_inv3(const double2 *__restrict__ T
     for (int j = 0; j < N; ++j) x[j] = T[off + (size_t)j * kWave];
     if (i >= nc) return;
     double *dst = qt + q_off[i] + (size_t)line * N;
-#pragma unroll 1
-    for (int k = 0; k < N; ++k) {
-        double re = 0.0;
-        int t = tw_first<N>(k);
-        const int st = tw_step<N>(k);
+    centred_dft<N, +1>(x);
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            const double2 w = roots[t];
-            re = fma(x[j].x, w.x, re);
-            re = fma(-x[j].y, w.y, re);
-            tw_next<N>(t, st);
-        }
-        dst[k] = re * scale;
-    }
+    for (int k = 0; k < N; ++k) dst[k] = x[k].x * scale;
 }
 #undef BZ_LINE_SETUP
 
