@@ -280,6 +280,18 @@ def closure_leg(args, torch, np, bz, W, N=24, L=7.0, snapshots=600, relax_cells=
             "max_abs_T_profile_deviation": float(np.max(np.abs(TA - TB)))}
 
 
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -492,6 +504,7 @@ def main():
             done += 1
         el = time.perf_counter() - t0
         cpu = {"value": done / el, "unit": "cell-collision evals/s", "cores": O.num_threads(), "kind": "oracle",
+               "cpu_model": cpu_model(),
                "sample": f"{done} of the {nc} N=32 cells, one FP64 evaluation each (transform, O(N^6) sum, "
                          f"inverse, projection), {el:.1f} s"}
 
