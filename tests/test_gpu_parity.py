@@ -156,11 +156,13 @@ def test_symmetric_schedule_equals_full_sum_fp64(dev, N, L, n):
         assert max_rel(sym[i], qt_o) < 1e-12, i
 
 
-@pytest.mark.parametrize("schedule", ["symmetric", "full"])
-def test_fine_split_equals_default_split_fp64(dev, schedule):
+@pytest.mark.parametrize("schedule,N,L,n", [("symmetric", 24, 7.0, 130), ("full", 24, 7.0, 130),
+                                             ("symmetric", 8, 4.0, 1)])
+def test_fine_split_equals_default_split_fp64(dev, schedule, N, L, n):
     """BZ_BATCH_FINE_SPLIT (rows cut into up to 8 partial sums for one group alone) gives the
-    default split's FP64 sums to rounding: 130 N=24 cells in three groups, the last ragged."""
-    N, L, lam, n = 24, 7.0, 1.0, 130
+    default split's FP64 sums to rounding: 130 N=24 cells in three groups, the last ragged, and
+    a single N=8 cell."""
+    lam = 1.0
     cells = list(W.random_smooth_cells(n, N, L, seed=41, umax=1.0))
     a, _ = run([(N, L, lam)], [0] * n, cells, "batched_f64", dev, project=False, schedule=schedule)
     b, _ = run([(N, L, lam)], [0] * n, cells, "batched_f64", dev, project=False, schedule=schedule,
@@ -287,15 +289,20 @@ def test_batched_fp32_is_deterministic(dev):
 # Projection and time stepping
 # ---------------------------------------------------------------------------
 def test_projection_matches_oracle_and_conserves(dev):
+    """Every mesh size (N^3 from 512 to 32768 values per cell: one to 32 per thread of the
+    projection block, with and without a ragged last round), two cells per mesh."""
     rng = np.random.default_rng(1)
-    meshes = [(16, 6.0, 1.0), (32, 8.0, 1.0)]
-    qt = [rng.standard_normal((16, 16, 16)), rng.standard_normal((32, 32, 32))]
-    c = bz.Collision(meshes, [0, 1], "batched_f32", weights_cache=_WCACHE)
+    meshes = [(8, 4.0, 1.0), (12, 5.0, 1.0), (16, 6.0, 1.0), (20, 6.0, 1.0), (24, 7.0, 1.0), (28, 7.0, 1.0),
+              (32, 8.0, 1.0)]
+    goc = [i for i in range(len(meshes)) for _ in range(2)]
+    qt = [rng.standard_normal((meshes[g][0],) * 3) for g in goc]
+    c = bz.Collision(meshes, goc, "batched_f32", weights_cache=_WCACHE)
     q = torch.from_numpy(c.pack(qt)).to(dev)
     c.project(q)
     out = c.unpack(q.cpu().numpy())
-    for x, ref, (N, L, _) in zip(out, qt, meshes):
-        assert max_rel(x, O.project(ref, L)) < 1e-12
+    for x, ref, g in zip(out, qt, goc):
+        N, L, _ = meshes[g]
+        assert max_rel(x, O.project(ref, L)) < 1e-12, N
         assert_conserved(x, N, L)
     c.close()
 
