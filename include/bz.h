@@ -281,7 +281,11 @@ bz_status bz_mlp_adam(bz_mlp n, void *d_params, const float *d_grad, int step, f
  * the cells that need the convolution (not gated, or judged) are packed into
  * the first 64-cell groups of the launch, and only those groups are
  * transformed and convolved; every cell's result is the same as in the
- * batch's own order.  Requires a batch on one mesh with n_in = n_out = N^3. */
+ * batch's own order.  The network runs on a second stream that the batch
+ * owns (default priority, created on the first closure call), ordered after
+ * the preparation and before the selection by events on `stream`, so that it
+ * overlaps the transforms and the convolution; the calls still only enqueue.
+ * Requires a batch on one mesh with n_in = n_out = N^3. */
 typedef struct {
     bz_mlp net;
     const void *d_params;   /* network parameters (bz_mlp_set_params / training) */

@@ -229,6 +229,10 @@ struct bz_batch_s {
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
     int closure_phase = 0;
+    // closure: the network runs on a second stream of default priority, forked from and joined to
+    // the caller's stream by events (created on the first closure call)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace bz {
@@ -592,6 +596,9 @@ void bz_batch_free(bz_batch b) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    if (b->side) (void)hipStreamDestroy(b->side);
     delete b;
 }
 
@@ -904,11 +911,25 @@ static bz_status closure_check(bz_batch b, const bz_closure *c, const char *who)
     return BZ_OK;
 }
 
+static bz_status closure_side(bz_batch b) {
+    if (b->side) return BZ_OK;
+    if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess) {
+        b->side = nullptr;
+        return fail(BZ_EDEVICE, "closure: hipStreamCreateWithFlags failed");
+    }
+    if (hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess)
+        return fail(BZ_EDEVICE, "closure: hipEventCreateWithFlags failed");
+    return BZ_OK;
+}
+
 static bz_status closure_collide_impl(bz_batch b, const bz_closure *c, const double *d_f, double *d_Qt, void *d_work,
                                       hipStream_t s) {
     const Part &p = b->parts[0];
     const int n = (int)p.cells.size(), N = p.g->N;
     ClosureView v = closure_view(b, c, d_work);
+    bz_status st = closure_side(b);
+    if (st != BZ_OK) return st;
     BZ_HIP(launch_sur_prepare(N, p.g->dv, n, d_f, p.d_f_off, c->gate, c->s_in, c->judge_every, b->closure_phase++,
                               v.state, v.x, s),
            "closure prepare");
@@ -920,9 +941,14 @@ static bz_status closure_collide_impl(bz_batch b, const bz_closure *c, const dou
         skip = v.skip;
         slot_off = v.slot_off;
     }
-    bz_status st = collide_impl(b, d_f, d_Qt, d_work, b->ws_total, s, skip, slot_off);
+    // the network (its own input, output and workspace) overlaps the transforms and the convolution
+    BZ_HIP(hipEventRecord(b->ev_fork, s), "closure fork");
+    BZ_HIP(hipStreamWaitEvent(b->side, b->ev_fork, 0), "closure fork");
+    st = bz_mlp_forward(c->net, c->d_params, v.x, n, v.y, v.mlp_work, v.mlp_bytes, b->side);
     if (st != BZ_OK) return st;
-    st = bz_mlp_forward(c->net, c->d_params, v.x, n, v.y, v.mlp_work, v.mlp_bytes, s);
+    BZ_HIP(hipEventRecord(b->ev_join, b->side), "closure join");
+    st = collide_impl(b, d_f, d_Qt, d_work, b->ws_total, s, skip, slot_off);
+    BZ_HIP(hipStreamWaitEvent(s, b->ev_join, 0), "closure join");
     if (st != BZ_OK) return st;
     BZ_HIP(launch_sur_finish(N, p.g->dv, p.g->linv, n, v.state, v.y, c->s_out, c->judge_floor, c->judge_tol,
                              p.d_f_off, d_Qt, v.stats, s),
