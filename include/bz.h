@@ -32,6 +32,13 @@
  *     call that returns an error has no side effect.  No C++ exception
  *     crosses this interface.  bz_last_error() returns a thread-local message
  *     for the last failing call of the calling thread.
+ *   - Threads: a mesh handle is immutable after bz_grid_init and may be
+ *     shared.  A batch handle carries per-call state (chosen kernel variants,
+ *     timing events, the closure's judge rotation and its second stream), so
+ *     the calls on one batch must not overlap in time from several host
+ *     threads; distinct batches are independent.  Calls that enqueue on one
+ *     batch with the same workspace on different streams race on the
+ *     workspace, as any two kernels writing one buffer would.
  */
 #ifndef BZ_H
 #define BZ_H
