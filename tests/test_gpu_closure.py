@@ -159,3 +159,29 @@ def test_harvest_train_serve_shock(dev):
     assert np.max(np.abs(ma - mb)) < 1e-2
     bz.bz_transport_free(t)
     c.close()
+
+
+def test_closure_n32_gate_closed_and_open(dev):
+    """The closure on the N=32 mesh (a 32768 -> 256 -> 256 -> 32768 network, untrained): 100
+    cells in two groups, the second ragged, on the fine item split.  Gate closed: the
+    convolution for every cell, exactly as without the closure.  Gate open and no judging:
+    every cell served (the untrained network predicts zero) and no group convolved."""
+    N32, L32 = 32, 8.0
+    m = ClosureModel(N32, L32, LAM, hidden=256, seed=5)
+    m.s_in, m.s_out = 0.05, 2.0 ** -6
+    cells = list(W.random_smooth_cells(100, N32, L32, seed=6, umax=1.0))
+    c = bz.Collision([(N32, L32, LAM)], [0] * 100, "batched_f32", weights_cache=m.wcache, fine_split=True)
+    f = torch.from_numpy(c.pack(cells)).to(dev)
+    ref = c.collide(f)
+    for gate, served in ((0.0, 0), (1e30, 100)):
+        d = m.desc(gate=gate, judge_every=0)
+        work = torch.zeros(bz.bz_closure_workspace_bytes(c.batch, d), dtype=torch.uint8, device=dev)
+        q = torch.full((c.elems,), 7.0, dtype=torch.float64, device=dev)
+        bz.bz_closure_collide(c.batch, d, f, q, work)
+        st = bz.bz_closure_read_stats(c.batch, d, work)
+        assert st["served"] == served and st["judged"] == 0
+        if served:
+            assert torch.all(q == 0.0)
+        else:
+            assert torch.equal(q, ref)
+    c.close()
