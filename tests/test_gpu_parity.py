@@ -212,6 +212,27 @@ def test_uneven_mixed_mesh_batch_fp32(dev):
     print("uneven batch FP32 rel L2: median %.2e max %.2e" % (np.median(errs), np.max(errs)))
 
 
+def test_uneven_batch_full_size_sampled(dev):
+    """The whole 1024-cell uneven draw in one batch, as the benchmark runs it: the first and
+    last cell of each mesh against the oracle, conservation for every cell."""
+    full = W.uneven_batch(n_cells=1024)
+    meshes = [(16, 6.0, 1.0), (24, 7.0, 1.0), (32, 8.0, 1.0)]
+    idx = {16: 0, 24: 1, 32: 2}
+    goc = [idx[int(n)] for n in full.Ns]
+    _, qs = run(meshes, goc, full.cells, "batched_f32", dev)
+    for N in (16, 24, 32):
+        members = [i for i in range(len(goc)) if int(full.Ns[i]) == N]
+        L = W.DOMAIN_FOR_N[N]
+        for i in (members[0], members[-1]):
+            _, q_o, _, _ = oracle_for(N, L, 1.0).collide(full.cells[i])
+            e = rel_l2(qs[i], q_o)
+            kap = _kappa(full.cells[i], N, L, 1.0)
+            assert e < max(1e-5, 8 * U32 * kap), (i, N, e, kap)
+    for i in range(len(goc)):
+        N = int(full.Ns[i])
+        assert_conserved(qs[i], N, W.DOMAIN_FOR_N[N])
+
+
 def test_shock_cells_fp32_full_size(dev):
     """All 256 cells of the N=24, L=7 shock problem in one launch; 8 sampled against the oracle."""
     N, L, lam = 24, 7.0, 1.0
