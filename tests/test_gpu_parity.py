@@ -159,7 +159,7 @@ def test_symmetric_schedule_equals_full_sum_fp64(dev, N, L, n):
 @pytest.mark.parametrize("schedule,N,L,n", [("symmetric", 24, 7.0, 130), ("full", 24, 7.0, 130),
                                              ("symmetric", 8, 4.0, 1)])
 def test_fine_split_equals_default_split_fp64(dev, schedule, N, L, n):
-    """BZ_BATCH_FINE_SPLIT (rows cut into up to 8 partial sums for one group alone) gives the
+    """BZ_BATCH_FINE_SPLIT (rows cut into up to 6 partial sums for one group alone) gives the
     default split's FP64 sums to rounding: 130 N=24 cells in three groups, the last ragged, and
     a single N=8 cell."""
     lam = 1.0
