@@ -32,12 +32,15 @@ __device__ inline double minmod(double a, double b) {
 }
 
 // sigma_w = sum_{v1 < 0} |v1| f_0 dv^3 / in_norm, one block, fixed reduction order.
-__global__ void __launch_bounds__(256) k_wall_sigma(int N, double dv, const double *__restrict__ f0, double in_norm,
+// N is a template parameter so that the loop has a fixed trip count and its loads are issued together
+template <int N>
+__global__ void __launch_bounds__(256) k_wall_sigma(double dv, const double *__restrict__ f0, double in_norm,
                                                     double *__restrict__ sigma) {
     __shared__ double red[4];
-    const int M = N * N * N;
+    constexpr int M = N * N * N;
     double s = 0.0;
-    for (int k = threadIdx.x; k < M; k += blockDim.x) {
+#pragma unroll 8
+    for (int k = threadIdx.x; k < M; k += 256) {
         const double v1 = dv * (k / (N * N) - N / 2);
         if (v1 < 0.0) s = fma(-v1, f0[k], s);
     }
@@ -59,13 +62,15 @@ __device__ inline double cellv(const double *__restrict__ f, const double *__res
     return f[(size_t)j * M + k];
 }
 
-// out = alpha * base + beta * (fin + dt * rhs(fin)) at every (cell, velocity).
-__global__ void __launch_bounds__(256) k_transport_stage(int N, int nx, double dv, double dx, double dt,
+// out = alpha * base + beta * (fin + dt * rhs(fin)) at every (cell, velocity).  N is a template
+// parameter so that the index splits are divisions by constants.
+template <int N>
+__global__ void __launch_bounds__(256) k_transport_stage(int nx, double dv, double dx, double dt,
                                                          const double *__restrict__ fin,
                                                          const double *__restrict__ base, double alpha, double beta,
                                                          const double *__restrict__ tab,
                                                          const double *__restrict__ sigma, double *__restrict__ out) {
-    const int M = N * N * N;
+    constexpr int M = N * N * N;
     const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     if (idx >= (size_t)nx * M) return;
     const int j = (int)(idx / M), k = (int)(idx - (size_t)j * M);
@@ -91,20 +96,35 @@ __global__ void __launch_bounds__(256) k_transport_stage(int N, int nx, double d
 
 }  // namespace
 
-static hipError_t transport_rk2(const bz_transport_s *t, double *f, double dt, double *fs, double *sigma,
-                                hipStream_t s) {
-    const int M = t->N * t->N * t->N;
-    const double dv = 2.0 * t->L / t->N;
+template <int N>
+static hipError_t transport_rk2_n(const bz_transport_s *t, double *f, double dt, double *fs, double *sigma,
+                                  hipStream_t s) {
+    constexpr int M = N * N * N;
+    const double dv = 2.0 * t->L / N;
     const size_t n = (size_t)t->nx * M;
     const unsigned blocks = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_wall_sigma, dim3(1), dim3(256), 0, s, t->N, dv, f, t->in_norm, sigma);
-    hipLaunchKernelGGL(k_transport_stage, dim3(blocks), dim3(256), 0, s, t->N, t->nx, dv, t->dx, dt, f, f, 0.0, 1.0,
+    hipLaunchKernelGGL(k_wall_sigma<N>, dim3(1), dim3(256), 0, s, dv, f, t->in_norm, sigma);
+    hipLaunchKernelGGL(k_transport_stage<N>, dim3(blocks), dim3(256), 0, s, t->nx, dv, t->dx, dt, f, f, 0.0, 1.0,
                        t->d_tab, sigma, fs);
-    hipLaunchKernelGGL(k_wall_sigma, dim3(1), dim3(256), 0, s, t->N, dv, fs, t->in_norm, sigma);
+    hipLaunchKernelGGL(k_wall_sigma<N>, dim3(1), dim3(256), 0, s, dv, fs, t->in_norm, sigma);
     // each thread reads f and fs at its own index only for the base term, so f may be the output
-    hipLaunchKernelGGL(k_transport_stage, dim3(blocks), dim3(256), 0, s, t->N, t->nx, dv, t->dx, dt, fs, f, 0.5, 0.5,
+    hipLaunchKernelGGL(k_transport_stage<N>, dim3(blocks), dim3(256), 0, s, t->nx, dv, t->dx, dt, fs, f, 0.5, 0.5,
                        t->d_tab, sigma, f);
     return hipGetLastError();
+}
+
+static hipError_t transport_rk2(const bz_transport_s *t, double *f, double dt, double *fs, double *sigma,
+                                hipStream_t s) {
+    switch (t->N) {
+    case 8: return transport_rk2_n<8>(t, f, dt, fs, sigma, s);
+    case 12: return transport_rk2_n<12>(t, f, dt, fs, sigma, s);
+    case 16: return transport_rk2_n<16>(t, f, dt, fs, sigma, s);
+    case 20: return transport_rk2_n<20>(t, f, dt, fs, sigma, s);
+    case 24: return transport_rk2_n<24>(t, f, dt, fs, sigma, s);
+    case 28: return transport_rk2_n<28>(t, f, dt, fs, sigma, s);
+    case 32: return transport_rk2_n<32>(t, f, dt, fs, sigma, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace bz
