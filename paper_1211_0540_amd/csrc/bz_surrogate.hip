@@ -48,7 +48,8 @@ __device__ inline unsigned short f2bf(float x) {
 }
 
 // one block per cell
-__global__ void __launch_bounds__(256) k_prepare(int N, double dv, const double *__restrict__ f,
+template <int N>
+__global__ void __launch_bounds__(256) k_prepare(double dv, const double *__restrict__ f,
                                                  const long long *__restrict__ f_off, double gate, double inv_s_in,
                                                  int judge_every, int phase, double *__restrict__ state,
                                                  unsigned short *__restrict__ x) {
@@ -151,7 +152,8 @@ struct Basis {
     double a[25];
 };
 
-__device__ inline void basis5(int N, double dv, const Basis &li, int j, double e[5]) {
+template <int N>
+__device__ inline void basis5(double dv, const Basis &li, int j, double e[5]) {
     const int j1 = j / (N * N), j2 = (j / N) % N, j3 = j % N;
     const double v1 = dv * (j1 - N / 2), v2 = dv * (j2 - N / 2), v3 = dv * (j3 - N / 2);
     const double w = dv * dv * dv;
@@ -164,7 +166,8 @@ __device__ inline void basis5(int N, double dv, const Basis &li, int j, double e
 }
 
 // one block per cell: select the closure or the convolution, judge sampled cells
-__global__ void __launch_bounds__(256) k_finish(int N, double dv, Basis li, const double *__restrict__ state,
+template <int N>
+__global__ void __launch_bounds__(256) k_finish(double dv, Basis li, const double *__restrict__ state,
                                                 const float *__restrict__ y, double s_out, double floor_,
                                                 double tol, const long long *__restrict__ q_off,
                                                 double *__restrict__ q, unsigned *__restrict__ stats) {
@@ -185,7 +188,7 @@ __global__ void __launch_bounds__(256) k_finish(int N, double dv, Basis li, cons
     double dd = 0, cc = 0, md[5] = {0, 0, 0, 0, 0}, mc[5] = {0, 0, 0, 0, 0};
     for (int j = threadIdx.x; j < M; j += blockDim.x) {
         double e[5];
-        basis5(N, dv, li, j, e);
+        basis5<N>(dv, li, j, e);
         const double qc = Q[j], dj = sc * (double)Y[j] - qc;
         dd += dj * dj;
         cc += qc * qc;
@@ -211,7 +214,8 @@ __global__ void __launch_bounds__(256) k_finish(int N, double dv, Basis li, cons
 }
 
 // y = Q / (rho |f - M|_2 s_out) for harvesting training targets (0 where f = M)
-__global__ void k_targets(int N, const double *__restrict__ state, const double *__restrict__ q,
+template <int N>
+__global__ void k_targets(const double *__restrict__ state, const double *__restrict__ q,
                           const long long *__restrict__ q_off, double inv_s_out, float *__restrict__ y) {
     const int c = blockIdx.y, M = N * N * N;
     const double *st = state + (size_t)c * kState;
@@ -223,11 +227,27 @@ __global__ void k_targets(int N, const double *__restrict__ state, const double 
 
 }  // namespace
 
+// the mesh sizes the library accepts (multiples of 4 from 8 to 32)
+#define BZ_SUR_FOR_N(CALL)                                   \
+    switch (N) {                                             \
+    case 8: CALL(8); break;                                  \
+    case 12: CALL(12); break;                                \
+    case 16: CALL(16); break;                                \
+    case 20: CALL(20); break;                                \
+    case 24: CALL(24); break;                                \
+    case 28: CALL(28); break;                                \
+    case 32: CALL(32); break;                                \
+    default: return hipErrorInvalidValue;                    \
+    }
+
 hipError_t launch_sur_prepare(int N, double dv, int n, const double *f, const long long *f_off, double gate,
                               double s_in, int judge_every, int phase, double *state, unsigned short *x,
                               hipStream_t s) {
-    hipLaunchKernelGGL(k_prepare, dim3(n), dim3(256), 0, s, N, dv, f, f_off, gate, 1.0 / s_in, judge_every, phase,
-                       state, x);
+#define BZ_PREP(NN)                                                                                             \
+    hipLaunchKernelGGL(k_prepare<NN>, dim3(n), dim3(256), 0, s, dv, f, f_off, gate, 1.0 / s_in, judge_every, \
+                       phase, state, x)
+    BZ_SUR_FOR_N(BZ_PREP)
+#undef BZ_PREP
     return hipGetLastError();
 }
 
@@ -242,14 +262,21 @@ hipError_t launch_sur_finish(int N, double dv, const double *linv, int n, const 
                              unsigned *stats, hipStream_t s) {
     Basis li;
     for (int i = 0; i < 25; ++i) li.a[i] = linv[i];
-    hipLaunchKernelGGL(k_finish, dim3(n), dim3(256), 0, s, N, dv, li, state, y, s_out, floor_, tol, q_off, q, stats);
+#define BZ_FIN(NN)                                                                                              \
+    hipLaunchKernelGGL(k_finish<NN>, dim3(n), dim3(256), 0, s, dv, li, state, y, s_out, floor_, tol, q_off, q, \
+                       stats)
+    BZ_SUR_FOR_N(BZ_FIN)
+#undef BZ_FIN
     return hipGetLastError();
 }
 
 hipError_t launch_sur_targets(int N, int n, const double *state, const double *q, const long long *q_off,
                               double s_out, float *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_targets, dim3(16, n), dim3(256), 0, s, N, state, q, q_off, 1.0 / s_out, y);
+#define BZ_TGT(NN) hipLaunchKernelGGL(k_targets<NN>, dim3(16, n), dim3(256), 0, s, state, q, q_off, 1.0 / s_out, y)
+    BZ_SUR_FOR_N(BZ_TGT)
+#undef BZ_TGT
     return hipGetLastError();
 }
+#undef BZ_SUR_FOR_N
 
 }  // namespace bz
