@@ -152,11 +152,11 @@ bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids,
  *   BZ_BATCH_FINE_SPLIT  cut the rows into work items small enough for the
  *                      rows of a single 64-cell group to fill the device (by
  *                      default the whole batch is counted; at most 6 pieces
- *                      per row).  For batches of
- *                      which only a few groups are usually convolved, as with
- *                      the gated closure; a full batch takes somewhat longer.
- *                      The same sum in more partial sums: results agree with
- *                      the default split to rounding.
+ *                      per row).  For batches of which only a few groups are
+ *                      usually convolved, as with the gated closure; a full
+ *                      batch takes somewhat longer.  The same sum in more
+ *                      partial sums: results agree with the default split to
+ *                      rounding.
  * Errors: as bz_batch_create, and BZ_EINVAL for unknown flags. */
 #define BZ_BATCH_FULL_SUM 1
 #define BZ_BATCH_FINE_SPLIT 2
