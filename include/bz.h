@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define BZ_API_VERSION 1
+#define BZ_API_VERSION 2
 
 typedef enum {
     BZ_OK = 0,
@@ -91,7 +91,26 @@ typedef struct {
     double dv;           /* 2L/N */
     double dzeta;        /* pi/L */
     long long pairs;     /* valid (zeta_k, xi_m) pairs of the convolution: (3N^2/4)^3 */
+    int core_r2;         /* radius^2 of the FP64 core ball in index units (0: no core) */
+    long long core_steps;/* steps of the core schedule (row pairs; 0 without a core) */
 } bz_grid_info;
+
+/* Low-frequency FP64 core of the batched FP32 mode.
+ *
+ * The terms of the sum of Sec. 3.2 are largest where both partners lie near
+ * zeta = 0 (the transform of a distribution is concentrated there).  Rounding
+ * fhat and the weights to FP32 perturbs each term by about 6e-8 of itself; on
+ * near-equilibrium cells, whose terms cancel to a Qhat hundreds to thousands of
+ * times smaller than their magnitudes, that leaves a relative error above
+ * 1e-5 however the sum is accumulated.  With a core, the pairs whose two
+ * partners both lie in the ball nc = |m - N/2|^2 <= core_r2 (index units) are
+ * summed by a separate FP64 kernel from FP64 fhat and FP64 weights, and their
+ * weights in the FP32 stream are zero: the same sum, split by frequency, each
+ * term evaluated once.  The core costs a few percent of the FP32 work.  It
+ * applies to BZ_MODE_BATCHED_F32 only (the FP64 modes are exact already, the
+ * plain FP32 mode keeps its single stream). */
+#define BZ_CORE_DEFAULT (-1)  /* the ball |zeta| < pi: nc <= ceil(L^2) - 1, capped as below */
+#define BZ_CORE_OFF (-2)      /* no core: every pair in FP32 */
 
 /* Create a mesh handle.  Host only, no device work.  Errors: BZ_EINVAL for N
  * not a multiple of 4, N outside [8, 32], L <= 0 or non-finite;
@@ -99,6 +118,12 @@ typedef struct {
  * spheres), the two exponents whose weight integral the library evaluates in
  * closed form. */
 bz_status bz_grid_init(int N, double L, double lambda, bz_grid *out);
+/* As bz_grid_init with an explicit core: core_r2 in [1, min(N^2/4, 81) - 1]
+ * (the ball stays off the k_d = 0 planes and within the kernel's half-width of
+ * 8), BZ_CORE_DEFAULT (what bz_grid_init uses) or BZ_CORE_OFF.  The core is a
+ * property of the mesh: it fixes the layout of its BZ_W_BATCHED_F32 weights.
+ * Errors: as bz_grid_init, and BZ_EINVAL for a core_r2 out of range. */
+bz_status bz_grid_init_ex(int N, double L, double lambda, int core_r2, bz_grid *out);
 void bz_grid_free(bz_grid g);
 bz_status bz_grid_query(bz_grid g, bz_grid_info *info);
 /* Host copies of the 1-D velocity and frequency nodes (N doubles each, either may be NULL). */
@@ -116,7 +141,8 @@ bz_status bz_grid_coords(bz_grid g, double *v, double *zeta);
 /* Bytes needed for a weight buffer of the given kind (0 for an unknown kind).
  * A batched buffer holds the weight stream of every output row in schedule
  * order and, after it, the stream of the edge pass of the conjugate-symmetric
- * schedule (bz_batch_create_ex). */
+ * schedule (bz_batch_create_ex); a BZ_W_BATCHED_F32 buffer of a mesh with a
+ * core then holds the FP64 weights of the core steps. */
 size_t bz_weights_bytes(bz_grid g, int kind);
 /* Fill d_w (bytes >= bz_weights_bytes) on `stream`.  Synchronises the stream
  * before returning (it uploads a host-built table).  Errors: BZ_EINVAL for a
@@ -376,6 +402,9 @@ bz_status bz_batch_autotune(bz_batch b, const double *d_f, double *d_Qt, void *d
  * the record. */
 bz_status bz_batch_timer(bz_batch b, int enable);
 bz_status bz_batch_timer_read(bz_batch b, double *conv_ms, int *launches);
+/* The FP64 core launches (bz_grid_init_ex) are timed separately by the same
+ * switch: their summed time and count as of the last bz_batch_timer_read. */
+bz_status bz_batch_core_timer(bz_batch b, double *core_ms, int *launches);
 
 const char *bz_status_string(bz_status s);
 const char *bz_last_error(void);

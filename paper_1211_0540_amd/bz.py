@@ -18,6 +18,7 @@ LIBPATH = os.path.join(_HERE, "libbz.so")
 BZ_OK, BZ_EINVAL, BZ_EUNSUPPORTED, BZ_EDEVICE, BZ_ENOMEM, BZ_ENONFINITE, BZ_ESTATE = 0, -1, -2, -3, -4, -5, -6
 BZ_W_BATCHED_F32, BZ_W_BATCHED_F64, BZ_W_PLAIN_F32, BZ_W_PLAIN_F64 = 1, 2, 3, 4
 BZ_MODE_PLAIN_F64, BZ_MODE_BATCHED_F32, BZ_MODE_BATCHED_F64, BZ_MODE_PLAIN_F32 = 1, 2, 3, 4
+BZ_CORE_DEFAULT, BZ_CORE_OFF = -1, -2
 BZ_BATCH_FULL_SUM = 1
 BZ_BATCH_FINE_SPLIT = 2
 SCHEDULES = {"symmetric": 0, "full": BZ_BATCH_FULL_SUM}
@@ -36,7 +37,8 @@ class BzError(RuntimeError):
 
 class GridInfo(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("L", ctypes.c_double), ("lambda_", ctypes.c_double),
-                ("dv", ctypes.c_double), ("dzeta", ctypes.c_double), ("pairs", ctypes.c_longlong)]
+                ("dv", ctypes.c_double), ("dzeta", ctypes.c_double), ("pairs", ctypes.c_longlong),
+                ("core_r2", ctypes.c_int), ("core_steps", ctypes.c_longlong)]
 
 
 _vp = ctypes.c_void_p
@@ -68,6 +70,8 @@ def lib():
         "bz_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "bz_last_error": (ctypes.c_char_p, []),
         "bz_grid_init": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.POINTER(_vp)]),
+        "bz_grid_init_ex": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                           ctypes.POINTER(_vp)]),
         "bz_grid_free": (None, [_vp]),
         "bz_grid_query": (ctypes.c_int, [_vp, ctypes.POINTER(GridInfo)]),
         "bz_grid_coords": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
@@ -124,6 +128,7 @@ def lib():
         "bz_batch_autotune": (ctypes.c_int, [_vp, _vp, _vp, _vp, _sz, ctypes.c_int, _vp]),
         "bz_batch_timer": (ctypes.c_int, [_vp, ctypes.c_int]),
         "bz_batch_timer_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
+        "bz_batch_core_timer": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -169,6 +174,12 @@ def bz_grid_init(N: int, L: float, lam: float) -> int:
     return h.value
 
 
+def bz_grid_init_ex(N: int, L: float, lam: float, core_r2: int = BZ_CORE_DEFAULT) -> int:
+    h = _vp()
+    _check(lib().bz_grid_init_ex(int(N), float(L), float(lam), int(core_r2), ctypes.byref(h)))
+    return h.value
+
+
 def bz_grid_free(g: int) -> None:
     lib().bz_grid_free(_vp(g))
 
@@ -177,7 +188,7 @@ def bz_grid_query(g: int) -> dict:
     info = GridInfo()
     _check(lib().bz_grid_query(_vp(g), ctypes.byref(info)))
     return {"N": info.N, "L": info.L, "lambda": info.lambda_, "dv": info.dv, "dzeta": info.dzeta,
-            "pairs": info.pairs}
+            "pairs": info.pairs, "core_r2": info.core_r2, "core_steps": info.core_steps}
 
 
 def bz_grid_coords(g: int):
@@ -458,13 +469,21 @@ def bz_batch_timer_read(b: int):
     return ms.value, n.value
 
 
+def bz_batch_core_timer(b: int):
+    ms = ctypes.c_double()
+    n = ctypes.c_int()
+    _check(lib().bz_batch_core_timer(_vp(b), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
 # ---------------------------------------------------------------------------
 # Convenience owner of handles and device buffers (still only marshalling).
 # ---------------------------------------------------------------------------
 class Collision:
     """A batch of cells on one or more meshes with its weights and workspace.
 
-    meshes: list of (N, L, lambda); grid_of_cell: mesh index per cell;
+    meshes: list of (N, L, lambda) or (N, L, lambda, core_r2) (core_r2 as in
+    bz_grid_init_ex; the default core otherwise); grid_of_cell: mesh index per cell;
     mode: one of MODE_NAMES or BZ_MODE_*; schedule: "symmetric" (conjugate
     symmetry halves the batched sum, the default) or "full"; fine_split: work
     items sized for a single 64-cell group to fill the device (for batches of
@@ -478,7 +497,7 @@ class Collision:
         self.mode = MODE_NAMES.get(mode, mode)
         self.kind = MODE_WEIGHTS[self.mode]
         self.meshes = [tuple(m) for m in meshes]
-        self.grids = [bz_grid_init(*m) for m in self.meshes]
+        self.grids = [bz_grid_init_ex(*m) for m in self.meshes]
         self.grid_of_cell = np.asarray(grid_of_cell, dtype=np.int32)
         self.schedule = schedule
         flags = SCHEDULES[schedule] | (BZ_BATCH_FINE_SPLIT if fine_split else 0)

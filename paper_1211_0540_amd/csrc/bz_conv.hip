@@ -363,6 +363,90 @@ __global__ void __launch_bounds__(64) k_conv_cells_f64(const double2 *__restrict
 }
 
 // ---------------------------------------------------------------------------
+// FP64 core of the batched FP32 mode (CoreSched in bz_internal.h): the pairs
+// whose two partners lie in the low-frequency ball carry the largest terms of
+// the sum, so they are summed here in FP64 from FP64 fhat, with FP64 weights.
+// Lane = cell, like the batched kernels; an item is one output row of one
+// group and one half of its outputs (k3 - N/2 in [-2R, 0] or [1, 2R]), so that
+// the accumulators of half a row and the two core rows of a step fit two
+// wavefronts per SIMD.  A step loads its two rows (2R + 1 values each) and
+// reads its (2R + 1)^2 weights from LDS, copied there during the previous step.
+// ---------------------------------------------------------------------------
+template <int R, int HALF>
+__device__ __forceinline__ void core_step(const double2 (&mr)[2 * R + 1], const double2 (&jr)[2 * R + 1],
+                                          const double *wl, double2 (&acc)[2 * R + 1]) {
+    constexpr int S = 2 * R + 1;
+#pragma unroll
+    for (int tm = 0; tm < S; ++tm)
+#pragma unroll
+        for (int tj = 0; tj < S; ++tj) {
+            const int e = tm + tj - 2 * R;   // k3 - N/2
+            if ((HALF == 0 && e <= 0) || (HALF == 1 && e > 0)) {
+                const int a = HALF == 0 ? e + 2 * R : e - 1;
+                const double wt = wl[tm * S + tj];
+                const double px = fma(mr[tm].x, jr[tj].x, -(mr[tm].y * jr[tj].y));
+                const double py = fma(mr[tm].x, jr[tj].y, mr[tm].y * jr[tj].x);
+                acc[a].x = fma(wt, px, acc[a].x);
+                acc[a].y = fma(wt, py, acc[a].y);
+            }
+        }
+}
+
+template <int R>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+k_conv_core(int N, int nD, const double2 *__restrict__ cf, const int4 *__restrict__ items, int n_items,
+            unsigned *__restrict__ counter, const int *__restrict__ steps, const double *__restrict__ w,
+            double2 *__restrict__ out, const unsigned char *__restrict__ skip) {
+    constexpr int S = 2 * R + 1, WS = core_wstride(R), CH = WS * 8 / 1024;
+    __shared__ __attribute__((aligned(16))) double wbuf[2][WS];
+    lds_char *const wl = lds_ptr(&wbuf[0][0]);
+    const int lane = threadIdx.x;
+    const int h = N / 2;
+    for (;;) {
+        const int it = pop_item(counter);
+        if (it >= n_items) break;
+        const int4 item = items[it];
+        const int g = item.x, r = item.y & 0xffff, half = item.y >> 16, s0 = item.z, s1 = item.w;
+        if (skip && skip[g]) continue;   // the closure serves every cell of the group
+        double2 *const o = out + ((size_t)g * N * N * N + (size_t)r * N) * kWave + lane;
+        const double2 *const G = cf + (size_t)g * nD * S * kWave + lane;
+        double2 acc[S];
+#pragma unroll
+        for (int a = 0; a < S; ++a) acc[a] = make_double2(0.0, 0.0);
+        const double *ws = w + (size_t)s0 * WS;
+        if (s0 < s1) prefetch_weights<CH>(ws, wl);
+        __builtin_amdgcn_s_waitcnt(0);
+        int buf = 0;
+        for (int s = s0; s < s1; ++s) {
+            const int st = steps[s];
+            const double2 *pm = G + (size_t)(st & 0xffff) * S * kWave;
+            const double2 *pj = G + (size_t)(st >> 16) * S * kWave;
+            double2 mr[S], jr[S];
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+                mr[t] = pm[t * kWave];
+                jr[t] = pj[t * kWave];
+            }
+            if (s + 1 < s1) prefetch_weights<CH>(ws + WS, wl + (buf ^ 1) * WS * 8);
+            if (half == 0) core_step<R, 0>(mr, jr, wbuf[buf], acc);
+            else core_step<R, 1>(mr, jr, wbuf[buf], acc);
+            ws += WS;
+            buf ^= 1;
+            __builtin_amdgcn_s_waitcnt(0);
+        }
+        if (half == 0) {
+#pragma unroll
+            for (int e = -2 * R; e <= 0; ++e)
+                if (h + e >= 0) o[(h + e) * kWave] = acc[e + 2 * R];
+        } else {
+#pragma unroll
+            for (int e = 1; e <= 2 * R; ++e)
+                if (h + e < N) o[(h + e) * kWave] = acc[e - 1];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Plain schedule, one cell.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int plain_rows_c(int N) {
@@ -502,6 +586,31 @@ static unsigned persistent_grid(int n_items) {
         cus = 256;
     unsigned g = (unsigned)cus * 8u;
     return (unsigned)n_items < g ? (unsigned)n_items : g;
+}
+
+template <int R>
+hipError_t core_launch(const CoreLaunch &p, unsigned grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_conv_core<R>, dim3(grid), dim3(64), 0, s, p.N, p.nD, p.cf, p.items, p.n_items, p.counter,
+                       p.steps, p.w, p.out, p.skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_core(const CoreLaunch &p, hipStream_t s) {
+    if (p.n_items <= 0) return hipSuccess;
+    if (p.r < 1 || p.r > kCoreMaxR) return hipErrorInvalidValue;
+    hipError_t e = launch_fill_u32(p.counter, 1, 0u, s);
+    if (e != hipSuccess) return e;
+    const unsigned grid = persistent_grid(p.n_items);
+    switch (p.r) {
+    case 1: return core_launch<1>(p, grid, s);
+    case 2: return core_launch<2>(p, grid, s);
+    case 3: return core_launch<3>(p, grid, s);
+    case 4: return core_launch<4>(p, grid, s);
+    case 5: return core_launch<5>(p, grid, s);
+    case 6: return core_launch<6>(p, grid, s);
+    case 7: return core_launch<7>(p, grid, s);
+    default: return core_launch<8>(p, grid, s);
+    }
 }
 
 #define BZ_FOR_EACH_N(X) X(8) X(12) X(16) X(20) X(24) X(28) X(32)

@@ -347,9 +347,12 @@ __global__ void __launch_bounds__(256) k_dftg_fwd2(const double2 *__restrict__ S
 // forward, axis 1: line (k2, k3): T (j1, k2, k3) -> fhat (k1, k2, k3), scaled, in the kernel's precision;
 // with copies = 4 also fhat with the axes ordered (2, 1, 3) and (3, 1, 2), and fhat with every k_d = 0
 // plane set to zero (axes in order), copy_stride elements apart
+// With cf non-NULL it also writes the FP64 rows of the low-frequency core (CoreFill).
 template <int N, typename Out>
 __global__ void __launch_bounds__(256) k_dftg_fwd3(const double2 *__restrict__ T, int nc, double scale,
                                                    Out *__restrict__ fh, int copies, long long copy_stride,
+                                                   double2 *__restrict__ cf, const int *__restrict__ disk_idx,
+                                                   int nD, int cr, int cr2,
     const unsigned char *__restrict__ skip) {
     BZ_LINE_SETUP
     const size_t off = (gb + (size_t)line) * kWave + lane;
@@ -374,6 +377,22 @@ __global__ void __launch_bounds__(256) k_dftg_fwd3(const double2 *__restrict__ T
             fh[3 * copy_stride + off + (size_t)k * N * N * kWave] = z;
         }
     }
+    if (cf) {
+        constexpr int h = N / 2;
+        const int k2 = line / N, k3 = line - k2 * N, t = k3 - (h - cr);
+        if (t >= 0 && t <= 2 * cr) {
+            const int b2 = (k2 - h) * (k2 - h), c2 = (k3 - h) * (k3 - h);
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const int a2 = (k - h) * (k - h);
+                if (a2 + b2 > cr2) continue;   // row (k, k2) is not in the core disk
+                const int d = disk_idx[k * N + k2];
+                const bool in = live && a2 + b2 + c2 <= cr2;
+                cf[(((size_t)g * nD + d) * (2 * cr + 1) + t) * kWave + lane] =
+                    in ? make_double2(x[k].x * scale, x[k].y * scale) : make_double2(0.0, 0.0);
+            }
+        }
+    }
 }
 
 // inverse, axis 1, conjugate-symmetric schedule: assemble Qhat(k1, k2, k3) of line (k2, k3) from the
@@ -386,8 +405,24 @@ __global__ void __launch_bounds__(256) k_dftg_fwd3(const double2 *__restrict__ T
 // E3 at (k3, k1, k2) if k3 < N/2.
 // Three wavefronts per SIMD: at N=32 that costs some register spills, but the 3 x 1024 lines of a
 // 190-cell batch then run in one round (139 instead of 157 us measured).
+// The FP64 core sum (CoreAdd; core NULL when off) is added to every output within 2cr of the centre.
+template <int N>
+__device__ __forceinline__ void add_core(double2 (&x)[N], const double2 *__restrict__ core, int cr, size_t gl, int k2,
+                                         int k3) {
+    constexpr int h = N / 2;
+    if (!core || abs(k2 - h) > 2 * cr || abs(k3 - h) > 2 * cr) return;
+#pragma unroll
+    for (int k1 = 0; k1 < N; ++k1) {
+        if (abs(k1 - h) > 2 * cr) continue;
+        const double2 c = core[gl + ((size_t)(k1 * N + k2) * N + k3) * kWave];
+        x[k1].x += c.x;
+        x[k1].y += c.y;
+    }
+}
+
 template <int N>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_dftg_inv1_herm(const double2 *__restrict__ qh, int nA, long long pstride,
+                                                        const double2 *__restrict__ core, int cr,
                                                         double2 *__restrict__ S,
     const unsigned char *__restrict__ skip) {
     BZ_LINE_SETUP
@@ -443,16 +478,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
             x[k1] = make_double2(i.x + e.x, e.y - i.y);
         }
     }
+    add_core<N>(x, core, cr, gl, k2, k3);
     line_dft<N, +1>(x, S + gl + (size_t)line * kWave, (size_t)N * N * kWave, 1.0);
 }
 
 // inverse, axis 1: line (k2, k3): sum of the partial buffers (k1, k2, k3) -> S (j1, k2, k3)
 template <int N>
 __global__ void __launch_bounds__(256) k_dftg_inv1(const double2 *__restrict__ qh, int nparts, long long pstride,
+                                                   const double2 *__restrict__ core, int cr,
                                                    double2 *__restrict__ S,
     const unsigned char *__restrict__ skip) {
     BZ_LINE_SETUP
     const size_t off = (gb + (size_t)line) * kWave + lane;
+    const int k2 = line / N, k3 = line - k2 * N;
     double2 x[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
@@ -464,6 +502,7 @@ __global__ void __launch_bounds__(256) k_dftg_inv1(const double2 *__restrict__ q
         }
         x[j] = a;
     }
+    add_core<N>(x, core, cr, gb * kWave + lane, k2, k3);
     line_dft<N, +1>(x, S + off, (size_t)N * N * kWave, 1.0);
 }
 
@@ -501,7 +540,8 @@ __global__ void __launch_bounds__(256) k_dftg_inv3(const double2 *__restrict__ T
 
 template <int N>
 hipError_t grouped_forward(double L, int nc, const double *f, const long long *f_off, double2 *S, double2 *T,
-                           void *fh, bool f32, int copies, const unsigned char *skip, hipStream_t s) {
+                           void *fh, bool f32, int copies, const CoreFill &cfill, const unsigned char *skip,
+                           hipStream_t s) {
     const int groups = (nc + kWave - 1) / kWave;
     const dim3 grid(N * N / 4, groups);
     const double dv = 2.0 * L / N;
@@ -511,25 +551,26 @@ hipError_t grouped_forward(double L, int nc, const double *f, const long long *f
     hipLaunchKernelGGL(k_dftg_fwd2<N>, grid, dim3(256), 0, s, S, T, skip);
     if (f32)
         hipLaunchKernelGGL((k_dftg_fwd3<N, float2>), grid, dim3(256), 0, s, T, nc, scale, (float2 *)fh, copies,
-                           cstride, skip);
+                           cstride, cfill.cf, cfill.disk_idx, cfill.nD, cfill.r, cfill.r2, skip);
     else
         hipLaunchKernelGGL((k_dftg_fwd3<N, double2>), grid, dim3(256), 0, s, T, nc, scale, (double2 *)fh, copies,
-                           cstride, skip);
+                           cstride, cfill.cf, cfill.disk_idx, cfill.nD, cfill.r, cfill.r2, skip);
     return hipGetLastError();
 }
 
 template <int N>
 hipError_t grouped_inverse(double L, int nc, const double2 *qh, int nparts, long long pstride,
-                           const HermAssembly &herm, double2 *S, double2 *T, double *qt, const long long *q_off,
-                           const unsigned char *skip, hipStream_t s) {
+                           const HermAssembly &herm, const CoreAdd &core, double2 *S, double2 *T, double *qt,
+                           const long long *q_off, const unsigned char *skip, hipStream_t s) {
     const int groups = (nc + kWave - 1) / kWave;
     const dim3 grid(N * N / 4, groups);
     const double dz = kPi / L;
     const double scale = pow(2.0 * kPi, -1.5) * dz * dz * dz;
     if (herm.on)
-        hipLaunchKernelGGL(k_dftg_inv1_herm<N>, grid, dim3(256), 0, s, qh, herm.nA, pstride, S, skip);
+        hipLaunchKernelGGL(k_dftg_inv1_herm<N>, grid, dim3(256), 0, s, qh, herm.nA, pstride, core.core, core.r, S,
+                           skip);
     else
-        hipLaunchKernelGGL(k_dftg_inv1<N>, grid, dim3(256), 0, s, qh, nparts, pstride, S, skip);
+        hipLaunchKernelGGL(k_dftg_inv1<N>, grid, dim3(256), 0, s, qh, nparts, pstride, core.core, core.r, S, skip);
     hipLaunchKernelGGL(k_dftg_inv2<N>, grid, dim3(256), 0, s, S, T, skip);
     hipLaunchKernelGGL(k_dftg_inv3<N>, grid, dim3(256), 0, s, T, nc, scale, qt, q_off, skip);
     return hipGetLastError();
@@ -541,11 +582,11 @@ hipError_t grouped_inverse(double L, int nc, const double2 *qh, int nparts, long
 
 hipError_t launch_dft_forward_grouped(int N, double L, int ncells, const double *f, const long long *d_f_off,
                                       double2 *S, double2 *T, void *fh, bool out_f32, int copies,
-                                      const unsigned char *skip, hipStream_t s) {
+                                      const CoreFill &core, const unsigned char *skip, hipStream_t s) {
     if (ncells <= 0) return hipSuccess;
     if (copies != 1 && copies != 4) return hipErrorInvalidValue;
 #define CASE(NN) \
-    case NN: return grouped_forward<NN>(L, ncells, f, d_f_off, S, T, fh, out_f32, copies, skip, s);
+    case NN: return grouped_forward<NN>(L, ncells, f, d_f_off, S, T, fh, out_f32, copies, core, skip, s);
     switch (N) {
         BZ_FOR_EACH_N(CASE)
     default:
@@ -555,11 +596,12 @@ hipError_t launch_dft_forward_grouped(int N, double L, int ncells, const double 
 }
 
 hipError_t launch_dft_inverse_grouped(int N, double L, int ncells, const double2 *qh, int nparts, long long pstride,
-                                      const HermAssembly &herm, double2 *S, double2 *T, double *qt,
-                                      const long long *d_q_off, const unsigned char *skip, hipStream_t s) {
+                                      const HermAssembly &herm, const CoreAdd &core, double2 *S, double2 *T,
+                                      double *qt, const long long *d_q_off, const unsigned char *skip,
+                                      hipStream_t s) {
     if (ncells <= 0) return hipSuccess;
 #define CASE(NN) \
-    case NN: return grouped_inverse<NN>(L, ncells, qh, nparts, pstride, herm, S, T, qt, d_q_off, skip, s);
+    case NN: return grouped_inverse<NN>(L, ncells, qh, nparts, pstride, herm, core, S, T, qt, d_q_off, skip, s);
     switch (N) {
         BZ_FOR_EACH_N(CASE)
     default:

@@ -121,6 +121,41 @@ struct HermAssembly {
     int nA;
 };
 
+// FP64 sum of the low-frequency core, added to every output by the first
+// inverse-transform pass: core[g][k][lane] (one full output buffer) holds it
+// for the outputs k with every |k_d - N/2| <= 2r; NULL when the core is off.
+struct CoreAdd {
+    const double2 *core;
+    int r;
+};
+
+// ---------------------------------------------------------------------------
+// Low-frequency core of the batched FP32 mode.
+//
+// Near the centre of the Fourier mesh |fhat| is largest, and so are the terms
+// of the sum of Sec. 3.2 there; rounding fhat and the weights to FP32 leaves an
+// error proportional to those terms, which for near-Maxwellian cells (whose
+// terms cancel to a small Qhat) exceeds a relative 1e-5.  The pairs whose two
+// partners both lie in the ball |m - N/2|^2 <= r2 (the "core") are therefore
+// summed in FP64 by a separate kernel, and their weights are zero in the FP32
+// stream.  The core sum is taken over every output, so it does not depend on
+// the conjugate-symmetric schedule; it is added after the assembly of the FP32
+// passes.  Same sum, split by frequency, each term evaluated once.
+//
+// Rows of the core: the disk (a - h)^2 + (b - h)^2 <= r2, numbered in
+// lexicographic order; a core row holds the S = 2r + 1 values m3 = h - r .. h + r
+// (zero outside the ball).  A core step of output row (k1, k2) is a pair of
+// core rows (m1, m2) <= (j1, j2) (lexicographic) with j = k + h - m on both
+// axes; its S x S weights are indexed (tm, tj) with m3 = h - r + tm,
+// j3 = h - r + tj, output k3 = m3 + j3 - h, zero off the ball, off the mesh and
+// for tm > tj in a diagonal step (m1, m2) = (j1, j2).
+// ---------------------------------------------------------------------------
+constexpr int kCoreMaxR = 8;
+__host__ __device__ constexpr int core_wstride(int r) {
+    // weights of one step, padded to whole KiB (128 doubles) for the direct-to-LDS copy
+    return ((2 * r + 1) * (2 * r + 1) + 127) / 128 * 128;
+}
+
 // ---------------------------------------------------------------------------
 // Plain ("lane = output") schedule, one cell at a time.
 //
@@ -143,6 +178,17 @@ __host__ __device__ inline long long plain_block_iters(int N, int k1, int kb) {
 // ---------------------------------------------------------------------------
 // Mesh handle.
 // ---------------------------------------------------------------------------
+struct CoreSched {
+    int r2 = -1;                      // radius^2 of the core ball; -1: no core
+    int r = 0;                        // floor(sqrt(r2)), the per-axis half-width
+    int nD = 0;                       // rows in the disk
+    std::vector<int> disk_idx;        // N*N: index of row (a, b) in the disk, -1 outside
+    std::vector<int> row_steps;       // N*N: core steps of output row (k1, k2)
+    std::vector<long long> row_soff;  // N*N: first step of the row in the step list
+    std::vector<int> steps;           // per step: disk index of the m row | (disk index of the j row) << 16
+    long long nsteps = 0;
+};
+
 struct Schedule {
     // batched: N*N rows, offsets in weights (elements), steps per row
     std::vector<long long> row_woff;
@@ -155,6 +201,7 @@ struct Schedule {
     // plain: N * (N / R) blocks
     std::vector<long long> blk_woff;
     long long plain_weights = 0;
+    CoreSched core;
 };
 
 }  // namespace bz
@@ -183,8 +230,9 @@ bz_status hip_fail(hipError_t e, const char *what);
 // Kernel launchers (defined in the .hip files).  All take a hipStream_t.
 // ---------------------------------------------------------------------------
 // Weight expansion from the FP64 universal table T[p * qstride + q].
+// Pairs with both partners in the core ball (core_r2 >= 0) get weight 0 (they are summed in FP64).
 hipError_t launch_expand_cells(int N, const double *dT, int qstride, double scale, const long long *d_row_woff,
-                               void *d_w, bool f64, hipStream_t s);
+                               void *d_w, bool f64, int core_r2, hipStream_t s);
 hipError_t launch_expand_plain(int N, const double *dT, int qstride, double scale, const long long *d_blk_woff,
                                void *d_w, bool f64, hipStream_t s);
 
@@ -198,12 +246,20 @@ hipError_t launch_expand_plain(int N, const double *dT, int qstride, double scal
 // (2, 1, 3) and (3, 1, 2), and fhat with its k_d = 0 planes zeroed, after the
 // first copy, G * N^3 * 64 elements apart.  Groups g with skip[g] != 0 (skip
 // may be NULL) are left untouched by both directions.
+// With core.cf non-NULL the last forward pass also writes the FP64 core rows (CoreSched) of every
+// group to cf[g][disk row][t][lane], t = m3 - (N/2 - r).
+struct CoreFill {
+    double2 *cf;
+    const int *disk_idx;   // device, N*N
+    int nD, r, r2;
+};
 hipError_t launch_dft_forward_grouped(int N, double L, int ncells, const double *f, const long long *d_f_off,
                                       double2 *S, double2 *T, void *fh, bool out_f32, int copies,
-                                      const unsigned char *skip, hipStream_t s);
+                                      const CoreFill &core, const unsigned char *skip, hipStream_t s);
 hipError_t launch_dft_inverse_grouped(int N, double L, int ncells, const double2 *qh, int nparts, long long pstride,
-                                      const HermAssembly &herm, double2 *S, double2 *T, double *qt,
-                                      const long long *d_q_off, const unsigned char *skip, hipStream_t s);
+                                      const HermAssembly &herm, const CoreAdd &core, double2 *S, double2 *T,
+                                      double *qt, const long long *d_q_off, const unsigned char *skip,
+                                      hipStream_t s);
 hipError_t launch_dft_forward(int N, double L, int ncells, const double *f, const long long *d_f_off,
                               double2 *scratch, void *out, bool out_f32, const long long *d_o_base,
                               long long o_stride, hipStream_t s);
@@ -253,6 +309,21 @@ hipError_t launch_build_e3(int N, const long long *d_row_woff, const long long *
 int conv_variant_count();
 int conv_variant_accuracy_rank(int v);
 hipError_t launch_conv_cells(const CellsLaunch &p, bool f64, hipStream_t s);
+
+// FP64 core sum of one mesh (CoreSched): items (group, output row | half << 16, first step, end step),
+// longest first; half 0 owns the outputs k3 - N/2 in [-2r, 0], half 1 those in [1, 2r].
+struct CoreLaunch {
+    int N, r, nD;
+    const double2 *cf;           // [G][nD][2r+1][64] FP64 core rows
+    const int4 *items;
+    int n_items;
+    unsigned *counter;           // device, zeroed by the launcher's fill kernel
+    const int *steps;            // device, CoreSched::steps
+    const double *w;             // core weight stream, core_wstride(r) doubles per step
+    double2 *out;                // [G][N^3][64]
+    const unsigned char *skip;   // device, per group (may be NULL)
+};
+hipError_t launch_conv_core(const CoreLaunch &p, hipStream_t s);
 
 // Plain convolution of one cell.
 struct PlainLaunch {

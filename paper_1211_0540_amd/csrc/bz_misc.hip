@@ -148,7 +148,8 @@ __device__ inline int sq3(int a, int b, int c) { return a * a + b * b + c * c; }
 
 template <typename W>
 __global__ void __launch_bounds__(256) k_expand_cells(int N, const double *__restrict__ T, int qs, double scale,
-                                                      const long long *__restrict__ row_woff, W *__restrict__ w) {
+                                                      const long long *__restrict__ row_woff, W *__restrict__ w,
+                                                      int core_r2) {
     const int h = N / 2;
     const int r = blockIdx.x;
     const int k1 = r / N, k2 = r % N;
@@ -181,6 +182,8 @@ __global__ void __launch_bounds__(256) k_expand_cells(int N, const double *__res
                     v = 0.0;
                 else
                     v = 2.0 * T[(size_t)na * qs + nb] - T[4 * ncm] - T[4 * ncj];
+                // both partners in the low-frequency core: summed in FP64 by the core kernel
+                if (core_r2 >= 0 && ncm <= core_r2 && ncj <= core_r2) v = 0.0;
                 out[step * PS + t] = (W)(scale * v);
             }
         }
@@ -298,13 +301,13 @@ hipError_t launch_build_e3(int N, const long long *d_row_woff, const long long *
 }
 
 hipError_t launch_expand_cells(int N, const double *dT, int qstride, double scale, const long long *d_row_woff,
-                               void *d_w, bool f64, hipStream_t s) {
+                               void *d_w, bool f64, int core_r2, hipStream_t s) {
     if (f64)
         hipLaunchKernelGGL(k_expand_cells<double>, dim3(N * N), dim3(256), 0, s, N, dT, qstride, scale, d_row_woff,
-                           (double *)d_w);
+                           (double *)d_w, core_r2);
     else
         hipLaunchKernelGGL(k_expand_cells<float>, dim3(N * N), dim3(256), 0, s, N, dT, qstride, scale, d_row_woff,
-                           (float *)d_w);
+                           (float *)d_w, core_r2);
     return hipGetLastError();
 }
 

@@ -176,6 +176,39 @@ static void build_schedules(bz_grid_s *g) {
     s.plain_weights = off;
 }
 
+// Low-frequency core (CoreSched): the disk rows, and for every output row its
+// core steps, pairs of disk rows (m1, m2) <= (j1, j2) with j = k + N/2 - m.
+static void build_core(bz_grid_s *g, int r2) {
+    bz::CoreSched &c = g->sched.core;
+    c = bz::CoreSched();
+    if (r2 < 1) return;
+    const int N = g->N, h = N / 2;
+    c.r2 = r2;
+    while ((c.r + 1) * (c.r + 1) <= r2) ++c.r;
+    c.disk_idx.assign(N * N, -1);
+    for (int a = 0; a < N; ++a)
+        for (int b = 0; b < N; ++b)
+            if ((a - h) * (a - h) + (b - h) * (b - h) <= r2) c.disk_idx[a * N + b] = c.nD++;
+    c.row_steps.assign(N * N, 0);
+    c.row_soff.assign(N * N, 0);
+    for (int k1 = 0; k1 < N; ++k1)
+        for (int k2 = 0; k2 < N; ++k2) {
+            const int row = k1 * N + k2;
+            c.row_soff[row] = (long long)c.steps.size();
+            for (int m1 = 0; m1 < N; ++m1)
+                for (int m2 = 0; m2 < N; ++m2) {
+                    const int dm = c.disk_idx[m1 * N + m2];
+                    const int j1 = k1 + h - m1, j2 = k2 + h - m2;
+                    if (dm < 0 || j1 < 0 || j1 >= N || j2 < 0 || j2 >= N) continue;
+                    const int dj = c.disk_idx[j1 * N + j2];
+                    if (dj < 0 || m1 > j1 || (m1 == j1 && m2 > j2)) continue;
+                    c.steps.push_back(dm | (dj << 16));
+                }
+            c.row_steps[row] = (int)((long long)c.steps.size() - c.row_soff[row]);
+        }
+    c.nsteps = (long long)c.steps.size();
+}
+
 static size_t kind_elem(int kind) {
     return (kind == BZ_W_BATCHED_F64 || kind == BZ_W_PLAIN_F64) ? 8 : 4;
 }
@@ -183,6 +216,50 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // byte offset of the pass-E3 stream in a batched weight buffer (after the main stream and its pad)
 static size_t e3_base_bytes(const bz_grid_s *g, size_t elem) {
     return align256((size_t)g->sched.cells_weights * elem + kWeightPadBytes);
+}
+// byte offset of the FP64 core stream in a batched FP32 weight buffer (after the E3 stream and its pad)
+static size_t core_base_bytes(const bz_grid_s *g) {
+    return align256(e3_base_bytes(g, 4) + (size_t)g->sched.e3_weights * 4 + kWeightPadBytes);
+}
+static size_t core_stream_bytes(const bz_grid_s *g) {
+    const CoreSched &c = g->sched.core;
+    return c.r2 < 1 ? 0 : (size_t)c.nsteps * core_wstride(c.r) * sizeof(double);
+}
+
+// Weights of the core steps in stream order (CoreSched), FP64, dzeta^3 folded in.
+static void core_weights(const bz_grid_s *g, const std::vector<double> &T, int qs, double scale,
+                         std::vector<double> &out) {
+    const CoreSched &c = g->sched.core;
+    const int N = g->N, h = N / 2, r = c.r, S = 2 * r + 1, WS = core_wstride(r);
+    out.assign((size_t)c.nsteps * WS, 0.0);
+    std::vector<int> da(c.nD), db(c.nD);
+    for (int a = 0; a < N; ++a)
+        for (int b = 0; b < N; ++b)
+            if (c.disk_idx[a * N + b] >= 0) {
+                da[c.disk_idx[a * N + b]] = a;
+                db[c.disk_idx[a * N + b]] = b;
+            }
+    auto sq = [](int x, int y, int z) { return x * x + y * y + z * z; };
+    for (int k1 = 0; k1 < N; ++k1)
+        for (int k2 = 0; k2 < N; ++k2) {
+            const int row = k1 * N + k2;
+            for (long long st = c.row_soff[row]; st < c.row_soff[row] + c.row_steps[row]; ++st) {
+                const int dm = c.steps[st] & 0xffff, dj = c.steps[st] >> 16;
+                const int m1 = da[dm], m2 = db[dm], j1 = da[dj], j2 = db[dj];
+                const bool diag = dm == dj;
+                for (int tm = 0; tm < S; ++tm)
+                    for (int tj = 0; tj < S; ++tj) {
+                        const int m3 = h - r + tm, j3 = h - r + tj, k3 = m3 + j3 - h;
+                        if (k3 < 0 || k3 >= N || (diag && tm > tj)) continue;
+                        const int ncm = sq(m1 - h, m2 - h, m3 - h), ncj = sq(j1 - h, j2 - h, j3 - h);
+                        if (ncm > c.r2 || ncj > c.r2) continue;
+                        const int na = sq(k1 - h, k2 - h, k3 - h), nb = sq(m1 - j1, m2 - j2, m3 - j3);
+                        const double v = (diag && tm == tj) ? T[(size_t)na * qs] - T[4 * ncm]
+                                                            : 2.0 * T[(size_t)na * qs + nb] - T[4 * ncm] - T[4 * ncj];
+                        out[(size_t)st * WS + tm * S + tj] = scale * v;
+                    }
+            }
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -208,8 +285,15 @@ struct Part {
     int parts = 1;                   // partial-sum buffers of pass A (and of pass Z) of the batched schedule
     int variant = 0;                 // convolution kernel variant
     std::vector<long long> f_off;    // host copy
+    // FP64 low-frequency core (batched FP32 mode with a core on the mesh)
+    bool core = false;
+    int4 *d_core_items = nullptr;
+    int n_core_items = 0;
+    int *d_core_steps = nullptr;
+    int *d_disk_idx = nullptr;
     // workspace offsets (bytes)
     size_t ws_fh = 0, ws_qh = 0, ws_counter = 0;
+    size_t ws_cf = 0, ws_cq = 0, ws_ccounter = 0;
 };
 
 }  // namespace bz
@@ -227,7 +311,9 @@ struct bz_batch_s {
     int plain_split = 4;
     // convolution timing
     bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
+    double core_ms = 0.0;            // FP64 core launches timed at the last bz_batch_timer_read
+    int core_launches = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free, ev_core_used;
     int closure_phase = 0;
     // closure: the network runs on a second stream of default priority, forked from and joined to
     // the caller's stream by events (created on the first closure call)
@@ -258,7 +344,7 @@ static int plain_split_for(int N) {
     return s;
 }
 
-static bool timer_pair(bz_batch_s *b, std::pair<hipEvent_t, hipEvent_t> &ev) {
+static bool timer_pair(bz_batch_s *b, std::pair<hipEvent_t, hipEvent_t> &ev, bool core = false) {
     if (b->ev_free.empty()) {
         hipEvent_t a, c;
         if (hipEventCreate(&a) != hipSuccess) return false;
@@ -270,7 +356,7 @@ static bool timer_pair(bz_batch_s *b, std::pair<hipEvent_t, hipEvent_t> &ev) {
     }
     ev = b->ev_free.back();
     b->ev_free.pop_back();
-    b->ev_used.push_back(ev);
+    (core ? b->ev_core_used : b->ev_used).push_back(ev);
     return true;
 }
 
@@ -302,6 +388,10 @@ const char *bz_status_string(bz_status s) {
 const char *bz_last_error(void) { return g_err.c_str(); }
 
 bz_status bz_grid_init(int N, double L, double lambda, bz_grid *out) {
+    return bz_grid_init_ex(N, L, lambda, BZ_CORE_DEFAULT, out);
+}
+
+bz_status bz_grid_init_ex(int N, double L, double lambda, int core_r2, bz_grid *out) {
     if (!out) return fail(BZ_EINVAL, "bz_grid_init: out is NULL");
     *out = nullptr;
     if (N < kMinN || N > kMaxN || (N % 4) != 0)
@@ -323,6 +413,16 @@ bz_status bz_grid_init(int N, double L, double lambda, bz_grid *out) {
         return fail(BZ_EINVAL, "bz_grid_init: constraint Gram matrix not positive definite");
     }
     build_schedules(g);
+    // core ball: the default is |zeta| < pi, i.e. nc < L^2 in index units, kept inside the
+    // interior of the mesh (r <= N/2 - 1) and within the kernel's largest half-width
+    const int h = N / 2, cmax = std::min(h * h - 1, (kCoreMaxR + 1) * (kCoreMaxR + 1) - 1);
+    int r2 = core_r2;
+    if (core_r2 == BZ_CORE_DEFAULT) r2 = std::min(cmax, (int)std::ceil(L * L) - 1);
+    else if (core_r2 != BZ_CORE_OFF && (core_r2 < 1 || core_r2 > cmax)) {
+        delete g;
+        return fail(BZ_EINVAL, "bz_grid_init: core_r2 must be in [1, min(N^2/4, 81) - 1], BZ_CORE_DEFAULT or BZ_CORE_OFF");
+    }
+    build_core(g, core_r2 == BZ_CORE_OFF ? 0 : r2);
     *out = g;
     return BZ_OK;
 }
@@ -337,6 +437,8 @@ bz_status bz_grid_query(bz_grid g, bz_grid_info *info) {
     info->dv = g->dv;
     info->dzeta = g->dzeta;
     info->pairs = g->pairs;
+    info->core_r2 = g->sched.core.r2 < 1 ? 0 : g->sched.core.r2;
+    info->core_steps = g->sched.core.nsteps;
     return BZ_OK;
 }
 
@@ -353,6 +455,8 @@ size_t bz_weights_bytes(bz_grid g, int kind) {
     if (!g) return 0;
     switch (kind) {
     case BZ_W_BATCHED_F32:
+        if (core_stream_bytes(g)) return core_base_bytes(g) + core_stream_bytes(g) + kWeightPadBytes;
+        return e3_base_bytes(g, 4) + (size_t)g->sched.e3_weights * 4 + kWeightPadBytes;
     case BZ_W_BATCHED_F64:
         return e3_base_bytes(g, kind_elem(kind)) + (size_t)g->sched.e3_weights * kind_elem(kind) + kWeightPadBytes;
     case BZ_W_PLAIN_F32:
@@ -387,9 +491,17 @@ bz_status bz_weights(bz_grid g, int kind, void *d_w, size_t bytes, void *stream)
         e = hipMemcpyAsync(dOff + off.size(), g->sched.e3_woff.data(), g->sched.e3_woff.size() * sizeof(long long),
                            hipMemcpyHostToDevice, s);
     const bool f64 = kind_elem(kind) == 8;
+    // the FP32 stream leaves the pairs of the low-frequency core to the FP64 core stream
+    const bool core = kind == BZ_W_BATCHED_F32 && core_stream_bytes(g) > 0;
     if (e == hipSuccess)
-        e = cells ? launch_expand_cells(g->N, dT, qs, weight_scale(g), dOff, d_w, f64, s)
+        e = cells ? launch_expand_cells(g->N, dT, qs, weight_scale(g), dOff, d_w, f64, core ? g->sched.core.r2 : -1, s)
                   : launch_expand_plain(g->N, dT, qs, weight_scale(g), dOff, d_w, f64, s);
+    std::vector<double> cw;
+    if (e == hipSuccess && core) {
+        core_weights(g, T, qs, weight_scale(g), cw);
+        e = hipMemcpyAsync((char *)d_w + core_base_bytes(g), cw.data(), cw.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s);
+    }
     // the pass-E3 stream is derived from the main stream
     if (e == hipSuccess && cells)
         e = launch_build_e3(g->N, dOff, dOff + off.size(), d_w, (char *)d_w + e3_base_bytes(g, kind_elem(kind)), f64,
@@ -462,7 +574,7 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
         std::memcpy(host.data() + o, src, bytes);
         return o;
     };
-    struct Offs { size_t f_off, fh_base, row, blk, zero, items, e3; };
+    struct Offs { size_t f_off, fh_base, row, blk, zero, items, e3, core_items, core_steps, disk; };
     std::vector<Offs> offs;
     size_t ws = 0, scratch = 0;
     for (Part &p : b->parts) {
@@ -532,6 +644,25 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
             p.n_items = (int)items.size();
             o.items = put(items.data(), items.size() * sizeof(int4));
             o.e3 = put(p.g->sched.e3_woff.data(), p.g->sched.e3_woff.size() * sizeof(long long));
+            const CoreSched &cs = p.g->sched.core;
+            p.core = mode == BZ_MODE_BATCHED_F32 && cs.r2 >= 1;
+            if (p.core) {
+                // one item per (group, output row within 2r of the centre, half of the row's outputs),
+                // every such row written (rows without core steps write zeros), longest first
+                std::vector<int4> ci;
+                for (int gq = 0; gq < p.groups; ++gq)
+                    for (int k1 = std::max(0, h - 2 * cs.r); k1 <= std::min(N - 1, h + 2 * cs.r); ++k1)
+                        for (int k2 = std::max(0, h - 2 * cs.r); k2 <= std::min(N - 1, h + 2 * cs.r); ++k2) {
+                            const int row = k1 * N + k2;
+                            const int a = (int)cs.row_soff[row], e = a + cs.row_steps[row];
+                            for (int half = 0; half < 2; ++half) ci.push_back(make_int4(gq, row | (half << 16), a, e));
+                        }
+                std::stable_sort(ci.begin(), ci.end(), [](const int4 &x, const int4 &y) { return x.w - x.z > y.w - y.z; });
+                p.n_core_items = (int)ci.size();
+                o.core_items = put(ci.data(), ci.size() * sizeof(int4));
+                o.core_steps = put(cs.steps.data(), cs.steps.size() * sizeof(int));
+                o.disk = put(cs.disk_idx.data(), cs.disk_idx.size() * sizeof(int));
+            }
         }
         offs.push_back(o);
         // workspace: fhat, qhat, counter
@@ -554,6 +685,16 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
         }
         p.ws_counter = ws;
         ws = align256(ws + 256);
+        if (p.core) {
+            // FP64 core rows [G][nD][2r+1][64] and the core sum [G][N^3][64]
+            const CoreSched &cs = p.g->sched.core;
+            p.ws_cf = ws;
+            ws = align256(ws + (size_t)p.groups * cs.nD * (2 * cs.r + 1) * kWave * 16);
+            p.ws_cq = ws;
+            ws = align256(ws + (size_t)p.groups * M * kWave * 16);
+            p.ws_ccounter = ws;
+            ws = align256(ws + 256);
+        }
         const size_t sc = (bat ? (size_t)p.groups * kWave : 1) * (size_t)M * 16;
         scratch = std::max(scratch, sc);
     }
@@ -581,6 +722,11 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
         p.d_blk_woff = (long long *)(base + offs[i].blk);
         p.d_items = bat ? (int4 *)(base + offs[i].items) : nullptr;
         p.d_e3_woff = bat ? (long long *)(base + offs[i].e3) : nullptr;
+        if (p.core) {
+            p.d_core_items = (int4 *)(base + offs[i].core_items);
+            p.d_core_steps = (int *)(base + offs[i].core_steps);
+            p.d_disk_idx = (int *)(base + offs[i].disk);
+        }
     }
     *out = b.release();
     return BZ_OK;
@@ -590,6 +736,10 @@ void bz_batch_free(bz_batch b) {
     if (!b) return;
     if (b->d_tables) (void)hipFree(b->d_tables);
     for (auto &e : b->ev_used) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    for (auto &e : b->ev_core_used) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
@@ -655,6 +805,24 @@ bz_status bz_batch_timer_read(bz_batch b, double *conv_ms, int *launches) {
     if (launches) *launches = (int)b->ev_used.size();
     b->ev_free.insert(b->ev_free.end(), b->ev_used.begin(), b->ev_used.end());
     b->ev_used.clear();
+    double ctot = 0.0;
+    for (auto &e : b->ev_core_used) {
+        BZ_HIP(hipEventSynchronize(e.second), "bz_batch_timer_read: sync");
+        float ms = 0.f;
+        BZ_HIP(hipEventElapsedTime(&ms, e.first, e.second), "bz_batch_timer_read: elapsed");
+        ctot += ms;
+    }
+    b->core_ms = ctot;
+    b->core_launches = (int)b->ev_core_used.size();
+    b->ev_free.insert(b->ev_free.end(), b->ev_core_used.begin(), b->ev_core_used.end());
+    b->ev_core_used.clear();
+    return BZ_OK;
+}
+
+bz_status bz_batch_core_timer(bz_batch b, double *core_ms, int *launches) {
+    if (!b) return fail(BZ_EINVAL, "bz_batch_core_timer: NULL batch");
+    if (core_ms) *core_ms = b->core_ms;
+    if (launches) *launches = b->core_launches;
     return BZ_OK;
 }
 
@@ -690,6 +858,8 @@ bz_status bz_batch_autotune(bz_batch b, const double *d_f, double *d_Qt, void *d
         }
         b->ev_free.insert(b->ev_free.end(), b->ev_used.begin(), b->ev_used.end());
         b->ev_used.clear();
+        b->ev_free.insert(b->ev_free.end(), b->ev_core_used.begin(), b->ev_core_used.end());
+        b->ev_core_used.clear();
     }
     b->timing = was;
     if (st != BZ_OK) {
@@ -761,8 +931,10 @@ static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void 
             const int nc = (int)p.cells.size();
             const long long *f_off = slot_off ? slot_off : p.d_f_off;
             // the first partial buffer of qh serves as the second scratch buffer of the transforms
-            BZ_HIP(launch_dft_forward_grouped(N, p.g->L, nc, d_f, f_off, scratch, qh, fh, !f64, p.herm ? 4 : 1, skip,
-                                              s),
+            const CoreSched &cs = p.g->sched.core;
+            const CoreFill cfill{p.core ? (double2 *)(ws + p.ws_cf) : nullptr, p.d_disk_idx, cs.nD, cs.r, cs.r2};
+            BZ_HIP(launch_dft_forward_grouped(N, p.g->L, nc, d_f, f_off, scratch, qh, fh, !f64, p.herm ? 4 : 1, cfill,
+                                              skip, s),
                    "forward transform");
             const long long pstride = (long long)p.groups * M * kWave;  // one copy of fhat, one output buffer
             CellsLaunch cl{N, fh, p.d_items, p.n_items, (unsigned *)(ws + p.ws_counter), qh, 0, skip, {}};
@@ -783,11 +955,26 @@ static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void 
             cl.variant = p.variant;
             BZ_HIP(launch_conv_cells(cl, f64, s), "batched convolution");
             if (b->timing) BZ_HIP(hipEventRecord(ev.second, s), "timer stop");
+            CoreAdd cadd{nullptr, cs.r};
+            if (p.core) {
+                const CoreLaunch co{N, cs.r, cs.nD, (const double2 *)(ws + p.ws_cf), p.d_core_items, p.n_core_items,
+                                    (unsigned *)(ws + p.ws_ccounter), p.d_core_steps,
+                                    (const double *)((const char *)p.w + core_base_bytes(p.g)),
+                                    (double2 *)(ws + p.ws_cq), skip};
+                std::pair<hipEvent_t, hipEvent_t> ce{};
+                if (b->timing) {
+                    if (!timer_pair(b, ce, true)) return fail(BZ_EDEVICE, "bz_collide_batch: hipEventCreate failed");
+                    BZ_HIP(hipEventRecord(ce.first, s), "core timer start");
+                }
+                BZ_HIP(launch_conv_core(co, s), "FP64 core convolution");
+                if (b->timing) BZ_HIP(hipEventRecord(ce.second, s), "core timer stop");
+                cadd.core = (const double2 *)(ws + p.ws_cq);
+            }
             const HermAssembly herm{p.herm, p.parts};
             // groups whose cells are all served by the closure (skip) need no transforms: the
             // closure writes their outputs
-            BZ_HIP(launch_dft_inverse_grouped(N, p.g->L, nc, qh, p.parts, pstride, herm, scratch, qh, d_Qt, f_off,
-                                              skip, s),
+            BZ_HIP(launch_dft_inverse_grouped(N, p.g->L, nc, qh, p.parts, pstride, herm, cadd, scratch, qh, d_Qt,
+                                              f_off, skip, s),
                    "inverse transform");
         } else {
             const int sp = plain_split_for(N);

@@ -24,7 +24,7 @@ def test_library_exports_every_declared_symbol():
     assert len(names) >= 20
     for n in names:
         assert hasattr(L, n), n
-    assert bz.bz_api_version() == 1
+    assert bz.bz_api_version() == 2
 
 
 def test_grid_validation_errors():
@@ -72,8 +72,9 @@ def test_batched_schedule_visits_each_unordered_pair_once(N):
     # the m1 = 0 block (one step per m2 of the band) of every row (k1 < N/2, k2)
     e3_steps = h * sum(_axis_range(N, k)[1] - _axis_range(N, k)[0] + 1 for k in range(N))
     up = lambda x: (x + 255) // 256 * 256
-    g = bz.bz_grid_init(N, 6.0, 1.0)
+    g = bz.bz_grid_init_ex(N, 6.0, 1.0, bz.BZ_CORE_OFF)
     try:
+        assert bz.bz_grid_query(g)["core_r2"] == 0 and bz.bz_grid_query(g)["core_steps"] == 0
         for kind, el in ((bz.BZ_W_BATCHED_F32, 4), (bz.BZ_W_BATCHED_F64, 8)):
             main = up(steps * (3 * N * N // 4) * el + 16384)
             assert bz.bz_weights_bytes(g, kind) == main + e3_steps * (3 * N * N // 4) * el + 16384
@@ -139,3 +140,55 @@ def test_mlp_shape_validation():
     n = bz.bz_mlp_create(13824, 1024, 13824)
     assert bz.bz_mlp_param_count(n) == 13824 * 1024 + 1024 + 1024 * 1024 + 1024 + 13824 * 1024 + 13824
     bz.bz_mlp_free(n)
+
+
+def _core_steps(N, r2):
+    """Core steps of the whole mesh: pairs of disk rows (m1, m2) <= (j1, j2) with
+    j = k + N/2 - m on the mesh, for every output row (k1, k2)."""
+    h = N // 2
+    disk = [(a, b) for a in range(N) for b in range(N) if (a - h) ** 2 + (b - h) ** 2 <= r2]
+    ds = set(disk)
+    n = 0
+    for k1 in range(N):
+        for k2 in range(N):
+            for (m1, m2) in disk:
+                j = (k1 + h - m1, k2 + h - m2)
+                if j in ds and (m1, m2) <= j:
+                    n += 1
+    return n
+
+
+@pytest.mark.parametrize("N,L,r2", [(8, 4.0, 15), (16, 6.0, 35), (24, 7.0, 48), (32, 8.0, 63)])
+def test_default_core_and_its_weight_stream(N, L, r2):
+    """The default core is the ball nc < L^2 (|zeta| < pi), capped inside the mesh
+    interior; the FP32 buffer ends with its FP64 stream, one padded block of
+    (2r+1)^2 weights per core step."""
+    g = bz.bz_grid_init(N, L, 1.0)
+    g0 = bz.bz_grid_init_ex(N, L, 1.0, bz.BZ_CORE_OFF)
+    try:
+        q = bz.bz_grid_query(g)
+        assert q["core_r2"] == r2
+        assert q["core_steps"] == _core_steps(N, r2)
+        r = int(np.floor(np.sqrt(r2)))
+        ws = ((2 * r + 1) ** 2 + 127) // 128 * 128
+        up = lambda x: (x + 255) // 256 * 256
+        base = up(bz.bz_weights_bytes(g0, bz.BZ_W_BATCHED_F32))
+        assert bz.bz_weights_bytes(g, bz.BZ_W_BATCHED_F32) == base + q["core_steps"] * ws * 8 + 16384
+        # the FP64 and plain kinds carry no core
+        assert bz.bz_weights_bytes(g, bz.BZ_W_BATCHED_F64) == bz.bz_weights_bytes(g0, bz.BZ_W_BATCHED_F64)
+        assert bz.bz_weights_bytes(g, bz.BZ_W_PLAIN_F32) == bz.bz_weights_bytes(g0, bz.BZ_W_PLAIN_F32)
+    finally:
+        bz.bz_grid_free(g)
+        bz.bz_grid_free(g0)
+
+
+def test_core_radius_validation():
+    for N, r2 in [(16, 0), (16, 64), (32, 81), (8, 16), (16, -3)]:
+        with pytest.raises(bz.BzError) as e:
+            bz.bz_grid_init_ex(N, 6.0, 1.0, r2)
+        assert e.value.status == bz.BZ_EINVAL
+    g = bz.bz_grid_init_ex(32, 8.0, 1.0, 80)
+    try:
+        assert bz.bz_grid_query(g)["core_r2"] == 80
+    finally:
+        bz.bz_grid_free(g)

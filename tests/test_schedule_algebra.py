@@ -12,7 +12,10 @@ import numpy as np
 import pytest
 
 
-def _model(N, seed=0):
+def _model(N, seed=0, core_r2=-1):
+    """With core_r2 >= 0 the pairs whose two partners lie in the ball |m - N/2|^2 <= core_r2
+    get weight 0 in every pass and are summed separately over every output (the
+    FP64 core of the batched FP32 mode), then added after the assembly."""
     h = N // 2
     rng = np.random.default_rng(seed)
     lo = lambda k: max(0, k - h + 1)
@@ -35,9 +38,11 @@ def _model(N, seed=0):
     def w_ordered(k, m):
         return Tg[sq([a - h for a in k]), sq([2 * b - a - h for a, b in zip(k, m)])] - Tl[sq([b - h for b in m])]
 
-    def w_pair(k, m, j):
+    def w_pair(k, m, j, core=False):
         na, nb = sq([a - h for a in k]), sq([a - b for a, b in zip(m, j)])
         ncm, ncj = sq([a - h for a in m]), sq([a - h for a in j])
+        if (ncm <= core_r2 and ncj <= core_r2) != core:
+            return 0.0
         if (m[0], m[1]) == (j[0], j[1]):
             if m[2] == j[2]:
                 return Tg[na, 0] - Tl[ncm]
@@ -85,6 +90,23 @@ def _model(N, seed=0):
         return ((E1[x1, x2, x3] if x1 < h else 0) + (E2[x2, x1, x3] if x2 < h else 0)
                 + (E3[x3, x1, x2] if x3 < h else 0))
 
+    # core: every output, unordered pairs of core rows (m1, m2) <= (j1, j2), m3 <= j3 on the diagonal
+    C = np.zeros((N, N, N), complex)
+    if core_r2 >= 0:
+        r = int(np.floor(np.sqrt(core_r2)))
+        disk = [(a, b) for a in range(N) for b in range(N) if (a - h) ** 2 + (b - h) ** 2 <= core_r2]
+        for k1 in range(N):
+            for k2 in range(N):
+                for (m1, m2) in disk:
+                    j1, j2 = k1 + h - m1, k2 + h - m2
+                    if (j1, j2) not in disk or (m1, m2) > (j1, j2):
+                        continue
+                    for m3 in range(h - r, h + r + 1):
+                        for j3 in range(h - r, h + r + 1):
+                            k3 = m3 + j3 - h
+                            if 0 <= k3 < N:
+                                w = w_pair((k1, k2, k3), (m1, m2, m3), (j1, j2, j3), core=True)
+                                C[k1, k2, k3] += w * fh[m1, m2, m3] * fh[j1, j2, j3]
     got = np.zeros((N, N, N), complex)
     want = np.zeros((N, N, N), complex)
     for k1 in range(N):
@@ -96,6 +118,7 @@ def _model(N, seed=0):
                     got[k1, k2, k3] = Z[0, k1, k2]
                 else:
                     got[k1, k2, k3] = np.conj(A[N - k1, N - k2, N - k3]) + edge(k1, k2, k3)
+                got[k1, k2, k3] += C[k1, k2, k3]
                 k = (k1, k2, k3)
                 for m1 in range(lo(k1), hi(k1) + 1):
                     for m2 in range(lo(k2), hi(k2) + 1):
@@ -108,6 +131,16 @@ def _model(N, seed=0):
 @pytest.mark.parametrize("N", [8])
 def test_conjugate_symmetric_schedule_reproduces_the_direct_sum(N):
     got, want = _model(N)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("core_r2", [0, 2, 5, 9])
+def test_core_split_reproduces_the_direct_sum(core_r2):
+    """The FP32 passes without the core-core pairs plus the core sum over every output
+    equal the direct sum, for balls up to the largest that stays off the k_d = 0 planes
+    (r2 = 9 at N = 8: the core outputs then reach k_d = 0, and the mirrored rows lose
+    their core part to the conjugation, which the separate core sum restores)."""
+    got, want = _model(8, seed=2, core_r2=core_r2)
     assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
 
 
