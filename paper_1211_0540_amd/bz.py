@@ -129,6 +129,7 @@ def lib():
         "bz_batch_timer": (ctypes.c_int, [_vp, ctypes.c_int]),
         "bz_batch_timer_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
         "bz_batch_core_timer": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
+        "bz_batch_set_core_waves": (ctypes.c_int, [_vp, ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -467,6 +468,10 @@ def bz_batch_timer_read(b: int):
     n = ctypes.c_int()
     _check(lib().bz_batch_timer_read(_vp(b), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def bz_batch_set_core_waves(b: int, waves: int) -> None:
+    _check(lib().bz_batch_set_core_waves(_vp(b), int(waves)))
 
 
 def bz_batch_core_timer(b: int):

@@ -600,7 +600,12 @@ hipError_t launch_conv_core(const CoreLaunch &p, hipStream_t s) {
     if (p.r < 1 || p.r > kCoreMaxR) return hipErrorInvalidValue;
     hipError_t e = launch_fill_u32(p.counter, 1, 0u, s);
     if (e != hipSuccess) return e;
-    const unsigned grid = persistent_grid(p.n_items);
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    const int want = p.waves > 0 ? p.waves : 8 * cus;
+    const unsigned grid = (unsigned)(p.n_items < want ? p.n_items : want);
     switch (p.r) {
     case 1: return core_launch<1>(p, grid, s);
     case 2: return core_launch<2>(p, grid, s);

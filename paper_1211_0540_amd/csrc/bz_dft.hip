@@ -406,6 +406,8 @@ __global__ void __launch_bounds__(256) k_dftg_fwd3(const double2 *__restrict__ T
 // Three wavefronts per SIMD: at N=32 that costs some register spills, but the 3 x 1024 lines of a
 // 190-cell batch then run in one round (139 instead of 157 us measured).
 // The FP64 core sum (CoreAdd; core NULL when off) is added to every output within 2cr of the centre.
+// The core holds it for the direct rows and for k3 = 0 of the derived rows; elsewhere a derived
+// output is the conjugate of its mirror N - k (the core pairs are interior, and the weights even).
 template <int N>
 __device__ __forceinline__ void add_core(double2 (&x)[N], const double2 *__restrict__ core, int cr, size_t gl, int k2,
                                          int k3) {
@@ -414,7 +416,13 @@ __device__ __forceinline__ void add_core(double2 (&x)[N], const double2 *__restr
 #pragma unroll
     for (int k1 = 0; k1 < N; ++k1) {
         if (abs(k1 - h) > 2 * cr) continue;
-        const double2 c = core[gl + ((size_t)(k1 * N + k2) * N + k3) * kWave];
+        double2 c;
+        if (herm_derived_row(N, k1, k2) && k3 >= 1) {
+            c = core[gl + ((size_t)((N - k1) * N + (N - k2)) * N + (N - k3)) * kWave];
+            c.y = -c.y;
+        } else {
+            c = core[gl + ((size_t)(k1 * N + k2) * N + k3) * kWave];
+        }
         x[k1].x += c.x;
         x[k1].y += c.y;
     }

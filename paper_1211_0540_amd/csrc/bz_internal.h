@@ -123,7 +123,8 @@ struct HermAssembly {
 
 // FP64 sum of the low-frequency core, added to every output by the first
 // inverse-transform pass: core[g][k][lane] (one full output buffer) holds it
-// for the outputs k with every |k_d - N/2| <= 2r; NULL when the core is off.
+// for the outputs k with every |k_d - N/2| <= 2r of the direct rows, and of the
+// derived rows at k3 = 0; NULL when the core is off.
 struct CoreAdd {
     const double2 *core;
     int r;
@@ -138,9 +139,11 @@ struct CoreAdd {
 // terms cancel to a small Qhat) exceeds a relative 1e-5.  The pairs whose two
 // partners both lie in the ball |m - N/2|^2 <= r2 (the "core") are therefore
 // summed in FP64 by a separate kernel, and their weights are zero in the FP32
-// stream.  The core sum is taken over every output, so it does not depend on
-// the conjugate-symmetric schedule; it is added after the assembly of the FP32
-// passes.  Same sum, split by frequency, each term evaluated once.
+// stream.  The core sum is added to the outputs after the assembly of the FP32
+// passes.  Same sum, split by frequency, each term evaluated once.  The core
+// pairs are interior pairs, so the core sum of a derived output with k3 >= 1 is
+// the conjugate of that of its mirror N - k: only the direct rows (and k3 = 0
+// of the derived rows, reached when 2r >= N/2) are summed.
 //
 // Rows of the core: the disk (a - h)^2 + (b - h)^2 <= r2, numbered in
 // lexicographic order; a core row holds the S = 2r + 1 values m3 = h - r .. h + r
@@ -322,6 +325,7 @@ struct CoreLaunch {
     const double *w;             // core weight stream, core_wstride(r) doubles per step
     double2 *out;                // [G][N^3][64]
     const unsigned char *skip;   // device, per group (may be NULL)
+    int waves;                   // persistent grid in wavefronts (0: eight per CU)
 };
 hipError_t launch_conv_core(const CoreLaunch &p, hipStream_t s);
 

@@ -319,6 +319,11 @@ struct bz_batch_s {
     // the caller's stream by events (created on the first closure call)
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // FP64 core: its own stream of default priority, forked from and joined to the caller's
+    // stream around the FP32 convolution; persistent grid (wavefronts, 0: the default)
+    hipStream_t core_stream = nullptr;
+    hipEvent_t ev_cfork = nullptr, ev_cjoin = nullptr;
+    int core_waves = 0;
 };
 
 namespace bz {
@@ -648,14 +653,19 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
             p.core = mode == BZ_MODE_BATCHED_F32 && cs.r2 >= 1;
             if (p.core) {
                 // one item per (group, output row within 2r of the centre, half of the row's outputs),
-                // every such row written (rows without core steps write zeros), longest first
+                // every such row written (rows without core steps write zeros), longest first.  The
+                // derived rows of the conjugate-symmetric schedule are conjugates of their mirrors
+                // except at k3 = 0, which the first half reaches when 2r >= N/2.
                 std::vector<int4> ci;
                 for (int gq = 0; gq < p.groups; ++gq)
                     for (int k1 = std::max(0, h - 2 * cs.r); k1 <= std::min(N - 1, h + 2 * cs.r); ++k1)
                         for (int k2 = std::max(0, h - 2 * cs.r); k2 <= std::min(N - 1, h + 2 * cs.r); ++k2) {
                             const int row = k1 * N + k2;
                             const int a = (int)cs.row_soff[row], e = a + cs.row_steps[row];
-                            for (int half = 0; half < 2; ++half) ci.push_back(make_int4(gq, row | (half << 16), a, e));
+                            const bool derived = herm_derived_row(N, k1, k2);
+                            if (derived && 2 * cs.r < h) continue;
+                            for (int half = 0; half < (derived ? 1 : 2); ++half)
+                                ci.push_back(make_int4(gq, row | (half << 16), a, e));
                         }
                 std::stable_sort(ci.begin(), ci.end(), [](const int4 &x, const int4 &y) { return x.w - x.z > y.w - y.z; });
                 p.n_core_items = (int)ci.size();
@@ -712,6 +722,20 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
             return hip_fail(e, "bz_batch_create: upload tables");
         }
     }
+    bool any_core = false;
+    for (const Part &p : b->parts) any_core = any_core || p.core;
+    if (any_core) {
+        if (hipStreamCreateWithFlags(&b->core_stream, hipStreamNonBlocking) != hipSuccess) {
+            b->core_stream = nullptr;
+            if (b->d_tables) (void)hipFree(b->d_tables);
+            return fail(BZ_EDEVICE, "bz_batch_create: hipStreamCreateWithFlags failed");
+        }
+        if (hipEventCreateWithFlags(&b->ev_cfork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&b->ev_cjoin, hipEventDisableTiming) != hipSuccess) {
+            bz_batch_free(b.release());
+            return fail(BZ_EDEVICE, "bz_batch_create: hipEventCreateWithFlags failed");
+        }
+    }
     char *base = (char *)b->d_tables;
     for (size_t i = 0; i < b->parts.size(); ++i) {
         Part &p = b->parts[i];
@@ -750,6 +774,9 @@ void bz_batch_free(bz_batch b) {
     if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     if (b->ev_join) (void)hipEventDestroy(b->ev_join);
     if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->ev_cfork) (void)hipEventDestroy(b->ev_cfork);
+    if (b->ev_cjoin) (void)hipEventDestroy(b->ev_cjoin);
+    if (b->core_stream) (void)hipStreamDestroy(b->core_stream);
     delete b;
 }
 
@@ -816,6 +843,13 @@ bz_status bz_batch_timer_read(bz_batch b, double *conv_ms, int *launches) {
     b->core_launches = (int)b->ev_core_used.size();
     b->ev_free.insert(b->ev_free.end(), b->ev_core_used.begin(), b->ev_core_used.end());
     b->ev_core_used.clear();
+    return BZ_OK;
+}
+
+bz_status bz_batch_set_core_waves(bz_batch b, int waves) {
+    if (!b) return fail(BZ_EINVAL, "bz_batch_set_core_waves: NULL batch");
+    if (waves < 0) return fail(BZ_EINVAL, "bz_batch_set_core_waves: negative count");
+    b->core_waves = waves;
     return BZ_OK;
 }
 
@@ -936,6 +970,25 @@ static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void 
             BZ_HIP(launch_dft_forward_grouped(N, p.g->L, nc, d_f, f_off, scratch, qh, fh, !f64, p.herm ? 4 : 1, cfill,
                                               skip, s),
                    "forward transform");
+            if (p.core) {
+                // the FP64 core runs on its own stream, alongside the FP32 convolution: it is bound by
+                // its row loads, the FP32 kernel by its arithmetic
+                hipStream_t cst = b->core_stream;
+                const CoreLaunch co{N, cs.r, cs.nD, (const double2 *)(ws + p.ws_cf), p.d_core_items, p.n_core_items,
+                                    (unsigned *)(ws + p.ws_ccounter), p.d_core_steps,
+                                    (const double *)((const char *)p.w + core_base_bytes(p.g)),
+                                    (double2 *)(ws + p.ws_cq), skip, b->core_waves};
+                BZ_HIP(hipEventRecord(b->ev_cfork, s), "core fork");
+                BZ_HIP(hipStreamWaitEvent(cst, b->ev_cfork, 0), "core fork");
+                std::pair<hipEvent_t, hipEvent_t> ce{};
+                if (b->timing) {
+                    if (!timer_pair(b, ce, true)) return fail(BZ_EDEVICE, "bz_collide_batch: hipEventCreate failed");
+                    BZ_HIP(hipEventRecord(ce.first, cst), "core timer start");
+                }
+                BZ_HIP(launch_conv_core(co, cst), "FP64 core convolution");
+                if (b->timing) BZ_HIP(hipEventRecord(ce.second, cst), "core timer stop");
+                BZ_HIP(hipEventRecord(b->ev_cjoin, cst), "core join");
+            }
             const long long pstride = (long long)p.groups * M * kWave;  // one copy of fhat, one output buffer
             CellsLaunch cl{N, fh, p.d_items, p.n_items, (unsigned *)(ws + p.ws_counter), qh, 0, skip, {}};
             const void *w_e3 = (const char *)p.w + e3_base_bytes(p.g, f64 ? 8 : 4);
@@ -955,21 +1008,8 @@ static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void 
             cl.variant = p.variant;
             BZ_HIP(launch_conv_cells(cl, f64, s), "batched convolution");
             if (b->timing) BZ_HIP(hipEventRecord(ev.second, s), "timer stop");
-            CoreAdd cadd{nullptr, cs.r};
-            if (p.core) {
-                const CoreLaunch co{N, cs.r, cs.nD, (const double2 *)(ws + p.ws_cf), p.d_core_items, p.n_core_items,
-                                    (unsigned *)(ws + p.ws_ccounter), p.d_core_steps,
-                                    (const double *)((const char *)p.w + core_base_bytes(p.g)),
-                                    (double2 *)(ws + p.ws_cq), skip};
-                std::pair<hipEvent_t, hipEvent_t> ce{};
-                if (b->timing) {
-                    if (!timer_pair(b, ce, true)) return fail(BZ_EDEVICE, "bz_collide_batch: hipEventCreate failed");
-                    BZ_HIP(hipEventRecord(ce.first, s), "core timer start");
-                }
-                BZ_HIP(launch_conv_core(co, s), "FP64 core convolution");
-                if (b->timing) BZ_HIP(hipEventRecord(ce.second, s), "core timer stop");
-                cadd.core = (const double2 *)(ws + p.ws_cq);
-            }
+            CoreAdd cadd{p.core ? (const double2 *)(ws + p.ws_cq) : nullptr, cs.r};
+            if (p.core) BZ_HIP(hipStreamWaitEvent(s, b->ev_cjoin, 0), "core join");
             const HermAssembly herm{p.herm, p.parts};
             // groups whose cells are all served by the closure (skip) need no transforms: the
             // closure writes their outputs

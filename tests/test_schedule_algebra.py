@@ -118,7 +118,12 @@ def _model(N, seed=0, core_r2=-1):
                     got[k1, k2, k3] = Z[0, k1, k2]
                 else:
                     got[k1, k2, k3] = np.conj(A[N - k1, N - k2, N - k3]) + edge(k1, k2, k3)
-                got[k1, k2, k3] += C[k1, k2, k3]
+                # the core is summed for the direct rows (and k3 = 0 of the derived rows);
+                # a derived output with k3 >= 1 takes the conjugate of its mirror's
+                if derived(k1, k2) and k3 >= 1:
+                    got[k1, k2, k3] += np.conj(C[N - k1, N - k2, N - k3])
+                else:
+                    got[k1, k2, k3] += C[k1, k2, k3]
                 k = (k1, k2, k3)
                 for m1 in range(lo(k1), hi(k1) + 1):
                     for m2 in range(lo(k2), hi(k2) + 1):
@@ -136,10 +141,9 @@ def test_conjugate_symmetric_schedule_reproduces_the_direct_sum(N):
 
 @pytest.mark.parametrize("core_r2", [0, 2, 5, 9])
 def test_core_split_reproduces_the_direct_sum(core_r2):
-    """The FP32 passes without the core-core pairs plus the core sum over every output
-    equal the direct sum, for balls up to the largest that stays off the k_d = 0 planes
-    (r2 = 9 at N = 8: the core outputs then reach k_d = 0, and the mirrored rows lose
-    their core part to the conjugation, which the separate core sum restores)."""
+    """The FP32 passes without the core-core pairs, plus the core sum of the direct rows
+    (and of k3 = 0 of the derived rows) with the derived outputs taken as conjugates of their
+    mirrors, equal the direct sum; r2 = 9 at N = 8 (r = 3) makes core outputs reach k_d = 0."""
     got, want = _model(8, seed=2, core_r2=core_r2)
     assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
 
