@@ -108,3 +108,28 @@ def test_training_reduces_loss(dev):
         hist.append(float(loss.item()))
     assert hist[-1] < 0.05 * hist[0]
     bz.bz_mlp_free(n)
+
+
+def test_real_shape_against_the_unmirrored_fp64_oracle(dev):
+    """The network at its real shape against the plain FP64 oracle (no bfloat16 mirroring,
+    whose own pin is finite differences): the loss, the output and every gradient within the
+    bfloat16 storage tolerance 1e-2 (the mirrored and plain oracles differ by about 4e-3)."""
+    n_in, n_h, n_out, B = 13824, 1024, 13824, 64
+    n, params, work, p = setup(n_in, n_h, n_out, B, 4, dev)
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((B, n_in))
+    T = rng.standard_normal((B, n_out))
+    x = torch.from_numpy(to_bf16_bits(X).view(np.int16)).to(dev)
+    t = torch.from_numpy(T.astype(np.float32)).to(dev)
+    y = torch.zeros(B, n_out, dtype=torch.float32, device=dev)
+    bz.bz_mlp_forward(n, params, x, B, y, work)
+    grad = torch.zeros(bz.bz_mlp_param_count(n), dtype=torch.float32, device=dev)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    bz.bz_mlp_backward(n, params, x, t, B, grad, loss, work)
+    L, g, Y = OM.loss_and_grads(p, X, T, bf16=False)
+    assert rel(y.cpu().numpy(), Y) < 1e-2
+    assert float(loss.item()) == pytest.approx(L, rel=1e-3)
+    gg = bz.mlp_unpack(grad.cpu().numpy(), n_in, n_h, n_out)
+    for k in g:
+        assert rel(gg[k], g[k]) < 1e-2, k
+    bz.bz_mlp_free(n)

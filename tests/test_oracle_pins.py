@@ -338,6 +338,62 @@ def test_weak_form_bruteforce_agreement_improves_with_N(lam, tol8, tol12):
 
 
 # ----------------------------------------------------------------------------
+# Cancellation factor kappa (the diagnostic behind the FP32-without-core bound)
+# ----------------------------------------------------------------------------
+def _kappa_bruteforce(f, L, lam):
+    """||sum_m |Ghat| |fhat_m| |fhat_j| || / ||Qhat|| with the library FFT for fhat and the
+    closed-form weights of _I2 (not the oracle's quadrature), vectorised over m."""
+    N = f.shape[0]
+    h = N // 2
+    fh = _numpy_transform(f, L)
+    dz = np.pi / L
+    c = 4 * np.pi / (2 * np.pi) ** 1.5
+    na_max, nb_max = 3 * h * h, 3 * (N - 1) ** 2
+    gain = np.array([[_I2(dz * np.sqrt(a) / 2, dz * np.sqrt(b) / 2, L, lam) for b in range(nb_max + 1)]
+                     for a in range(na_max + 1)])
+    loss = np.array([_I2(dz * np.sqrt(e), 0.0, L, lam) for e in range(na_max + 1)])
+    idx = np.arange(N)
+    q = np.zeros((N, N, N), complex)
+    a = np.zeros((N, N, N))
+    for k in itertools.product(range(N), repeat=3):
+        lo = [max(0, kd - h + 1) for kd in k]
+        hi = [min(N - 1, kd + h) for kd in k]
+        m = np.stack(np.meshgrid(*[idx[lo[d]:hi[d] + 1] for d in range(3)], indexing="ij"), -1).reshape(-1, 3)
+        j = np.array(k) - m + h
+        na = sum((kd - h) ** 2 for kd in k)
+        nb = ((2 * m - np.array(k) - h) ** 2).sum(1)
+        nc = ((m - h) ** 2).sum(1)
+        G = c * (gain[na, nb] - loss[nc])
+        t = G * fh[m[:, 0], m[:, 1], m[:, 2]] * fh[j[:, 0], j[:, 1], j[:, 2]]
+        q[k] = t.sum()
+        a[k] = np.abs(t).sum()
+    return float(np.linalg.norm(a) / np.linalg.norm(q)), q * dz ** 3
+
+
+@pytest.mark.parametrize("lam", [0.0, 1.0])
+def test_kappa_matches_a_bruteforce_evaluation(lam):
+    N, L = 8, 4.0
+    f = _smooth_random(N, L, 21)
+    kb, qb = _kappa_bruteforce(f, L, int(lam))
+    o = O.Oracle(N, L, lam)
+    qh, _ = o.collide_hat(O.dft_forward(f, L))
+    assert np.max(np.abs(qh - qb)) < 1e-12 * np.max(np.abs(qb))
+    assert o.kappa(f) == pytest.approx(kb, rel=1e-10)
+    assert o.kappa(3.0 * f) == pytest.approx(o.kappa(f), rel=1e-12)   # scale-free
+    assert o.kappa(f) >= 1.0
+
+
+def test_kappa_grows_towards_equilibrium():
+    """A Maxwellian's terms cancel far more than a two-beam mixture's (on this coarse mesh the
+    Maxwellian's discretisation residual keeps its kappa near 90; it is ~2400 at N=16)."""
+    N, L = 8, 4.0
+    o = O.Oracle(N, L, 1.0)
+    km = o.kappa(W.maxwellian(N, L, 1.0, (0.2, 0, 0), 0.7))
+    kx = o.kappa(0.5 * W.maxwellian(N, L, 1, (0.8, 0, 0), 0.5) + 0.5 * W.maxwellian(N, L, 1, (-0.8, 0, 0), 0.5))
+    assert km > 5 * kx > 5.0
+
+
+# ----------------------------------------------------------------------------
 # Pin strength: each planted mistake in the oracle is caught by a pin above
 # ----------------------------------------------------------------------------
 def _pins_pass():
