@@ -244,6 +244,17 @@ typedef struct bz_transport_s *bz_transport;
  * length or temperatures, negative density. */
 bz_status bz_transport_create(bz_grid g, int nx, double x_length, double T_wall, double far_rho, double far_u1,
                               double far_T, bz_transport *out);
+/* As bz_transport_create on cells of the given widths (Sec. 3.4: cells of
+ * size dx_j, "not necessarily uniform"): dx (host, nx positive values,
+ * copied) lists cell 0 at the wall first.  The minmod slope of cell j uses
+ * the distances between cell centres, (dx_{j-1} + dx_j)/2 and
+ * (dx_j + dx_{j+1})/2; the cell is reconstructed to its faces with dx_j/2
+ * and updated with the flux difference over dx_j; ghost cells take the width
+ * of the cell they border.  Equal widths give bitwise the uniform scheme.
+ * Errors: as bz_transport_create, and BZ_EINVAL for a NULL, non-positive or
+ * non-finite width. */
+bz_status bz_transport_create_ex(bz_grid g, int nx, const double *dx, double T_wall, double far_rho, double far_u1,
+                                 double far_T, bz_transport *out);
 void bz_transport_free(bz_transport t);
 size_t bz_transport_workspace_bytes(bz_transport t);
 /* Heun RK2 over dt of df/dt + v1 df/dx = 0 for the nx cells of d_f (layout
@@ -256,6 +267,17 @@ bz_status bz_transport_step(bz_transport t, double *d_f, double dt, void *d_work
 size_t bz_strang_workspace_bytes(bz_batch b, bz_transport t);
 bz_status bz_strang_step(bz_batch b, bz_transport t, double *d_f, double dt, double eps, void *d_work,
                          size_t work_bytes, void *stream);
+
+/* Diagnostics of the sudden-heating run (Sec. 5: evolution of the bulk
+ * velocity and of the marginal distribution near the wall), FP64.
+ * bz_cell_moments writes for every cell c of the batch, at d_mom[5 c ..],
+ * the density rho = sum f dv^3, the bulk velocity u_d = sum v_d f dv^3 / rho
+ * (d = 1..3) and the temperature T = sum |v - u|^2 f dv^3 / (3 rho).
+ * bz_marginal_v1 writes the N values sum_{k2,k3} f(k1, k2, k3) dv^2 of cell
+ * `cell` to d_out.  Errors: BZ_EINVAL for NULL pointers or a cell index out
+ * of range. */
+bz_status bz_cell_moments(bz_batch b, const double *d_f, double *d_mom, void *stream);
+bz_status bz_marginal_v1(bz_batch b, const double *d_f, int cell, double *d_out, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* Learned closure: network kernels.  A 3-layer perceptron                */

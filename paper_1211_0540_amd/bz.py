@@ -93,6 +93,11 @@ def lib():
         "bz_step_check": (ctypes.c_int, [_vp, _vp, _vp]),
         "bz_transport_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                ctypes.c_double, ctypes.c_double, ctypes.POINTER(_vp)]),
+        "bz_transport_create_ex": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                                  ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                  ctypes.POINTER(_vp)]),
+        "bz_cell_moments": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+        "bz_marginal_v1": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]),
         "bz_transport_free": (None, [_vp]),
         "bz_transport_workspace_bytes": (_sz, [_vp]),
         "bz_transport_step": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _vp, _sz, _vp]),
@@ -283,6 +288,26 @@ def bz_transport_create(g: int, nx: int, x_length: float, T_wall: float, far_rho
     _check(lib().bz_transport_create(_vp(g), int(nx), float(x_length), float(T_wall), float(far_rho),
                                      float(far_u1), float(far_T), ctypes.byref(h)))
     return h.value
+
+
+def bz_transport_create_ex(g: int, dx, T_wall: float, far_rho: float, far_u1: float, far_T: float) -> int:
+    w = np.ascontiguousarray(dx, dtype=np.float64)
+    h = _vp()
+    _check(lib().bz_transport_create_ex(_vp(g), int(w.size), w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        float(T_wall), float(far_rho), float(far_u1), float(far_T), ctypes.byref(h)))
+    return h.value
+
+
+def bz_cell_moments(b: int, f, mom, stream=None) -> None:
+    _dev(f, "f")
+    _dev(mom, "moments")
+    _check(lib().bz_cell_moments(_vp(b), _vp(_ptr(f)), _vp(_ptr(mom)), _stream(stream)))
+
+
+def bz_marginal_v1(b: int, f, cell: int, out, stream=None) -> None:
+    _dev(f, "f")
+    _dev(out, "marginal")
+    _check(lib().bz_marginal_v1(_vp(b), _vp(_ptr(f)), int(cell), _vp(_ptr(out)), _stream(stream)))
 
 
 def bz_transport_free(t: int) -> None:

@@ -340,6 +340,12 @@ struct PlainLaunch {
 };
 hipError_t launch_conv_plain(const PlainLaunch &p, bool f64, hipStream_t s);
 
+// Diagnostics: per cell (f at f + off[c], mesh nn[c], spacing dvs[c]) rho, u1, u2, u3, T into
+// mom[5 c ..]; the v1 marginal of one cell (f at f) into out[N].
+hipError_t launch_cell_moments(int ncells, const double *f, const long long *off, const int *nn, const double *dvs,
+                               double *mom, hipStream_t s);
+hipError_t launch_marginal_v1(int N, double dv, const double *f, double *out, hipStream_t s);
+
 // Projection (Sec. 3.3) of ncells cells of one mesh, in place, two passes.
 hipError_t launch_project(int N, double dv, const double *linv, int ncells, double *q, const long long *d_off,
                           hipStream_t s);

@@ -141,6 +141,64 @@ __global__ void k_fill_u32(unsigned *p, int n, unsigned v) {
 }
 
 // ---------------------------------------------------------------------------
+// Diagnostics (Sec. 5: bulk velocity, marginal near the wall).  One block of
+// 256 threads per cell, fixed reduction order: density and bulk velocity in a
+// first pass, the temperature about that velocity in a second.
+// ---------------------------------------------------------------------------
+__device__ inline double block_sum256(double x, double *red) {
+    x = wave_sum(x);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(256) k_cell_moments(const double *__restrict__ f, const long long *__restrict__ off,
+                                                      const int *__restrict__ nn, const double *__restrict__ dvs,
+                                                      double *__restrict__ mom) {
+    __shared__ double red[4];
+    const int c = blockIdx.x, N = nn[c], M = N * N * N, h = N / 2;
+    const double dv = dvs[c];
+    const double *F = f + off[c];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int k = threadIdx.x; k < M; k += 256) {
+        const double x = F[k];
+        a0 += x;
+        a1 = fma(dv * (k / (N * N) - h), x, a1);
+        a2 = fma(dv * ((k / N) % N - h), x, a2);
+        a3 = fma(dv * (k % N - h), x, a3);
+    }
+    const double rho = block_sum256(a0, red);
+    const double u1 = block_sum256(a1, red) / rho, u2 = block_sum256(a2, red) / rho, u3 = block_sum256(a3, red) / rho;
+    double e = 0.0;
+    for (int k = threadIdx.x; k < M; k += 256) {
+        const double w1 = dv * (k / (N * N) - h) - u1, w2 = dv * ((k / N) % N - h) - u2, w3 = dv * (k % N - h) - u3;
+        e = fma(w1 * w1 + w2 * w2 + w3 * w3, F[k], e);
+    }
+    const double E = block_sum256(e, red);
+    if (threadIdx.x == 0) {
+        double *o = mom + 5 * (size_t)c;
+        o[0] = rho * dv * dv * dv;
+        o[1] = u1;
+        o[2] = u2;
+        o[3] = u3;
+        o[4] = E / (3.0 * rho);
+    }
+}
+
+// marginal of one cell in v1: out[k1] = dv^2 sum_{k2,k3} f(k1, k2, k3); one wavefront per k1
+__global__ void __launch_bounds__(256) k_marginal_v1(int N, double dv, const double *__restrict__ F,
+                                                     double *__restrict__ out) {
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int k1 = wid; k1 < N; k1 += 4) {
+        double s = 0.0;
+        for (int t = lane; t < N * N; t += 64) s += F[(size_t)k1 * N * N + t];
+        s = wave_sum(s);
+        if (lane == 0) out[k1] = s * dv * dv;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Weight expansion.  T[p * qs + q] = T_lambda(p, q) of the universal table;
 // scale = 4pi (2pi)^{-3/2} L^{lambda+3} dzeta^3.
 // ---------------------------------------------------------------------------
@@ -297,6 +355,18 @@ hipError_t launch_build_e3(int N, const long long *d_row_woff, const long long *
     else
         hipLaunchKernelGGL(k_build_e3<float>, grid, dim3(256), 0, s, N, d_row_woff, d_e3_woff,
                            (const float *)w_main, (float *)w_e3);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_moments(int ncells, const double *f, const long long *off, const int *nn, const double *dvs,
+                               double *mom, hipStream_t s) {
+    if (ncells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cell_moments, dim3(ncells), dim3(256), 0, s, f, off, nn, dvs, mom);
+    return hipGetLastError();
+}
+
+hipError_t launch_marginal_v1(int N, double dv, const double *f, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_marginal_v1, dim3(1), dim3(256), 0, s, N, dv, f, out);
     return hipGetLastError();
 }
 

@@ -307,6 +307,10 @@ struct bz_batch_s {
     size_t elems = 0;
     std::vector<bz::Part> parts;   // one per mesh used, largest N first
     void *d_tables = nullptr;
+    // per cell, in batch order (device, inside d_tables): f offset, N, dv
+    long long *d_cell_off = nullptr;
+    int *d_cell_N = nullptr;
+    double *d_cell_dv = nullptr;
     size_t ws_scratch = 0, ws_flag = 0, ws_total = 0;
     int plain_split = 4;
     // convolution timing
@@ -708,6 +712,16 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
         const size_t sc = (bat ? (size_t)p.groups * kWave : 1) * (size_t)M * 16;
         scratch = std::max(scratch, sc);
     }
+    // per-cell tables of the diagnostics
+    std::vector<int> cn(n_cells);
+    std::vector<double> cdv(n_cells);
+    for (int c = 0; c < n_cells; ++c) {
+        cn[c] = grids[grid_of_cell[c]]->N;
+        cdv[c] = grids[grid_of_cell[c]]->dv;
+    }
+    const size_t o_coff = put(b->cell_off.data(), n_cells * sizeof(long long));
+    const size_t o_cn = put(cn.data(), n_cells * sizeof(int));
+    const size_t o_cdv = put(cdv.data(), n_cells * sizeof(double));
     b->ws_scratch = ws;
     ws = align256(ws + scratch);
     b->ws_flag = ws;
@@ -737,6 +751,9 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
         }
     }
     char *base = (char *)b->d_tables;
+    b->d_cell_off = (long long *)(base + o_coff);
+    b->d_cell_N = (int *)(base + o_cn);
+    b->d_cell_dv = (double *)(base + o_cdv);
     for (size_t i = 0; i < b->parts.size(); ++i) {
         Part &p = b->parts[i];
         p.d_f_off = (long long *)(base + offs[i].f_off);
@@ -1042,6 +1059,21 @@ bz_status bz_project(bz_batch b, double *d_Q, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     for (const Part &p : b->parts)
         BZ_HIP(launch_project(p.g->N, p.g->dv, p.g->linv, (int)p.cells.size(), d_Q, p.d_f_off, s), "projection");
+    return BZ_OK;
+}
+
+bz_status bz_cell_moments(bz_batch b, const double *d_f, double *d_mom, void *stream) {
+    if (!b || !d_f || !d_mom) return fail(BZ_EINVAL, "bz_cell_moments: NULL argument");
+    BZ_HIP(launch_cell_moments(b->n_cells, d_f, b->d_cell_off, b->d_cell_N, b->d_cell_dv, d_mom, (hipStream_t)stream),
+           "bz_cell_moments");
+    return BZ_OK;
+}
+
+bz_status bz_marginal_v1(bz_batch b, const double *d_f, int cell, double *d_out, void *stream) {
+    if (!b || !d_f || !d_out) return fail(BZ_EINVAL, "bz_marginal_v1: NULL argument");
+    if (cell < 0 || cell >= b->n_cells) return fail(BZ_EINVAL, "bz_marginal_v1: cell index out of range");
+    const bz_grid g = b->grids[b->grid_of_cell[cell]];
+    BZ_HIP(launch_marginal_v1(g->N, g->dv, d_f + b->cell_off[cell], d_out, (hipStream_t)stream), "bz_marginal_v1");
     return BZ_OK;
 }
 

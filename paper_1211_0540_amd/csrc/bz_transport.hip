@@ -2,14 +2,17 @@
 // (Sec. 2.1, eq. BC) and far-field ghost cells, advanced with Heun's RK2, and
 // the Strang-split step T(dt/2) C(dt) T(dt/2) of Sec. 3.1.
 //
-// Layout: f[j][k], cell j = 0..nx-1 along x (uniform dx), k the flat velocity
-// index of the cell's N^3 mesh; v1 = dv (k1 - N/2) is the transport velocity.
-// Fluxes at face j-1/2:  v1 (f_{j-1} + dx/2 s_{j-1})  if v1 >= 0,
-//                        v1 (f_j     - dx/2 s_j)      otherwise,
-// s_j = minmod((f_j - f_{j-1})/dx, (f_{j+1} - f_j)/dx).  Left end: two ghost
-// cells copy cell 0 (slope 0 there); the wall face flux is v1 sigma_w M_w for
+// Layout: f[j][k], cell j = 0..nx-1 along x, of width dx_j (Sec. 3.4: cells
+// "not necessarily uniform"), k the flat velocity index of the cell's N^3 mesh;
+// v1 = dv (k1 - N/2) is the transport velocity.
+// Fluxes at face j-1/2:  v1 (f_{j-1} + dx_{j-1}/2 s_{j-1})  if v1 >= 0,
+//                        v1 (f_j     - dx_j/2 s_j)          otherwise,
+// s_j = minmod((f_j - f_{j-1})/d_{j-1/2}, (f_{j+1} - f_j)/d_{j+1/2}) with the
+// centre distances d_{j+1/2} = (dx_j + dx_{j+1})/2, and the update divides by
+// dx_j (on a uniform mesh, the printed formula).  Left end: two ghost cells of
+// width dx_0 copy cell 0 (slope 0 there); the wall face flux is v1 sigma_w M_w for
 // v1 > 0 and v1 f_0 for v1 < 0 with sigma_w = sum_{v1<0}|v1| f_0 / sum_{v1>0} v1 M_w,
-// so the net wall mass flux is zero.  Right end: ghosts hold M_far.
+// so the net wall mass flux is zero.  Right end: ghosts of width dx_{nx-1} hold M_far.
 // Memory-bound (5 reads + 1-2 reads + 1 write of 8 bytes per (cell, velocity));
 // negligible next to the collision step.
 #include <cmath>
@@ -20,8 +23,9 @@
 
 struct bz_transport_s {
     int N = 0, nx = 0;
-    double L = 0, dx = 0, T_wall = 0, in_norm = 0;
-    double *d_tab = nullptr;  // [2][N^3]: M_wall, M_far
+    double L = 0, T_wall = 0, in_norm = 0;
+    double *d_tab = nullptr;  // [2][N^3]: M_wall, M_far; then the nx cell widths
+    const double *d_dx = nullptr;
 };
 
 namespace bz {
@@ -62,10 +66,15 @@ __device__ inline double cellv(const double *__restrict__ f, const double *__res
     return f[(size_t)j * M + k];
 }
 
+// width of cell j, ghosts taking the width of the cell they border
+__device__ inline double cellw(const double *__restrict__ dx, int nx, int j) {
+    return dx[j < 0 ? 0 : (j >= nx ? nx - 1 : j)];
+}
+
 // out = alpha * base + beta * (fin + dt * rhs(fin)) at every (cell, velocity).  N is a template
 // parameter so that the index splits are divisions by constants.
 template <int N>
-__global__ void __launch_bounds__(256) k_transport_stage(int nx, double dv, double dx, double dt,
+__global__ void __launch_bounds__(256) k_transport_stage(int nx, double dv, const double *__restrict__ dx, double dt,
                                                          const double *__restrict__ fin,
                                                          const double *__restrict__ base, double alpha, double beta,
                                                          const double *__restrict__ tab,
@@ -79,18 +88,22 @@ __global__ void __launch_bounds__(256) k_transport_stage(int nx, double dv, doub
     const double a = cellv(fin, mfar, nx, M, j - 2, k), b = cellv(fin, mfar, nx, M, j - 1, k);
     const double c = cellv(fin, mfar, nx, M, j, k), d = cellv(fin, mfar, nx, M, j + 1, k);
     const double e = cellv(fin, mfar, nx, M, j + 2, k);
-    const double sb = minmod((b - a) / dx, (c - b) / dx);
-    const double sc = minmod((c - b) / dx, (d - c) / dx);
-    const double sd = minmod((d - c) / dx, (e - d) / dx);
+    const double wa = cellw(dx, nx, j - 2), wb = cellw(dx, nx, j - 1), wc = cellw(dx, nx, j);
+    const double wd = cellw(dx, nx, j + 1), we = cellw(dx, nx, j + 2);
+    // centre distances
+    const double dab = 0.5 * (wa + wb), dbc = 0.5 * (wb + wc), dcd = 0.5 * (wc + wd), dde = 0.5 * (wd + we);
+    const double sb = minmod((b - a) / dab, (c - b) / dbc);
+    const double sc = minmod((c - b) / dbc, (d - c) / dcd);
+    const double sd = minmod((d - c) / dcd, (e - d) / dde);
     // face j-1/2
     double Fl;
     if (j == 0)
         Fl = v1 > 0.0 ? v1 * sigma[0] * mwall[k] : v1 * c;
     else
-        Fl = v1 >= 0.0 ? v1 * (b + 0.5 * dx * sb) : v1 * (c - 0.5 * dx * sc);
+        Fl = v1 >= 0.0 ? v1 * (b + 0.5 * wb * sb) : v1 * (c - 0.5 * wc * sc);
     // face j+1/2
-    const double Fr = v1 >= 0.0 ? v1 * (c + 0.5 * dx * sc) : v1 * (d - 0.5 * dx * sd);
-    const double y = c + dt * (-(Fr - Fl) / dx);
+    const double Fr = v1 >= 0.0 ? v1 * (c + 0.5 * wc * sc) : v1 * (d - 0.5 * wd * sd);
+    const double y = c + dt * (-(Fr - Fl) / wc);
     out[idx] = (alpha != 0.0 ? alpha * base[idx] : 0.0) + beta * y;
 }
 
@@ -104,11 +117,11 @@ static hipError_t transport_rk2_n(const bz_transport_s *t, double *f, double dt,
     const size_t n = (size_t)t->nx * M;
     const unsigned blocks = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_wall_sigma<N>, dim3(1), dim3(256), 0, s, dv, f, t->in_norm, sigma);
-    hipLaunchKernelGGL(k_transport_stage<N>, dim3(blocks), dim3(256), 0, s, t->nx, dv, t->dx, dt, f, f, 0.0, 1.0,
+    hipLaunchKernelGGL(k_transport_stage<N>, dim3(blocks), dim3(256), 0, s, t->nx, dv, t->d_dx, dt, f, f, 0.0, 1.0,
                        t->d_tab, sigma, fs);
     hipLaunchKernelGGL(k_wall_sigma<N>, dim3(1), dim3(256), 0, s, dv, fs, t->in_norm, sigma);
     // each thread reads f and fs at its own index only for the base term, so f may be the output
-    hipLaunchKernelGGL(k_transport_stage<N>, dim3(blocks), dim3(256), 0, s, t->nx, dv, t->dx, dt, fs, f, 0.5, 0.5,
+    hipLaunchKernelGGL(k_transport_stage<N>, dim3(blocks), dim3(256), 0, s, t->nx, dv, t->d_dx, dt, fs, f, 0.5, 0.5,
                        t->d_tab, sigma, f);
     return hipGetLastError();
 }
@@ -137,9 +150,20 @@ bz_status bz_transport_create(bz_grid g, int nx, double x_length, double T_wall,
                               double far_T, bz_transport *out) {
     if (!out) return fail(BZ_EINVAL, "bz_transport_create: out is NULL");
     *out = nullptr;
-    if (!g) return fail(BZ_EINVAL, "bz_transport_create: NULL grid");
     if (nx < 1) return fail(BZ_EINVAL, "bz_transport_create: nx must be >= 1");
     if (!(x_length > 0) || !std::isfinite(x_length)) return fail(BZ_EINVAL, "bz_transport_create: bad length");
+    std::vector<double> w((size_t)nx, x_length / nx);
+    return bz_transport_create_ex(g, nx, w.data(), T_wall, far_rho, far_u1, far_T, out);
+}
+
+bz_status bz_transport_create_ex(bz_grid g, int nx, const double *dx, double T_wall, double far_rho, double far_u1,
+                                 double far_T, bz_transport *out) {
+    if (!out) return fail(BZ_EINVAL, "bz_transport_create: out is NULL");
+    *out = nullptr;
+    if (!g || !dx) return fail(BZ_EINVAL, "bz_transport_create: NULL grid or widths");
+    if (nx < 1) return fail(BZ_EINVAL, "bz_transport_create: nx must be >= 1");
+    for (int j = 0; j < nx; ++j)
+        if (!(dx[j] > 0) || !std::isfinite(dx[j])) return fail(BZ_EINVAL, "bz_transport_create: bad cell width");
     if (!(T_wall > 0) || !(far_T > 0) || !(far_rho >= 0) || !std::isfinite(far_u1))
         return fail(BZ_EINVAL, "bz_transport_create: bad wall or far-field state");
     bz_transport_s *t = new (std::nothrow) bz_transport_s();
@@ -148,9 +172,9 @@ bz_status bz_transport_create(bz_grid g, int nx, double x_length, double T_wall,
     t->N = N;
     t->L = g->L;
     t->nx = nx;
-    t->dx = x_length / nx;
     t->T_wall = T_wall;
-    std::vector<double> tab(2 * (size_t)M);
+    std::vector<double> tab(2 * (size_t)M + nx);
+    for (int j = 0; j < nx; ++j) tab[2 * (size_t)M + j] = dx[j];
     const double dv = g->dv;
     double in_norm = 0.0;
     for (int k = 0; k < M; ++k) {
@@ -164,6 +188,7 @@ bz_status bz_transport_create(bz_grid g, int nx, double x_length, double T_wall,
     t->in_norm = in_norm * dv * dv * dv;
     hipError_t e = hipMalloc(&t->d_tab, tab.size() * sizeof(double));
     if (e == hipSuccess) e = hipMemcpy(t->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+    t->d_dx = t->d_tab + 2 * (size_t)M;
     if (e != hipSuccess) {
         if (t->d_tab) (void)hipFree(t->d_tab);
         delete t;

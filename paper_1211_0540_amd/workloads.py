@@ -85,6 +85,27 @@ def shock_initial(n_cells: int = 256, N: int = 24, L: float = 7.0) -> np.ndarray
     return np.broadcast_to(m, (n_cells, N, N, N)).copy()
 
 
+def wall_refined_widths(eps: float = 1.0, length: float = 30.0, wall_per_mfp: int = 8, inner_per_mfp: int = 2,
+                        wall_mfp: float = 1.0, ratio: float = 1.1) -> np.ndarray:
+    """Cell widths of the sudden-heating run of Sec. 5, wall first: eight cells per mean free
+    path next to the wall, two in the interior.  The mean free path is taken as eps (the
+    scaled Knudsen number is its ratio to the unit length).  Cells of width eps/wall_per_mfp
+    fill the first wall_mfp mean free paths, then each cell is `ratio` times wider than the
+    last up to eps/inner_per_mfp, which fills the rest of [0, length]; what is left at the
+    far end (less than one interior cell) is added to the last cell.  Geometry only: the
+    widths are input data."""
+    wmin, wmax = eps / wall_per_mfp, eps / inner_per_mfp
+    w = [wmin] * max(1, int(round(wall_mfp * wall_per_mfp)))
+    while len(w) > 1 and sum(w) > length:
+        w.pop()
+    while w[-1] * ratio < wmax and sum(w) + w[-1] * ratio <= length:
+        w.append(w[-1] * ratio)
+    while sum(w) + wmax <= length:
+        w.append(wmax)
+    w[-1] += length - sum(w)
+    return np.array(w)
+
+
 def perturbed_maxwellian(rng: np.random.Generator, N: int, L: float, rho: float, u, T: float,
                          amp: float = 0.1, modes: int = 6) -> np.ndarray:
     """M (1 + amp p) with a smooth random p, scaled so that ||M p||_2 = ||M||_2 on the mesh."""
