@@ -87,7 +87,7 @@ typedef struct bz_grid_s *bz_grid;
 typedef struct {
     int N;               /* points per axis */
     double L;            /* half-width of the velocity cube [-L, L)^3 */
-    double lambda;       /* exponent of |u| in B = |u|^lambda b (0: Maxwell molecules, 1: hard spheres) */
+    double lambda;       /* exponent of |u| in B = |u|^lambda b, in (-3, 1] (0: Maxwell molecules, 1: hard spheres) */
     double dv;           /* 2L/N */
     double dzeta;        /* pi/L */
     long long pairs;     /* valid (zeta_k, xi_m) pairs of the convolution: (3N^2/4)^3 */
@@ -112,11 +112,13 @@ typedef struct {
 #define BZ_CORE_DEFAULT (-1)  /* the ball |zeta| < pi: nc <= ceil(L^2) - 1, capped as below */
 #define BZ_CORE_OFF (-2)      /* no core: every pair in FP32 */
 
-/* Create a mesh handle.  Host only, no device work.  Errors: BZ_EINVAL for N
- * not a multiple of 4, N outside [8, 32], L <= 0 or non-finite;
- * BZ_EUNSUPPORTED for lambda other than 0 (Maxwell molecules) or 1 (hard
- * spheres), the two exponents whose weight integral the library evaluates in
- * closed form. */
+/* Create a mesh handle.  Host only, no device work.  lambda is the exponent
+ * of |u| in the collision kernel (Sec. 2): -3 < lambda <= 1, i.e. soft
+ * potentials (< 0), Maxwell molecules (0), variable hard potentials (0..1) and
+ * hard spheres (1).  For lambda = 0 and 1 the weight integral of eq.
+ * (GHat_calc) is evaluated in closed form, otherwise by quadrature (see
+ * bz_weight_table).  Errors: BZ_EINVAL for N not a multiple of 4, N outside
+ * [8, 32], L <= 0 or non-finite; BZ_EUNSUPPORTED for lambda outside (-3, 1]. */
 bz_status bz_grid_init(int N, double L, double lambda, bz_grid *out);
 /* As bz_grid_init with an explicit core: core_r2 in [1, min(N^2/4, 81) - 1]
  * (the ball stays off the k_d = 0 planes and within the kernel's half-width of
@@ -138,6 +140,19 @@ bz_status bz_grid_coords(bz_grid g, double *v, double *zeta);
 /* and are expanded into the caller's buffer in the order the chosen      */
 /* schedule reads them (dzeta^3 folded in).                               */
 /* ------------------------------------------------------------------ */
+/* The universal table T_lambda(p, q), p = 0..3N^2/4, q = 0..3N^2, row-major
+ * (bz_weight_table_size(N) doubles, 0 for a bad N), into host memory `out`.
+ * For lambda = 0, 1 in closed form; otherwise
+ *   T = int_0^1 s^{lambda+2} sinc(a s) sinc(b s) ds
+ * by composite Gauss-Legendre quadrature: 16 nodes on each of 15 uniform
+ * panels of [1/16, 1], on 40 panels [0.3^{k+1}, 0.3^k]/16 graded towards
+ * s = 0 (which resolve the endpoint behaviour of s^{lambda+2}), and the exact
+ * integral of s^{lambda+2} on the remaining [0, 0.3^40/16].  Host only,
+ * threaded.  Errors: BZ_EINVAL for a bad N or NULL, BZ_EUNSUPPORTED for
+ * lambda outside (-3, 1]. */
+size_t bz_weight_table_size(int N);
+bz_status bz_weight_table(int N, double lambda, double *out);
+
 /* Bytes needed for a weight buffer of the given kind (0 for an unknown kind).
  * A batched buffer holds the weight stream of every output row in schedule
  * order and, after it, the stream of the edge pass of the conjugate-symmetric

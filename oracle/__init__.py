@@ -10,7 +10,8 @@ Functions
 ---------
 grid(N, L)                    Sec. 3.1 eq. (meshpoints)
 gauss_legendre(n)             quadrature nodes used for eq. (GHat_calc)
-ghat(xi, zeta, lam, L)        Sec. 2.2 eq. (GHat_calc), cut off at r0 = L
+radial_rule(lam, L, nq)       Gauss-Jacobi nodes for the radial integral of eq. (GHat_calc)
+ghat(xi, zeta, lam, L)        Sec. 2.2 eq. (GHat_calc), cut off at r0 = L, any lam > -3
 dft_forward(f, L)             Sec. 2.2 transform, sampled as in Sec. 3.2
 dft_inverse(qhat, L)          Sec. 3.2 inverse transform (real part kept)
 Oracle(N, L, lam).collide_hat Sec. 3.2 trapezoid-rule weighted convolution
@@ -52,6 +53,10 @@ def _load():
     lib.bzo_dft_inverse.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
     lib.bzo_ctx_create.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int]
     lib.bzo_ctx_create.restype = ctypes.c_void_p
+    lib.bzo_ctx_create_q.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp, _dp]
+    lib.bzo_ctx_create_q.restype = ctypes.c_void_p
+    lib.bzo_ghat_q.argtypes = [_dp, _dp, ctypes.c_int, _dp, _dp]
+    lib.bzo_ghat_q.restype = ctypes.c_double
     lib.bzo_ctx_free.argtypes = [ctypes.c_void_p]
     lib.bzo_ctx_ghat.argtypes = [ctypes.c_void_p, _ip, _ip]
     lib.bzo_ctx_ghat.restype = ctypes.c_double
@@ -98,11 +103,36 @@ def gauss_legendre(n: int):
     return x, w
 
 
-def ghat(xi, zeta, lam: float, L: float, nq: int = 400) -> float:
-    """Ghat(xi, zeta) of eq. (GHat_calc) by nq-point Gauss-Legendre quadrature on [0, L]."""
+def radial_rule(lam: float, L: float, nq: int):
+    """Gauss-Jacobi rule for int_0^L r^{lam+2} g(r) dr (lam > -3): the weight r^{lam+2} is
+    integrated exactly, so the rule converges geometrically in nq for the entire g of
+    eq. (GHat_calc) whatever the endpoint behaviour of r^{lam+2}.  Nodes r_i in [0, L] and
+    weights that hold r^{lam+2}; the nodes come from scipy (a library routine)."""
+    from scipy.special import roots_jacobi
+    a = lam + 2.0
+    if not a > -1.0:
+        raise ValueError("lambda must exceed -3")
+    x, w = roots_jacobi(int(nq), 0.0, a)        # weight (1 + x)^a on [-1, 1]
+    r = 0.5 * L * (x + 1.0)
+    return np.ascontiguousarray(r), np.ascontiguousarray(w * (0.5 * L) ** (a + 1.0))
+
+
+def _integer_lambda(lam: float) -> bool:
+    return lam in (0.0, 1.0)
+
+
+def ghat(xi, zeta, lam: float, L: float, nq: int = 400, jacobi: bool | None = None) -> float:
+    """Ghat(xi, zeta) of eq. (GHat_calc), cut off at r0 = L, by nq-point quadrature:
+    Gauss-Legendre with r^{lam+2} in the weights for lam = 0, 1, Gauss-Jacobi otherwise
+    (or as `jacobi` says)."""
     xi = np.ascontiguousarray(xi, dtype=np.float64)
     zeta = np.ascontiguousarray(zeta, dtype=np.float64)
-    return float(_load().bzo_ghat(_p(xi), _p(zeta), lam, L, nq))
+    if jacobi is None:
+        jacobi = not _integer_lambda(float(lam))
+    if not jacobi:
+        return float(_load().bzo_ghat(_p(xi), _p(zeta), lam, L, nq))
+    r, w = radial_rule(float(lam), L, nq)
+    return float(_load().bzo_ghat_q(_p(xi), _p(zeta), int(nq), _p(r), _p(w)))
 
 
 def _as_cube(f):
@@ -144,9 +174,15 @@ def project(qt, L: float):
 class Oracle:
     """Per-mesh oracle context: the Ghat quadrature is memoised on creation."""
 
-    def __init__(self, N: int, L: float, lam: float, nq: int = 400):
+    def __init__(self, N: int, L: float, lam: float, nq: int = 400, jacobi: bool | None = None):
         self.N, self.L, self.lam = N, float(L), float(lam)
-        self._h = _load().bzo_ctx_create(N, self.L, self.lam, nq)
+        if jacobi is None:
+            jacobi = not _integer_lambda(self.lam)
+        if jacobi:
+            r, w = radial_rule(self.lam, self.L, nq)
+            self._h = _load().bzo_ctx_create_q(N, self.L, self.lam, int(nq), _p(r), _p(w))
+        else:
+            self._h = _load().bzo_ctx_create(N, self.L, self.lam, nq)
         if not self._h:
             raise ValueError("bad oracle parameters")
 

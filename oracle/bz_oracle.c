@@ -104,6 +104,12 @@ static double sinc(double x) { return x == 0.0 ? 1.0 : sin(x) / x; }
 
 /* ------------------------------------------------------------------ */
 /* Convolution weights, Sec. 2.2 eq. (GHat_calc), isotropic b = 1/4pi, */
+/* for any lambda > -3 (the text after the equation: a one-dimensional   */
+/* integral for other values of lambda, evaluated by quadrature).  The   */
+/* default rule is Gauss-Legendre with the factor r^{lambda+2} folded    */
+/* into the weights, exact enough for the integer lambda = 0, 1; for other */
+/* lambda the Python side passes a Gauss-Jacobi rule whose weight is     */
+/* r^{lambda+2} itself (bzo_ctx_create_q, bzo_ghat_q).                   */
 /* beta = 1 (elastic law of eq. (velocity_interact)), integral cut off */
 /* at r0 = L (Sec. 3.1).  The two pieces are returned separately:       */
 /*   gain(|zeta|, |xi - zeta/2|) = int_0^L r^{l+2} sinc(r|zeta|/2)      */
@@ -131,6 +137,19 @@ static int quad_init(quad_t *q, int n, double L, double lambda)
     return 0;
 }
 
+/* Explicit radial rule: n nodes r_i in [0, L] and weights that already hold
+ * the factor r^{lambda+2} (for a weight the nodes integrate exactly). */
+static int quad_init_explicit(quad_t *q, int n, const double *r, const double *w)
+{
+    q->n = n;
+    q->x = (double *)malloc(sizeof(double) * n);
+    q->w = (double *)malloc(sizeof(double) * n);
+    if (!q->x || !q->w) return -1;
+    memcpy(q->x, r, sizeof(double) * n);
+    memcpy(q->w, w, sizeof(double) * n);
+    return 0;
+}
+
 static void quad_free(quad_t *q) { free(q->x); free(q->w); }
 
 static double quad_gain(const quad_t *q, double zeta_abs, double xh_abs)
@@ -150,11 +169,30 @@ static double quad_loss(const quad_t *q, double xi_abs)
     return s;
 }
 
+static double ghat_with(const quad_t *q, const double *xi, const double *zeta);
+
 /* Ghat(xi, zeta) for explicit vectors, by quadrature with nq nodes. */
 double bzo_ghat(const double *xi, const double *zeta, double lambda, double L, int nq)
 {
     quad_t q;
     if (quad_init(&q, nq, L, lambda)) return NAN;
+    double g = ghat_with(&q, xi, zeta);
+    quad_free(&q);
+    return g;
+}
+
+/* Same with an explicit radial rule (nodes in [0, L], weights holding r^{lambda+2}). */
+double bzo_ghat_q(const double *xi, const double *zeta, int n, const double *r, const double *w)
+{
+    quad_t q;
+    if (quad_init_explicit(&q, n, r, w)) return NAN;
+    double g = ghat_with(&q, xi, zeta);
+    quad_free(&q);
+    return g;
+}
+
+static double ghat_with(const quad_t *q, const double *xi, const double *zeta)
+{
     double za = 0, xh = 0, xa = 0;
     for (int d = 0; d < 3; ++d) {
         za += zeta[d] * zeta[d];
@@ -163,9 +201,7 @@ double bzo_ghat(const double *xi, const double *zeta, double lambda, double L, i
         xa += xi[d] * xi[d];
     }
     double c0 = 4.0 * BZO_PI / pow(2.0 * BZO_PI, 1.5);
-    double g = c0 * (quad_gain(&q, sqrt(za), sqrt(xh)) - quad_loss(&q, sqrt(xa)));
-    quad_free(&q);
-    return g;
+    return c0 * (quad_gain(q, sqrt(za), sqrt(xh)) - quad_loss(q, sqrt(xa)));
 }
 
 /* The integrand depends on (xi, zeta) only through |zeta|, |xi - zeta/2| and
@@ -180,7 +216,18 @@ typedef struct {
     double *loss; /* [nc_max+1] */
 } ghat_cache_t;
 
+static int ghat_cache_fill(ghat_cache_t *c, int N, double L, const quad_t *q);
+
 static int ghat_cache_build(ghat_cache_t *c, int N, double L, double lambda, int nq)
+{
+    quad_t q;
+    if (quad_init(&q, nq, L, lambda)) return -1;
+    int rc = ghat_cache_fill(c, N, L, &q);
+    quad_free(&q);
+    return rc;
+}
+
+static int ghat_cache_fill(ghat_cache_t *c, int N, double L, const quad_t *qp)
 {
     double dz = BZO_PI / L;
     c->N = N;
@@ -191,16 +238,13 @@ static int ghat_cache_build(ghat_cache_t *c, int N, double L, double lambda, int
     c->gain = (double *)malloc(sizeof(double) * ng);
     c->loss = (double *)malloc(sizeof(double) * (c->nc_max + 1));
     if (!c->gain || !c->loss) return -1;
-    quad_t q;
-    if (quad_init(&q, nq, L, lambda)) return -1;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int na = 0; na <= c->na_max; ++na) {
         double za = dz * sqrt((double)na);
         for (int nb = 0; nb <= c->nb_max; ++nb)
-            c->gain[(size_t)na * (c->nb_max + 1) + nb] = quad_gain(&q, za, 0.5 * dz * sqrt((double)nb));
+            c->gain[(size_t)na * (c->nb_max + 1) + nb] = quad_gain(qp, za, 0.5 * dz * sqrt((double)nb));
     }
-    for (int nc = 0; nc <= c->nc_max; ++nc) c->loss[nc] = quad_loss(&q, dz * sqrt((double)nc));
-    quad_free(&q);
+    for (int nc = 0; nc <= c->nc_max; ++nc) c->loss[nc] = quad_loss(qp, dz * sqrt((double)nc));
     return 0;
 }
 
@@ -322,6 +366,20 @@ bzo_ctx *bzo_ctx_create(int N, double L, double lambda, int nq)
     bzo_ctx *c = (bzo_ctx *)calloc(1, sizeof(bzo_ctx));
     c->N = N; c->L = L; c->lambda = lambda; c->nq = nq > 0 ? nq : 400;
     if (ghat_cache_build(&c->cache, N, L, lambda, c->nq)) { free(c); return NULL; }
+    return c;
+}
+
+/* Context whose weight cache comes from an explicit radial rule (see bzo_ghat_q). */
+bzo_ctx *bzo_ctx_create_q(int N, double L, double lambda, int n, const double *r, const double *w)
+{
+    if (N < 2 || N > 64 || (N & 1) || !(L > 0) || n < 1) return NULL;
+    bzo_ctx *c = (bzo_ctx *)calloc(1, sizeof(bzo_ctx));
+    c->N = N; c->L = L; c->lambda = lambda; c->nq = n;
+    quad_t q;
+    if (quad_init_explicit(&q, n, r, w)) { free(c); return NULL; }
+    int rc = ghat_cache_fill(&c->cache, N, L, &q);
+    quad_free(&q);
+    if (rc) { free(c); return NULL; }
     return c;
 }
 

@@ -73,6 +73,8 @@ def lib():
         "bz_grid_init_ex": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                            ctypes.POINTER(_vp)]),
         "bz_grid_free": (None, [_vp]),
+        "bz_weight_table_size": (_sz, [ctypes.c_int]),
+        "bz_weight_table": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
         "bz_grid_query": (ctypes.c_int, [_vp, ctypes.POINTER(GridInfo)]),
         "bz_grid_coords": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
         "bz_weights_bytes": (_sz, [_vp, ctypes.c_int]),
@@ -184,6 +186,14 @@ def bz_grid_init_ex(N: int, L: float, lam: float, core_r2: int = BZ_CORE_DEFAULT
     h = _vp()
     _check(lib().bz_grid_init_ex(int(N), float(L), float(lam), int(core_r2), ctypes.byref(h)))
     return h.value
+
+
+def bz_weight_table(N: int, lam: float) -> np.ndarray:
+    """The universal table T_lambda(p, q) as a (3N^2/4 + 1, 3N^2 + 1) host array."""
+    n = int(lib().bz_weight_table_size(int(N)))
+    out = np.zeros(max(n, 1))
+    _check(lib().bz_weight_table(int(N), float(lam), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out.reshape(3 * N * N // 4 + 1, 3 * N * N + 1)
 
 
 def bz_grid_free(g: int) -> None:

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 def test_grid_validation_errors():
     for N, L, lam, st in [(7, 6.0, 1.0, bz.BZ_EINVAL), (36, 6.0, 1.0, bz.BZ_EINVAL), (18, 6.0, 1.0, bz.BZ_EINVAL),
                           (16, -1.0, 1.0, bz.BZ_EINVAL), (16, float("nan"), 1.0, bz.BZ_EINVAL),
-                          (16, 6.0, 0.5, bz.BZ_EUNSUPPORTED)]:
+                          (16, 6.0, 1.5, bz.BZ_EUNSUPPORTED)]:
         with pytest.raises(bz.BzError) as e:
             bz.bz_grid_init(N, L, lam)
         assert e.value.status == st
@@ -192,3 +192,43 @@ def test_core_radius_validation():
         assert bz.bz_grid_query(g)["core_r2"] == 80
     finally:
         bz.bz_grid_free(g)
+
+
+def _T_mp(lam, p, q):
+    """T_lambda(p, q) to 30 digits: the singular part exactly, the rest by tanh-sinh."""
+    import mpmath
+    mpmath.mp.dps = 30
+    al = mpmath.mpf(lam) + 2
+    a, b = mpmath.pi * mpmath.sqrt(p) / 2, mpmath.pi * mpmath.sqrt(q) / 2
+    sc = lambda x: mpmath.mpf(1) if x == 0 else mpmath.sin(x) / x
+    rest = mpmath.quad(lambda s: s ** al * (sc(a * s) * sc(b * s) - 1), mpmath.linspace(0, 1, 17))
+    return float(rest + 1 / (al + 1))
+
+
+@pytest.mark.parametrize("lam", [0.5, -1.5, -2.9])
+def test_weight_table_for_general_lambda(lam):
+    """The library's graded Gauss-Legendre table against a 30-digit evaluation."""
+    T = bz.bz_weight_table(24, lam)
+    assert T.shape == (3 * 24 * 24 // 4 + 1, 3 * 24 * 24 + 1)
+    rng = np.random.default_rng(int(10 * lam) + 50)
+    for p, q in [(0, 0), (0, T.shape[1] - 1), (T.shape[0] - 1, T.shape[1] - 1)] + \
+            [(int(rng.integers(0, T.shape[0])), int(rng.integers(0, T.shape[1]))) for _ in range(5)]:
+        assert T[p, q] == pytest.approx(_T_mp(lam, p, q), rel=1e-13, abs=1e-15), (p, q)
+
+
+@pytest.mark.parametrize("lam", [0.0, 1.0])
+def test_quadrature_table_equals_closed_form(lam):
+    """Just off an integer lambda the library integrates; at it, it uses the closed form."""
+    near = np.nextafter(lam, -1.0)
+    a, b = bz.bz_weight_table(16, near), bz.bz_weight_table(16, lam)
+    assert np.max(np.abs(a - b)) < 1e-14
+
+
+def test_lambda_range():
+    for lam in (-3.0, 1.5, float("nan")):
+        with pytest.raises(bz.BzError) as e:
+            bz.bz_grid_init(16, 6.0, lam)
+        assert e.value.status == bz.BZ_EUNSUPPORTED
+    g = bz.bz_grid_init(16, 6.0, -1.5)
+    assert bz.bz_grid_query(g)["lambda"] == -1.5
+    bz.bz_grid_free(g)

@@ -434,3 +434,36 @@ def test_autotune_keeps_results(dev):
     assert np.array_equal(q1, q2)           # the tuned choice is kept and deterministic
     assert rel_l2(q1, q0) < 2 * TOL32   # variants differ only by FP32 rounding
     c.close()
+
+
+# ---------------------------------------------------------------------------
+# Other collision exponents (text after eq. GHat_calc): variable hard spheres and
+# soft potentials, weights from the library's quadrature table
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("lam", [0.5, -1.5])
+@pytest.mark.parametrize("mode", ["batched_f64", "plain_f64", "batched_f32"])
+def test_general_lambda_matches_oracle(dev, lam, mode):
+    N, L = 12, 5.0
+    n = 2 if mode == "plain_f64" else 66
+    cells = list(W.random_smooth_cells(n, N, L, seed=int(10 * lam) + 60, umax=1.0))
+    qts, qs = run([(N, L, lam)], [0] * n, cells, mode, dev)
+    o = oracle_for(N, L, lam)
+    for i in sorted({0, n // 2, n - 1}):
+        qt_o, q_o, _, _ = o.collide(cells[i])
+        if mode == "batched_f32":
+            assert rel_l2(qs[i], q_o) < TOL32, i
+        else:
+            assert max_rel(qts[i], qt_o) < 1e-12, i
+            assert max_rel(qs[i], q_o) < 1e-12, i
+        assert_conserved(qs[i], N, L)
+
+
+def test_general_lambda_shock_mesh_fp64(dev):
+    """lambda = 0.5 on the N=24, L=7 mesh of the shock problem, batched FP64."""
+    N, L, lam = 24, 7.0, 0.5
+    cells = list(W.random_smooth_cells(3, N, L, seed=61, umax=1.0))
+    qts, _ = run([(N, L, lam)], [0] * 3, cells, "batched_f64", dev)
+    o = oracle_for(N, L, lam)
+    for i in range(3):
+        qt_o, _, _, _ = o.collide(cells[i])
+        assert max_rel(qts[i], qt_o) < 1e-12, i

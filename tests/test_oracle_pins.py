@@ -107,6 +107,46 @@ def test_ghat_quadrature_matches_closed_form(N, L, lam):
     assert worst < 1e-11 * L ** (lam + 3)
 
 
+def _radial_mp(lam, a, b, L):
+    """int_0^L r^{lam+2} sinc(a r) sinc(b r) dr to 30 digits (mpmath): the singular part
+    int_0^L r^{lam+2} dr is taken exactly and the regular rest by tanh-sinh quadrature."""
+    import mpmath
+    mpmath.mp.dps = 30
+    al = mpmath.mpf(lam) + 2
+    Lm = mpmath.mpf(L)
+    sc = lambda x: mpmath.mpf(1) if x == 0 else mpmath.sin(x) / x
+    rest = mpmath.quad(lambda r: r ** al * (sc(a * r) * sc(b * r) - 1), mpmath.linspace(0, Lm, 9))
+    return float(rest + Lm ** (al + 1) / (al + 1))
+
+
+@pytest.mark.parametrize("lam", [0.5, -1.5, -2.5])
+def test_ghat_for_general_lambda_against_arbitrary_precision(lam):
+    """Other lambda (text after eq. GHat_calc): the Gauss-Jacobi radial rule against a
+    30-digit evaluation of the same integral, and against itself with half the nodes."""
+    L = 6.0
+    c = 4 * np.pi / (2 * np.pi) ** 1.5
+    rng = np.random.default_rng(int(10 * lam) + 40)
+    for _ in range(4):
+        xi, zeta = rng.uniform(-3, 3, 3), rng.uniform(-3, 3, 3)
+        ref = c * (_radial_mp(lam, np.linalg.norm(zeta) / 2, np.linalg.norm(xi - zeta / 2), L)
+                   - _radial_mp(lam, np.linalg.norm(xi), 0.0, L))
+        g400 = O.ghat(xi, zeta, lam, L)
+        g200 = O.ghat(xi, zeta, lam, L, nq=200)
+        assert abs(g400 - ref) < 1e-12 * L ** (lam + 3)
+        assert abs(g400 - g200) < 1e-12 * L ** (lam + 3)
+
+
+@pytest.mark.parametrize("lam", [0.0, 1.0])
+def test_jacobi_rule_equals_legendre_rule_at_integer_lambda(lam):
+    L = 6.0
+    rng = np.random.default_rng(int(lam) + 7)
+    for _ in range(6):
+        xi, zeta = rng.uniform(-3, 3, 3), rng.uniform(-3, 3, 3)
+        a = O.ghat(xi, zeta, lam, L, jacobi=False)
+        b = O.ghat(xi, zeta, lam, L, jacobi=True)
+        assert abs(a - b) < 1e-12 * L ** (lam + 3)
+
+
 def test_ghat_vanishes_at_zero_frequency_and_is_even():
     N, L = 16, 6.0
     _, z, _, _ = O.grid(N, L)
@@ -114,8 +154,8 @@ def test_ghat_vanishes_at_zero_frequency_and_is_even():
     for _ in range(20):
         xi = z[rng.integers(1, N, 3)]
         zeta = z[rng.integers(1, N, 3)]
-        for lam in (0.0, 1.0):
-            assert abs(O.ghat(xi, np.zeros(3), lam, L)) < 1e-13
+        for lam in (0.0, 1.0, 0.5, -1.5):
+            assert abs(O.ghat(xi, np.zeros(3), lam, L)) < 1e-13 * L ** (lam + 3)
             assert O.ghat(-xi, -zeta, lam, L) == pytest.approx(O.ghat(xi, zeta, lam, L), abs=1e-13)
             p = rng.permutation(3)
             assert O.ghat(xi[p], zeta[p], lam, L) == pytest.approx(O.ghat(xi, zeta, lam, L), abs=1e-13)
