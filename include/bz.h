@@ -93,7 +93,22 @@ typedef struct {
     long long pairs;     /* valid (zeta_k, xi_m) pairs of the convolution: (3N^2/4)^3 */
     int core_r2;         /* radius^2 of the FP64 core ball in index units (0: no core) */
     long long core_steps;/* steps of the core schedule (row pairs; 0 without a core) */
+    double beta;         /* 1: elastic; < 1: inelastic (bz_grid_create) */
 } bz_grid_info;
+
+/* Parameters of bz_grid_create.  beta is the factor of eq. (G_eqn) and
+ * (GHat_calc): 1 for the elastic interaction law of eq. (velocity_interact),
+ * beta in [1/2, 1) for inelastic collisions with restitution coefficient
+ * 2 beta - 1 (post-collisional velocities v' = v + (beta/2)(|u| sigma - u)).
+ * Inelastic collisions do not preserve energy (Sec. 3.3): the conservation
+ * projection of such a mesh keeps mass and momentum only. */
+typedef struct {
+    int N;
+    double L;
+    double lambda;
+    int core_r2;         /* as for bz_grid_init_ex */
+    double beta;
+} bz_grid_params;
 
 /* Low-frequency FP64 core of the batched FP32 mode.
  *
@@ -126,6 +141,12 @@ bz_status bz_grid_init(int N, double L, double lambda, bz_grid *out);
  * property of the mesh: it fixes the layout of its BZ_W_BATCHED_F32 weights.
  * Errors: as bz_grid_init, and BZ_EINVAL for a core_r2 out of range. */
 bz_status bz_grid_init_ex(int N, double L, double lambda, int core_r2, bz_grid *out);
+/* The general form: bz_grid_init_ex with beta.  With beta < 1 the gain part
+ * of every weight, sinc(beta r |zeta|/2) sinc(r |xi - beta zeta/2|), no longer
+ * factors through integer norms: it is evaluated per weight slot in closed
+ * form, so beta < 1 needs lambda = 0 or 1 (BZ_EUNSUPPORTED otherwise).
+ * Errors: as bz_grid_init_ex, BZ_EINVAL for beta outside [1/2, 1] or NULL. */
+bz_status bz_grid_create(const bz_grid_params *p, bz_grid *out);
 void bz_grid_free(bz_grid g);
 bz_status bz_grid_query(bz_grid g, bz_grid_info *info);
 /* Host copies of the 1-D velocity and frequency nodes (N doubles each, either may be NULL). */

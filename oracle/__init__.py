@@ -15,8 +15,9 @@ ghat(xi, zeta, lam, L)        Sec. 2.2 eq. (GHat_calc), cut off at r0 = L, any l
 dft_forward(f, L)             Sec. 2.2 transform, sampled as in Sec. 3.2
 dft_inverse(qhat, L)          Sec. 3.2 inverse transform (real part kept)
 Oracle(N, L, lam).collide_hat Sec. 3.2 trapezoid-rule weighted convolution
-project(Qt, L)                Sec. 3.3 constrained L2 projection (sign read
+project(Qt, L, rows)          Sec. 3.3 constrained L2 projection (sign read
                               from the stated minimisation problem)
+InelasticOracle(N, L, lam, beta)  eq. (GHat_calc) with beta < 1, 4-row projection
 Oracle.rk2(f, dt, eps, steps) Sec. 3.1 Heun second-order Runge-Kutta
 moments(f, L)                 density, bulk velocity, temperature
 """
@@ -68,6 +69,11 @@ def _load():
     lib.bzo_num_threads.restype = ctypes.c_int
     lib.bzo_set_mutation.argtypes = [ctypes.c_int]
     lib.bzo_collide_hat_abs.argtypes = [ctypes.c_void_p, _dp, _dp]
+    lib.bzo_project_rows.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp, _dp, _dp]
+    lib.bzo_inel_create.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp, _dp]
+    lib.bzo_inel_create.restype = ctypes.c_void_p
+    lib.bzo_inel_free.argtypes = [ctypes.c_void_p]
+    lib.bzo_inel_collide_hat.argtypes = [ctypes.c_void_p, _dp, _dp]
     _lib = lib
     return lib
 
@@ -161,12 +167,14 @@ def dft_inverse(qhat, L: float):
     return out, mi.value
 
 
-def project(qt, L: float):
-    """Q = Qt - C^T (C C^T)^{-1} C Qt (Sec. 3.3, 5x5 Gaussian elimination)."""
+def project(qt, L: float, rows: int = 5):
+    """Q = Qt - C^T (C C^T)^{-1} C Qt (Sec. 3.3, Gaussian elimination) with the first `rows`
+    constraints: 5 (mass, momentum, energy) for elastic collisions, 4 without the energy
+    row for inelastic ones."""
     qt, N = _as_cube(qt)
     out = np.zeros_like(qt)
     lam = np.zeros(5)
-    if _load().bzo_project(N, L, _p(qt), _p(out), _p(lam)):
+    if _load().bzo_project_rows(N, L, int(rows), _p(qt), _p(out), _p(lam)):
         raise RuntimeError("singular constraint Gram matrix")
     return out
 
@@ -234,6 +242,36 @@ class Oracle:
         if _load().bzo_rk2_homogeneous(self._h, _p(f), cells, dt, eps, steps):
             raise RuntimeError("oracle rk2 failed")
         return f
+
+
+class InelasticOracle:
+    """Collision operator with the restitution factor beta of eq. (G_eqn) kept in the weights
+    of eq. (GHat_calc) (beta = 1 elastic, beta < 1 inelastic; Sec. 3.3: such collisions do
+    not preserve energy, so the projection keeps mass and momentum only)."""
+
+    def __init__(self, N: int, L: float, lam: float, beta: float, nq: int = 400):
+        self.N, self.L, self.lam, self.beta = N, float(L), float(lam), float(beta)
+        r, w = radial_rule(self.lam, self.L, nq)
+        self._h = _load().bzo_inel_create(N, self.L, self.beta, int(nq), _p(r), _p(w))
+        if not self._h:
+            raise ValueError("bad oracle parameters")
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _load().bzo_inel_free(self._h)
+            self._h = None
+
+    def collide_hat(self, fhat):
+        fhat = np.ascontiguousarray(fhat, dtype=np.complex128)
+        out = np.zeros_like(fhat)
+        _load().bzo_inel_collide_hat(self._h, fhat.ctypes.data_as(_dp), out.ctypes.data_as(_dp))
+        return out
+
+    def collide(self, f):
+        """f -> (Qt unprojected, Q projected onto mass and momentum (energy too if beta = 1))."""
+        f, N = _as_cube(f)
+        qt, _ = dft_inverse(self.collide_hat(dft_forward(f, self.L)), self.L)
+        return qt, project(qt, self.L, 5 if self.beta == 1.0 else 4)
 
 
 def moments(f, L: float):

@@ -42,7 +42,8 @@
 /* Planted-mistake switch for the pin tests (always 0 outside them):
  *   1 drop the loss term of Ghat        2 swap the roles of xi and zeta in Ghat
  *   3 wrong partner index j = k + m - N/2  4 drop dv^3 from the forward transform
- *   5 flip the sign of the projection   6 conjugate the partner fhat           */
+ *   5 flip the sign of the projection   6 conjugate the partner fhat
+ *   7 inelastic weights: drop beta from the first sinc                          */
 int bzo_mutation = 0;
 void bzo_set_mutation(int m) { bzo_mutation = m; }
 
@@ -535,61 +536,190 @@ static void constraint_row(int N, double L, size_t j, double *row)
     row[4] = (v[j1] * v[j1] + v[j2] * v[j2] + v[j3] * v[j3]) * w;
 }
 
-static int gauss_solve5(const double A_in[25], const double b_in[5], double x[5])
+/* n x n system (n <= 5), Gaussian elimination with partial pivoting. */
+static int gauss_solve(int n, const double *A_in, const double *b_in, double *x)
 {
     double A[5][6];
-    for (int i = 0; i < 5; ++i) {
-        for (int j = 0; j < 5; ++j) A[i][j] = A_in[i * 5 + j];
-        A[i][5] = b_in[i];
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n; ++j) A[i][j] = A_in[i * n + j];
+        A[i][n] = b_in[i];
     }
-    for (int col = 0; col < 5; ++col) {
+    for (int col = 0; col < n; ++col) {
         int p = col;
-        for (int r = col + 1; r < 5; ++r)
+        for (int r = col + 1; r < n; ++r)
             if (fabs(A[r][col]) > fabs(A[p][col])) p = r;
         if (A[p][col] == 0.0) return -1;
         if (p != col)
-            for (int j = 0; j < 6; ++j) { double t = A[col][j]; A[col][j] = A[p][j]; A[p][j] = t; }
-        for (int r = col + 1; r < 5; ++r) {
+            for (int j = 0; j <= n; ++j) { double t = A[col][j]; A[col][j] = A[p][j]; A[p][j] = t; }
+        for (int r = col + 1; r < n; ++r) {
             double f = A[r][col] / A[col][col];
-            for (int j = col; j < 6; ++j) A[r][j] -= f * A[col][j];
+            for (int j = col; j <= n; ++j) A[r][j] -= f * A[col][j];
         }
     }
-    for (int i = 4; i >= 0; --i) {
-        double s = A[i][5];
-        for (int j = i + 1; j < 5; ++j) s -= A[i][j] * x[j];
+    for (int i = n - 1; i >= 0; --i) {
+        double s = A[i][n];
+        for (int j = i + 1; j < n; ++j) s -= A[i][j] * x[j];
         x[i] = s / A[i][i];
     }
     return 0;
 }
 
-int bzo_project(int N, double L, const double *qt, double *q, double *lambda_out)
+/* Projection onto the first `nrows` constraints: 5 (mass, momentum, energy) for
+ * elastic collisions, 4 (mass, momentum) for inelastic ones, which do not
+ * preserve energy (Sec. 3.3). */
+int bzo_project_rows(int N, double L, int nrows, const double *qt, double *q, double *lambda_out)
 {
+    if (nrows < 1 || nrows > 5) return -1;
     size_t M = (size_t)N * N * N;
+    const int n = nrows;
     double G[25] = {0}, mu[5] = {0};
     for (size_t j = 0; j < M; ++j) {
         double r[5];
         constraint_row(N, L, j, r);
-        for (int a = 0; a < 5; ++a) {
+        for (int a = 0; a < n; ++a) {
             mu[a] += r[a] * qt[j];
-            for (int b = 0; b < 5; ++b) G[a * 5 + b] += r[a] * r[b];
+            for (int b = 0; b < n; ++b) G[a * n + b] += r[a] * r[b];
         }
     }
-    double lam[5], res[5], dl[5];
-    if (gauss_solve5(G, mu, lam)) return -1;
-    for (int a = 0; a < 5; ++a) {
+    double lam[5] = {0}, res[5], dl[5];
+    if (gauss_solve(n, G, mu, lam)) return -1;
+    for (int a = 0; a < n; ++a) {
         res[a] = mu[a];
-        for (int b = 0; b < 5; ++b) res[a] -= G[a * 5 + b] * lam[b];
+        for (int b = 0; b < n; ++b) res[a] -= G[a * n + b] * lam[b];
     }
-    if (gauss_solve5(G, res, dl)) return -1;
-    for (int a = 0; a < 5; ++a) lam[a] += dl[a];
+    if (gauss_solve(n, G, res, dl)) return -1;
+    for (int a = 0; a < n; ++a) lam[a] += dl[a];
     for (size_t j = 0; j < M; ++j) {
         double r[5];
         constraint_row(N, L, j, r);
         double s = 0.0;
-        for (int a = 0; a < 5; ++a) s += r[a] * lam[a];
+        for (int a = 0; a < n; ++a) s += r[a] * lam[a];
         q[j] = bzo_mutation == 5 ? qt[j] + s : qt[j] - s;
     }
-    if (lambda_out) memcpy(lambda_out, lam, sizeof lam);
+    if (lambda_out) memcpy(lambda_out, lam, sizeof(double) * n);
+    return 0;
+}
+
+int bzo_project(int N, double L, const double *qt, double *q, double *lambda_out)
+{
+    return bzo_project_rows(N, L, 5, qt, q, lambda_out);
+}
+
+/* ------------------------------------------------------------------ */
+/* Inelastic collisions: eq. (GHat_calc) with the factor beta of eq.    */
+/* (G_eqn) kept (beta = 1 is the elastic law; beta < 1 loses energy):   */
+/*   Ghat = 4pi (2pi)^{-3/2} int_0^L r^{lambda+2} [sinc(beta r|zeta|/2)   */
+/*          sinc(r |xi - beta zeta/2|) - sinc(r |xi|)] dr.                 */
+/* On the mesh |zeta|^2 = dzeta^2 na, |xi|^2 = dzeta^2 nc and            */
+/* |xi - beta zeta/2|^2 = dzeta^2 (nc - beta d + beta^2 na / 4) with the  */
+/* integer d = (m - N/2).(k - N/2): the gain integrals are memoised by    */
+/* (na, nc, d), computed for the triples the sum meets.                  */
+/* ------------------------------------------------------------------ */
+typedef struct bzo_inel_s {
+    int N;
+    double L, beta;
+    int nmax, dmax;
+    double *gain;   /* [(nmax+1)][(nmax+1)][2 dmax + 1], NaN where unused */
+    double *loss;   /* [nmax+1] */
+} bzo_inel;
+
+static size_t inel_idx(const bzo_inel *c, long na, long nc, long d)
+{
+    return ((size_t)na * (c->nmax + 1) + (size_t)nc) * (2 * c->dmax + 1) + (size_t)(d + c->dmax);
+}
+
+bzo_inel *bzo_inel_create(int N, double L, double beta, int n, const double *r, const double *w)
+{
+    if (N < 2 || N > 32 || (N & 1) || !(L > 0) || !(beta > 0) || n < 1) return NULL;
+    bzo_inel *c = (bzo_inel *)calloc(1, sizeof(bzo_inel));
+    int h = N / 2;
+    c->N = N; c->L = L; c->beta = beta;
+    c->nmax = 3 * h * h;
+    c->dmax = 3 * h * h;
+    size_t ng = (size_t)(c->nmax + 1) * (c->nmax + 1) * (2 * c->dmax + 1);
+    c->gain = (double *)malloc(sizeof(double) * ng);
+    c->loss = (double *)malloc(sizeof(double) * (c->nmax + 1));
+    unsigned char *used = (unsigned char *)calloc(ng, 1);
+    quad_t q;
+    if (!c->gain || !c->loss || !used || quad_init_explicit(&q, n, r, w)) return NULL;
+    /* mark the (na, nc, d) the sum meets */
+    for (int k1 = 0; k1 < N; ++k1) for (int k2 = 0; k2 < N; ++k2) for (int k3 = 0; k3 < N; ++k3) {
+        int k[3] = {k1, k2, k3};
+        long na = 0;
+        for (int e = 0; e < 3; ++e) na += (long)(k[e] - h) * (k[e] - h);
+        for (int m1 = 0; m1 < N; ++m1) for (int m2 = 0; m2 < N; ++m2) for (int m3 = 0; m3 < N; ++m3) {
+            int m[3] = {m1, m2, m3};
+            long nc = 0, d = 0;
+            int ok = 1;
+            for (int e = 0; e < 3; ++e) {
+                int j = k[e] - m[e] + h;
+                if (j < 0 || j >= N) ok = 0;
+                nc += (long)(m[e] - h) * (m[e] - h);
+                d += (long)(m[e] - h) * (k[e] - h);
+            }
+            if (ok) used[inel_idx(c, na, nc, d)] = 1;
+        }
+    }
+    double dz = BZO_PI / L;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long na = 0; na <= c->nmax; ++na)
+        for (long nc = 0; nc <= c->nmax; ++nc)
+            for (long d = -c->dmax; d <= c->dmax; ++d) {
+                size_t i = inel_idx(c, na, nc, d);
+                if (!used[i]) { c->gain[i] = NAN; continue; }
+                double xh2 = (double)nc - beta * (double)d + 0.25 * beta * beta * (double)na;
+                double xh = dz * sqrt(xh2 > 0.0 ? xh2 : 0.0);
+                double za = beta * dz * sqrt((double)na);   /* quad_gain halves it: sinc(beta r |zeta| / 2) */
+                c->gain[i] = bzo_mutation == 7 ? quad_gain(&q, dz * sqrt((double)na), xh) : quad_gain(&q, za, xh);
+            }
+    for (long nc = 0; nc <= c->nmax; ++nc) c->loss[nc] = quad_loss(&q, dz * sqrt((double)nc));
+    quad_free(&q);
+    free(used);
+    return c;
+}
+
+void bzo_inel_free(bzo_inel *c)
+{
+    if (!c) return;
+    free(c->gain); free(c->loss); free(c);
+}
+
+/* Qhat of Sec. 3.2 with the inelastic weights (same trapezoid sum as bzo_collide_hat). */
+int bzo_inel_collide_hat(const bzo_inel *c, const double *fhat, double *qhat)
+{
+    int N = c->N, h = N / 2;
+    size_t M = (size_t)N * N * N;
+    double dz = BZO_PI / c->L;
+    double w = dz * dz * dz;
+    double c0 = 4.0 * BZO_PI / pow(2.0 * BZO_PI, 1.5);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long kk = 0; kk < (long)M; ++kk) {
+        int k[3] = {(int)(kk / (N * N)), (int)((kk / N) % N), (int)(kk % N)};
+        long na = 0;
+        for (int e = 0; e < 3; ++e) na += (long)(k[e] - h) * (k[e] - h);
+        double re = 0.0, im = 0.0;
+        for (int m1 = 0; m1 < N; ++m1) for (int m2 = 0; m2 < N; ++m2) for (int m3 = 0; m3 < N; ++m3) {
+            int m[3] = {m1, m2, m3}, j[3];
+            long nc = 0, d = 0;
+            int ok = 1;
+            for (int e = 0; e < 3; ++e) {
+                j[e] = k[e] - m[e] + h;
+                if (j[e] < 0 || j[e] >= N) ok = 0;
+                nc += (long)(m[e] - h) * (m[e] - h);
+                d += (long)(m[e] - h) * (k[e] - h);
+            }
+            if (!ok) continue;
+            double G = c0 * (c->gain[inel_idx(c, na, nc, d)] - c->loss[nc]);
+            size_t im_ = ((size_t)m1 * N + m2) * N + m3;
+            size_t ij_ = ((size_t)j[0] * N + j[1]) * N + j[2];
+            double ar = fhat[2 * im_], ai = fhat[2 * im_ + 1];
+            double br = fhat[2 * ij_], bi = fhat[2 * ij_ + 1];
+            re += G * (ar * br - ai * bi);
+            im += G * (ar * bi + ai * br);
+        }
+        qhat[2 * kk] = w * re;
+        qhat[2 * kk + 1] = w * im;
+    }
     return 0;
 }
 

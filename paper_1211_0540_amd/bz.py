@@ -38,7 +38,12 @@ class BzError(RuntimeError):
 class GridInfo(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("L", ctypes.c_double), ("lambda_", ctypes.c_double),
                 ("dv", ctypes.c_double), ("dzeta", ctypes.c_double), ("pairs", ctypes.c_longlong),
-                ("core_r2", ctypes.c_int), ("core_steps", ctypes.c_longlong)]
+                ("core_r2", ctypes.c_int), ("core_steps", ctypes.c_longlong), ("beta", ctypes.c_double)]
+
+
+class GridParams(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("L", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("core_r2", ctypes.c_int), ("beta", ctypes.c_double)]
 
 
 _vp = ctypes.c_void_p
@@ -72,6 +77,7 @@ def lib():
         "bz_grid_init": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.POINTER(_vp)]),
         "bz_grid_init_ex": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                            ctypes.POINTER(_vp)]),
+        "bz_grid_create": (ctypes.c_int, [ctypes.POINTER(GridParams), ctypes.POINTER(_vp)]),
         "bz_grid_free": (None, [_vp]),
         "bz_weight_table_size": (_sz, [ctypes.c_int]),
         "bz_weight_table": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
@@ -188,6 +194,13 @@ def bz_grid_init_ex(N: int, L: float, lam: float, core_r2: int = BZ_CORE_DEFAULT
     return h.value
 
 
+def bz_grid_create(N: int, L: float, lam: float, core_r2: int = BZ_CORE_DEFAULT, beta: float = 1.0) -> int:
+    p = GridParams(int(N), float(L), float(lam), int(core_r2), float(beta))
+    h = _vp()
+    _check(lib().bz_grid_create(ctypes.byref(p), ctypes.byref(h)))
+    return h.value
+
+
 def bz_weight_table(N: int, lam: float) -> np.ndarray:
     """The universal table T_lambda(p, q) as a (3N^2/4 + 1, 3N^2 + 1) host array."""
     n = int(lib().bz_weight_table_size(int(N)))
@@ -204,7 +217,7 @@ def bz_grid_query(g: int) -> dict:
     info = GridInfo()
     _check(lib().bz_grid_query(_vp(g), ctypes.byref(info)))
     return {"N": info.N, "L": info.L, "lambda": info.lambda_, "dv": info.dv, "dzeta": info.dzeta,
-            "pairs": info.pairs, "core_r2": info.core_r2, "core_steps": info.core_steps}
+            "pairs": info.pairs, "core_r2": info.core_r2, "core_steps": info.core_steps, "beta": info.beta}
 
 
 def bz_grid_coords(g: int):
@@ -522,8 +535,9 @@ def bz_batch_core_timer(b: int):
 class Collision:
     """A batch of cells on one or more meshes with its weights and workspace.
 
-    meshes: list of (N, L, lambda) or (N, L, lambda, core_r2) (core_r2 as in
-    bz_grid_init_ex; the default core otherwise); grid_of_cell: mesh index per cell;
+    meshes: list of (N, L, lambda), (N, L, lambda, core_r2) or (N, L, lambda, core_r2, beta)
+    (core_r2 and beta as in bz_grid_create; the default core and elastic collisions
+    otherwise); grid_of_cell: mesh index per cell;
     mode: one of MODE_NAMES or BZ_MODE_*; schedule: "symmetric" (conjugate
     symmetry halves the batched sum, the default) or "full"; fine_split: work
     items sized for a single 64-cell group to fill the device (for batches of
@@ -537,7 +551,7 @@ class Collision:
         self.mode = MODE_NAMES.get(mode, mode)
         self.kind = MODE_WEIGHTS[self.mode]
         self.meshes = [tuple(m) for m in meshes]
-        self.grids = [bz_grid_init_ex(*m) for m in self.meshes]
+        self.grids = [bz_grid_create(*m) for m in self.meshes]
         self.grid_of_cell = np.asarray(grid_of_cell, dtype=np.int32)
         self.schedule = schedule
         flags = SCHEDULES[schedule] | (BZ_BATCH_FINE_SPLIT if fine_split else 0)

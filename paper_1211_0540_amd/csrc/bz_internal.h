@@ -27,6 +27,57 @@ __host__ __device__ inline int axis_hi(int N, int k) { return k + N / 2 < N - 1 
 __host__ __device__ inline int axis_cnt(int N, int k) { return axis_hi(N, k) - axis_lo(N, k) + 1; }
 
 // ---------------------------------------------------------------------------
+// T_lambda(a, b) = int_0^1 s^{lambda+2} sinc(a s) sinc(b s) ds for lambda = 0, 1
+// and real a, b >= 0 (the gain integral of eq. GHat_calc in units r = L s; with
+// inelastic collisions, beta < 1, its second argument is no longer the root of
+// an integer).  With a >= b:
+//   b >= a/2:  [F(a - b) - F(a + b)] / (2ab),  F = S (lambda 0) or U (lambda 1),
+//              S(x) = sin x / x,  U(x) = int_0^1 s cos(xs) ds = S(x) - 2 sin^2(x/2)/x^2;
+//   b <  a/2:  the same expression expanded with the addition theorems, which
+//              removes the division by b:
+//      lambda 0:  [sin a cos b - a cos a S(b)] / (a (a^2 - b^2))
+//      lambda 1:  that + [2 (cos a cos b - 1) + (a^2 + b^2) sin a S(b) / a] / (a^2 - b^2)^2;
+//   b = 0:     the one-sided limits, a = b = 0: 1 / (lambda + 3).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline double sinc_d(double x) { return x == 0.0 ? 1.0 : sin(x) / x; }
+__host__ __device__ inline double ucos_d(double x) {
+    if (x == 0.0) return 0.5;
+    const double hs = sin(0.5 * x);
+    return sin(x) / x - 2.0 * hs * hs / (x * x);
+}
+__host__ __device__ inline double T_real(int lam, double a, double b) {
+    if (a < b) {
+        const double t = a;
+        a = b;
+        b = t;
+    }
+    if (a == 0.0) return 1.0 / (lam + 3);
+    if (b == 0.0) {
+        const double sc = sin(a), cc = cos(a), hs = sin(0.5 * a);
+        if (lam == 0) return (sc - a * cc) / (a * a * a);
+        return (-cc / a + 2.0 * sc / (a * a) - 4.0 * hs * hs / (a * a * a)) / a;
+    }
+    if (b >= 0.5 * a) {
+        if (lam == 0) return (sinc_d(a - b) - sinc_d(a + b)) / (2.0 * a * b);
+        return (ucos_d(a - b) - ucos_d(a + b)) / (2.0 * a * b);
+    }
+    const double sa = sin(a), ca = cos(a), cb = cos(b), sb = sinc_d(b), d = a * a - b * b;
+    const double t0 = (sa * cb - a * ca * sb) / (a * d);
+    if (lam == 0) return t0;
+    return t0 + (2.0 * (ca * cb - 1.0) + (a * a + b * b) * sa * sb / a) / (d * d);
+}
+
+// Gain part of the weight for output k and partner m of an inelastic collision (beta):
+// T(beta pi |k - N/2| / 2, pi |2(m - N/2) - beta (k - N/2)| / 2).
+__host__ __device__ inline double gain_beta(int lam, double beta, int h, int k1, int k2, int k3, int m1, int m2,
+                                            int m3) {
+    constexpr double kHalfPi = 1.57079632679489661923;
+    const double y1 = k1 - h, y2 = k2 - h, y3 = k3 - h;
+    const double w1 = 2.0 * (m1 - h) - beta * y1, w2 = 2.0 * (m2 - h) - beta * y2, w3 = 2.0 * (m3 - h) - beta * y3;
+    return T_real(lam, beta * kHalfPi * sqrt(y1 * y1 + y2 * y2 + y3 * y3), kHalfPi * sqrt(w1 * w1 + w2 * w2 + w3 * w3));
+}
+
+// ---------------------------------------------------------------------------
 // Batched ("lane = cell") schedule.
 //
 // A work item is one output row (k1, k2, 0..N-1) of 64 cells on the same mesh.
@@ -211,9 +262,9 @@ struct Schedule {
 
 struct bz_grid_s {
     int N;
-    double L, lambda, dv, dzeta;
+    double L, lambda, beta, dv, dzeta;
     long long pairs;
-    double linv[25];  // L^{-1} with C C^T = L L^T (Cholesky), row-major
+    double linv[25];  // L^{-1} with C C^T = L L^T (Cholesky), row-major; energy row zero when beta < 1
     bz::Schedule sched;
 };
 
@@ -234,10 +285,11 @@ bz_status hip_fail(hipError_t e, const char *what);
 // ---------------------------------------------------------------------------
 // Weight expansion from the FP64 universal table T[p * qstride + q].
 // Pairs with both partners in the core ball (core_r2 >= 0) get weight 0 (they are summed in FP64).
+// beta < 1 (inelastic, lambda 0 or 1): the gain parts come from gain_beta, the loss parts from T.
 hipError_t launch_expand_cells(int N, const double *dT, int qstride, double scale, const long long *d_row_woff,
-                               void *d_w, bool f64, int core_r2, hipStream_t s);
+                               void *d_w, bool f64, int core_r2, int lam, double beta, hipStream_t s);
 hipError_t launch_expand_plain(int N, const double *dT, int qstride, double scale, const long long *d_blk_woff,
-                               void *d_w, bool f64, hipStream_t s);
+                               void *d_w, bool f64, int lam, double beta, hipStream_t s);
 
 // Forward transform of `ncells` cells of one mesh.  Cell c's f starts at
 // f + f_off[c]; fhat element k of cell c is written at out + o_base[c] + k*o_stride

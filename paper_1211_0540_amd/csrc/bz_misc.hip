@@ -207,7 +207,7 @@ __device__ inline int sq3(int a, int b, int c) { return a * a + b * b + c * c; }
 template <typename W>
 __global__ void __launch_bounds__(256) k_expand_cells(int N, const double *__restrict__ T, int qs, double scale,
                                                       const long long *__restrict__ row_woff, W *__restrict__ w,
-                                                      int core_r2) {
+                                                      int core_r2, int lam, double beta) {
     const int h = N / 2;
     const int r = blockIdx.x;
     const int k1 = r / N, k2 = r % N;
@@ -234,7 +234,16 @@ __global__ void __launch_bounds__(256) k_expand_cells(int N, const double *__res
                 const int ncj = sq3(j1 - h, j2 - h, j3 - h);
                 double v;
                 const bool diag = (m1 == j1) && (m2 == j2);
-                if (diag && m3 == j3)
+                if (beta != 1.0) {
+                    // inelastic: the gain of (k, m) and of (k, j) differ
+                    const double gm = gain_beta(lam, beta, h, k1, k2, k3, m1, m2, m3);
+                    if (diag && m3 == j3)
+                        v = gm - T[4 * ncm];
+                    else if (diag && m3 > j3)
+                        v = 0.0;
+                    else
+                        v = gm + gain_beta(lam, beta, h, k1, k2, k3, j1, j2, j3) - T[4 * ncm] - T[4 * ncj];
+                } else if (diag && m3 == j3)
                     v = T[(size_t)na * qs] - T[4 * ncm];
                 else if (diag && m3 > j3)
                     v = 0.0;
@@ -250,7 +259,8 @@ __global__ void __launch_bounds__(256) k_expand_cells(int N, const double *__res
 
 template <typename W>
 __global__ void __launch_bounds__(256) k_expand_plain(int N, const double *__restrict__ T, int qs, double scale,
-                                                      const long long *__restrict__ blk_woff, W *__restrict__ w) {
+                                                      const long long *__restrict__ blk_woff, W *__restrict__ w,
+                                                      int lam, double beta) {
     const int h = N / 2;
     const int R = plain_rows(N), NB = N / R, LN = R * N;
     const int b = blockIdx.x;
@@ -272,7 +282,8 @@ __global__ void __launch_bounds__(256) k_expand_plain(int N, const double *__res
             const int na = sq3(k1 - h, k2 - h, k3 - h);
             const int nb = sq3(m1 - j1, m2 - j2, m3 - j3);
             const int ncm = sq3(m1 - h, m2 - h, m3 - h);
-            v = T[(size_t)na * qs + nb] - T[4 * ncm];
+            const double g = beta != 1.0 ? gain_beta(lam, beta, h, k1, k2, k3, m1, m2, m3) : T[(size_t)na * qs + nb];
+            v = g - T[4 * ncm];
         }
         out[e] = (W)(scale * v);
     }
@@ -371,25 +382,25 @@ hipError_t launch_marginal_v1(int N, double dv, const double *f, double *out, hi
 }
 
 hipError_t launch_expand_cells(int N, const double *dT, int qstride, double scale, const long long *d_row_woff,
-                               void *d_w, bool f64, int core_r2, hipStream_t s) {
+                               void *d_w, bool f64, int core_r2, int lam, double beta, hipStream_t s) {
     if (f64)
         hipLaunchKernelGGL(k_expand_cells<double>, dim3(N * N), dim3(256), 0, s, N, dT, qstride, scale, d_row_woff,
-                           (double *)d_w, core_r2);
+                           (double *)d_w, core_r2, lam, beta);
     else
         hipLaunchKernelGGL(k_expand_cells<float>, dim3(N * N), dim3(256), 0, s, N, dT, qstride, scale, d_row_woff,
-                           (float *)d_w, core_r2);
+                           (float *)d_w, core_r2, lam, beta);
     return hipGetLastError();
 }
 
 hipError_t launch_expand_plain(int N, const double *dT, int qstride, double scale, const long long *d_blk_woff,
-                               void *d_w, bool f64, hipStream_t s) {
+                               void *d_w, bool f64, int lam, double beta, hipStream_t s) {
     const int nb = N * (N / plain_rows(N));
     if (f64)
         hipLaunchKernelGGL(k_expand_plain<double>, dim3(nb), dim3(256), 0, s, N, dT, qstride, scale, d_blk_woff,
-                           (double *)d_w);
+                           (double *)d_w, lam, beta);
     else
         hipLaunchKernelGGL(k_expand_plain<float>, dim3(nb), dim3(256), 0, s, N, dT, qstride, scale, d_blk_woff,
-                           (float *)d_w);
+                           (float *)d_w, lam, beta);
     return hipGetLastError();
 }
 

@@ -363,8 +363,17 @@ static void core_weights(const bz_grid_s *g, const std::vector<double> &T, int q
                         const int ncm = sq(m1 - h, m2 - h, m3 - h), ncj = sq(j1 - h, j2 - h, j3 - h);
                         if (ncm > c.r2 || ncj > c.r2) continue;
                         const int na = sq(k1 - h, k2 - h, k3 - h), nb = sq(m1 - j1, m2 - j2, m3 - j3);
-                        const double v = (diag && tm == tj) ? T[(size_t)na * qs] - T[4 * ncm]
-                                                            : 2.0 * T[(size_t)na * qs + nb] - T[4 * ncm] - T[4 * ncj];
+                        double v;
+                        if (g->beta != 1.0) {
+                            const int lam = (int)g->lambda;
+                            const double gm = gain_beta(lam, g->beta, h, k1, k2, k3, m1, m2, m3);
+                            v = (diag && tm == tj) ? gm - T[4 * ncm]
+                                                   : gm + gain_beta(lam, g->beta, h, k1, k2, k3, j1, j2, j3) -
+                                                         T[4 * ncm] - T[4 * ncj];
+                        } else {
+                            v = (diag && tm == tj) ? T[(size_t)na * qs] - T[4 * ncm]
+                                                   : 2.0 * T[(size_t)na * qs + nb] - T[4 * ncm] - T[4 * ncj];
+                        }
                         out[(size_t)st * WS + tm * S + tj] = scale * v;
                     }
             }
@@ -510,18 +519,31 @@ bz_status bz_grid_init(int N, double L, double lambda, bz_grid *out) {
 }
 
 bz_status bz_grid_init_ex(int N, double L, double lambda, int core_r2, bz_grid *out) {
+    const bz_grid_params p{N, L, lambda, core_r2, 1.0};
+    return bz_grid_create(&p, out);
+}
+
+bz_status bz_grid_create(const bz_grid_params *prm, bz_grid *out) {
     if (!out) return fail(BZ_EINVAL, "bz_grid_init: out is NULL");
+    if (!prm) return fail(BZ_EINVAL, "bz_grid_init: NULL parameters");
+    const int N = prm->N, core_r2 = prm->core_r2;
+    const double L = prm->L, lambda = prm->lambda, beta = prm->beta;
     *out = nullptr;
     if (N < kMinN || N > kMaxN || (N % 4) != 0)
         return fail(BZ_EINVAL, "bz_grid_init: N must be a multiple of 4 in [8, 32]");
     if (!(L > 0) || !std::isfinite(L)) return fail(BZ_EINVAL, "bz_grid_init: L must be positive and finite");
     if (!(lambda > -3.0 && lambda <= 1.0))
         return fail(BZ_EUNSUPPORTED, "bz_grid_init: lambda must lie in (-3, 1]");
+    if (!(beta >= 0.5 && beta <= 1.0))
+        return fail(BZ_EINVAL, "bz_grid_init: beta must lie in [1/2, 1] (restitution 2 beta - 1 in [0, 1])");
+    if (beta != 1.0 && !(lambda == 0.0 || lambda == 1.0))
+        return fail(BZ_EUNSUPPORTED, "bz_grid_init: inelastic collisions need lambda = 0 or 1");
     bz_grid_s *g = new (std::nothrow) bz_grid_s();
     if (!g) return fail(BZ_ENOMEM, "bz_grid_init: allocation failed");
     g->N = N;
     g->L = L;
     g->lambda = lambda;
+    g->beta = beta;
     g->dv = 2.0 * L / N;
     g->dzeta = kPi / L;
     const long long a = 3LL * N * N / 4;
@@ -530,6 +552,11 @@ bz_status bz_grid_init_ex(int N, double L, double lambda, int core_r2, bz_grid *
         delete g;
         return fail(BZ_EINVAL, "bz_grid_init: constraint Gram matrix not positive definite");
     }
+    // inelastic collisions do not preserve energy (Sec. 3.3): the leading 4 x 4 block of the
+    // Cholesky factor is that of the mass and momentum rows alone, so zeroing the energy row of
+    // L^{-1} leaves the projection onto those four constraints
+    if (beta != 1.0)
+        for (int j = 0; j < 5; ++j) g->linv[4 * 5 + j] = 0.0;
     build_schedules(g);
     // core ball: the default is |zeta| < pi, i.e. nc < L^2 in index units, kept inside the
     // interior of the mesh (r <= N/2 - 1) and within the kernel's largest half-width
@@ -556,6 +583,7 @@ bz_status bz_grid_query(bz_grid g, bz_grid_info *info) {
     info->dzeta = g->dzeta;
     info->pairs = g->pairs;
     info->core_r2 = g->sched.core.r2 < 1 ? 0 : g->sched.core.r2;
+    info->beta = g->beta;
     info->core_steps = g->sched.core.nsteps;
     return BZ_OK;
 }
@@ -628,8 +656,9 @@ bz_status bz_weights(bz_grid g, int kind, void *d_w, size_t bytes, void *stream)
     // the FP32 stream leaves the pairs of the low-frequency core to the FP64 core stream
     const bool core = kind == BZ_W_BATCHED_F32 && core_stream_bytes(g) > 0;
     if (e == hipSuccess)
-        e = cells ? launch_expand_cells(g->N, dT, qs, weight_scale(g), dOff, d_w, f64, core ? g->sched.core.r2 : -1, s)
-                  : launch_expand_plain(g->N, dT, qs, weight_scale(g), dOff, d_w, f64, s);
+        e = cells ? launch_expand_cells(g->N, dT, qs, weight_scale(g), dOff, d_w, f64, core ? g->sched.core.r2 : -1,
+                                        (int)g->lambda, g->beta, s)
+                  : launch_expand_plain(g->N, dT, qs, weight_scale(g), dOff, d_w, f64, (int)g->lambda, g->beta, s);
     std::vector<double> cw;
     if (e == hipSuccess && core) {
         core_weights(g, T, qs, weight_scale(g), cw);

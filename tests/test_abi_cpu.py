@@ -232,3 +232,13 @@ def test_lambda_range():
     g = bz.bz_grid_init(16, 6.0, -1.5)
     assert bz.bz_grid_query(g)["lambda"] == -1.5
     bz.bz_grid_free(g)
+
+
+def test_inelastic_grid_parameters():
+    g = bz.bz_grid_create(16, 6.0, 1.0, bz.BZ_CORE_DEFAULT, 0.8)
+    assert bz.bz_grid_query(g)["beta"] == 0.8
+    bz.bz_grid_free(g)
+    for lam, beta, st in [(1.0, 0.4, bz.BZ_EINVAL), (1.0, 1.2, bz.BZ_EINVAL), (0.5, 0.8, bz.BZ_EUNSUPPORTED)]:
+        with pytest.raises(bz.BzError) as e:
+            bz.bz_grid_create(16, 6.0, lam, bz.BZ_CORE_DEFAULT, beta)
+        assert e.value.status == st

@@ -467,3 +467,33 @@ def test_general_lambda_shock_mesh_fp64(dev):
     for i in range(3):
         qt_o, _, _, _ = o.collide(cells[i])
         assert max_rel(qts[i], qt_o) < 1e-12, i
+
+
+# ---------------------------------------------------------------------------
+# Inelastic collisions (beta < 1 in eq. GHat_calc; mass and momentum projection)
+# ---------------------------------------------------------------------------
+_INEL = {}
+
+
+@pytest.mark.parametrize("lam", [0.0, 1.0])
+@pytest.mark.parametrize("mode", ["batched_f64", "plain_f64", "batched_f32"])
+def test_inelastic_matches_oracle(dev, lam, mode):
+    N, L, beta = 12, 5.0, 0.8
+    n = 2 if mode == "plain_f64" else 66
+    cells = list(W.random_smooth_cells(n, N, L, seed=70 + int(lam), umax=1.0))
+    qts, qs = run([(N, L, lam, bz.BZ_CORE_DEFAULT, beta)], [0] * n, cells, mode, dev)
+    key = (N, L, lam, beta)
+    if key not in _INEL:
+        _INEL[key] = O.InelasticOracle(N, L, lam, beta)
+    o = _INEL[key]
+    C = constraints(N, L)
+    for i in sorted({0, n // 2, n - 1}):
+        qt_o, q_o = o.collide(cells[i])
+        if mode == "batched_f32":
+            assert rel_l2(qs[i], q_o) < TOL32, i
+        else:
+            assert max_rel(qts[i], qt_o) < 1e-12, i
+            assert max_rel(qs[i], q_o) < 1e-12, i
+        for a in range(4):   # mass and momentum, not energy
+            assert abs((C[a] * qs[i]).sum()) <= 1e-12 * np.abs(C[a] * qs[i]).sum()
+        assert abs((C[4] * qs[i]).sum()) > 1e-6 * np.abs(C[4] * qs[i]).sum()

@@ -473,3 +473,50 @@ def test_planted_mistake_is_caught(mutation):
         assert not _pins_pass()
     finally:
         O.set_mutation(0)
+
+
+# ----------------------------------------------------------------------------
+# Inelastic collisions: beta < 1 in eq. (G_eqn) / (GHat_calc), energy row dropped
+# ----------------------------------------------------------------------------
+def _energy_rate(q, N, L):
+    v, _, dv, _ = O.grid(N, L)
+    V = np.meshgrid(v, v, v, indexing="ij")
+    return ((V[0] ** 2 + V[1] ** 2 + V[2] ** 2) * q).sum() * dv ** 3
+
+
+@pytest.mark.parametrize("beta", [0.8, 0.6])
+def test_inelastic_maxwell_molecule_cooling_rate(beta):
+    """Maxwell molecules, b = 1/4pi, v' = v + (beta/2)(|u| sigma - u): averaging |v'|^2 - |v|^2
+    over sigma gives -beta v.u + beta^2 |u|^2 / 2, and the double integral of |u|^2 f f* is
+    6 rho^2 T, so d/dt int |v|^2 f = -3 beta (1 - beta) rho^2 T (Haff cooling; zero when
+    beta = 1).  Mass and momentum stay conserved after the 4-row projection."""
+    N, L = 16, 8.0
+    f = W.maxwellian(N, L, 1.2, (0.3, 0.0, 0.0), 1.0)
+    rho, u, T, _ = O.moments(f, L)
+    qt, q = O.InelasticOracle(N, L, 0.0, beta).collide(f)
+    assert _energy_rate(q, N, L) == pytest.approx(-3 * beta * (1 - beta) * rho ** 2 * T, rel=2e-3)
+    C = _constraints(N, L)
+    for a in range(4):
+        assert abs(C[a] @ q.ravel()) <= 1e-12 * (np.abs(C[a]) @ np.abs(q.ravel()))
+
+
+def test_inelastic_oracle_at_beta_one_is_the_elastic_oracle():
+    N, L = 12, 5.0
+    f = _smooth_random(N, L, 31)
+    qt1, q1 = O.InelasticOracle(N, L, 1.0, 1.0).collide(f)
+    qte, qe, _, _ = O.Oracle(N, L, 1.0).collide(f)
+    assert np.max(np.abs(qt1 - qte)) < 1e-12 * np.max(np.abs(qte))
+    assert np.max(np.abs(q1 - qe)) < 1e-12 * np.max(np.abs(qe))
+
+
+def test_planted_inelastic_mistake_is_caught():
+    """beta dropped from the first sinc (|zeta|/2 instead of beta |zeta|/2) fails the cooling rate."""
+    N, L, beta = 16, 8.0, 0.8
+    f = W.maxwellian(N, L, 1.2, (0.3, 0.0, 0.0), 1.0)
+    rho, u, T, _ = O.moments(f, L)
+    O.set_mutation(7)
+    try:
+        _, q = O.InelasticOracle(N, L, 0.0, beta).collide(f)
+    finally:
+        O.set_mutation(0)
+    assert abs(_energy_rate(q, N, L) / (-3 * beta * (1 - beta) * rho ** 2 * T) - 1) > 0.05
