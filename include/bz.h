@@ -211,6 +211,13 @@ bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids,
  *                      up to rounding as the full sum; about 0.61 / 0.65 / 0.71
  *                      of its work at N = 32 / 24 / 16.
  *   BZ_BATCH_FULL_SUM  every output row is summed directly.
+ *   BZ_BATCH_PER_MESH  (BZ_MODE_BATCHED_F32 with two to four meshes) one
+ *                      convolution launch per mesh with its autotuned variant.
+ *                      By default the work items of all meshes share one
+ *                      persistent launch and one queue ordered by cost, each
+ *                      item naming its mesh (the variant with FOLD 16 and four
+ *                      interleaved partials for every mesh); the transforms
+ *                      stay one launch per mesh and pass.
  *   BZ_BATCH_FINE_SPLIT  cut the rows into work items small enough for the
  *                      rows of a single 64-cell group to fill the device (by
  *                      default the whole batch is counted; at most 6 pieces
@@ -222,6 +229,7 @@ bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids,
  * Errors: as bz_batch_create, and BZ_EINVAL for unknown flags. */
 #define BZ_BATCH_FULL_SUM 1
 #define BZ_BATCH_FINE_SPLIT 2
+#define BZ_BATCH_PER_MESH 4
 bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_grids, const bz_grid *grids,
                              int mode, int flags, bz_batch *out);
 void bz_batch_free(bz_batch b);

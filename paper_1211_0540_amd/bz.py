@@ -21,6 +21,7 @@ BZ_MODE_PLAIN_F64, BZ_MODE_BATCHED_F32, BZ_MODE_BATCHED_F64, BZ_MODE_PLAIN_F32 =
 BZ_CORE_DEFAULT, BZ_CORE_OFF = -1, -2
 BZ_BATCH_FULL_SUM = 1
 BZ_BATCH_FINE_SPLIT = 2
+BZ_BATCH_PER_MESH = 4
 SCHEDULES = {"symmetric": 0, "full": BZ_BATCH_FULL_SUM}
 
 MODE_WEIGHTS = {BZ_MODE_PLAIN_F64: BZ_W_PLAIN_F64, BZ_MODE_BATCHED_F32: BZ_W_BATCHED_F32,
@@ -546,7 +547,7 @@ class Collision:
     """
 
     def __init__(self, meshes, grid_of_cell, mode="batched_f32", weights_cache=None, device="cuda",
-                 schedule="symmetric", fine_split=False):
+                 schedule="symmetric", fine_split=False, per_mesh=False):
         import torch
         self.mode = MODE_NAMES.get(mode, mode)
         self.kind = MODE_WEIGHTS[self.mode]
@@ -554,7 +555,7 @@ class Collision:
         self.grids = [bz_grid_create(*m) for m in self.meshes]
         self.grid_of_cell = np.asarray(grid_of_cell, dtype=np.int32)
         self.schedule = schedule
-        flags = SCHEDULES[schedule] | (BZ_BATCH_FINE_SPLIT if fine_split else 0)
+        flags = SCHEDULES[schedule] | (BZ_BATCH_FINE_SPLIT if fine_split else 0) | (BZ_BATCH_PER_MESH if per_mesh else 0)
         self.batch = bz_batch_create_ex(self.grid_of_cell, self.grids, self.mode, flags)
         cache = weights_cache if weights_cache is not None else {}
         self.weights = []

@@ -160,145 +160,196 @@ __device__ inline int pop_item(unsigned *counter) {
 }
 
 // ---------------------------------------------------------------------------
-// Batched FP32 with compensated accumulation.
+// Batched FP32 with compensated accumulation.  One work item: the body is
+// shared by the one-mesh kernel and by the kernel whose queue holds the items
+// of several meshes (an item names its mesh; N is wavefront-uniform).
 // ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) float lds_float;
+
+template <int N, int FOLD, int COMP, int WP, int RP, int SPLIT>
+__device__ __forceinline__ void cells_f32_item(const float2 *__restrict__ fh, double2 *__restrict__ qh,
+                                               const unsigned char *__restrict__ skip, const ConvPass &cp,
+                                               const int4 item, lds_char *const wl, lds_char *const rl) {
+    constexpr int h = N / 2, M = N * N * N, PS = 3 * N * N / 4;
+    constexpr int CH = (PS * 4 + 1023) / 1024;       // KiB per step of weights
+    constexpr int RCH = N * kWave * 8 / 1024;        // KiB per fhat row of 64 cells
+    const int lane = threadIdx.x;
+    const int g = item.x, r = item.y & 0xffff, part = (item.y >> 16) & 0xf, s0 = item.z, s1 = item.w;
+    const int k1 = r / N, k2 = r - k1 * N;
+    double2 *const out = qh + cp.out_off + part * cp.pstride + g * cp.gstride + (size_t)(r - cp.row0) * N * kWave + lane;
+    if (skip && skip[g]) {
+        // every cell of the group is served elsewhere: leave zeros in this item's outputs
+#pragma unroll
+        for (int t = 0; t < N; ++t) out[t * kWave] = make_double2(0.0, 0.0);
+        return;
+    }
+    const float *w = (const float *)cp.w + cp.row_woff[r] + (long long)s0 * PS;
+    const float2 *G = fh + cp.fh_off + (size_t)g * M * kWave;   // this group's fhat (copy of the pass)
+    const float2 *F = G + lane;
+    const lds_float *const rbuf = (const lds_float *)rl;   // rows as (re, im) float pairs
+
+    float pr[N], pi[N];
+    float hr[N], hi[N], lr[N], li[N];
+    double dr[N], di[N];
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
+        pr[t] = pi[t] = 0.f;
+        if (COMP == 1) hr[t] = hi[t] = lr[t] = li[t] = 0.f;
+        else if (COMP == 0) dr[t] = di[t] = 0.0;
+    }
+    bool first = true;
+    auto fold = [&]() {
+        if (COMP == 2) {
+            // the FP64 total lives in this item's own output slot (no other item writes it)
+#pragma unroll
+            for (int t = 0; t < N; ++t) {
+                double2 o = make_double2(0.0, 0.0);
+                if (!first) o = out[t * kWave];
+                o.x += (double)pr[t];
+                o.y += (double)pi[t];
+                out[t * kWave] = o;
+                pr[t] = pi[t] = 0.f;
+            }
+            first = false;
+            return;
+        }
+#pragma unroll
+        for (int t = 0; t < N; ++t) {
+            if (COMP == 1) {
+                two_sum_acc(hr[t], lr[t], pr[t]);
+                two_sum_acc(hi[t], li[t], pi[t]);
+            } else {
+                dr[t] += (double)pr[t];
+                di[t] += (double)pi[t];
+            }
+            pr[t] = pi[t] = 0.f;
+        }
+    };
+    // rows of step (m1, m2): fhat(m1, m2, .) and fhat(j1, j2, .) of the 64 cells, N/2 KiB each
+    auto prefetch_rows = [&](int a1, int a2) {
+        prefetch_weights<RCH>(G + (size_t)((a1 * N + a2) * N) * kWave, rl);
+        prefetch_weights<RCH>(G + (size_t)(((k1 + h - a1) * N + (k2 + h - a2)) * N) * kWave, rl + RCH * 1024);
+    };
+
+    int m1, m2;
+    seek_step<N>(k1, k2, s0, m1, m2);
+    const int lo2 = axis_lo(N, k2);
+    prefetch_weights<CH>(w, wl);
+    if (RP && s0 < s1) prefetch_rows(m1, m2);
+    __builtin_amdgcn_s_waitcnt(0);
+    int buf = 0, nst = 0;
+    for (int s = s0; s < s1; ++s) {
+        const int j1 = k1 + h - m1, j2 = k2 + h - m2;
+        // on a plane-zeroed copy a step with m2 = 0 or j2 = 0 has only zero products
+        const bool live = !cp.zero_planes || (m2 != 0 && j2 != 0);
+        // (m1, m2) of the next step in the row's order
+        int n1 = m1, n2 = m2 + 1;
+        if (n2 > cells_m2_last(N, k1, k2, m1)) {
+            ++n1;
+            n2 = lo2;
+        }
+        float2 mv[N], jv[N];
+        if (RP) {
+#pragma unroll
+            for (int t = 0; t < N; ++t) {
+                const int a = 2 * (t * kWave + lane), b = 2 * (N * kWave + t * kWave + lane);
+                mv[t] = make_float2(rbuf[a], rbuf[a + 1]);
+                jv[t] = make_float2(rbuf[b], rbuf[b + 1]);
+            }
+            __builtin_amdgcn_s_waitcnt(0);        // rows are in registers: the buffer is free
+            if (s + 1 < s1) prefetch_rows(n1, n2);
+        } else {
+            load_row<float, N>(F + (size_t)((m1 * N + m2) * N) * kWave, mv);
+            load_row<float, N>(F + (size_t)((j1 * N + j2) * N) * kWave, jv);
+        }
+        if (WP == 0) {
+            // next step's weights into the other LDS half; this step reads its half
+            prefetch_weights<CH>(w + PS, wl + (buf ^ 1) * CH * 1024);
+            if (live) cells_step<float, N, SPLIT>(mv, jv, (const lds_float *)(wl + buf * CH * 1024), pr, pi);
+        } else if (WP == 1) {
+            // next step's weights pulled into L2 (the LDS copy is discarded); this
+            // step's weights, pulled last step, are read through the scalar cache
+            prefetch_weights<CH>(w + PS, wl + CH * 1024);
+            if (live)
+                cells_step<float, N, SPLIT>(mv, jv, (const __attribute__((address_space(4))) float *)w, pr, pi);
+        } else {
+            // as 1, but the weights are read by uniform-address vector loads
+            prefetch_weights<CH>(w + PS, wl + CH * 1024);
+            if (live) cells_step<float, N, SPLIT>(mv, jv, w, pr, pi);
+        }
+        w += PS;
+        buf ^= 1;
+        if (++nst == FOLD) {
+            fold();
+            nst = 0;
+        }
+        m1 = n1;
+        m2 = n2;
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+    fold();
+    if (COMP == 2) return;
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
+        if (COMP == 1)
+            out[t * kWave] = make_double2((double)hr[t] + (double)lr[t], (double)hi[t] + (double)li[t]);
+        else
+            out[t * kWave] = make_double2(dr[t], di[t]);
+    }
+}
+
 template <int N, int FOLD, int COMP, int WP, int RP, int SPLIT>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(COMP == 2 ? 2 : 1)))
 k_conv_cells_f32(const float2 *__restrict__ fh, const int4 *__restrict__ items, int n_items,
                  unsigned *__restrict__ counter, double2 *__restrict__ qh,
                  const unsigned char *__restrict__ skip, const ConvPasses ps) {
-    constexpr int h = N / 2, M = N * N * N, PS = 3 * N * N / 4;
-    constexpr int CH = (PS * 4 + 1023) / 1024;       // KiB per step of weights
-    constexpr int RCH = N * kWave * 8 / 1024;        // KiB per fhat row of 64 cells
+    constexpr int PS = 3 * N * N / 4;
+    constexpr int CH = (PS * 4 + 1023) / 1024;
     __shared__ __attribute__((aligned(16))) float wbuf[2][CH * 256];
     __shared__ __attribute__((aligned(16))) float2 rbuf[RP ? 2 * N * kWave : 2];
     lds_char *const wl = lds_ptr(&wbuf[0][0]);
     lds_char *const rl = lds_ptr(&rbuf[0]);
-    const int lane = threadIdx.x;
     for (;;) {
         const int it = pop_item(counter);
         if (it >= n_items) break;
         const int4 item = items[it];
-        const int g = item.x, r = item.y & 0xffff, part = (item.y >> 16) & 0xf, s0 = item.z, s1 = item.w;
-        const ConvPass cp = pick_pass(ps, item.y >> 20);
-        const int k1 = r / N, k2 = r - k1 * N;
-        double2 *const out = qh + cp.out_off + part * cp.pstride + g * cp.gstride + (size_t)(r - cp.row0) * N * kWave + lane;
-        if (skip && skip[g]) {
-            // every cell of the group is served elsewhere: leave zeros in this item's outputs
-#pragma unroll
-            for (int t = 0; t < N; ++t) out[t * kWave] = make_double2(0.0, 0.0);
-            continue;
-        }
-        const float *w = (const float *)cp.w + cp.row_woff[r] + (long long)s0 * PS;
-        const float2 *G = fh + cp.fh_off + (size_t)g * M * kWave;   // this group's fhat (copy of the pass)
-        const float2 *F = G + lane;
+        const ConvPass cp = pick_pass(ps, (item.y >> 20) & 0xf);
+        cells_f32_item<N, FOLD, COMP, WP, RP, SPLIT>(fh, qh, skip, cp, item, wl, rl);
+    }
+}
 
-        float pr[N], pi[N];
-        float hr[N], hi[N], lr[N], li[N];
-        double dr[N], di[N];
-#pragma unroll
-        for (int t = 0; t < N; ++t) {
-            pr[t] = pi[t] = 0.f;
-            if (COMP == 1) hr[t] = hi[t] = lr[t] = li[t] = 0.f;
-            else if (COMP == 0) dr[t] = di[t] = 0.0;
-        }
-        bool first = true;
-        auto fold = [&]() {
-            if (COMP == 2) {
-                // the FP64 total lives in this item's own output slot (no other item writes it)
-#pragma unroll
-                for (int t = 0; t < N; ++t) {
-                    double2 o = make_double2(0.0, 0.0);
-                    if (!first) o = out[t * kWave];
-                    o.x += (double)pr[t];
-                    o.y += (double)pi[t];
-                    out[t * kWave] = o;
-                    pr[t] = pi[t] = 0.f;
-                }
-                first = false;
-                return;
-            }
-#pragma unroll
-            for (int t = 0; t < N; ++t) {
-                if (COMP == 1) {
-                    two_sum_acc(hr[t], lr[t], pr[t]);
-                    two_sum_acc(hi[t], li[t], pi[t]);
-                } else {
-                    dr[t] += (double)pr[t];
-                    di[t] += (double)pi[t];
-                }
-                pr[t] = pi[t] = 0.f;
-            }
-        };
-        // rows of step (m1, m2): fhat(m1, m2, .) and fhat(j1, j2, .) of the 64 cells, N/2 KiB each
-        auto prefetch_rows = [&](int a1, int a2) {
-            prefetch_weights<RCH>(G + (size_t)((a1 * N + a2) * N) * kWave, rl);
-            prefetch_weights<RCH>(G + (size_t)(((k1 + h - a1) * N + (k2 + h - a2)) * N) * kWave, rl + RCH * 1024);
-        };
+// Items of several meshes in one persistent launch: the mesh index sits in bits 24..27
+// of the item word; its descriptor (N, buffer offsets in the workspace, one ConvPass per
+// pass) is read from a device table with wavefront-uniform loads.  Every mesh runs the
+// output-slot accumulation with FOLD 16 and four interleaved partials (tuning variant
+// 10), two wavefronts per SIMD.
+template <int N>
+__device__ __forceinline__ void multi_item(const MeshConvDesc &d, char *ws, int pass, const int4 item, lds_char *wl) {
+    const ConvPass cp = d.ps.p[pass];
+    cells_f32_item<N, 16, 2, 0, 0, 4>((const float2 *)(ws + d.fh_bytes), (double2 *)(ws + d.qh_bytes), nullptr, cp,
+                                      item, wl, nullptr);
+}
 
-        int m1, m2;
-        seek_step<N>(k1, k2, s0, m1, m2);
-        const int lo2 = axis_lo(N, k2);
-        prefetch_weights<CH>(w, wl);
-        if (RP && s0 < s1) prefetch_rows(m1, m2);
-        __builtin_amdgcn_s_waitcnt(0);
-        int buf = 0, nst = 0;
-        for (int s = s0; s < s1; ++s) {
-            const int j1 = k1 + h - m1, j2 = k2 + h - m2;
-            // on a plane-zeroed copy a step with m2 = 0 or j2 = 0 has only zero products
-            const bool live = !cp.zero_planes || (m2 != 0 && j2 != 0);
-            // (m1, m2) of the next step in the row's order
-            int n1 = m1, n2 = m2 + 1;
-            if (n2 > cells_m2_last(N, k1, k2, m1)) {
-                ++n1;
-                n2 = lo2;
-            }
-            float2 mv[N], jv[N];
-            if (RP) {
-#pragma unroll
-                for (int t = 0; t < N; ++t) {
-                    mv[t] = rbuf[t * kWave + lane];
-                    jv[t] = rbuf[N * kWave + t * kWave + lane];
-                }
-                __builtin_amdgcn_s_waitcnt(0);        // rows are in registers: the buffer is free
-                if (s + 1 < s1) prefetch_rows(n1, n2);
-            } else {
-                load_row<float, N>(F + (size_t)((m1 * N + m2) * N) * kWave, mv);
-                load_row<float, N>(F + (size_t)((j1 * N + j2) * N) * kWave, jv);
-            }
-            if (WP == 0) {
-                // next step's weights into the other LDS half; this step reads its half
-                prefetch_weights<CH>(w + PS, wl + (buf ^ 1) * CH * 1024);
-                if (live) cells_step<float, N, SPLIT>(mv, jv, (const float *)wbuf[buf], pr, pi);
-            } else if (WP == 1) {
-                // next step's weights pulled into L2 (the LDS copy is discarded); this
-                // step's weights, pulled last step, are read through the scalar cache
-                prefetch_weights<CH>(w + PS, wl + CH * 1024);
-                if (live)
-                    cells_step<float, N, SPLIT>(mv, jv, (const __attribute__((address_space(4))) float *)w, pr, pi);
-            } else {
-                // as 1, but the weights are read by uniform-address vector loads
-                prefetch_weights<CH>(w + PS, wl + CH * 1024);
-                if (live) cells_step<float, N, SPLIT>(mv, jv, w, pr, pi);
-            }
-            w += PS;
-            buf ^= 1;
-            if (++nst == FOLD) {
-                fold();
-                nst = 0;
-            }
-            m1 = n1;
-            m2 = n2;
-            __builtin_amdgcn_s_waitcnt(0);
-        }
-        fold();
-        if (COMP == 2) continue;
-#pragma unroll
-        for (int t = 0; t < N; ++t) {
-            if (COMP == 1)
-                out[t * kWave] = make_double2((double)hr[t] + (double)lr[t], (double)hi[t] + (double)li[t]);
-            else
-                out[t * kWave] = make_double2(dr[t], di[t]);
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+k_conv_cells_f32_multi(const int4 *__restrict__ items, int n_items, unsigned *__restrict__ counter,
+                       const MeshConvDesc *__restrict__ desc, char *__restrict__ ws) {
+    // the largest step's weights (N = 32: 3 KiB), double-buffered
+    __shared__ __attribute__((aligned(16))) float wbuf[2 * 3 * 256];
+    lds_char *const wl = lds_ptr(&wbuf[0]);
+    for (;;) {
+        const int it = pop_item(counter);
+        if (it >= n_items) break;
+        const int4 item = items[it];
+        const int mi = (item.y >> 24) & 0xf, pass = (item.y >> 20) & 0xf;
+        const MeshConvDesc &d = desc[mi];
+        switch (d.N) {
+        case 8: multi_item<8>(d, ws, pass, item, wl); break;
+        case 12: multi_item<12>(d, ws, pass, item, wl); break;
+        case 16: multi_item<16>(d, ws, pass, item, wl); break;
+        case 20: multi_item<20>(d, ws, pass, item, wl); break;
+        case 24: multi_item<24>(d, ws, pass, item, wl); break;
+        case 28: multi_item<28>(d, ws, pass, item, wl); break;
+        default: multi_item<32>(d, ws, pass, item, wl); break;
         }
     }
 }
@@ -321,7 +372,7 @@ __global__ void __launch_bounds__(64) k_conv_cells_f64(const double2 *__restrict
         if (it >= n_items) break;
         const int4 item = items[it];
         const int g = item.x, r = item.y & 0xffff, part = (item.y >> 16) & 0xf, s0 = item.z, s1 = item.w;
-        const ConvPass cp = pick_pass(ps, item.y >> 20);
+        const ConvPass cp = pick_pass(ps, (item.y >> 20) & 0xf);
         const int k1 = r / N, k2 = r - k1 * N;
         double2 *const out = qh + cp.out_off + part * cp.pstride + g * cp.gstride + (size_t)(r - cp.row0) * N * kWave + lane;
         if (skip && skip[g]) {
@@ -592,6 +643,15 @@ template <int R>
 hipError_t core_launch(const CoreLaunch &p, unsigned grid, hipStream_t s) {
     hipLaunchKernelGGL(k_conv_core<R>, dim3(grid), dim3(64), 0, s, p.N, p.nD, p.cf, p.items, p.n_items, p.counter,
                        p.steps, p.w, p.out, p.skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_cells_multi(const MultiLaunch &p, hipStream_t s) {
+    if (p.n_items <= 0) return hipSuccess;
+    hipError_t e = launch_fill_u32(p.counter, 1, 0u, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_conv_cells_f32_multi, dim3(persistent_grid(p.n_items)), dim3(64), 0, s, p.items, p.n_items,
+                       p.counter, p.desc, p.ws);
     return hipGetLastError();
 }
 

@@ -357,6 +357,24 @@ struct CellsLaunch {
     const unsigned char *skip;   // device, per group: 1 = outputs not needed (may be NULL)
     ConvPasses passes;
 };
+// Batched FP32 convolution of several meshes in one persistent launch: item words carry the
+// mesh index (bits 24..27) into a device table of descriptors (uploaded when the weights are
+// bound), ordered by cost (steps x pairs per step), longest first.
+constexpr int kMaxMultiMeshes = 4;
+struct MeshConvDesc {
+    long long fh_bytes;          // fhat copies [copies][G][N^3][64] float2, offset in the workspace
+    long long qh_bytes;          // output buffers, offset in the workspace
+    int N;
+    ConvPasses ps;
+};
+struct MultiLaunch {
+    const int4 *items;
+    int n_items;
+    unsigned *counter;
+    const MeshConvDesc *desc;    // device
+    char *ws;                    // the call's workspace
+};
+hipError_t launch_conv_cells_multi(const MultiLaunch &p, hipStream_t s);
 hipError_t launch_build_e3(int N, const long long *d_row_woff, const long long *d_e3_woff, const void *w_main,
                            void *w_e3, bool f64, hipStream_t s);
 // batched FP32 variants: count, and a rank that grows with the accuracy of the

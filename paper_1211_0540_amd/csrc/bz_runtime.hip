@@ -403,6 +403,7 @@ struct Part {
     int parts = 1;                   // partial-sum buffers of pass A (and of pass Z) of the batched schedule
     int variant = 0;                 // convolution kernel variant
     std::vector<long long> f_off;    // host copy
+    std::vector<int4> h_items;       // host copy of the work items
     // FP64 low-frequency core (batched FP32 mode with a core on the mesh)
     bool core = false;
     int4 *d_core_items = nullptr;
@@ -435,6 +436,12 @@ struct bz_batch_s {
     bool timing = false;
     double core_ms = 0.0;            // FP64 core launches timed at the last bz_batch_timer_read
     int core_launches = 0;
+    // batched FP32 mode with several meshes: one convolution launch for all of them (NULL: one per mesh)
+    int4 *d_multi_items = nullptr;
+    int n_multi_items = 0;
+    bz::MeshConvDesc *d_desc = nullptr;   // per mesh, uploaded by bz_batch_set_weights
+    size_t ws_mcounter = 0;
+    bool per_mesh_now = false;       // the autotuner times each mesh's own launch
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free, ev_core_used;
     int closure_phase = 0;
     // closure: the network runs on a second stream of default priority, forked from and joined to
@@ -684,7 +691,8 @@ bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids,
 bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_grids, const bz_grid *grids, int mode,
                              int flags, bz_batch *out) {
     if (!out) return fail(BZ_EINVAL, "bz_batch_create: out is NULL");
-    if (flags & ~(BZ_BATCH_FULL_SUM | BZ_BATCH_FINE_SPLIT)) return fail(BZ_EINVAL, "bz_batch_create: unknown flags");
+    if (flags & ~(BZ_BATCH_FULL_SUM | BZ_BATCH_FINE_SPLIT | BZ_BATCH_PER_MESH))
+        return fail(BZ_EINVAL, "bz_batch_create: unknown flags");
     *out = nullptr;
     if (n_cells < 1 || !grid_of_cell || n_grids < 1 || !grids)
         return fail(BZ_EINVAL, "bz_batch_create: empty batch or NULL argument");
@@ -805,6 +813,7 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
             std::stable_sort(items.begin(), items.end(),
                              [](const int4 &x, const int4 &y) { return x.w - x.z > y.w - y.z; });
             p.n_items = (int)items.size();
+            p.h_items = items;
             o.items = put(items.data(), items.size() * sizeof(int4));
             o.e3 = put(p.g->sched.e3_woff.data(), p.g->sched.e3_woff.size() * sizeof(long long));
             const CoreSched &cs = p.g->sched.core;
@@ -866,6 +875,29 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
         const size_t sc = (bat ? (size_t)p.groups * kWave : 1) * (size_t)M * 16;
         scratch = std::max(scratch, sc);
     }
+    // one convolution launch for the items of every mesh: the mesh's index in bits 24..27, all
+    // items ordered by cost (steps x pairs per step), longest first
+    size_t o_multi = 0, o_desc = 0;
+    const bool multi = mode == BZ_MODE_BATCHED_F32 && b->parts.size() >= 2 &&
+                       b->parts.size() <= (size_t)kMaxMultiMeshes && !(flags & BZ_BATCH_PER_MESH);
+    std::vector<int4> mitems;
+    if (multi) {
+        for (size_t mi = 0; mi < b->parts.size(); ++mi)
+            for (int4 it : b->parts[mi].h_items) {
+                it.y |= (int)mi << 24;
+                mitems.push_back(it);
+            }
+        auto cost = [&](const int4 &x) {
+            const int N = b->parts[(x.y >> 24) & 0xf].g->N;
+            return (long long)(x.w - x.z) * pairs_per_step(N);
+        };
+        std::stable_sort(mitems.begin(), mitems.end(), [&](const int4 &x, const int4 &y) { return cost(x) > cost(y); });
+        o_multi = put(mitems.data(), mitems.size() * sizeof(int4));
+        std::vector<MeshConvDesc> zero(b->parts.size());
+        o_desc = put(zero.data(), zero.size() * sizeof(MeshConvDesc));
+        b->ws_mcounter = ws;
+        ws = align256(ws + 256);
+    }
     // per-cell tables of the diagnostics
     std::vector<int> cn(n_cells);
     std::vector<double> cdv(n_cells);
@@ -905,6 +937,11 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
         }
     }
     char *base = (char *)b->d_tables;
+    if (multi) {
+        b->d_multi_items = (int4 *)(base + o_multi);
+        b->n_multi_items = (int)mitems.size();
+        b->d_desc = (MeshConvDesc *)(base + o_desc);
+    }
     b->d_cell_off = (long long *)(base + o_coff);
     b->d_cell_N = (int *)(base + o_cn);
     b->d_cell_dv = (double *)(base + o_cdv);
@@ -951,6 +988,8 @@ void bz_batch_free(bz_batch b) {
     delete b;
 }
 
+static ConvPasses conv_passes(const Part &p, bool f64);
+
 bz_status bz_batch_set_weights(bz_batch b, int grid_index, int kind, const void *d_w) {
     if (!b || !d_w) return fail(BZ_EINVAL, "bz_batch_set_weights: NULL argument");
     if (grid_index < 0 || grid_index >= (int)b->grids.size())
@@ -962,6 +1001,20 @@ bz_status bz_batch_set_weights(bz_batch b, int grid_index, int kind, const void 
             p.w = d_w;
             p.wkind = kind;
         }
+    // the descriptors of the one-launch convolution, once every mesh has its weights
+    if (b->d_desc) {
+        std::vector<MeshConvDesc> d(b->parts.size());
+        for (size_t i = 0; i < b->parts.size(); ++i) {
+            const Part &p = b->parts[i];
+            if (!p.w) return BZ_OK;
+            d[i].fh_bytes = (long long)p.ws_fh;
+            d[i].qh_bytes = (long long)p.ws_qh;
+            d[i].N = p.g->N;
+            d[i].ps = conv_passes(p, false);
+        }
+        BZ_HIP(hipMemcpy(b->d_desc, d.data(), d.size() * sizeof(MeshConvDesc), hipMemcpyHostToDevice),
+               "bz_batch_set_weights: upload descriptors");
+    }
     return BZ_OK;
 }
 
@@ -1037,6 +1090,7 @@ bz_status bz_batch_autotune(bz_batch b, const double *d_f, double *d_Qt, void *d
     if (reps < 1) reps = 1;
     if (!batched(b->mode)) return BZ_OK;  // the plain schedule has no variants
     const bool was = b->timing;
+    b->per_mesh_now = true;   // each mesh's own launch is timed
     std::vector<int> saved;
     for (Part &p : b->parts) saved.push_back(p.variant);
     // time every variant for all parts at once (each part's launch is timed separately)
@@ -1067,6 +1121,7 @@ bz_status bz_batch_autotune(bz_batch b, const double *d_f, double *d_Qt, void *d
         b->ev_core_used.clear();
     }
     b->timing = was;
+    b->per_mesh_now = false;
     if (st != BZ_OK) {
         for (size_t i = 0; i < b->parts.size(); ++i) b->parts[i].variant = saved[i];
         return st;
@@ -1113,6 +1168,105 @@ bz_status bz_collide_batch(bz_batch b, const double *d_f, double *d_Qt, void *d_
     return collide_impl(b, d_f, d_Qt, d_work, work_bytes, stream, nullptr, nullptr);
 }
 
+// The five passes of a mesh's batched convolution (HermAssembly layout; the full-sum schedule
+// uses pass A only): offsets relative to the mesh's fhat copies and output buffers.
+static ConvPasses conv_passes(const Part &p, bool f64) {
+    const int N = p.g->N;
+    const long long M = (long long)N * N * N;
+    const long long pstride = (long long)p.groups * M * kWave;  // one copy of fhat, one output buffer
+    const void *w_e3 = (const char *)p.w + e3_base_bytes(p.g, f64 ? 8 : 4);
+    const long long P = p.parts, gM = M * kWave, gE = gM / 2, gZ = (long long)(N / 2) * N * kWave;
+    const long long e0 = P * pstride, z0 = e0 + 3 * (pstride / 2);
+    ConvPasses ps{};
+    ps.p[kPassA] = ConvPass{p.herm ? 3 * pstride : 0, 0, p.w, p.d_row_woff, p.herm ? 1 : 0, 0, gM, pstride};
+    ps.p[kPassE1] = ConvPass{0, e0, p.w, p.d_row_woff, 0, 0, gE, 0};
+    ps.p[kPassE2] = ConvPass{pstride, e0 + pstride / 2, p.w, p.d_row_woff, 0, 0, gE, 0};
+    ps.p[kPassE3] = ConvPass{2 * pstride, e0 + pstride, w_e3, p.d_e3_woff, 0, 0, gE, 0};
+    ps.p[kPassZ] = ConvPass{2 * pstride, z0, p.w, p.d_row_woff, 0, N / 2, gZ, pstride / (2 * N)};
+    return ps;
+}
+
+// Batched modes: forward transforms of every mesh, the FP64 cores on their own stream, the
+// convolution (one launch for all meshes, or one per mesh), then the inverse transforms.
+static bz_status collide_batched(bz_batch b, const double *d_f, double *d_Qt, char *ws, hipStream_t s,
+                                 const unsigned char *skip, const long long *slot_off) {
+    double2 *scratch = (double2 *)(ws + b->ws_scratch);
+    const bool f64 = mode_f64(b->mode);
+    const bool merged = b->d_multi_items && !b->per_mesh_now && !skip && !slot_off;
+    for (const Part &p : b->parts) {
+        const CoreSched &cs = p.g->sched.core;
+        const long long *f_off = slot_off ? slot_off : p.d_f_off;
+        // the first output buffer of the mesh serves as the second scratch buffer of the transforms
+        const CoreFill cfill{p.core ? (double2 *)(ws + p.ws_cf) : nullptr, p.d_disk_idx, cs.nD, cs.r, cs.r2};
+        BZ_HIP(launch_dft_forward_grouped(p.g->N, p.g->L, (int)p.cells.size(), d_f, f_off, scratch,
+                                          (double2 *)(ws + p.ws_qh), ws + p.ws_fh, !f64, p.herm ? 4 : 1, cfill, skip,
+                                          s),
+               "forward transform");
+    }
+    // the FP64 cores run on their own stream, alongside the FP32 convolution: they are bound by
+    // their row loads, the FP32 kernel by its arithmetic
+    bool cores = false;
+    for (const Part &p : b->parts) {
+        if (!p.core) continue;
+        hipStream_t cst = b->core_stream;
+        if (!cores) {
+            BZ_HIP(hipEventRecord(b->ev_cfork, s), "core fork");
+            BZ_HIP(hipStreamWaitEvent(cst, b->ev_cfork, 0), "core fork");
+            cores = true;
+        }
+        const CoreSched &cs = p.g->sched.core;
+        const CoreLaunch co{p.g->N, cs.r, cs.nD, (const double2 *)(ws + p.ws_cf), p.d_core_items, p.n_core_items,
+                            (unsigned *)(ws + p.ws_ccounter), p.d_core_steps,
+                            (const double *)((const char *)p.w + core_base_bytes(p.g)), (double2 *)(ws + p.ws_cq),
+                            skip, b->core_waves};
+        std::pair<hipEvent_t, hipEvent_t> ce{};
+        if (b->timing) {
+            if (!timer_pair(b, ce, true)) return fail(BZ_EDEVICE, "bz_collide_batch: hipEventCreate failed");
+            BZ_HIP(hipEventRecord(ce.first, cst), "core timer start");
+        }
+        BZ_HIP(launch_conv_core(co, cst), "FP64 core convolution");
+        if (b->timing) BZ_HIP(hipEventRecord(ce.second, cst), "core timer stop");
+    }
+    if (cores) BZ_HIP(hipEventRecord(b->ev_cjoin, b->core_stream), "core join");
+    if (merged) {
+        const MultiLaunch ml{b->d_multi_items, b->n_multi_items, (unsigned *)(ws + b->ws_mcounter), b->d_desc, ws};
+        std::pair<hipEvent_t, hipEvent_t> ev{};
+        if (b->timing) {
+            if (!timer_pair(b, ev)) return fail(BZ_EDEVICE, "bz_collide_batch: hipEventCreate failed");
+            BZ_HIP(hipEventRecord(ev.first, s), "timer start");
+        }
+        BZ_HIP(launch_conv_cells_multi(ml, s), "batched convolution (all meshes)");
+        if (b->timing) BZ_HIP(hipEventRecord(ev.second, s), "timer stop");
+    } else {
+        for (const Part &p : b->parts) {
+            CellsLaunch cl{p.g->N, ws + p.ws_fh, p.d_items, p.n_items, (unsigned *)(ws + p.ws_counter),
+                           (double2 *)(ws + p.ws_qh), p.variant, skip, conv_passes(p, f64)};
+            std::pair<hipEvent_t, hipEvent_t> ev{};
+            if (b->timing) {
+                if (!timer_pair(b, ev)) return fail(BZ_EDEVICE, "bz_collide_batch: hipEventCreate failed");
+                BZ_HIP(hipEventRecord(ev.first, s), "timer start");
+            }
+            BZ_HIP(launch_conv_cells(cl, f64, s), "batched convolution");
+            if (b->timing) BZ_HIP(hipEventRecord(ev.second, s), "timer stop");
+        }
+    }
+    if (cores) BZ_HIP(hipStreamWaitEvent(s, b->ev_cjoin, 0), "core join");
+    for (const Part &p : b->parts) {
+        const CoreSched &cs = p.g->sched.core;
+        const long long *f_off = slot_off ? slot_off : p.d_f_off;
+        const long long pstride = (long long)p.groups * p.g->N * p.g->N * p.g->N * kWave;
+        const CoreAdd cadd{p.core ? (const double2 *)(ws + p.ws_cq) : nullptr, cs.r};
+        const HermAssembly herm{p.herm, p.parts};
+        double2 *qh = (double2 *)(ws + p.ws_qh);
+        // groups whose cells are all served by the closure (skip) need no transforms: the
+        // closure writes their outputs
+        BZ_HIP(launch_dft_inverse_grouped(p.g->N, p.g->L, (int)p.cells.size(), qh, p.parts, pstride, herm, cadd,
+                                          scratch, qh, d_Qt, f_off, skip, s),
+               "inverse transform");
+    }
+    return BZ_OK;
+}
+
 // skip (device, per group of the batched modes, may be NULL): groups whose outputs are not needed.
 // slot_off (device, may be NULL): offsets of f and Qt of the cell in each slot of a one-mesh batch,
 // in place of the batch's own cell order.
@@ -1125,6 +1279,7 @@ static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void 
         if (!p.w) return fail(BZ_ESTATE, "bz_collide_batch: no weights bound for a mesh of the batch");
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)d_work;
+    if (batched(b->mode)) return collide_batched(b, d_f, d_Qt, ws, s, skip, slot_off);
     double2 *scratch = (double2 *)(ws + b->ws_scratch);
     const bool f64 = mode_f64(b->mode);
     for (const Part &p : b->parts) {
@@ -1132,77 +1287,20 @@ static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void 
         const long long M = (long long)N * N * N;
         void *fh = ws + p.ws_fh;
         double2 *qh = (double2 *)(ws + p.ws_qh);
-        if (batched(b->mode)) {
-            const int nc = (int)p.cells.size();
-            const long long *f_off = slot_off ? slot_off : p.d_f_off;
-            // the first partial buffer of qh serves as the second scratch buffer of the transforms
-            const CoreSched &cs = p.g->sched.core;
-            const CoreFill cfill{p.core ? (double2 *)(ws + p.ws_cf) : nullptr, p.d_disk_idx, cs.nD, cs.r, cs.r2};
-            BZ_HIP(launch_dft_forward_grouped(N, p.g->L, nc, d_f, f_off, scratch, qh, fh, !f64, p.herm ? 4 : 1, cfill,
-                                              skip, s),
+        const int sp = plain_split_for(N);
+        for (size_t i = 0; i < p.cells.size(); ++i) {
+            BZ_HIP(launch_dft_forward(N, p.g->L, 1, d_f, p.d_f_off + i, scratch, fh, !f64, p.d_zero, 1, s),
                    "forward transform");
-            if (p.core) {
-                // the FP64 core runs on its own stream, alongside the FP32 convolution: it is bound by
-                // its row loads, the FP32 kernel by its arithmetic
-                hipStream_t cst = b->core_stream;
-                const CoreLaunch co{N, cs.r, cs.nD, (const double2 *)(ws + p.ws_cf), p.d_core_items, p.n_core_items,
-                                    (unsigned *)(ws + p.ws_ccounter), p.d_core_steps,
-                                    (const double *)((const char *)p.w + core_base_bytes(p.g)),
-                                    (double2 *)(ws + p.ws_cq), skip, b->core_waves};
-                BZ_HIP(hipEventRecord(b->ev_cfork, s), "core fork");
-                BZ_HIP(hipStreamWaitEvent(cst, b->ev_cfork, 0), "core fork");
-                std::pair<hipEvent_t, hipEvent_t> ce{};
-                if (b->timing) {
-                    if (!timer_pair(b, ce, true)) return fail(BZ_EDEVICE, "bz_collide_batch: hipEventCreate failed");
-                    BZ_HIP(hipEventRecord(ce.first, cst), "core timer start");
-                }
-                BZ_HIP(launch_conv_core(co, cst), "FP64 core convolution");
-                if (b->timing) BZ_HIP(hipEventRecord(ce.second, cst), "core timer stop");
-                BZ_HIP(hipEventRecord(b->ev_cjoin, cst), "core join");
-            }
-            const long long pstride = (long long)p.groups * M * kWave;  // one copy of fhat, one output buffer
-            CellsLaunch cl{N, fh, p.d_items, p.n_items, (unsigned *)(ws + p.ws_counter), qh, 0, skip, {}};
-            const void *w_e3 = (const char *)p.w + e3_base_bytes(p.g, f64 ? 8 : 4);
-            // output layout as HermAssembly describes; the full schedule has pass A only
-            const long long P = p.parts, gM = M * kWave, gE = gM / 2, gZ = (long long)(N / 2) * N * kWave;
-            const long long e0 = P * pstride, z0 = e0 + 3 * (pstride / 2);
-            cl.passes.p[kPassA] = ConvPass{p.herm ? 3 * pstride : 0, 0, p.w, p.d_row_woff, p.herm ? 1 : 0, 0, gM, pstride};
-            cl.passes.p[kPassE1] = ConvPass{0, e0, p.w, p.d_row_woff, 0, 0, gE, 0};
-            cl.passes.p[kPassE2] = ConvPass{pstride, e0 + pstride / 2, p.w, p.d_row_woff, 0, 0, gE, 0};
-            cl.passes.p[kPassE3] = ConvPass{2 * pstride, e0 + pstride, w_e3, p.d_e3_woff, 0, 0, gE, 0};
-            cl.passes.p[kPassZ] = ConvPass{2 * pstride, z0, p.w, p.d_row_woff, 0, N / 2, gZ, pstride / (2 * N)};
+            PlainLaunch pl{N, fh, p.w, p.d_blk_woff, sp, qh};
             std::pair<hipEvent_t, hipEvent_t> ev{};
             if (b->timing) {
                 if (!timer_pair(b, ev)) return fail(BZ_EDEVICE, "bz_collide_batch: hipEventCreate failed");
                 BZ_HIP(hipEventRecord(ev.first, s), "timer start");
             }
-            cl.variant = p.variant;
-            BZ_HIP(launch_conv_cells(cl, f64, s), "batched convolution");
+            BZ_HIP(launch_conv_plain(pl, f64, s), "plain convolution");
             if (b->timing) BZ_HIP(hipEventRecord(ev.second, s), "timer stop");
-            CoreAdd cadd{p.core ? (const double2 *)(ws + p.ws_cq) : nullptr, cs.r};
-            if (p.core) BZ_HIP(hipStreamWaitEvent(s, b->ev_cjoin, 0), "core join");
-            const HermAssembly herm{p.herm, p.parts};
-            // groups whose cells are all served by the closure (skip) need no transforms: the
-            // closure writes their outputs
-            BZ_HIP(launch_dft_inverse_grouped(N, p.g->L, nc, qh, p.parts, pstride, herm, cadd, scratch, qh, d_Qt,
-                                              f_off, skip, s),
+            BZ_HIP(launch_dft_inverse(N, p.g->L, 1, qh, p.d_zero, 1, sp, M, scratch, d_Qt, p.d_f_off + i, s),
                    "inverse transform");
-        } else {
-            const int sp = plain_split_for(N);
-            for (size_t i = 0; i < p.cells.size(); ++i) {
-                BZ_HIP(launch_dft_forward(N, p.g->L, 1, d_f, p.d_f_off + i, scratch, fh, !f64, p.d_zero, 1, s),
-                       "forward transform");
-                PlainLaunch pl{N, fh, p.w, p.d_blk_woff, sp, qh};
-                std::pair<hipEvent_t, hipEvent_t> ev{};
-                if (b->timing) {
-                    if (!timer_pair(b, ev)) return fail(BZ_EDEVICE, "bz_collide_batch: hipEventCreate failed");
-                    BZ_HIP(hipEventRecord(ev.first, s), "timer start");
-                }
-                BZ_HIP(launch_conv_plain(pl, f64, s), "plain convolution");
-                if (b->timing) BZ_HIP(hipEventRecord(ev.second, s), "timer stop");
-                BZ_HIP(launch_dft_inverse(N, p.g->L, 1, qh, p.d_zero, 1, sp, M, scratch, d_Qt, p.d_f_off + i, s),
-                       "inverse transform");
-            }
         }
     }
     return BZ_OK;

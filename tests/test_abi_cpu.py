@@ -120,7 +120,7 @@ def test_batch_flags_are_validated():
     g = bz.bz_grid_init(8, 4.0, 1.0)
     try:
         with pytest.raises(bz.BzError) as e:
-            bz.bz_batch_create_ex([0], [g], bz.BZ_MODE_BATCHED_F32, 6)
+            bz.bz_batch_create_ex([0], [g], bz.BZ_MODE_BATCHED_F32, 8)
         assert e.value.status == bz.BZ_EINVAL
     finally:
         bz.bz_grid_free(g)

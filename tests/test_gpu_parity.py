@@ -497,3 +497,37 @@ def test_inelastic_matches_oracle(dev, lam, mode):
         for a in range(4):   # mass and momentum, not energy
             assert abs((C[a] * qs[i]).sum()) <= 1e-12 * np.abs(C[a] * qs[i]).sum()
         assert abs((C[4] * qs[i]).sum()) > 1e-6 * np.abs(C[4] * qs[i]).sum()
+
+
+# ---------------------------------------------------------------------------
+# One convolution launch for cells on several meshes
+# ---------------------------------------------------------------------------
+def test_one_launch_for_several_meshes_equals_per_mesh_launches(dev):
+    """The default batched FP32 batch on three meshes issues one convolution launch whose queue
+    holds the items of every mesh; with the per-mesh launches set to the same accumulation
+    variant the results are bitwise equal (each item's arithmetic does not depend on the
+    queue), and both match the oracle."""
+    meshes = [(16, 6.0, 1.0), (24, 7.0, 1.0), (32, 8.0, 1.0)]
+    cells = (list(W.random_smooth_cells(70, 16, 6.0, seed=80)) + list(W.random_smooth_cells(3, 24, 7.0, seed=81))
+             + list(W.random_smooth_cells(2, 32, 8.0, seed=82)))
+    goc = [0] * 70 + [1] * 3 + [2] * 2
+    merged = bz.Collision(meshes, goc, "batched_f32", weights_cache=_WCACHE)
+    per = bz.Collision(meshes, goc, "batched_f32", weights_cache=_WCACHE, per_mesh=True)
+    per.set_variant(10)
+    f = torch.from_numpy(merged.pack(cells)).to(dev)
+    bz.bz_batch_timer(merged.batch, True)
+    qa = merged.collide(f)
+    torch.cuda.synchronize()
+    _, launches = bz.bz_batch_timer_read(merged.batch)
+    assert launches == 1
+    qb = per.collide(f)
+    torch.cuda.synchronize()
+    assert torch.equal(qa, qb)
+    q = merged.unpack(merged.project(qa).cpu().numpy())
+    for i in (0, 69, 70, 72, 74):
+        N = meshes[goc[i]][0]
+        L = meshes[goc[i]][1]
+        _, q_o, _, _ = oracle_for(N, L, 1.0).collide(cells[i])
+        assert rel_l2(q[i], q_o) < TOL32, i
+    merged.close()
+    per.close()
