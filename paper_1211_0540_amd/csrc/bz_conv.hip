@@ -165,6 +165,7 @@ __device__ inline int pop_item(unsigned *counter) {
 // of several meshes (an item names its mesh; N is wavefront-uniform).
 // ---------------------------------------------------------------------------
 typedef __attribute__((address_space(3))) float lds_float;
+typedef __attribute__((address_space(3))) double lds_double;
 
 template <int N, int FOLD, int COMP, int WP, int RP, int SPLIT>
 __device__ __forceinline__ void cells_f32_item(const float2 *__restrict__ fh, double2 *__restrict__ qh,
@@ -318,11 +319,117 @@ k_conv_cells_f32(const float2 *__restrict__ fh, const int4 *__restrict__ items, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 core of the batched FP32 mode (CoreSched in bz_internal.h): the pairs
+// whose two partners lie in the low-frequency ball carry the largest terms of
+// the sum, so they are summed here in FP64 from FP64 fhat, with FP64 weights.
+// Lane = cell, like the batched kernels; an item is one output row of one
+// group.  A step loads its two rows (2R + 1 values each) and reads its
+// (2R + 1)^2 weights from LDS, copied there during the previous step.  Item
+// kinds (bits 16..17 of the row word): 2 = every output of the row
+// (k3 - N/2 in [-2R, 2R]); 0 = only k3 - N/2 in [-2R, 0] (rows whose other
+// outputs follow from conjugate symmetry); 1 = only [1, 2R].  A full row
+// loads each row value once for 2R + 1 products.
+// ---------------------------------------------------------------------------
+template <int R, int KIND>
+struct CoreOut {
+    static constexpr int lo = KIND == 1 ? 1 : -2 * R;
+    static constexpr int hi = KIND == 0 ? 0 : 2 * R;
+    static constexpr int n = hi - lo + 1;
+};
+
+template <int R, int KIND>
+__device__ __forceinline__ void core_step(const double2 *pm, const double2 *pj, const lds_double *wl,
+                                          double2 (&acc)[CoreOut<R, KIND>::n]) {
+    constexpr int S = 2 * R + 1, LO = CoreOut<R, KIND>::lo, HI = CoreOut<R, KIND>::hi;
+    double2 jr[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) jr[t] = pj[t * kWave];
+#pragma unroll
+    for (int tm = 0; tm < S; ++tm) {
+        const double2 mv = pm[tm * kWave];
+#pragma unroll
+        for (int tj = 0; tj < S; ++tj) {
+            const int e = tm + tj - 2 * R;   // k3 - N/2
+            if (e >= LO && e <= HI) {
+                const double wt = wl[tm * S + tj];
+                const double px = fma(mv.x, jr[tj].x, -(mv.y * jr[tj].y));
+                const double py = fma(mv.x, jr[tj].y, mv.y * jr[tj].x);
+                acc[e - LO].x = fma(wt, px, acc[e - LO].x);
+                acc[e - LO].y = fma(wt, py, acc[e - LO].y);
+            }
+        }
+    }
+}
+
+template <int R, int KIND>
+__device__ __forceinline__ void core_rows(int N, const double2 *G, const int *steps, const double *ws, int s0, int s1,
+                                          double2 *o, lds_char *wl) {
+    constexpr int S = 2 * R + 1, WS = core_wstride(R), CH = WS * 8 / 1024;
+    constexpr int LO = CoreOut<R, KIND>::lo, NO = CoreOut<R, KIND>::n;
+    const int h = N / 2;
+    double2 acc[NO];
+#pragma unroll
+    for (int a = 0; a < NO; ++a) acc[a] = make_double2(0.0, 0.0);
+    if (s0 < s1) prefetch_weights<CH>(ws, wl);
+    __builtin_amdgcn_s_waitcnt(0);
+    int buf = 0;
+    for (int s = s0; s < s1; ++s) {
+        const int st = steps[s];
+        const double2 *pm = G + (size_t)(st & 0xffff) * S * kWave;
+        const double2 *pj = G + (size_t)(st >> 16) * S * kWave;
+        if (s + 1 < s1) prefetch_weights<CH>(ws + WS, wl + (buf ^ 1) * WS * 8);
+        core_step<R, KIND>(pm, pj, (const lds_double *)(wl + buf * WS * 8), acc);
+        ws += WS;
+        buf ^= 1;
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+#pragma unroll
+    for (int a = 0; a < NO; ++a) {
+        const int k3 = h + LO + a;
+        if (k3 >= 0 && k3 < N) o[k3 * kWave] = acc[a];
+    }
+}
+
+// One core item: group g, output row, kind; rows of the group from cf, weights of
+// step s at w + s * core_wstride(R), outputs into out [G][N^3][64].
+template <int R>
+__device__ __forceinline__ void core_item(int N, int nD, const double2 *cf, const int *steps, const double *w,
+                                          double2 *out, const int4 item, lds_char *wl) {
+    constexpr int S = 2 * R + 1, WS = core_wstride(R);
+    const int lane = threadIdx.x;
+    const int g = item.x, row = item.y & 0xffff, kind = (item.y >> 16) & 3, s0 = item.z, s1 = item.w;
+    double2 *const o = out + ((size_t)g * N * N * N + (size_t)row * N) * kWave + lane;
+    const double2 *const G = cf + (size_t)g * nD * S * kWave + lane;
+    const double *ws = w + (size_t)s0 * WS;
+    if (kind == 2) core_rows<R, 2>(N, G, steps, ws, s0, s1, o, wl);
+    else if (kind == 0) core_rows<R, 0>(N, G, steps, ws, s0, s1, o, wl);
+    else core_rows<R, 1>(N, G, steps, ws, s0, s1, o, wl);
+}
+
+template <int R>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+k_conv_core(int N, int nD, const double2 *__restrict__ cf, const int4 *__restrict__ items, int n_items,
+            unsigned *__restrict__ counter, const int *__restrict__ steps, const double *__restrict__ w,
+            double2 *__restrict__ out, const unsigned char *__restrict__ skip) {
+    __shared__ __attribute__((aligned(16))) double wbuf[2 * core_wstride(R)];
+    lds_char *const wl = lds_ptr(&wbuf[0]);
+    for (;;) {
+        const int it = pop_item(counter);
+        if (it >= n_items) break;
+        const int4 item = items[it];
+        if (skip && skip[item.x]) continue;   // the closure serves every cell of the group
+        core_item<R>(N, nD, cf, steps, w, out, item, wl);
+    }
+}
+
 // Items of several meshes in one persistent launch: the mesh index sits in bits 24..27
 // of the item word; its descriptor (N, buffer offsets in the workspace, one ConvPass per
-// pass) is read from a device table with wavefront-uniform loads.  Every mesh runs the
-// output-slot accumulation with FOLD 16 and four interleaved partials (tuning variant
-// 10), two wavefronts per SIMD.
+// pass, its FP64 core) is read from a device table with wavefront-uniform loads.  Every
+// mesh runs the output-slot accumulation with FOLD 16 and four interleaved partials
+// (tuning variant 10), two wavefronts per SIMD.  Items with kCoreItemBit are rows of an
+// FP64 core (core_item): spread through the queue, their row loads overlap the FP32
+// arithmetic of the other wavefront on the SIMD.
 template <int N>
 __device__ __forceinline__ void multi_item(const MeshConvDesc &d, char *ws, int pass, const int4 item, lds_char *wl) {
     const ConvPass cp = d.ps.p[pass];
@@ -330,11 +437,21 @@ __device__ __forceinline__ void multi_item(const MeshConvDesc &d, char *ws, int 
                                       item, wl, nullptr);
 }
 
+template <int R>
+__device__ __forceinline__ void multi_core(const MeshConvDesc &d, char *ws, const int4 item, lds_char *wl) {
+    core_item<R>(d.N, d.nD, (const double2 *)(ws + d.cf_bytes), d.core_steps, d.core_w, (double2 *)(ws + d.cq_bytes),
+                 item, wl);
+}
+
+// LDS of the one-launch kernel: the largest FP32 step's weights (N = 32: 3 KiB) or the largest
+// core step's (r = 8: 17^2 doubles padded to 3 KiB), double-buffered
+constexpr int kMultiLdsBytes = 2 * 3 * 1024;
+static_assert(2 * core_wstride(kCoreMaxR) * 8 <= kMultiLdsBytes, "core weights exceed the one-launch LDS buffer");
+
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 k_conv_cells_f32_multi(const int4 *__restrict__ items, int n_items, unsigned *__restrict__ counter,
                        const MeshConvDesc *__restrict__ desc, char *__restrict__ ws) {
-    // the largest step's weights (N = 32: 3 KiB), double-buffered
-    __shared__ __attribute__((aligned(16))) float wbuf[2 * 3 * 256];
+    __shared__ __attribute__((aligned(16))) double wbuf[kMultiLdsBytes / 8];
     lds_char *const wl = lds_ptr(&wbuf[0]);
     for (;;) {
         const int it = pop_item(counter);
@@ -342,6 +459,20 @@ k_conv_cells_f32_multi(const int4 *__restrict__ items, int n_items, unsigned *__
         const int4 item = items[it];
         const int mi = (item.y >> 24) & 0xf, pass = (item.y >> 20) & 0xf;
         const MeshConvDesc &d = desc[mi];
+        if (item.y & kCoreItemBit) {
+            const int4 ci = make_int4(item.x, item.y & 0x3ffff, item.z, item.w);
+            switch (d.core_r) {
+            case 1: multi_core<1>(d, ws, ci, wl); break;
+            case 2: multi_core<2>(d, ws, ci, wl); break;
+            case 3: multi_core<3>(d, ws, ci, wl); break;
+            case 4: multi_core<4>(d, ws, ci, wl); break;
+            case 5: multi_core<5>(d, ws, ci, wl); break;
+            case 6: multi_core<6>(d, ws, ci, wl); break;
+            case 7: multi_core<7>(d, ws, ci, wl); break;
+            default: multi_core<8>(d, ws, ci, wl); break;
+            }
+            continue;
+        }
         switch (d.N) {
         case 8: multi_item<8>(d, ws, pass, item, wl); break;
         case 12: multi_item<12>(d, ws, pass, item, wl); break;
@@ -410,90 +541,6 @@ __global__ void __launch_bounds__(64) k_conv_cells_f64(const double2 *__restrict
         }
 #pragma unroll
         for (int t = 0; t < N; ++t) out[t * kWave] = make_double2(pr[t], pi[t]);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// FP64 core of the batched FP32 mode (CoreSched in bz_internal.h): the pairs
-// whose two partners lie in the low-frequency ball carry the largest terms of
-// the sum, so they are summed here in FP64 from FP64 fhat, with FP64 weights.
-// Lane = cell, like the batched kernels; an item is one output row of one
-// group and one half of its outputs (k3 - N/2 in [-2R, 0] or [1, 2R]), so that
-// the accumulators of half a row and the two core rows of a step fit two
-// wavefronts per SIMD.  A step loads its two rows (2R + 1 values each) and
-// reads its (2R + 1)^2 weights from LDS, copied there during the previous step.
-// ---------------------------------------------------------------------------
-template <int R, int HALF>
-__device__ __forceinline__ void core_step(const double2 (&mr)[2 * R + 1], const double2 (&jr)[2 * R + 1],
-                                          const double *wl, double2 (&acc)[2 * R + 1]) {
-    constexpr int S = 2 * R + 1;
-#pragma unroll
-    for (int tm = 0; tm < S; ++tm)
-#pragma unroll
-        for (int tj = 0; tj < S; ++tj) {
-            const int e = tm + tj - 2 * R;   // k3 - N/2
-            if ((HALF == 0 && e <= 0) || (HALF == 1 && e > 0)) {
-                const int a = HALF == 0 ? e + 2 * R : e - 1;
-                const double wt = wl[tm * S + tj];
-                const double px = fma(mr[tm].x, jr[tj].x, -(mr[tm].y * jr[tj].y));
-                const double py = fma(mr[tm].x, jr[tj].y, mr[tm].y * jr[tj].x);
-                acc[a].x = fma(wt, px, acc[a].x);
-                acc[a].y = fma(wt, py, acc[a].y);
-            }
-        }
-}
-
-template <int R>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
-k_conv_core(int N, int nD, const double2 *__restrict__ cf, const int4 *__restrict__ items, int n_items,
-            unsigned *__restrict__ counter, const int *__restrict__ steps, const double *__restrict__ w,
-            double2 *__restrict__ out, const unsigned char *__restrict__ skip) {
-    constexpr int S = 2 * R + 1, WS = core_wstride(R), CH = WS * 8 / 1024;
-    __shared__ __attribute__((aligned(16))) double wbuf[2][WS];
-    lds_char *const wl = lds_ptr(&wbuf[0][0]);
-    const int lane = threadIdx.x;
-    const int h = N / 2;
-    for (;;) {
-        const int it = pop_item(counter);
-        if (it >= n_items) break;
-        const int4 item = items[it];
-        const int g = item.x, r = item.y & 0xffff, half = item.y >> 16, s0 = item.z, s1 = item.w;
-        if (skip && skip[g]) continue;   // the closure serves every cell of the group
-        double2 *const o = out + ((size_t)g * N * N * N + (size_t)r * N) * kWave + lane;
-        const double2 *const G = cf + (size_t)g * nD * S * kWave + lane;
-        double2 acc[S];
-#pragma unroll
-        for (int a = 0; a < S; ++a) acc[a] = make_double2(0.0, 0.0);
-        const double *ws = w + (size_t)s0 * WS;
-        if (s0 < s1) prefetch_weights<CH>(ws, wl);
-        __builtin_amdgcn_s_waitcnt(0);
-        int buf = 0;
-        for (int s = s0; s < s1; ++s) {
-            const int st = steps[s];
-            const double2 *pm = G + (size_t)(st & 0xffff) * S * kWave;
-            const double2 *pj = G + (size_t)(st >> 16) * S * kWave;
-            double2 mr[S], jr[S];
-#pragma unroll
-            for (int t = 0; t < S; ++t) {
-                mr[t] = pm[t * kWave];
-                jr[t] = pj[t * kWave];
-            }
-            if (s + 1 < s1) prefetch_weights<CH>(ws + WS, wl + (buf ^ 1) * WS * 8);
-            if (half == 0) core_step<R, 0>(mr, jr, wbuf[buf], acc);
-            else core_step<R, 1>(mr, jr, wbuf[buf], acc);
-            ws += WS;
-            buf ^= 1;
-            __builtin_amdgcn_s_waitcnt(0);
-        }
-        if (half == 0) {
-#pragma unroll
-            for (int e = -2 * R; e <= 0; ++e)
-                if (h + e >= 0) o[(h + e) * kWave] = acc[e + 2 * R];
-        } else {
-#pragma unroll
-            for (int e = 1; e <= 2 * R; ++e)
-                if (h + e < N) o[(h + e) * kWave] = acc[e - 1];
-        }
     }
 }
 

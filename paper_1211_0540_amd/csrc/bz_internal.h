@@ -366,7 +366,15 @@ struct MeshConvDesc {
     long long qh_bytes;          // output buffers, offset in the workspace
     int N;
     ConvPasses ps;
+    // FP64 core of the mesh (core_r = 0: none): rows [G][nD][2r+1][64] and sums [G][N^3][64]
+    // at these workspace offsets, core steps and core weights (device)
+    long long cf_bytes, cq_bytes;
+    const int *core_steps;
+    const double *core_w;
+    int nD, core_r;
 };
+// bit 28 of an item's row word marks an FP64 core item in the one-launch queue
+constexpr int kCoreItemBit = 1 << 28;
 struct MultiLaunch {
     const int4 *items;
     int n_items;
@@ -383,8 +391,9 @@ int conv_variant_count();
 int conv_variant_accuracy_rank(int v);
 hipError_t launch_conv_cells(const CellsLaunch &p, bool f64, hipStream_t s);
 
-// FP64 core sum of one mesh (CoreSched): items (group, output row | half << 16, first step, end step),
-// longest first; half 0 owns the outputs k3 - N/2 in [-2r, 0], half 1 those in [1, 2r].
+// FP64 core sum of one mesh (CoreSched): items (group, output row | kind << 16, first step, end step),
+// longest first; kind 2 writes the outputs k3 - N/2 in [-2r, 2r], kind 0 those in [-2r, 0],
+// kind 1 those in [1, 2r].
 struct CoreLaunch {
     int N, r, nD;
     const double2 *cf;           // [G][nD][2r+1][64] FP64 core rows

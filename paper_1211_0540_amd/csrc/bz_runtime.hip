@@ -285,6 +285,9 @@ static void build_schedules(bz_grid_s *g) {
     s.plain_weights = off;
 }
 
+// Core items of the one-launch queue are spread over the first 3/5 of its FP32 items.
+constexpr size_t kCoreSpreadNum = 3, kCoreSpreadDen = 5;
+
 // Low-frequency core (CoreSched): the disk rows, and for every output row its
 // core steps, pairs of disk rows (m1, m2) <= (j1, j2) with j = k + N/2 - m.
 static void build_core(bz_grid_s *g, int r2) {
@@ -404,6 +407,7 @@ struct Part {
     int variant = 0;                 // convolution kernel variant
     std::vector<long long> f_off;    // host copy
     std::vector<int4> h_items;       // host copy of the work items
+    std::vector<int4> h_core_items;  // host copy of the FP64 core items
     // FP64 low-frequency core (batched FP32 mode with a core on the mesh)
     bool core = false;
     int4 *d_core_items = nullptr;
@@ -819,10 +823,11 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
             const CoreSched &cs = p.g->sched.core;
             p.core = mode == BZ_MODE_BATCHED_F32 && cs.r2 >= 1;
             if (p.core) {
-                // one item per (group, output row within 2r of the centre, half of the row's outputs),
-                // every such row written (rows without core steps write zeros), longest first.  The
-                // derived rows of the conjugate-symmetric schedule are conjugates of their mirrors
-                // except at k3 = 0, which the first half reaches when 2r >= N/2.
+                // one item per (group, output row within 2r of the centre), every such row written
+                // (rows without core steps write zeros), longest first.  The derived rows of the
+                // conjugate-symmetric schedule are conjugates of their mirrors except at k3 = 0, which
+                // the outputs k3 <= N/2 (item kind 0) reach when 2r >= N/2; other rows take all their
+                // outputs (kind 2).
                 std::vector<int4> ci;
                 for (int gq = 0; gq < p.groups; ++gq)
                     for (int k1 = std::max(0, h - 2 * cs.r); k1 <= std::min(N - 1, h + 2 * cs.r); ++k1)
@@ -831,11 +836,11 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
                             const int a = (int)cs.row_soff[row], e = a + cs.row_steps[row];
                             const bool derived = herm_derived_row(N, k1, k2);
                             if (derived && 2 * cs.r < h) continue;
-                            for (int half = 0; half < (derived ? 1 : 2); ++half)
-                                ci.push_back(make_int4(gq, row | (half << 16), a, e));
+                            ci.push_back(make_int4(gq, row | ((derived ? 0 : 2) << 16), a, e));
                         }
                 std::stable_sort(ci.begin(), ci.end(), [](const int4 &x, const int4 &y) { return x.w - x.z > y.w - y.z; });
                 p.n_core_items = (int)ci.size();
+                p.h_core_items = ci;
                 o.core_items = put(ci.data(), ci.size() * sizeof(int4));
                 o.core_steps = put(cs.steps.data(), cs.steps.size() * sizeof(int));
                 o.disk = put(cs.disk_idx.data(), cs.disk_idx.size() * sizeof(int));
@@ -875,23 +880,43 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
         const size_t sc = (bat ? (size_t)p.groups * kWave : 1) * (size_t)M * 16;
         scratch = std::max(scratch, sc);
     }
-    // one convolution launch for the items of every mesh: the mesh's index in bits 24..27, all
-    // items ordered by cost (steps x pairs per step), longest first
+    // one convolution launch for the items of every mesh: the mesh's index in bits 24..27, the
+    // FP32 items ordered by cost (steps x pairs per step), longest first, and the FP64 core items
+    // (kCoreItemBit) spread evenly through the first part of that order, so that at any time a
+    // few wavefronts load core rows while the others do FP32 arithmetic.  A one-mesh batch with
+    // a core takes the same launch.
     size_t o_multi = 0, o_desc = 0;
-    const bool multi = mode == BZ_MODE_BATCHED_F32 && b->parts.size() >= 2 &&
+    bool has_core = false;
+    for (const Part &p : b->parts) has_core = has_core || p.core;
+    const bool multi = mode == BZ_MODE_BATCHED_F32 && (b->parts.size() >= 2 || has_core) &&
                        b->parts.size() <= (size_t)kMaxMultiMeshes && !(flags & BZ_BATCH_PER_MESH);
     std::vector<int4> mitems;
     if (multi) {
-        for (size_t mi = 0; mi < b->parts.size(); ++mi)
+        std::vector<int4> conv, core;
+        for (size_t mi = 0; mi < b->parts.size(); ++mi) {
             for (int4 it : b->parts[mi].h_items) {
                 it.y |= (int)mi << 24;
-                mitems.push_back(it);
+                conv.push_back(it);
             }
+            for (int4 it : b->parts[mi].h_core_items) {
+                it.y |= ((int)mi << 24) | kCoreItemBit;
+                core.push_back(it);
+            }
+        }
         auto cost = [&](const int4 &x) {
             const int N = b->parts[(x.y >> 24) & 0xf].g->N;
             return (long long)(x.w - x.z) * pairs_per_step(N);
         };
-        std::stable_sort(mitems.begin(), mitems.end(), [&](const int4 &x, const int4 &y) { return cost(x) > cost(y); });
+        std::stable_sort(conv.begin(), conv.end(), [&](const int4 &x, const int4 &y) { return cost(x) > cost(y); });
+        std::stable_sort(core.begin(), core.end(), [](const int4 &x, const int4 &y) { return x.w - x.z > y.w - y.z; });
+        const size_t span = (conv.size() * kCoreSpreadNum) / kCoreSpreadDen;
+        size_t ci = 0;
+        for (size_t i = 0; i < conv.size(); ++i) {
+            // core items due before FP32 item i: ceil(i * ncore / span)
+            while (ci < core.size() && (span == 0 || ci * span < i * core.size())) mitems.push_back(core[ci++]);
+            mitems.push_back(conv[i]);
+        }
+        while (ci < core.size()) mitems.push_back(core[ci++]);
         o_multi = put(mitems.data(), mitems.size() * sizeof(int4));
         std::vector<MeshConvDesc> zero(b->parts.size());
         o_desc = put(zero.data(), zero.size() * sizeof(MeshConvDesc));
@@ -1011,6 +1036,15 @@ bz_status bz_batch_set_weights(bz_batch b, int grid_index, int kind, const void 
             d[i].qh_bytes = (long long)p.ws_qh;
             d[i].N = p.g->N;
             d[i].ps = conv_passes(p, false);
+            if (p.core) {
+                const CoreSched &cs = p.g->sched.core;
+                d[i].cf_bytes = (long long)p.ws_cf;
+                d[i].cq_bytes = (long long)p.ws_cq;
+                d[i].core_steps = p.d_core_steps;
+                d[i].core_w = (const double *)((const char *)p.w + core_base_bytes(p.g));
+                d[i].nD = cs.nD;
+                d[i].core_r = cs.r;
+            }
         }
         BZ_HIP(hipMemcpy(b->d_desc, d.data(), d.size() * sizeof(MeshConvDesc), hipMemcpyHostToDevice),
                "bz_batch_set_weights: upload descriptors");
@@ -1203,11 +1237,11 @@ static bz_status collide_batched(bz_batch b, const double *d_f, double *d_Qt, ch
                                           s),
                "forward transform");
     }
-    // the FP64 cores run on their own stream, alongside the FP32 convolution: they are bound by
-    // their row loads, the FP32 kernel by its arithmetic
+    // the FP64 cores: in the one-launch queue, or else on their own stream after the forward
+    // transforms
     bool cores = false;
     for (const Part &p : b->parts) {
-        if (!p.core) continue;
+        if (!p.core || merged) continue;   // the one-launch queue holds the core items
         hipStream_t cst = b->core_stream;
         if (!cores) {
             BZ_HIP(hipEventRecord(b->ev_cfork, s), "core fork");
