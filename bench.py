@@ -5,23 +5,25 @@ draw (perturbed Maxwellians, rho ~ U[.5,2], |u| ~ U[0,1.5], T ~ U[.5,2]).
 One bench step is one Heun (second-order Runge-Kutta) step of the space-
 homogeneous equation for every cell of the batch: two collision evaluations
 per cell (forward transform, batched FP32 convolution with compensated
-accumulation, inverse transform, FP64 projection) and the Heun updates.
+accumulation and its FP64 low-frequency core in the same persistent launch,
+inverse transform, FP64 projection) and the Heun updates.
 
 The JSON line also carries:
-  roofline      the batched convolution kernel against the FP32 vector peak
-                (its launches are timed with HIP events on the library's stream
-                inside the timed region).  `achieved` counts the algorithmic
-                10 flops per ordered pair of the full sum; the conjugate-
-                symmetric schedule processes only `slots_vs_full_sum` of the
-                full schedule's weight slots, so the rate on the work actually
-                processed is also given.
+  roofline      the convolution launch against the FP32 vector peak, timed with
+                HIP events on the library's stream inside the timed region.
+                `achieved` counts the FP32 work the launch executes: 10 flops
+                (4 FMA + 2 MUL) per weight slot the conjugate-symmetric schedule
+                visits, per cell.  The full sum's algorithmic flops over the same
+                time are reported apart as `effective_tflops` (never in `frac`);
+                so are the FP64 core's flops and the issue ceiling of the kernel's
+                instruction mix without packed FP32.
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same cells
-  comparisons   the plain unbatched FP64 path on the same GPU, the batched
-                FP64 path, the relative L2 error of the FP32 result against
-                the FP64 plain result for every cell, the accuracy-oriented
-                accumulation variants, graph replay, the full-sum schedule,
-                the N=32 relaxation, the whole uneven batch, and the gated
-                closure on the shock problem at N=24 and N=32
+  comparisons   the plain unbatched and the batched FP64 paths on the same GPU,
+                the relative L2 error of every cell against the plain FP64
+                result, the per-mesh launch, the batch without its FP64 core,
+                graph replay, the full-sum schedule, the N=32 relaxation, the
+                whole uneven batch, and the gated closure on the shock problem
+                at N=24 and N=32
 """
 import argparse
 import hashlib
@@ -34,7 +36,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "cell-collision evals/s at N=32: FP32 batched & surrogate vs FP64 plain; rel L2 err"
-PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector, published
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector, published (packed FP32: two lanes' FMAs per instruction)
+# Without packed FP32 one FMA per lane issues per 4 cycles per SIMD (78.6 TFLOP/s, half the peak);
+# the kernel's 4 FMA + 2 MUL per slot carry 10 flops in 6 instructions: 0.5 * 10 / 12 of the peak.
+ISSUE_CEILING_FRAC = 0.5 * 10.0 / 12.0
 TRAIN_STEPS = 30000        # closure training: Adam steps of 512 rows
 HBM_TBPS = 8.0
 
@@ -53,18 +58,73 @@ def conv_source_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(cells, variant):
-    """HBM bytes per launch of the batched N=32 kernel from the committed counter
-    summary, if it was taken on the current kernel source, variant and batch."""
-    p = os.path.join(ROOT, "profiles", "conv_cells_f32_n32_traffic.json")
+TRAFFIC_FILE = os.path.join("profiles", "conv_multi_n32_traffic.json")
+
+
+def measured_traffic(cells):
+    """HBM bytes per launch of the N=32 convolution launch from the committed counter
+    summary (rocprofv3 FETCH_SIZE and WRITE_SIZE passes of `bench.py --profile-run`),
+    if it was taken on the current kernel and schedule sources and the same batch."""
     try:
-        with open(p) as fh:
+        with open(os.path.join(ROOT, TRAFFIC_FILE)) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_src_sha") != conv_source_sha() or d.get("cells") != cells or d.get("variant") != variant:
+    if d.get("kernel_src_sha") != conv_source_sha() or d.get("cells") != cells:
         return None
     return d.get("traffic_bytes_per_launch")
+
+
+def core_products(N, r2):
+    """Complex products per cell and evaluation of the FP64 core (r2 = 0: none): for every
+    output row (k1, k2) within 2r of the centre, the pairs of disk rows m <= j with
+    m + j = k + N/2 (the core steps), (2r+1)^2 products each, or (r+1)(2r+1) on the derived
+    rows of the conjugate-symmetric schedule (only their outputs k3 <= N/2), which are
+    skipped when 2r < N/2."""
+    if r2 < 1:
+        return 0
+    import numpy as np
+    h = N // 2
+    r = int(np.floor(np.sqrt(r2)))
+    while (r + 1) ** 2 <= r2:
+        r += 1
+    S = 2 * r + 1
+    a = np.arange(N)
+    disk = ((a[:, None] - h) ** 2 + (a[None, :] - h) ** 2) <= r2
+    pts = np.argwhere(disk)
+    total = 0
+    for k1 in range(max(0, h - 2 * r), min(N - 1, h + 2 * r) + 1):
+        for k2 in range(max(0, h - 2 * r), min(N - 1, h + 2 * r) + 1):
+            derived = k1 >= 1 and k2 >= 1 and (k1 > h or (k1 == h and k2 > h))
+            if derived and 2 * r < h:
+                continue
+            j = np.stack([k1 + h - pts[:, 0], k2 + h - pts[:, 1]], 1)
+            ok = (j >= 0).all(1) & (j < N).all(1)
+            ok[ok] &= disk[j[ok, 0], j[ok, 1]]
+            m_le_j = (pts[:, 0] < j[:, 0]) | ((pts[:, 0] == j[:, 0]) & (pts[:, 1] <= j[:, 1]))
+            steps = int((ok & m_le_j).sum())
+            total += steps * (S * (r + 1) if derived else S * S)
+    return total
+
+
+def timed_steps(torch, step, steps):
+    """Run `steps` steps, each bracketed by HIP events on the current stream; the total
+    (first start to last stop) and the per-step times in milliseconds."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        step()
+        b.record()
+    torch.cuda.synchronize()
+    per = [a.elapsed_time(b) for a, b in ev]
+    return ev[0][0].elapsed_time(ev[-1][1]), per
+
+
+def spread(np, x):
+    x = np.asarray(x, dtype=float)
+    q1, q2, q3 = np.percentile(x, [25, 50, 75])
+    return {"median": float(q2), "iqr": float(q3 - q1), "min": float(x.min()), "max": float(x.max())}
 
 
 def schedule_slots(N, symmetric):
@@ -104,26 +164,27 @@ def schedule_slots(N, symmetric):
     return rows * 3 * N * N // 4
 
 
-def full_schedule_leg(torch, bz, N, L, lam, f0, variant, wcache, steps=3):
-    """The same step with the full-sum schedule (every output row summed directly)."""
-    c = bz.Collision([(N, L, lam)], [0] * (f0.numel() // N ** 3), "batched_f32", weights_cache=wcache,
-                     schedule="full")
-    c.set_variant(variant)
+def step_leg(torch, np, bz, meshes, gidx, f0, wcache, steps=5, per_mesh=False, schedule="symmetric",
+             autotune=False):
+    """Heun steps of one batch configuration: median step time, convolution launches per
+    evaluation and their mean time."""
+    c = bz.Collision(meshes, gidx, "batched_f32", weights_cache=wcache, per_mesh=per_mesh, schedule=schedule)
+    variants = c.autotune(f0, reps=2) if autotune else None
     f = f0.clone()
     c.step(f, 0.01)
     torch.cuda.synchronize()
     bz.bz_batch_timer_read(c.batch)
     bz.bz_batch_timer(c.batch, True)
-    a = time.perf_counter()
-    for _ in range(steps):
-        c.step(f, 0.01)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - a) / steps * 1e3
+    _, per = timed_steps(torch, lambda: c.step(f, 0.01), steps)
     bz.bz_batch_timer(c.batch, False)
     conv, k = bz.bz_batch_timer_read(c.batch)
     c.check()
+    out = {"step_ms": spread(np, per), "conv_launches_per_eval": k / (2 * steps),
+           "conv_ms_per_eval": conv / (2 * steps), "one_launch": bz.bz_batch_one_launch(c.batch)}
+    if variants is not None:
+        out["variants"] = variants
     c.close()
-    return {"ms_per_step": ms, "conv_avg_ms": conv / max(k, 1)}
+    return out
 
 
 def relaxation_leg(torch, np, bz, W):
@@ -162,39 +223,40 @@ def relaxation_leg(torch, np, bz, W):
             "fp64_plain_ms_per_step": res["plain_f64"][1], "fp32_batched_ms_per_step": res["batched_f32"][1]}
 
 
-def uneven_leg(torch, np, bz, W, steps=5):
-    """All 1024 cells of the uneven draw (N = 16, 24, 32 in one batch): autotuned
-    FP32 Heun steps, and per-mesh FP32 vs batched-FP64 errors of one evaluation."""
+def uneven_leg(torch, np, bz, W, n32_step_ms, steps=5):
+    """All 1024 cells of the uneven draw (N = 16, 24, 32 in one batch): FP32 Heun steps with
+    the one persistent launch for every mesh and core (the default) and with one launch per
+    mesh (autotuned variants); the step time against the N=32-only step of this run and
+    against the ratio of executed FP32 work; per-mesh FP32 vs batched-FP64 errors of one
+    evaluation; graph replay."""
     batch = W.uneven_batch(n_cells=1024)
     meshes = [(16, 6.0, 1.0), (24, 7.0, 1.0), (32, 8.0, 1.0)]
     gidx = [{16: 0, 24: 1, 32: 2}[int(n)] for n in batch.Ns]
-    c32 = bz.Collision(meshes, gidx, "batched_f32")
+    wc = {}
+    c32 = bz.Collision(meshes, gidx, "batched_f32", weights_cache=wc)
     f0 = torch.from_numpy(c32.pack(batch.cells)).cuda()
-    variants = c32.autotune(f0, reps=2)
     q32 = c32.project(c32.collide(f0)).cpu().numpy()
-    c64 = bz.Collision(meshes, gidx, "batched_f64")
+    c64 = bz.Collision(meshes, gidx, "batched_f64", weights_cache=wc)
     q64 = c64.project(c64.collide(f0)).cpu().numpy()
     c64.close()
     errs = {16: [], 24: [], 32: []}
     for n, x, y in zip(batch.Ns, c32.unpack(q32), c32.unpack(q64)):
         errs[int(n)].append(float(np.linalg.norm(x - y) / np.linalg.norm(y)))
-    f = f0.clone()
-    c32.step(f, 0.01)
-    torch.cuda.synchronize()
-    a = time.perf_counter()
-    for _ in range(steps):
-        c32.step(f, 0.01)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - a) / steps * 1e3
-    c32.check()
+    one = step_leg(torch, np, bz, meshes, gidx, f0, wc, steps=steps)
+    per = step_leg(torch, np, bz, meshes, gidx, f0, wc, steps=steps, per_mesh=True, autotune=True)
+    tuned = step_leg(torch, np, bz, meshes, gidx, f0, wc, steps=steps, autotune=True)
+    # executed FP32 slots: every 64-cell group of a mesh runs its schedule (idle lanes included)
+    Ns, counts = np.unique(batch.Ns, return_counts=True)
+    work = sum(schedule_slots(int(n), True) * -(-int(k) // 64) for n, k in zip(Ns, counts))
+    work32 = schedule_slots(32, True) * -(-int(counts[list(Ns).index(32)]) // 64)
     # the same step captured as one HIP graph (three meshes, all their launches) and replayed
     graph = None
     try:
+        f = f0.clone()
         gs = torch.cuda.Stream()
-        fg = f.clone()
         wg = torch.zeros_like(c32.work)
         with torch.cuda.stream(gs):
-            gh = bz.bz_graph_capture_step(c32.batch, fg, 0.01, wg, gs)
+            gh = bz.bz_graph_capture_step(c32.batch, f, 0.01, wg, gs)
         torch.cuda.synchronize()
         bz.bz_graph_launch(gh, gs)
         gs.synchronize()
@@ -209,12 +271,16 @@ def uneven_leg(torch, np, bz, W, steps=5):
     except Exception as exc:
         graph = {"error": str(exc)}
     c32.close()
+    ms = one["step_ms"]["median"]
     return {"workload": "1024 cells of the seeded uneven draw (521 N=16, 313 N=24, 190 N=32), one batch",
-            "ms_per_step": ms, "cell_evals_per_s": 2 * len(batch.Ns) / ms * 1e3, "graph_replay": graph,
-            "variants_N16_N24_N32": variants,
-            "rel_l2_fp32_vs_fp64": {str(k): {"median": float(np.median(v)), "max": float(np.max(v)),
-                                             "frac_le_1e-5": float(np.mean(np.array(v) <= 1e-5))}
-                                    for k, v in errs.items()}}
+            "ms_per_step": ms, "cell_evals_per_s": 2 * len(batch.Ns) / ms * 1e3,
+            "one_launch": one, "per_mesh_launches_autotuned": per, "autotuned_choice": tuned,
+            "step_vs_n32_only_step": ms / n32_step_ms,
+            "executed_fp32_work_vs_n32_only": work / work32,
+            "graph_replay": graph,
+            "rel_l2_fp32_vs_fp64_batched": {str(k): {"median": float(np.median(v)), "max": float(np.max(v)),
+                                                     "frac_le_1e-5": float(np.mean(np.array(v) <= 1e-5))}
+                                            for k, v in errs.items()}}
 
 
 def closure_leg(args, torch, np, bz, W, N=24, L=7.0, snapshots=600, relax_cells=512):
@@ -261,6 +327,7 @@ def closure_leg(args, torch, np, bz, W, N=24, L=7.0, snapshots=600, relax_cells=
     torch.cuda.synchronize()
     tb = time.perf_counter() - a
     st = bz.bz_closure_read_stats(cf.batch, d, work)
+    served = served_errors(torch, np, bz, cf, d, fb, work, N)
     A = fa.cpu().numpy().reshape(nx, N, N, N)
     B = fb.cpu().numpy().reshape(nx, N, N, N)
     TA = np.array([O.moments(A[j], L)[2] for j in range(nx)])
@@ -277,7 +344,35 @@ def closure_leg(args, torch, np, bz, W, N=24, L=7.0, snapshots=600, relax_cells=
             "speedup": ta / tb, "closure_cell_evals_per_s": evals / tb, "served_fraction": st["served"] / evals,
             "judged": st["judged"], "judge_failed": st["failed"],
             "judge_pass_fraction": 1.0 - st["failed"] / max(st["judged"], 1), "judge_max_rel_err": st["max_err"],
+            "served_cells_one_evaluation": served,
             "max_abs_T_profile_deviation": float(np.max(np.abs(TA - TB)))}
+
+
+def served_errors(torch, np, bz, col, desc, f, work, N):
+    """Every cell the gate serves in one evaluation of the final state, against the
+    convolution: err = |P(Q_s - Q_c)| / (|P Q_c| + floor rho |M|_2), the judge's measure,
+    with the library's FP64 projection P."""
+    n = len(col.grid_of_cell)
+    d0 = bz.ClosureDesc(desc.net, desc.d_params, desc.gate, desc.s_in, desc.s_out, 0, desc.judge_tol,
+                        desc.judge_floor)
+    state = torch.zeros(n * 10, dtype=torch.float64, device=f.device)
+    x = torch.zeros(n * N ** 3, dtype=torch.int16, device=f.device)
+    bz.bz_closure_prepare(col.batch, f, desc.gate, desc.s_in, state, x)
+    qs = torch.zeros(col.elems, dtype=torch.float64, device=f.device)
+    bz.bz_closure_collide(col.batch, d0, f, qs, work)
+    bz.bz_closure_read_stats(col.batch, d0, work)
+    qc = col.collide(f)
+    col.project(qs)
+    col.project(qc)
+    st = state.view(n, 10)
+    D = (qs - qc).view(n, -1).norm(dim=1)
+    C = qc.view(n, -1).norm(dim=1)
+    err = (D / (C + desc.judge_floor * st[:, 0] * st[:, 8]))[st[:, 6] != 0].cpu().numpy()
+    if err.size == 0:
+        return {"served": 0}
+    return {"served": int(err.size), "median": float(np.median(err)), "p90": float(np.percentile(err, 90)),
+            "max": float(err.max()), "frac_le_judge_tol": float(np.mean(err <= desc.judge_tol)),
+            "judge_tol": desc.judge_tol}
 
 
 def cpu_model():
@@ -300,10 +395,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
-    ap.add_argument("--variant", type=int, default=None,
-                    help="use this convolution variant instead of autotuning (as a profiled run of the bench needs)")
     ap.add_argument("--profile-run", action="store_true",
-                    help="timed steps only (default kernel variant, no comparisons, no CPU leg)")
+                    help="timed steps only (default launch configuration, no comparisons, no CPU leg)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -328,15 +421,10 @@ def main():
 
     wcache = {}
     col = bz.Collision([(N, L, lam)], [0] * nc, "batched_f32", weights_cache=wcache)
+    info = bz.bz_grid_query(col.grids[0])
     f0 = torch.from_numpy(col.pack(cells)).to(dev)
-    if args.variant is not None:
-        col.set_variant(args.variant)
-        variant = args.variant
-    elif args.profile_run:
-        variant = bz.bz_batch_get_variant(col.batch, 0)
-    else:
-        variant = col.autotune(f0, reps=3)[0]
-    log(f"convolution variant {variant}")
+    one_launch = bz.bz_batch_one_launch(col.batch)
+    log(f"convolution: {'one launch for the FP32 items and the FP64 core' if one_launch else 'per-mesh launch'}")
 
     # FP32 result of one evaluation (kept for the error report)
     q32 = col.collide(f0)
@@ -349,23 +437,18 @@ def main():
     torch.cuda.synchronize()
     bz.bz_batch_timer_read(col.batch)  # clear
     bz.bz_batch_timer(col.batch, True)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        col.step(f, dt_over_eps)
-    stop.record()
-    torch.cuda.synchronize()
+    total_ms, per_step = timed_steps(torch, lambda: col.step(f, dt_over_eps), args.steps)
     bz.bz_batch_timer(col.batch, False)
     col.check()
-    total_ms = start.elapsed_time(stop)
     conv_ms, conv_launches = bz.bz_batch_timer_read(col.batch)
     ms_step = total_ms / args.steps
     evals = 2 * nc * args.steps
     value = evals / (total_ms * 1e-3)
     conv_avg_ms = conv_ms / max(conv_launches, 1)
-    achieved = 10.0 * P * nc / (conv_avg_ms * 1e-3) / 1e12
+    slots = schedule_slots(N, True)           # weight slots per cell the schedule visits
+    fp32_flops = 10.0 * slots * nc
+    core_flops = 10.0 * core_products(N, info["core_r2"]) * nc
+    achieved = fp32_flops / (conv_avg_ms * 1e-3) / 1e12
     log(f"step {ms_step:.3f} ms, {value:.0f} evals/s, conv {conv_avg_ms:.3f} ms/launch ({conv_launches} launches)")
 
     # the same step captured as a HIP graph and replayed
@@ -400,7 +483,7 @@ def main():
 
     if args.profile_run:
         print(json.dumps({"profile_run": True, "ms_per_step": ms_step, "conv_avg_ms": conv_avg_ms,
-                          "cells": nc}), flush=True)
+                          "cells": nc, "kernel_src_sha": conv_source_sha()}), flush=True)
         col.close()
         return 0
 
@@ -412,48 +495,23 @@ def main():
     plain.project(q64)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    reps = 1
-    for _ in range(reps):
-        qq = plain.collide(f0)
-        plain.project(qq)
+    qq = plain.collide(f0)
+    plain.project(qq)
     torch.cuda.synchronize()
-    plain_s = (time.perf_counter() - t0) / reps
+    plain_s = time.perf_counter() - t0
     comp["plain_fp64_evals_per_s"] = nc / plain_s
-    a = q32.cpu().numpy()
     b64 = q64.cpu().numpy()
-    errs = [float(np.linalg.norm(x - y) / np.linalg.norm(y)) for x, y in zip(col.unpack(a), plain.unpack(b64))]
-    comp["rel_l2_fp32_batched_vs_fp64_plain"] = {"median": float(np.median(errs)), "max": float(np.max(errs)),
-                                                 "frac_le_1e-5": float(np.mean(np.array(errs) <= 1e-5)),
-                                                 "cells": nc}
-    # the accumulation variants that fold into the FP64 total more often: accuracy against speed
-    acc = {}
-    for v in (14, 15):
-        try:
-            col.set_variant(v)
-            qv = col.project(col.collide(f0))
-            fv = f0.clone()
-            col.step(fv, dt_over_eps)
-            torch.cuda.synchronize()
-            bz.bz_batch_timer_read(col.batch)
-            bz.bz_batch_timer(col.batch, True)
-            t0 = time.perf_counter()
-            for _ in range(3):
-                col.step(fv, dt_over_eps)
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) / 3 * 1e3
-            bz.bz_batch_timer(col.batch, False)
-            cms, k = bz.bz_batch_timer_read(col.batch)
-            ev = np.array([np.linalg.norm(x - y) / np.linalg.norm(y)
-                           for x, y in zip(col.unpack(qv.cpu().numpy()), plain.unpack(b64))])
-            acc[str(v)] = {"ms_per_step": ms, "cell_evals_per_s": 2 * nc / ms * 1e3, "conv_avg_ms": cms / max(k, 1),
-                           "rel_l2_vs_fp64": {"median": float(np.median(ev)), "max": float(ev.max()),
-                                              "frac_le_1e-5": float(np.mean(ev <= 1e-5))}}
-        except Exception as exc:
-            acc[str(v)] = {"error": str(exc)}
-    col.set_variant(variant)
-    comp["accuracy_variants"] = acc
+    ref = plain.unpack(b64)
     plain.close()
-    # batched FP64
+    del qq
+
+    def errs_of(q):
+        e = np.array([np.linalg.norm(x - y) / np.linalg.norm(y) for x, y in zip(col.unpack(q.cpu().numpy()), ref)])
+        return {"median": float(np.median(e)), "max": float(e.max()), "frac_le_1e-5": float(np.mean(e <= 1e-5)),
+                "cells": int(e.size)}
+
+    comp["rel_l2_fp32_batched_vs_fp64_plain"] = errs_of(q32)
+    # batched FP64: every cell of the batch in the FP64 kernel
     b64c = bz.Collision([(N, L, lam)], [0] * nc, "batched_f64", weights_cache=wcache)
     qb = b64c.collide(f0)
     torch.cuda.synchronize()
@@ -463,20 +521,31 @@ def main():
     torch.cuda.synchronize()
     comp["batched_fp64_evals_per_s"] = nc / (time.perf_counter() - t0)
     b64c.close()
+    del qb
     comp["fp32_batched_step_evals_per_s"] = value
     comp["speedup_fp32_batched_vs_fp64_plain"] = value / comp["plain_fp64_evals_per_s"]
+    comp["speedup_fp32_batched_vs_fp64_batched"] = value / comp["batched_fp64_evals_per_s"]
     comp["graph_replay"] = graph
-    try:
-        comp["full_sum_schedule"] = full_schedule_leg(torch, bz, N, L, lam, f0, variant, wcache)
-    except Exception as exc:
-        comp["full_sum_schedule"] = {"error": str(exc)}
+    # the same batch with one launch for the FP32 items and the core on a second stream
+    # (autotuned variant), and without the FP64 core (FP32 only)
+    for key, meshes, kw in (("per_mesh_launch", [(N, L, lam)], dict(per_mesh=True, autotune=True)),
+                            ("fp64_core_off", [(N, L, lam, bz.BZ_CORE_OFF)], dict(autotune=True)),
+                            ("full_sum_schedule", [(N, L, lam)], dict(schedule="full"))):
+        try:
+            comp[key] = step_leg(torch, np, bz, meshes, [0] * nc, f0, wcache, **kw)
+            if key == "fp64_core_off":
+                c = bz.Collision(meshes, [0] * nc, "batched_f32", weights_cache=wcache)
+                comp[key]["rel_l2_vs_fp64_plain"] = errs_of(c.project(c.collide(f0)))
+                c.close()
+        except Exception as exc:
+            comp[key] = {"error": str(exc)}
     wcache.clear()
     col.close()
     torch.cuda.empty_cache()
 
     # ---- homogeneous relaxation (N=32) and the whole uneven batch --------
     for key, fn in (("relaxation_n32", lambda: relaxation_leg(torch, np, bz, W)),
-                    ("uneven_batch_1024", lambda: uneven_leg(torch, np, bz, W))):
+                    ("uneven_batch_1024", lambda: uneven_leg(torch, np, bz, W, float(np.median(per_step))))):
         try:
             comp[key] = fn()
         except Exception as exc:
@@ -508,8 +577,8 @@ def main():
                "sample": f"{done} of the {nc} N=32 cells, one FP64 evaluation each (transform, O(N^6) sum, "
                          f"inverse, projection), {el:.1f} s"}
 
-    traffic = measured_traffic(nc, variant)
-    slot_frac = schedule_slots(N, True) / schedule_slots(N, False)
+    traffic = measured_traffic(nc)
+    kernel = "k_conv_cells_f32_multi (FP32 items + FP64 core items)" if one_launch else "k_conv_cells_f32<32>"
     out = {
         "metric": METRIC,
         "value": value,
@@ -518,25 +587,30 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "step_ms": spread(np, per_step),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "N=32 cells of the seeded 1024-cell uneven batch, Heun RK2 step, batched FP32 "
-                               "convolution with compensated accumulation + FP64 projection",
+                               "convolution with compensated accumulation and an FP64 low-frequency core, "
+                               "FP64 projection",
                    "cells": nc, "N": N, "L": L, "lambda": lam, "dt_over_eps": dt_over_eps,
-                   "evals_per_step": 2 * nc, "variant": variant},
+                   "evals_per_step": 2 * nc, "core_r2": info["core_r2"], "one_launch": one_launch},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
-                     "kernel": "k_conv_cells_f32<32>", "flops_per_launch": 10.0 * P * nc,
-                     "avg_launch_ms": conv_avg_ms, "launches": conv_launches,
+                     "traffic_source": (TRAFFIC_FILE + " (rocprofv3 --pmc FETCH_SIZE, WRITE_SIZE on this kernel "
+                                        "source and batch, scaled by a 1 GiB copy)") if traffic else None,
+                     "kernel": kernel, "avg_launch_ms": conv_avg_ms, "launches": conv_launches,
+                     "fp32_flops_per_launch": fp32_flops,
+                     "fp32_slots_per_cell": slots, "slots_vs_full_sum_pairs": slots / P,
+                     "issue_ceiling_frac": ISSUE_CEILING_FRAC,
+                     "fp64_core_flops_per_launch": core_flops,
+                     "frac_incl_fp64_core": (fp32_flops + core_flops) / (conv_avg_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+                     "effective_tflops": 10.0 * P * nc / (conv_avg_ms * 1e-3) / 1e12,
                      "traffic_gb_per_s": (traffic / (conv_avg_ms * 1e-3) / 1e9) if traffic else None,
-                     "hbm_peak_gb_per_s": HBM_TBPS * 1e3,
-                     "schedule": "conjugate-symmetric",
-                     "slots_vs_full_sum": slot_frac,
-                     "achieved_on_processed_slots": achieved * slot_frac,
-                     "frac_on_processed_slots": achieved * slot_frac / PEAK_FP32_TFLOPS},
+                     "hbm_peak_gb_per_s": HBM_TBPS * 1e3},
         "cpu_baseline": cpu,
         "comparisons": comp,
     }

@@ -211,13 +211,18 @@ bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids,
  *                      up to rounding as the full sum; about 0.61 / 0.65 / 0.71
  *                      of its work at N = 32 / 24 / 16.
  *   BZ_BATCH_FULL_SUM  every output row is summed directly.
- *   BZ_BATCH_PER_MESH  (BZ_MODE_BATCHED_F32 with two to four meshes) one
- *                      convolution launch per mesh with its autotuned variant.
- *                      By default the work items of all meshes share one
- *                      persistent launch and one queue ordered by cost, each
- *                      item naming its mesh (the variant with FOLD 16 and four
- *                      interleaved partials for every mesh); the transforms
- *                      stay one launch per mesh and pass.
+ *   BZ_BATCH_PER_MESH  (BZ_MODE_BATCHED_F32) one convolution launch per mesh
+ *                      with its autotuned variant, and the FP64 cores on a
+ *                      second stream of the batch.  By default a batch of up
+ *                      to four meshes, or of one mesh with an FP64 core, runs
+ *                      the work items of all meshes and all cores in one
+ *                      persistent launch from one queue: the FP32 items
+ *                      ordered by cost, each naming its mesh (the variant
+ *                      with FOLD 16 and four interleaved partials for every
+ *                      mesh), and the FP64 core items spread through the
+ *                      first 3/5 of it; the transforms stay one launch per
+ *                      mesh and pass.  bz_batch_autotune may switch a batch
+ *                      to the per-mesh launches when they are faster.
  *   BZ_BATCH_FINE_SPLIT  cut the rows into work items small enough for the
  *                      rows of a single 64-cell group to fill the device (by
  *                      default the whole batch is counted; at most 6 pieces
@@ -456,11 +461,17 @@ int bz_batch_get_variant(bz_batch b, int grid_index);
  * bz_collide_batch; d_Qt receives a result), `reps` launches each, with HIP
  * events on `stream`, and keep per mesh, among the variants within 3% of the
  * fastest, the one with the most accurate accumulation (more interleaved
- * partials, then the shorter fold interval).  Synchronous.  The result is
- * also remembered per (N, number of wavefront groups, mode) for the rest of
- * the process. */
+ * partials, then the shorter fold interval).  Then, for a batch that has the
+ * one-launch queue (BZ_BATCH_PER_MESH), time `reps` whole evaluations with
+ * it and with the per-mesh launches and keep the faster.  Synchronous.  The
+ * variants are also remembered per (N, number of wavefront groups, mode) for
+ * the rest of the process. */
 bz_status bz_batch_autotune(bz_batch b, const double *d_f, double *d_Qt, void *d_work, size_t work_bytes,
                             int reps, void *stream);
+/* 1 if the batch's convolution currently runs as the one persistent launch
+ * for all its meshes and cores (see BZ_BATCH_PER_MESH), else 0 (also for
+ * NULL). */
+int bz_batch_one_launch(bz_batch b);
 /* enable = 1: record a HIP event pair around every convolution launch of
  * this batch (on the stream the launch uses); enable = 0: stop recording.
  * bz_batch_timer_read synchronises on the recorded events, returns the

@@ -143,6 +143,7 @@ def lib():
         "bz_batch_timer": (ctypes.c_int, [_vp, ctypes.c_int]),
         "bz_batch_timer_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
         "bz_batch_core_timer": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
+        "bz_batch_one_launch": (ctypes.c_int, [_vp]),
         "bz_batch_set_core_waves": (ctypes.c_int, [_vp, ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
@@ -521,6 +522,10 @@ def bz_batch_timer_read(b: int):
 
 def bz_batch_set_core_waves(b: int, waves: int) -> None:
     _check(lib().bz_batch_set_core_waves(_vp(b), int(waves)))
+
+
+def bz_batch_one_launch(b: int) -> bool:
+    return bool(lib().bz_batch_one_launch(_vp(b)))
 
 
 def bz_batch_core_timer(b: int):

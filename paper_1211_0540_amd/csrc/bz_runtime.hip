@@ -445,7 +445,7 @@ struct bz_batch_s {
     int n_multi_items = 0;
     bz::MeshConvDesc *d_desc = nullptr;   // per mesh, uploaded by bz_batch_set_weights
     size_t ws_mcounter = 0;
-    bool per_mesh_now = false;       // the autotuner times each mesh's own launch
+    bool per_mesh_now = false;       // one launch per mesh in place of the one-launch queue (autotuner)
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free, ev_core_used;
     int closure_phase = 0;
     // closure: the network runs on a second stream of default priority, forked from and joined to
@@ -1154,9 +1154,10 @@ bz_status bz_batch_autotune(bz_batch b, const double *d_f, double *d_Qt, void *d
         b->ev_free.insert(b->ev_free.end(), b->ev_core_used.begin(), b->ev_core_used.end());
         b->ev_core_used.clear();
     }
-    b->timing = was;
+    b->timing = false;
     b->per_mesh_now = false;
     if (st != BZ_OK) {
+        b->timing = was;
         for (size_t i = 0; i < b->parts.size(); ++i) b->parts[i].variant = saved[i];
         return st;
     }
@@ -1183,8 +1184,37 @@ bz_status bz_batch_autotune(bz_batch b, const double *d_f, double *d_Qt, void *d
             }
         if (!found) g_tuned.emplace_back(key, best);
     }
-    return BZ_OK;
+    // one launch for every mesh (and the cores) or one launch per mesh with the variants just
+    // chosen: the whole evaluation is timed both ways and the faster kept
+    if (b->d_multi_items) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            if (e0) (void)hipEventDestroy(e0);
+            b->timing = was;
+            return fail(BZ_EDEVICE, "bz_batch_autotune: hipEventCreate failed");
+        }
+        double t[2] = {0.0, 0.0};
+        for (int per = 0; per < 2 && st == BZ_OK; ++per) {
+            b->per_mesh_now = per != 0;
+            st = bz_collide_batch(b, d_f, d_Qt, d_work, work_bytes, stream);   // warm-up
+            if (st != BZ_OK) break;
+            if (hipEventRecord(e0, (hipStream_t)stream) != hipSuccess) st = fail(BZ_EDEVICE, "bz_batch_autotune: event");
+            for (int r = 0; r < reps && st == BZ_OK; ++r) st = bz_collide_batch(b, d_f, d_Qt, d_work, work_bytes, stream);
+            float ms = 0.f;
+            if (st == BZ_OK && (hipEventRecord(e1, (hipStream_t)stream) != hipSuccess ||
+                                hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                st = fail(BZ_EDEVICE, "bz_batch_autotune: event timing");
+            t[per] = ms;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        b->per_mesh_now = st == BZ_OK && t[1] < t[0];
+    }
+    b->timing = was;
+    return st;
 }
+
+int bz_batch_one_launch(bz_batch b) { return b && b->d_multi_items && !b->per_mesh_now ? 1 : 0; }
 
 size_t bz_batch_elems(bz_batch b) { return b ? b->elems : 0; }
 size_t bz_batch_cell_offset(bz_batch b, int cell) {

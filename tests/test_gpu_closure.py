@@ -185,3 +185,77 @@ def test_closure_n32_gate_closed_and_open(dev):
         else:
             assert torch.equal(q, ref)
     c.close()
+
+
+def test_served_and_judged_values_match_numpy_from_the_same_network_output(dev):
+    """A non-zero network (uniform random weights in every layer): the served closure
+    Q_s = rho |f - M|_2 s_out y of every gated cell, element by element, and the judge
+    error of every judged cell, err = |P(Q_s - Q_c)| / (|P Q_c| + floor rho |M|_2), against
+    a numpy evaluation from the same network output y (the library's forward on the
+    library's network input) with the oracle's projection P of Sec. 3.3 and the oracle's
+    moments.  Cells are Maxwellians plus a scaled perturbation, deviations from 1e-3 to 0.2
+    around the gate 0.05, 130 cells in three groups (the last ragged)."""
+    import oracle.mlp as OM
+    n, H, gate, floor_ = 130, 256, 0.05, 1e-3
+    m = ClosureModel(N, L, LAM, hidden=H, seed=21)
+    bz.bz_mlp_set_params(m.net, m.params, bz.mlp_pack(OM.init_params(N ** 3, H, N ** 3, 22)))
+    m.s_in, m.s_out = 0.05, 2.0 ** -6
+    rng = np.random.default_rng(23)
+    cells, Ms = [], []
+    for f in _cells(n, 24):
+        rho, u, T, _ = O.moments(f, L)
+        M = W.maxwellian(N, L, rho, u, T)
+        d0 = np.linalg.norm(f - M) / np.linalg.norm(M)
+        cells.append(M + (10.0 ** rng.uniform(-3, np.log10(0.2)) / d0) * (f - M))
+    c = bz.Collision([(N, L, LAM)], [0] * n, "batched_f32", weights_cache=m.wcache)
+    f = torch.from_numpy(c.pack(cells)).to(dev)
+    state = torch.zeros(n * 10, dtype=torch.float64, device=dev)
+    x = torch.zeros(n * N ** 3, dtype=torch.int16, device=dev)
+    bz.bz_closure_prepare(c.batch, f, gate, m.s_in, state, x)
+    y = torch.zeros(n * N ** 3, dtype=torch.float32, device=dev)
+    mw = torch.zeros(bz.bz_mlp_workspace_bytes(m.net, n), dtype=torch.uint8, device=dev)
+    bz.bz_mlp_forward(m.net, m.params, x, n, y, mw)
+    ref = c.collide(f)
+    torch.cuda.synchronize()
+    st = state.view(n, 10).cpu().numpy()
+    Y = y.view(n, -1).cpu().numpy().astype(np.float64)
+    Qc = np.stack(c.unpack(ref.cpu().numpy())).reshape(n, -1)
+    gated = st[:, 6] != 0.0
+    assert 20 < gated.sum() < n - 20
+    # the moments behind the scale, from the oracle
+    for i in range(0, n, 13):
+        rho, u, T, _ = O.moments(cells[i], L)
+        M = W.maxwellian(N, L, rho, u, T)
+        assert st[i, 0] * st[i, 5] * st[i, 8] == pytest.approx(rho * np.linalg.norm(cells[i] - M), rel=1e-9)
+    Qs = (st[:, 0] * st[:, 5] * st[:, 8] * m.s_out)[:, None] * Y
+    assert np.abs(Qs[gated]).max() > 0
+    # served: judge off
+    work = torch.zeros(bz.bz_closure_workspace_bytes(c.batch, m.desc(gate=gate, judge_every=0)), dtype=torch.uint8,
+                       device=dev)
+    q = torch.zeros(c.elems, dtype=torch.float64, device=dev)
+    bz.bz_closure_collide(c.batch, m.desc(gate=gate, judge_every=0), f, q, work)
+    s0 = bz.bz_closure_read_stats(c.batch, m.desc(gate=gate, judge_every=0), work)
+    got = np.stack(c.unpack(q.cpu().numpy())).reshape(n, -1)
+    assert s0["served"] == gated.sum() and s0["judged"] == 0
+    scale = np.abs(Qs[gated]).max()
+    assert np.allclose(got[gated], Qs[gated], rtol=1e-6, atol=1e-6 * scale)
+    assert np.array_equal(got[~gated], Qc[~gated])
+    # judged: every gated cell (judge_every = 1), numpy error with the oracle's projection
+    err = np.full(n, np.nan)
+    for i in np.flatnonzero(gated):
+        D = O.project((Qs[i] - Qc[i]).reshape(N, N, N), L)
+        PQ = O.project(Qc[i].reshape(N, N, N), L)
+        err[i] = np.linalg.norm(D) / (np.linalg.norm(PQ) + floor_ * st[i, 0] * st[i, 8])
+    e = np.sort(err[gated])
+    gaps = np.diff(e)
+    k = int(np.argmax(gaps[len(e) // 4: 3 * len(e) // 4])) + len(e) // 4   # a tolerance between two errors
+    tol = 0.5 * (e[k] + e[k + 1])
+    dj = m.desc(gate=gate, judge_every=1, judge_tol=tol, judge_floor=floor_)
+    bz.bz_closure_collide(c.batch, dj, f, q, work)
+    s1 = bz.bz_closure_read_stats(c.batch, dj, work)
+    got = np.stack(c.unpack(q.cpu().numpy())).reshape(n, -1)
+    assert s1["served"] == 0 and s1["judged"] == gated.sum()
+    assert s1["failed"] == int((err[gated] > tol).sum())
+    assert s1["max_err"] == pytest.approx(np.nanmax(err), rel=1e-5)
+    assert np.array_equal(got, Qc)   # judged cells keep the convolution result
+    c.close()
