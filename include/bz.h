@@ -258,6 +258,21 @@ size_t bz_workspace_bytes(bz_batch b);
 bz_status bz_collide_batch(bz_batch b, const double *d_f, double *d_Qt, void *d_work, size_t work_bytes,
                            void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * bz_collide_batch with the library's own workspace, a static device array
+ * of BZ_STATIC_SCRATCH_BYTES (256 MiB) per GPU, held from the library's
+ * load until the process ends; the call itself allocates nothing.  The
+ * caller passes the inputs and outputs as for bz_collide_batch.  Every call
+ * on one GPU shares that GPU's array and leaves its contents behind, so
+ * calls that overlap on one GPU (on different streams, or from different
+ * threads) race; calls ordered on one stream do not.  Errors: BZ_EINVAL for
+ * NULL pointers or a batch whose bz_workspace_bytes exceeds
+ * BZ_STATIC_SCRATCH_BYTES, BZ_ESTATE when the batch's timer is on (it
+ * creates events) or a mesh has no weights bound. */
+#define BZ_STATIC_SCRATCH_BYTES (256u * 1024u * 1024u)
+bz_status bz_collide_batch_static(bz_batch b, const double *d_f, double *d_Qt, void *stream);
+
 /* In place, per cell: Q <- Q - C^T (C C^T)^{-1} C Q (Sec. 3.3; the sign and
  * transposition are those of the Lagrange solution of the stated problem).
  * FP64 throughout; the moments are reduced twice (one refinement pass). */

@@ -144,6 +144,7 @@ def lib():
         "bz_batch_timer_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
         "bz_batch_core_timer": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
         "bz_batch_one_launch": (ctypes.c_int, [_vp]),
+        "bz_collide_batch_static": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
         "bz_batch_set_core_waves": (ctypes.c_int, [_vp, ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
@@ -522,6 +523,16 @@ def bz_batch_timer_read(b: int):
 
 def bz_batch_set_core_waves(b: int, waves: int) -> None:
     _check(lib().bz_batch_set_core_waves(_vp(b), int(waves)))
+
+
+BZ_STATIC_SCRATCH_BYTES = 256 * 1024 * 1024
+
+
+def bz_collide_batch_static(b: int, f, qt, stream=None) -> None:
+    """bz_collide_batch on the library's static per-GPU workspace (allocates nothing)."""
+    _dev(f, "f")
+    _dev(qt, "Qt")
+    _check(lib().bz_collide_batch_static(_vp(b), _vp(_ptr(f)), _vp(_ptr(qt)), _stream(stream)))
 
 
 def bz_batch_one_launch(b: int) -> bool:

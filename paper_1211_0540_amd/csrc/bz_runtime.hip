@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <thread>
@@ -1230,6 +1231,49 @@ static bz_status collide_impl(bz_batch b, const double *d_f, double *d_Qt, void 
 bz_status bz_collide_batch(bz_batch b, const double *d_f, double *d_Qt, void *d_work, size_t work_bytes,
                            void *stream) {
     return collide_impl(b, d_f, d_Qt, d_work, work_bytes, stream, nullptr, nullptr);
+}
+
+}  // extern "C"
+
+// Workspace of bz_collide_batch_static: one array per GPU, resident for the life of the process.
+// Host code never uses the array's own name as a device address: the address on each device
+// comes from hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) char scratch[BZ_STATIC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::vector<void *> g_scratch_ptr;   // per device id; nullptr until looked up
+
+static bz_status static_scratch(void **out) {
+    int dev = 0;
+    BZ_HIP(hipGetDevice(&dev), "bz_collide_batch_static: hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        BZ_HIP(hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)), "bz_collide_batch_static: hipGetSymbolAddress");
+        if (!ptr) return fail(BZ_EDEVICE, "bz_collide_batch_static: no device address for the static scratch");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return BZ_OK;
+}
+
+extern "C" {
+
+bz_status bz_collide_batch_static(bz_batch b, const double *d_f, double *d_Qt, void *stream) {
+    if (!b || !d_f || !d_Qt) return fail(BZ_EINVAL, "bz_collide_batch_static: NULL argument");
+    if (b->ws_total > (size_t)BZ_STATIC_SCRATCH_BYTES) {
+        char msg[200];
+        std::snprintf(msg, sizeof msg,
+                      "bz_collide_batch_static: the batch needs %zu bytes of workspace, the static scratch holds %zu",
+                      b->ws_total, (size_t)BZ_STATIC_SCRATCH_BYTES);
+        return fail(BZ_EINVAL, msg);
+    }
+    // the convolution timer would create HIP events on demand
+    if (b->timing) return fail(BZ_ESTATE, "bz_collide_batch_static: switch the batch's timer off first");
+    void *ws = nullptr;
+    const bz_status st = static_scratch(&ws);
+    if (st != BZ_OK) return st;
+    return collide_impl(b, d_f, d_Qt, ws, (size_t)BZ_STATIC_SCRATCH_BYTES, stream, nullptr, nullptr);
 }
 
 // The five passes of a mesh's batched convolution (HermAssembly layout; the full-sum schedule
