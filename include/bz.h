@@ -287,9 +287,17 @@ bz_status bz_project(bz_batch b, double *d_Q, void *stream);
 size_t bz_step_workspace_bytes(bz_batch b);
 bz_status bz_step(bz_batch b, double *d_f, double dt_over_eps, void *d_work, size_t work_bytes, void *stream);
 /* Synchronises `stream` and returns BZ_ENONFINITE if any bz_step enqueued
- * with this workspace since the last check produced a non-finite value
- * (then clears the flag), BZ_OK otherwise. */
+ * with this workspace since the last check produced a non-finite value,
+ * BZ_OK otherwise; clears the flags of bz_step_flags. */
 bz_status bz_step_check(bz_batch b, void *d_work, void *stream);
+/* Flags of the bz_step calls enqueued with this workspace since the last
+ * check: BZ_FLAG_NONFINITE when a value of the new f was not finite,
+ * BZ_FLAG_NEGATIVE when one was below zero (the projection of Sec. 3.3
+ * restores the moments, not the sign of f; a diagnostic, not an error).
+ * Synchronises `stream`, writes the flags to *flags and clears them. */
+#define BZ_FLAG_NONFINITE 1u
+#define BZ_FLAG_NEGATIVE 2u
+bz_status bz_step_flags(bz_batch b, void *d_work, unsigned *flags, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* 1-D transport (Sec. 3.4, eq. upwind) with a diffuse wall (Sec. 2.1,    */
@@ -505,6 +513,7 @@ bz_status bz_batch_core_timer(bz_batch b, double *core_ms, int *launches);
 bz_status bz_batch_set_core_waves(bz_batch b, int waves);
 
 const char *bz_status_string(bz_status s);
+const char *bz_status_str(bz_status s);   /* the same text */
 const char *bz_last_error(void);
 int bz_api_version(void);
 

@@ -144,6 +144,8 @@ def lib():
         "bz_batch_timer_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
         "bz_batch_core_timer": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
         "bz_batch_one_launch": (ctypes.c_int, [_vp]),
+        "bz_step_flags": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_uint), _vp]),
+        "bz_status_str": (ctypes.c_char_p, [ctypes.c_int]),
         "bz_collide_batch_static": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
         "bz_batch_set_core_waves": (ctypes.c_int, [_vp, ctypes.c_int]),
     }
@@ -523,6 +525,17 @@ def bz_batch_timer_read(b: int):
 
 def bz_batch_set_core_waves(b: int, waves: int) -> None:
     _check(lib().bz_batch_set_core_waves(_vp(b), int(waves)))
+
+
+BZ_FLAG_NONFINITE = 1
+BZ_FLAG_NEGATIVE = 2
+
+
+def bz_step_flags(b: int, work, stream=None) -> int:
+    """BZ_FLAG_* bits of the steps since the last check (then cleared)."""
+    v = ctypes.c_uint(0)
+    _check(lib().bz_step_flags(_vp(b), _vp(_ptr(work)), ctypes.byref(v), _stream(stream)))
+    return int(v.value)
 
 
 BZ_STATIC_SCRATCH_BYTES = 256 * 1024 * 1024

@@ -126,13 +126,14 @@ __global__ void k_axpy(size_t n, const double *__restrict__ a, const double *__r
 
 __global__ void k_heun_final(size_t n, const double *__restrict__ f, const double *__restrict__ fs,
                              const double *__restrict__ q, double c, double *__restrict__ out, unsigned *flag) {
-    bool bad = false;
+    bool bad = false, neg = false;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         double y = 0.5 * (f[i] + fma(c, q[i], fs[i]));
         out[i] = y;
         bad |= !isfinite(y);
+        neg |= y < 0.0;
     }
-    if (bad) atomicOr(flag, 1u);
+    if (bad || neg) atomicOr(flag, (bad ? 1u : 0u) | (neg ? 2u : 0u));
 }
 
 __global__ void k_fill_u32(unsigned *p, int n, unsigned v) {

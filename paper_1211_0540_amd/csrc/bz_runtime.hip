@@ -524,6 +524,8 @@ const char *bz_status_string(bz_status s) {
     return "unknown status";
 }
 
+const char *bz_status_str(bz_status s) { return bz_status_string(s); }
+
 const char *bz_last_error(void) { return g_err.c_str(); }
 
 bz_status bz_grid_init(int N, double L, double lambda, bz_grid *out) {
@@ -1465,10 +1467,20 @@ bz_status bz_step_check(bz_batch b, void *d_work, void *stream) {
     unsigned h = 0;
     BZ_HIP(hipMemcpyAsync(&h, flag, sizeof h, hipMemcpyDeviceToHost, s), "bz_step_check: read flag");
     BZ_HIP(hipStreamSynchronize(s), "bz_step_check: sync");
-    if (h) {
-        BZ_HIP(launch_fill_u32(flag, 1, 0u, s), "bz_step_check: clear flag");
-        return fail(BZ_ENONFINITE, "bz_step: a non-finite value was produced");
-    }
+    if (h) BZ_HIP(launch_fill_u32(flag, 1, 0u, s), "bz_step_check: clear flag");
+    if (h & BZ_FLAG_NONFINITE) return fail(BZ_ENONFINITE, "bz_step: a non-finite value was produced");
+    return BZ_OK;
+}
+
+bz_status bz_step_flags(bz_batch b, void *d_work, unsigned *flags, void *stream) {
+    if (!b || !d_work || !flags) return fail(BZ_EINVAL, "bz_step_flags: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned *flag = (unsigned *)((char *)d_work + b->ws_flag);
+    unsigned h = 0;
+    BZ_HIP(hipMemcpyAsync(&h, flag, sizeof h, hipMemcpyDeviceToHost, s), "bz_step_flags: read flag");
+    BZ_HIP(hipStreamSynchronize(s), "bz_step_flags: sync");
+    if (h) BZ_HIP(launch_fill_u32(flag, 1, 0u, s), "bz_step_flags: clear flag");
+    *flags = h;
     return BZ_OK;
 }
 

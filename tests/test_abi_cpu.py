@@ -130,6 +130,8 @@ def test_status_strings():
     L = bz.lib()
     assert L.bz_status_string(0) == b"ok"
     assert L.bz_status_string(-5) == b"non-finite value"
+    for st in (0, -1, -2, -3, -4, -5, -6, -99):
+        assert L.bz_status_str(st) == L.bz_status_string(st)
 
 
 def test_mlp_shape_validation():

@@ -380,6 +380,33 @@ def test_nonfinite_input_is_reported(dev):
     c.close()
 
 
+def test_step_flags_report_negative_and_nonfinite_values(dev):
+    """BZ_FLAG_NEGATIVE after a step whose new f has a value below zero (a Maxwellian with one
+    entry set to -1, which one small step cannot lift), none for a Maxwellian; the flags clear
+    on reading; BZ_FLAG_NONFINITE with a NaN entry, and bz_step_check then raises."""
+    N, L, lam = 8, 4.0, 1.0
+    M = W.maxwellian(N, L, 1.0, (0, 0, 0), 1.0)
+    c = bz.Collision([(N, L, lam)], [0, 0], "batched_f32", weights_cache=_WCACHE)
+    f = torch.from_numpy(c.pack([M, M])).to(dev)
+    c.step(f, 0.01)
+    assert bz.bz_step_flags(c.batch, c.work) == 0
+    g = M.copy()
+    g[4, 4, 4] = -1.0
+    f = torch.from_numpy(c.pack([M, g])).to(dev)
+    c.step(f, 1e-3)
+    assert bz.bz_step_flags(c.batch, c.work) == bz.BZ_FLAG_NEGATIVE
+    assert bz.bz_step_flags(c.batch, c.work) == 0
+    g[1, 2, 3] = np.nan
+    f = torch.from_numpy(c.pack([M, g])).to(dev)
+    c.step(f, 1e-3)
+    assert bz.bz_step_flags(c.batch, c.work) & bz.BZ_FLAG_NONFINITE
+    c.step(f, 1e-3)
+    with pytest.raises(bz.BzError) as e:
+        c.check()
+    assert e.value.status == bz.BZ_ENONFINITE
+    c.close()
+
+
 def test_unbound_weights_and_short_workspace(dev):
     g = bz.bz_grid_init(8, 4.0, 1.0)
     b = bz.bz_batch_create([0], [g], bz.BZ_MODE_BATCHED_F32)
