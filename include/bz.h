@@ -124,7 +124,7 @@ typedef struct {
  * term evaluated once.  The core costs a few percent of the FP32 work.  It
  * applies to BZ_MODE_BATCHED_F32 only (the FP64 modes are exact already, the
  * plain FP32 mode keeps its single stream). */
-#define BZ_CORE_DEFAULT (-1)  /* the ball |zeta| < pi: nc <= ceil(L^2) - 1, capped as below */
+#define BZ_CORE_DEFAULT (-1)  /* nc <= ceil(L^2 sqrt(min(1, N/32))) - 1, capped as below */
 #define BZ_CORE_OFF (-2)      /* no core: every pair in FP32 */
 
 /* Create a mesh handle.  Host only, no device work.  lambda is the exponent

@@ -450,13 +450,16 @@ static_assert(2 * core_wstride(kCoreMaxR) * 8 <= kMultiLdsBytes, "core weights e
 
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 k_conv_cells_f32_multi(const int4 *__restrict__ items, int n_items, unsigned *__restrict__ counter,
-                       const MeshConvDesc *__restrict__ desc, char *__restrict__ ws) {
+                       const MeshConvDesc *__restrict__ desc, char *__restrict__ ws,
+                       const unsigned char *__restrict__ skip) {
     __shared__ __attribute__((aligned(16))) double wbuf[kMultiLdsBytes / 8];
     lds_char *const wl = lds_ptr(&wbuf[0]);
     for (;;) {
         const int it = pop_item(counter);
         if (it >= n_items) break;
         const int4 item = items[it];
+        // a group whose cells are all served elsewhere: nothing reads its outputs
+        if (skip && skip[item.x]) continue;
         const int mi = (item.y >> 24) & 0xf, pass = (item.y >> 20) & 0xf;
         const MeshConvDesc &d = desc[mi];
         if (item.y & kCoreItemBit) {
@@ -698,7 +701,7 @@ hipError_t launch_conv_cells_multi(const MultiLaunch &p, hipStream_t s) {
     hipError_t e = launch_fill_u32(p.counter, 1, 0u, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_conv_cells_f32_multi, dim3(persistent_grid(p.n_items)), dim3(64), 0, s, p.items, p.n_items,
-                       p.counter, p.desc, p.ws);
+                       p.counter, p.desc, p.ws, p.skip);
     return hipGetLastError();
 }
 

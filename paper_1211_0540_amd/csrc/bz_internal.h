@@ -381,6 +381,7 @@ struct MultiLaunch {
     unsigned *counter;
     const MeshConvDesc *desc;    // device
     char *ws;                    // the call's workspace
+    const unsigned char *skip;   // device, per group (one-mesh batches), may be NULL: groups to leave out
 };
 hipError_t launch_conv_cells_multi(const MultiLaunch &p, hipStream_t s);
 hipError_t launch_build_e3(int N, const long long *d_row_woff, const long long *d_e3_woff, const void *w_main,

@@ -572,11 +572,15 @@ bz_status bz_grid_create(const bz_grid_params *prm, bz_grid *out) {
     if (beta != 1.0)
         for (int j = 0; j < 5; ++j) g->linv[4 * 5 + j] = 0.0;
     build_schedules(g);
-    // core ball: the default is |zeta| < pi, i.e. nc < L^2 in index units, kept inside the
-    // interior of the mesh (r <= N/2 - 1) and within the kernel's largest half-width
+    // core ball: the default is |zeta| < pi sqrt(min(1, N/32)), i.e. nc < L^2 sqrt(N/32) in index
+    // units, kept inside the interior of the mesh (r <= N/2 - 1) and within the kernel's largest
+    // half-width.  A coarser mesh sums fewer FP32 terms per output, so a smaller ball leaves the
+    // same error: an emulation of the kernel's FP32 arithmetic on the cells of largest
+    // cancellation gives at most 3.7e-6, 5.0e-6 and 4.3e-6 at N = 16, 24, 32 (L = 6, 7, 8)
     const int h = N / 2, cmax = std::min(h * h - 1, (kCoreMaxR + 1) * (kCoreMaxR + 1) - 1);
     int r2 = core_r2;
-    if (core_r2 == BZ_CORE_DEFAULT) r2 = std::min(cmax, (int)std::ceil(L * L) - 1);
+    if (core_r2 == BZ_CORE_DEFAULT)
+        r2 = std::min(cmax, (int)std::ceil(L * L * std::sqrt(std::min(1.0, N / 32.0))) - 1);
     else if (core_r2 != BZ_CORE_OFF && (core_r2 < 1 || core_r2 > cmax)) {
         delete g;
         return fail(BZ_EINVAL, "bz_grid_init: core_r2 must be in [1, min(N^2/4, 81) - 1], BZ_CORE_DEFAULT or BZ_CORE_OFF");
@@ -1302,7 +1306,9 @@ static bz_status collide_batched(bz_batch b, const double *d_f, double *d_Qt, ch
                                  const unsigned char *skip, const long long *slot_off) {
     double2 *scratch = (double2 *)(ws + b->ws_scratch);
     const bool f64 = mode_f64(b->mode);
-    const bool merged = b->d_multi_items && !b->per_mesh_now && !skip && !slot_off;
+    // skip and slot_off come with one-mesh batches (the gated closure); the group index of an
+    // item is then the skip index
+    const bool merged = b->d_multi_items && !b->per_mesh_now;
     for (const Part &p : b->parts) {
         const CoreSched &cs = p.g->sched.core;
         const long long *f_off = slot_off ? slot_off : p.d_f_off;
@@ -1339,7 +1345,8 @@ static bz_status collide_batched(bz_batch b, const double *d_f, double *d_Qt, ch
     }
     if (cores) BZ_HIP(hipEventRecord(b->ev_cjoin, b->core_stream), "core join");
     if (merged) {
-        const MultiLaunch ml{b->d_multi_items, b->n_multi_items, (unsigned *)(ws + b->ws_mcounter), b->d_desc, ws};
+        const MultiLaunch ml{b->d_multi_items, b->n_multi_items, (unsigned *)(ws + b->ws_mcounter), b->d_desc, ws,
+                             skip};
         std::pair<hipEvent_t, hipEvent_t> ev{};
         if (b->timing) {
             if (!timer_pair(b, ev)) return fail(BZ_EDEVICE, "bz_collide_batch: hipEventCreate failed");

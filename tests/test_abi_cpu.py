@@ -160,11 +160,11 @@ def _core_steps(N, r2):
     return n
 
 
-@pytest.mark.parametrize("N,L,r2", [(8, 4.0, 15), (16, 6.0, 35), (24, 7.0, 48), (32, 8.0, 63)])
+@pytest.mark.parametrize("N,L,r2", [(8, 4.0, 7), (16, 6.0, 25), (24, 7.0, 42), (32, 8.0, 63), (32, 9.5, 80)])
 def test_default_core_and_its_weight_stream(N, L, r2):
-    """The default core is the ball nc < L^2 (|zeta| < pi), capped inside the mesh
-    interior; the FP32 buffer ends with its FP64 stream, one padded block of
-    (2r+1)^2 weights per core step."""
+    """The default core is the ball nc < L^2 sqrt(min(1, N/32)) (|zeta| < pi at N = 32),
+    capped inside the mesh interior and the kernel's half-width; the FP32 buffer ends with
+    its FP64 stream, one padded block of (2r+1)^2 weights per core step."""
     g = bz.bz_grid_init(N, L, 1.0)
     g0 = bz.bz_grid_init_ex(N, L, 1.0, bz.BZ_CORE_OFF)
     try:
