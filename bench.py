@@ -375,6 +375,52 @@ def served_errors(torch, np, bz, col, desc, f, work, N):
             "judge_tol": desc.judge_tol}
 
 
+def mlp_profile_run(args, n_in=13824, hidden=1024, rows=512, cells=256):
+    """Training steps (forward, backward, Adam) and serving forwards of the closure network at
+    its configured shape on seeded synthetic BF16 inputs; one JSON line with the times and the
+    matrix-product rates."""
+    import numpy as np
+    import torch
+    from paper_1211_0540_amd import bz
+    net = bz.bz_mlp_create(n_in, hidden, n_in)
+    params = torch.zeros(bz.bz_mlp_param_bytes(net), dtype=torch.uint8, device="cuda")
+    rng = np.random.default_rng(1211)
+    parts = []
+    for o, i in ((hidden, n_in), (hidden, hidden), (n_in, hidden)):
+        sc = 1.0 / np.sqrt(i)
+        parts += [rng.uniform(-sc, sc, o * i).astype(np.float32), rng.uniform(-sc, sc, o).astype(np.float32)]
+    bz.bz_mlp_set_params(net, params, np.concatenate(parts))
+    x = torch.randn(rows, n_in, device="cuda").to(torch.bfloat16).view(torch.int16)
+    y = torch.randn(rows, n_in, device="cuda")
+    work = torch.zeros(bz.bz_mlp_workspace_bytes(net, rows), dtype=torch.uint8, device="cuda")
+    grad = torch.zeros(bz.bz_mlp_param_count(net), dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    out = torch.zeros(cells, n_in, dtype=torch.float32, device="cuda")
+
+    def train():
+        bz.bz_mlp_backward(net, params, x, y, rows, grad, loss, work)
+        bz.bz_mlp_adam(net, params, grad, 1, 1e-4)
+
+    def serve():
+        bz.bz_mlp_forward(net, params, x[:cells], cells, out, work)
+
+    for fn in (train, serve):
+        fn()
+    steps = max(args.steps, 10)
+    t_train, _ = timed_steps(torch, train, steps)
+    t_serve, _ = timed_steps(torch, serve, steps)
+    fwd = 2.0 * (n_in * hidden + hidden * hidden + hidden * n_in)
+    # training: forward, weight gradients (the same flops) and the activation gradients of layers 2, 3
+    train_flops = rows * (2 * fwd + 2.0 * (hidden * hidden + n_in * hidden))
+    out_line = {"profile_mlp": True, "shape": [n_in, hidden, hidden, n_in], "train_rows": rows,
+                "train_ms_per_step": t_train / steps, "train_tflops": train_flops / (t_train / steps * 1e-3) / 1e12,
+                "serve_cells": cells, "serve_ms": t_serve / steps,
+                "serve_tflops": cells * fwd / (t_serve / steps * 1e-3) / 1e12, "peak_bf16_tflops": 2500.0}
+    print(json.dumps(out_line), flush=True)
+    bz.bz_mlp_free(net)
+    return 0
+
+
 def cpu_model():
     """The host CPU's model name (Linux /proc/cpuinfo), or None."""
     try:
@@ -399,11 +445,16 @@ def main():
                     help="timed steps only (default launch configuration, no comparisons, no CPU leg)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
+    ap.add_argument("--profile-mlp", action="store_true",
+                    help="only the closure network's kernels: training steps of 512 rows and forwards of 256 "
+                         "cells of the N=24 network on synthetic data")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)
         return 2
+    if args.profile_mlp:
+        return mlp_profile_run(args)
 
     import numpy as np
     import torch
