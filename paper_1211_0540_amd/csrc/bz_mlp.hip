@@ -9,9 +9,13 @@
 //   forward   Z1 = X W1^T, Z2 = A1 W2^T, Y = A2 W3^T         (weights stored [out][in])
 //   backward  dA2 = dY W3, dA1 = dZ2 W2                       (transposed copies W3, W2)
 //             dW3 = dY^T A2, dW2 = dZ2^T A1, dW1 = dZ1^T X     (transposed activations)
-// Tile 128 x 128 x 32 per 256-thread workgroup (4 waves of 64 x 64, 16 MFMAs
-// each per k step), next k tile prefetched into registers while the current
-// one is consumed from LDS.  K must be a multiple of 32.
+// Tile 128 x 128 x 64 per 256-thread workgroup (4 waves of 64 x 64, 32 MFMAs
+// each per k tile): two LDS buffers, the next k tile loaded into registers and
+// stored to the other buffer while the current one feeds the MFMAs, so one
+// barrier per k tile.  The rows of a tile are 128 bytes; 16-byte chunk c of
+// row r sits at chunk c ^ (r & 7), so that the 16 lanes that read one chunk
+// of 16 consecutive rows hit different banks.  K must be a multiple of 32 (a
+// last half tile is zero-filled).
 #include <cmath>
 #include <new>
 #include <vector>
@@ -45,7 +49,8 @@ __device__ inline float gelu_prime(float z) {
 
 enum { EPI_F32 = 0, EPI_GELU = 1, EPI_PARTIAL = 2 };
 
-constexpr int TBM = 128, TBN = 128, TBK = 32, LDSK = TBK + 8;
+constexpr int TBM = 128, TBN = 128, TBK = 64;
+constexpr int kTileBytes = TBM * TBK * 2;   // one operand tile, 16 KiB
 
 // EPI_F32:  C32[m][n] = alpha * acc + (bias ? bias[n] : 0)
 // EPI_GELU: Z = acc + bias[n]; C32 = Z; Cbf = bf16(gelu(Z))
@@ -57,55 +62,71 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const unsi
                                                  const unsigned short *__restrict__ B, int ldb, float alpha,
                                                  const float *__restrict__ bias, float *__restrict__ C32, int ldc,
                                                  unsigned short *__restrict__ Cbf, int ldcb) {
-    __shared__ __attribute__((aligned(16))) unsigned short As[TBM * LDSK];
-    __shared__ __attribute__((aligned(16))) unsigned short Bs[TBN * LDSK];
+    // [buffer][A, B][128 rows x 8 chunks of 16 bytes], 64 KiB
+    __shared__ __attribute__((aligned(16))) uint4 lds[2][2][TBM * 8];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
-    // global -> register loads: thread t moves row t/2, k half (t%2)*16 of each tile (2 x 16 bytes)
-    const int lr = tid >> 1, lk = (tid & 1) * 16;
+    // global -> register loads: thread t moves chunks 4 (t % 2) .. 4 (t % 2) + 3 of row t / 2 of each tile
+    const int lr = tid >> 1, lc = (tid & 1) * 4;
     const int am = m0 + lr, bn = n0 + lr;
     const bool aok = am < M, bok = bn < N;
-    const uint4 *ap = (const uint4 *)(A + (size_t)(aok ? am : 0) * lda + lk);
-    const uint4 *bp = (const uint4 *)(B + (size_t)(bok ? bn : 0) * ldb + lk);
+    const uint4 *ap = (const uint4 *)(A + (size_t)(aok ? am : 0) * lda);
+    const uint4 *bp = (const uint4 *)(B + (size_t)(bok ? bn : 0) * ldb);
     const uint4 z4 = make_uint4(0, 0, 0, 0);
-    const int nk_all = K / TBK;
+    const int kc = K / 8;                      // 16-byte chunks per row
+    const int nk_all = (K + TBK - 1) / TBK;
     const int kt0 = (int)((long long)nk_all * blockIdx.z / gridDim.z);
     const int nk = (int)((long long)nk_all * (blockIdx.z + 1) / gridDim.z);
-    const int o0 = kt0 * TBK / 8;  // first k tile of this workgroup, in uint4 units
-    uint4 ra0 = aok ? ap[o0] : z4, ra1 = aok ? ap[o0 + 1] : z4;
-    uint4 rb0 = bok ? bp[o0] : z4, rb1 = bok ? bp[o0 + 1] : z4;
+    // the four chunks of each operand live in named registers (an indexed array would be
+    // placed in LDS by the compiler)
+    uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+#define BZ_LD(r, p, ok, c) r = (ok) && o + (c) < kc ? (p)[o + (c)] : z4
+    auto load = [&](int kt) {
+        const int o = kt * (TBK / 8) + lc;   // first chunk index along K
+        BZ_LD(ra0, ap, aok, 0); BZ_LD(ra1, ap, aok, 1); BZ_LD(ra2, ap, aok, 2); BZ_LD(ra3, ap, aok, 3);
+        BZ_LD(rb0, bp, bok, 0); BZ_LD(rb1, bp, bok, 1); BZ_LD(rb2, bp, bok, 2); BZ_LD(rb3, bp, bok, 3);
+    };
+#undef BZ_LD
+    auto store = [&](int buf) {
+        uint4 *la = &lds[buf][0][lr * 8], *lb = &lds[buf][1][lr * 8];
+        const int sw = lr & 7;
+        la[(lc + 0) ^ sw] = ra0; la[(lc + 1) ^ sw] = ra1; la[(lc + 2) ^ sw] = ra2; la[(lc + 3) ^ sw] = ra3;
+        lb[(lc + 0) ^ sw] = rb0; lb[(lc + 1) ^ sw] = rb1; lb[(lc + 2) ^ sw] = rb2; lb[(lc + 3) ^ sw] = rb3;
+    };
     f32x4 acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (kt0 < nk) {
+        load(kt0);
+        store(0);
+    }
+    __syncthreads();
+    int cur = 0;
     for (int kt = kt0; kt < nk; ++kt) {
-        __syncthreads();
-        *(uint4 *)(As + lr * LDSK + lk) = ra0;
-        *(uint4 *)(As + lr * LDSK + lk + 8) = ra1;
-        *(uint4 *)(Bs + lr * LDSK + lk) = rb0;
-        *(uint4 *)(Bs + lr * LDSK + lk + 8) = rb1;
-        __syncthreads();
-        if (kt + 1 < nk) {
-            const int o = (kt + 1) * TBK / 8;  // in uint4 units
-            ra0 = aok ? ap[o] : z4;
-            ra1 = aok ? ap[o + 1] : z4;
-            rb0 = bok ? bp[o] : z4;
-            rb1 = bok ? bp[o + 1] : z4;
+        if (kt + 1 < nk) load(kt + 1);
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            bf16x8 af[4], bfr[4];
+            const int ch = kk * 4 + (lane >> 4);   // this lane's k chunk of the 32-deep half
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = wm * 64 + i * 16 + (lane & 15);
+                af[i] = *(const bf16x8 *)&lds[cur][0][row * 8 + (ch ^ (row & 7))];
+                const int col = wn * 64 + i * 16 + (lane & 15);
+                bfr[i] = *(const bf16x8 *)&lds[cur][1][col * 8 + (ch ^ (col & 7))];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
         }
-        bf16x8 af[4], bfr[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = wm * 64 + i * 16 + (lane & 15);
-            af[i] = *(const bf16x8 *)(As + row * LDSK + (lane >> 4) * 8);
-            const int col = wn * 64 + i * 16 + (lane & 15);
-            bfr[i] = *(const bf16x8 *)(Bs + col * LDSK + (lane >> 4) * 8);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        if (kt + 1 < nk) store(cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -342,15 +363,15 @@ static size_t work_bytes(const bz_mlp_s *n, int B) {
 
 // C = alpha A B^T (+ bias, epilogue).  A product with fewer output tiles than
 // there are compute units and a long K is split over K into up to kMaxSplit
-// slices (at least 8 k tiles each) when the workspace slice buffer holds them.
+// slices (at least 4 k tiles each) when the workspace slice buffer holds them.
 static hipError_t gemm(int epi, int M, int N, int K, const unsigned short *A, int lda, const unsigned short *B, int ldb,
                        float alpha, const float *bias, float *C32, int ldc, unsigned short *Cbf, int ldcb,
                        const WorkView &wv, hipStream_t s) {
     dim3 grid((N + TBN - 1) / TBN, (M + TBM - 1) / TBM);
-    const int tiles = (int)(grid.x * grid.y), nk = K / TBK;
+    const int tiles = (int)(grid.x * grid.y), nk = (K + TBK - 1) / TBK;
     int split = 1;
     if (tiles < 128) {
-        split = std::min(std::min(kMaxSplit, nk / 8), (256 + tiles - 1) / tiles);
+        split = std::min(std::min(kMaxSplit, nk / 4), (256 + tiles - 1) / tiles);
         const size_t cap = wv.split_floats / ((size_t)M * N);
         if ((size_t)split > cap) split = (int)cap;
     }
