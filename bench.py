@@ -344,6 +344,7 @@ def closure_leg(args, torch, np, bz, W, N=24, L=7.0, snapshots=600, relax_cells=
             "speedup": ta / tb, "closure_cell_evals_per_s": evals / tb, "served_fraction": st["served"] / evals,
             "judged": st["judged"], "judge_failed": st["failed"],
             "judge_pass_fraction": 1.0 - st["failed"] / max(st["judged"], 1), "judge_max_rel_err": st["max_err"],
+            "unbounded_served": st["unbounded"], "gate_cap": st["gate_cap"],
             "served_cells_one_evaluation": served,
             "max_abs_T_profile_deviation": float(np.max(np.abs(TA - TB)))}
 

@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define BZ_API_VERSION 2
+#define BZ_API_VERSION 3
 
 typedef enum {
     BZ_OK = 0,
@@ -405,6 +405,11 @@ bz_status bz_mlp_adam(bz_mlp n, void *d_params, const float *d_grad, int step, f
  * whose Q is only the discretisation residual, are judged against the
  * collision rate),
  * counted as failed if err > judge_tol, and keeps the convolution result.
+ * A failed judge also caps the gate of every later evaluation with this
+ * workspace at that cell's deviation d, so no cell at least as far from
+ * equilibrium is served again (the cap lives in the workspace's closure
+ * counters: zeroing the workspace lifts it), and the cells served in an
+ * evaluation whose judge failed are counted as unbounded.
  * The FP64 projection of Sec. 3.3 is always applied.  In the batched modes
  * the cells that need the convolution (not gated, or judged) are packed into
  * the first 64-cell groups of the launch, and only those groups are
@@ -429,6 +434,8 @@ typedef struct {
     unsigned judged;        /* gated cells also convolved and compared */
     unsigned failed;        /* judged cells with err > judge_tol */
     float max_err;          /* largest judged err */
+    unsigned unbounded;     /* served cells of evaluations in which a judge failed */
+    double gate_cap;        /* the gate cap set by failed judges (0: none) */
 } bz_closure_stats;
 
 /* Workspace of the closure calls: bz_step_workspace_bytes plus the closure's
@@ -451,7 +458,8 @@ bz_status bz_closure_step(bz_batch b, const bz_closure *c, double *d_f, double d
                           size_t work_bytes, void *stream);
 bz_status bz_closure_strang_step(bz_batch b, bz_transport t, const bz_closure *c, double *d_f, double dt,
                                  double eps, void *d_work, size_t work_bytes, void *stream);
-/* Counters accumulated since the last read (synchronises `stream`, then clears them). */
+/* Counters accumulated since the last read (synchronises `stream`, then clears
+ * them; the gate cap persists). */
 bz_status bz_closure_read_stats(bz_batch b, const bz_closure *c, void *d_work, bz_closure_stats *out, void *stream);
 
 /* ------------------------------------------------------------------ */

@@ -60,7 +60,7 @@ class ClosureDesc(ctypes.Structure):
 
 class ClosureStats(ctypes.Structure):
     _fields_ = [("served", ctypes.c_uint), ("judged", ctypes.c_uint), ("failed", ctypes.c_uint),
-                ("max_err", ctypes.c_float)]
+                ("max_err", ctypes.c_float), ("unbounded", ctypes.c_uint), ("gate_cap", ctypes.c_double)]
 
 
 def lib():
@@ -476,7 +476,8 @@ def bz_closure_read_stats(b: int, desc: ClosureDesc, work, stream=None) -> dict:
     st = ClosureStats()
     _check(lib().bz_closure_read_stats(_vp(b), ctypes.byref(desc), _vp(_ptr(work)), ctypes.byref(st),
                                        _stream(stream)))
-    return {"served": st.served, "judged": st.judged, "failed": st.failed, "max_err": st.max_err}
+    return {"served": st.served, "judged": st.judged, "failed": st.failed, "max_err": st.max_err,
+            "unbounded": st.unbounded, "gate_cap": st.gate_cap}
 
 
 def mlp_pack(p: dict) -> np.ndarray:

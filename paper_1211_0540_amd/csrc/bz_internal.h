@@ -438,9 +438,10 @@ hipError_t launch_heun_final(size_t n, const double *f, const double *fs, const 
 hipError_t launch_fill_u32(unsigned *p, int n, unsigned v, hipStream_t s);
 
 // Gated closure helpers (bz_surrogate.hip).
+// stats (may be NULL): the closure counters, whose gate cap (set by failed judges) lowers `gate`
 hipError_t launch_sur_prepare(int N, double dv, int n, const double *f, const long long *f_off, double gate,
-                              double s_in, int judge_every, int phase, double *state, unsigned short *x,
-                              hipStream_t s);
+                              double s_in, int judge_every, int phase, const unsigned *stats, double *state,
+                              unsigned short *x, hipStream_t s);
 hipError_t launch_pack_slots(int n, const double *state, const long long *f_off, long long *slot_off,
                              unsigned char *skip, hipStream_t s);
 hipError_t launch_sur_finish(int N, double dv, const double *linv, int n, const double *state, const float *y,

@@ -1570,7 +1570,7 @@ static bz_status closure_collide_impl(bz_batch b, const bz_closure *c, const dou
     bz_status st = closure_side(b);
     if (st != BZ_OK) return st;
     BZ_HIP(launch_sur_prepare(N, p.g->dv, n, d_f, p.d_f_off, c->gate, c->s_in, c->judge_every, b->closure_phase++,
-                              v.state, v.x, s),
+                              v.stats, v.state, v.x, s),
            "closure prepare");
     const unsigned char *skip = nullptr;
     const long long *slot_off = nullptr;
@@ -1606,7 +1606,7 @@ bz_status bz_closure_prepare(bz_batch b, const double *d_f, double gate, double 
     if (b->parts.size() != 1) return fail(BZ_EUNSUPPORTED, "bz_closure_prepare: needs a one-mesh batch");
     if (!(s_in > 0)) return fail(BZ_EINVAL, "bz_closure_prepare: s_in must be positive");
     const Part &p = b->parts[0];
-    BZ_HIP(launch_sur_prepare(p.g->N, p.g->dv, (int)p.cells.size(), d_f, p.d_f_off, gate, s_in, 0, 0, d_state,
+    BZ_HIP(launch_sur_prepare(p.g->N, p.g->dv, (int)p.cells.size(), d_f, p.d_f_off, gate, s_in, 0, 0, nullptr, d_state,
                               (unsigned short *)d_x, (hipStream_t)stream),
            "bz_closure_prepare");
     return BZ_OK;
@@ -1663,7 +1663,7 @@ bz_status bz_closure_read_stats(bz_batch b, const bz_closure *c, void *d_work, b
     if (!d_work || !out) return fail(BZ_EINVAL, "bz_closure_read_stats: NULL argument");
     hipStream_t s = (hipStream_t)stream;
     ClosureView v = closure_view(b, c, d_work);
-    unsigned h[4] = {0, 0, 0, 0};
+    unsigned h[10] = {};
     BZ_HIP(hipMemcpyAsync(h, v.stats, sizeof h, hipMemcpyDeviceToHost, s), "read closure stats");
     BZ_HIP(hipStreamSynchronize(s), "read closure stats sync");
     out->served = h[0];
@@ -1672,7 +1672,15 @@ bz_status bz_closure_read_stats(bz_batch b, const bz_closure *c, void *d_work, b
     std::memcpy(&e, &h[2], sizeof e);
     out->max_err = e;
     out->failed = h[3];
-    BZ_HIP(launch_fill_u32(v.stats, 4, 0u, s), "clear closure stats");
+    out->unbounded = h[6];
+    unsigned long long cap;
+    std::memcpy(&cap, &h[8], sizeof cap);
+    cap = ~cap;
+    double g = 0.0;
+    if (~cap) std::memcpy(&g, &cap, sizeof g);   // a stored 0 (no cap) reads as 0
+    out->gate_cap = g;
+    // the counters restart; the gate cap persists (zero the workspace to lift it)
+    BZ_HIP(launch_fill_u32(v.stats, 7, 0u, s), "clear closure stats");
     return BZ_OK;
 }
 

@@ -16,7 +16,10 @@
 // (the floor is on the scale of the loss term rho nu f, so that cells at
 // equilibrium, whose Q is only the discretisation residual, are judged
 // against the collision rate rather than against that residual)
-// and keeps the convolution result (fallback).  The FP64 projection of
+// and keeps the convolution result (fallback).  A failed judge also caps the
+// gate of later evaluations at that cell's deviation (no cell at least as far
+// from equilibrium is served again), and the cells served in an evaluation
+// with a failed judge are counted as unbounded.  The FP64 projection of
 // Sec. 3.3 is applied to every cell afterwards.  The batched modes pack the
 // cells that need the convolution into the first 64-cell groups of the launch
 // and skip the groups left with served cells only.
@@ -29,6 +32,11 @@ namespace bz {
 namespace {
 
 constexpr int kState = 10;  // rho, u1, u2, u3, T, d, gated, judged, |M|_2, unused
+// closure counters (unsigned words): total served, judged, max err (float bits), failed; this
+// evaluation's served and failed; unbounded served; pad; at words 8..9 the gate cap as the
+// complement of its double's bits (0: no cap), so that a smaller cap is a larger word
+enum { kStServed = 0, kStJudged = 1, kStMaxErr = 2, kStFailed = 3, kStEvalServed = 4, kStEvalFailed = 5,
+       kStUnbounded = 6, kStCap = 8 };
 
 __device__ inline double block_sum(double x, double *red) {
 #pragma unroll
@@ -51,8 +59,8 @@ __device__ inline unsigned short f2bf(float x) {
 template <int N>
 __global__ void __launch_bounds__(256) k_prepare(double dv, const double *__restrict__ f,
                                                  const long long *__restrict__ f_off, double gate, double inv_s_in,
-                                                 int judge_every, int phase, double *__restrict__ state,
-                                                 unsigned short *__restrict__ x) {
+                                                 int judge_every, int phase, const unsigned *__restrict__ stats,
+                                                 double *__restrict__ state, unsigned short *__restrict__ x) {
     __shared__ double red[4];
     const int c = blockIdx.x, M = N * N * N;
     const double *F = f + f_off[c];
@@ -92,6 +100,10 @@ __global__ void __launch_bounds__(256) k_prepare(double dv, const double *__rest
     for (int j = threadIdx.x; j < M; j += blockDim.x)
         x[(size_t)c * M + j] = f2bf((float)(j == 0 ? d * inv_s_in : (F[j] - maxwell(j)) * sx));
     if (threadIdx.x == 0) {
+        if (stats) {
+            const unsigned long long cap = *(const unsigned long long *)(stats + kStCap);
+            if (cap) gate = fmin(gate, __longlong_as_double((long long)~cap));
+        }
         const bool gated = d < gate && rho > 0 && T > 0;
         // judge the gated cells of one 64-cell index range in judge_every per evaluation
         // (rotating), so that at most 64 served cells per evaluation are also convolved
@@ -181,7 +193,10 @@ __global__ void __launch_bounds__(256) k_finish(double dv, Basis li, const doubl
     const float *Y = y + (size_t)c * M;
     if (!judged) {
         for (int j = threadIdx.x; j < M; j += blockDim.x) Q[j] = sc * (double)Y[j];
-        if (threadIdx.x == 0) atomicAdd(&stats[0], 1u);
+        if (threadIdx.x == 0) {
+            atomicAdd(&stats[kStServed], 1u);
+            atomicAdd(&stats[kStEvalServed], 1u);
+        }
         return;
     }
     // judged: |P D|^2 = |D|^2 - sum_a (e_a . D)^2 with D = Q_s - Q_c, same for Q_c
@@ -206,11 +221,27 @@ __global__ void __launch_bounds__(256) k_finish(double dv, Basis li, const doubl
     if (threadIdx.x == 0) {
         const double err = sqrt(fmax(D2, 0.0)) / (sqrt(fmax(C2, 0.0)) + floor_ * st[0] * st[8]);
         const float ef = (float)err;
-        atomicMax(&stats[2], __float_as_uint(ef));  // non-negative floats order as unsigned
-        atomicAdd(&stats[1], 1u);
-        if (err > tol) atomicAdd(&stats[3], 1u);
+        atomicMax(&stats[kStMaxErr], __float_as_uint(ef));  // non-negative floats order as unsigned
+        atomicAdd(&stats[kStJudged], 1u);
+        if (err > tol) {
+            atomicAdd(&stats[kStFailed], 1u);
+            atomicAdd(&stats[kStEvalFailed], 1u);
+            // cap the gate at this cell's deviation: the complement of the bits of a smaller
+            // positive double is a larger word
+            atomicMax((unsigned long long *)(stats + kStCap), ~(unsigned long long)__double_as_longlong(st[5]));
+        }
     }
     // the judged cell keeps the convolution result (fallback)
+}
+
+// After the selection of an evaluation: its served cells are unbounded if one of its judges
+// failed; the evaluation's counters restart.
+__global__ void k_judge_close(unsigned *__restrict__ stats) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (stats[kStEvalFailed]) stats[kStUnbounded] += stats[kStEvalServed];
+        stats[kStEvalServed] = 0;
+        stats[kStEvalFailed] = 0;
+    }
 }
 
 // y = Q / (rho |f - M|_2 s_out) for harvesting training targets (0 where f = M)
@@ -241,11 +272,11 @@ __global__ void k_targets(const double *__restrict__ state, const double *__rest
     }
 
 hipError_t launch_sur_prepare(int N, double dv, int n, const double *f, const long long *f_off, double gate,
-                              double s_in, int judge_every, int phase, double *state, unsigned short *x,
-                              hipStream_t s) {
+                              double s_in, int judge_every, int phase, const unsigned *stats, double *state,
+                              unsigned short *x, hipStream_t s) {
 #define BZ_PREP(NN)                                                                                             \
     hipLaunchKernelGGL(k_prepare<NN>, dim3(n), dim3(256), 0, s, dv, f, f_off, gate, 1.0 / s_in, judge_every, \
-                       phase, state, x)
+                       phase, stats, state, x)
     BZ_SUR_FOR_N(BZ_PREP)
 #undef BZ_PREP
     return hipGetLastError();
@@ -267,6 +298,7 @@ hipError_t launch_sur_finish(int N, double dv, const double *linv, int n, const 
                        stats)
     BZ_SUR_FOR_N(BZ_FIN)
 #undef BZ_FIN
+    hipLaunchKernelGGL(k_judge_close, dim3(1), dim3(64), 0, s, stats);
     return hipGetLastError();
 }
 

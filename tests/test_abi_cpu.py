@@ -24,7 +24,7 @@ def test_library_exports_every_declared_symbol():
     assert len(names) >= 20
     for n in names:
         assert hasattr(L, n), n
-    assert bz.bz_api_version() == 2
+    assert bz.bz_api_version() == 3
 
 
 def test_grid_validation_errors():

@@ -259,3 +259,42 @@ def test_served_and_judged_values_match_numpy_from_the_same_network_output(dev):
     assert s1["max_err"] == pytest.approx(np.nanmax(err), rel=1e-5)
     assert np.array_equal(got, Qc)   # judged cells keep the convolution result
     c.close()
+
+
+def test_failed_judge_caps_the_gate_and_counts_unbounded_cells(dev):
+    """The untrained closure (zero output) fails every judge.  Evaluation 1, judge_every = 2:
+    groups 0 and 2 are judged and fail, group 1 is served: its 64 cells are counted as
+    unbounded, and the gate is capped at the smallest judged deviation.  Evaluation 2 (groups
+    1 judged): only cells below that cap are gated; the judged ones among them fail and lower
+    the cap to their smallest deviation; the others are served and unbounded."""
+    m = ClosureModel(N, L, LAM, hidden=256, seed=31)
+    m.s_in, m.s_out = 0.05, 2.0 ** -6
+    n = 150
+    cells = _cells(n, 32)
+    c = bz.Collision([(N, L, LAM)], [0] * n, "batched_f32", weights_cache=m.wcache)
+    f = torch.from_numpy(c.pack(cells)).to(dev)
+    state = torch.zeros(n * 10, dtype=torch.float64, device=dev)
+    x = torch.zeros(n * N ** 3, dtype=torch.int16, device=dev)
+    bz.bz_closure_prepare(c.batch, f, 1e30, m.s_in, state, x)
+    d = state.view(n, 10)[:, 5].cpu().numpy()
+    grp = np.arange(n) // 64
+    desc = m.desc(gate=1e30, judge_every=2)
+    work = torch.zeros(bz.bz_closure_workspace_bytes(c.batch, desc), dtype=torch.uint8, device=dev)
+    q = torch.zeros(c.elems, dtype=torch.float64, device=dev)
+    bz.bz_closure_collide(c.batch, desc, f, q, work)
+    s1 = bz.bz_closure_read_stats(c.batch, desc, work)
+    j1 = grp % 2 == 0
+    cap1 = d[j1].min()
+    assert s1["judged"] == j1.sum() and s1["failed"] == j1.sum()
+    assert s1["served"] == (~j1).sum() == 64 and s1["unbounded"] == 64
+    assert s1["gate_cap"] == cap1
+    bz.bz_closure_collide(c.batch, desc, f, q, work)
+    s2 = bz.bz_closure_read_stats(c.batch, desc, work)
+    gated = d < cap1
+    j2 = gated & (grp % 2 == 1)
+    served2 = gated & ~j2
+    assert s2["judged"] == j2.sum() and s2["failed"] == j2.sum()
+    assert s2["served"] == served2.sum()
+    assert s2["unbounded"] == (served2.sum() if j2.any() else 0)
+    assert s2["gate_cap"] == (min(cap1, d[j2].min()) if j2.any() else cap1)
+    c.close()
