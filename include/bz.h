@@ -218,7 +218,7 @@ bz_status bz_batch_create(int n_cells, const int32_t *grid_of_cell, int n_grids,
  *                      the work items of all meshes and all cores in one
  *                      persistent launch from one queue: the FP32 items
  *                      ordered by cost, each naming its mesh (the variant
- *                      with FOLD 16 and four interleaved partials for every
+ *                      with FOLD 16 and two interleaved partials for every
  *                      mesh), and the FP64 core items spread through the
  *                      first 3/5 of it; the transforms stay one launch per
  *                      mesh and pass.  bz_batch_autotune may switch a batch

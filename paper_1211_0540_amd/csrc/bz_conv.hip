@@ -426,14 +426,15 @@ k_conv_core(int N, int nD, const double2 *__restrict__ cf, const int4 *__restric
 // Items of several meshes in one persistent launch: the mesh index sits in bits 24..27
 // of the item word; its descriptor (N, buffer offsets in the workspace, one ConvPass per
 // pass, its FP64 core) is read from a device table with wavefront-uniform loads.  Every
-// mesh runs the output-slot accumulation with FOLD 16 and four interleaved partials
-// (tuning variant 10), two wavefronts per SIMD.  Items with kCoreItemBit are rows of an
+// mesh runs the output-slot accumulation with FOLD 16 and two interleaved partials
+// (tuning variant 12: with the FP64 core as accurate as four, and 1% faster), two
+// wavefronts per SIMD.  Items with kCoreItemBit are rows of an
 // FP64 core (core_item): spread through the queue, their row loads overlap the FP32
 // arithmetic of the other wavefront on the SIMD.
 template <int N>
 __device__ __forceinline__ void multi_item(const MeshConvDesc &d, char *ws, int pass, const int4 item, lds_char *wl) {
     const ConvPass cp = d.ps.p[pass];
-    cells_f32_item<N, 16, 2, 0, 0, 4>((const float2 *)(ws + d.fh_bytes), (double2 *)(ws + d.qh_bytes), nullptr, cp,
+    cells_f32_item<N, 16, 2, 0, 0, 2>((const float2 *)(ws + d.fh_bytes), (double2 *)(ws + d.qh_bytes), nullptr, cp,
                                       item, wl, nullptr);
 }
 
@@ -674,6 +675,10 @@ hipError_t plain_launch(const PlainLaunch &p, hipStream_t s) {
 
 int conv_variant_count() { return (int)(sizeof(kVariantAcc) / sizeof(kVariantAcc[0])); }
 
+// The compensation form does not enter the rank: the FP64 total (in registers or in the
+// output slot) and the TwoSum (hi, lo) pair both carry the folded total to at least 48
+// bits, far below the FP32 rounding of the running sum between folds, which the fold
+// interval and the interleaved partials set.
 int conv_variant_accuracy_rank(int v) {
     if (v < 0 || v >= conv_variant_count()) return -1;
     return kVariantAcc[v].split * 1000 - kVariantAcc[v].fold;

@@ -542,7 +542,7 @@ def test_one_launch_for_several_meshes_equals_per_mesh_launches(dev):
     goc = [0] * 70 + [1] * 3 + [2] * 2
     merged = bz.Collision(meshes, goc, "batched_f32", weights_cache=_WCACHE)
     per = bz.Collision(meshes, goc, "batched_f32", weights_cache=_WCACHE, per_mesh=True)
-    per.set_variant(10)
+    per.set_variant(12)
     f = torch.from_numpy(merged.pack(cells)).to(dev)
     bz.bz_batch_timer(merged.batch, True)
     qa = merged.collide(f)
