@@ -560,3 +560,28 @@ def test_one_launch_for_several_meshes_equals_per_mesh_launches(dev):
         assert rel_l2(q[i], q_o) < TOL32, i
     merged.close()
     per.close()
+
+
+@pytest.mark.parametrize("meshes,counts,one", [
+    ([(8, 4.0, 1.0), (12, 5.0, 1.0), (20, 6.0, 1.0), (28, 7.0, 1.0)], [3, 66, 2, 1], True),
+    ([(8, 4.0, 1.0), (12, 5.0, 1.0), (16, 6.0, 1.0), (20, 6.0, 1.0), (24, 7.0, 1.0)], [2, 2, 65, 1, 1], False)])
+def test_one_launch_covers_every_mesh_size(dev, meshes, counts, one):
+    """FP32 with the default FP64 cores on the mesh sizes the other tests leave out of the one
+    launch (N = 8, 12, 20, 28: four meshes, the most one launch takes, ragged groups), and a
+    five-mesh batch, which falls back to one launch per mesh: sampled cells against the
+    oracle at 1e-5, conservation after projection."""
+    cells, goc = [], []
+    for gi, ((N, L, lam), k) in enumerate(zip(meshes, counts)):
+        cells += list(W.random_smooth_cells(k, N, L, seed=60 + N))
+        goc += [gi] * k
+    c = bz.Collision(meshes, goc, "batched_f32", weights_cache=_WCACHE)
+    assert bz.bz_batch_one_launch(c.batch) == one
+    f = torch.from_numpy(c.pack(cells)).to(dev)
+    q = c.unpack(c.project(c.collide(f)).cpu().numpy())
+    c.close()
+    start = np.cumsum([0] + counts)
+    for gi, (N, L, lam) in enumerate(meshes):
+        for i in sorted({start[gi], start[gi + 1] - 1}):
+            _, q_o, _, _ = oracle_for(N, L, lam).collide(cells[i])
+            assert rel_l2(q[i], q_o) < TOL32, (N, i, rel_l2(q[i], q_o))
+            assert_conserved(q[i], N, L)
