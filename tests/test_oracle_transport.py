@@ -258,3 +258,9 @@ def test_moments_and_marginal_of_a_maxwellian():
     assert np.allclose(u[0], (0.3, -0.2, 0.1), atol=1e-9)
     m = T.marginal_v1(f[0], Nw, Lw)
     assert m.sum() * (2 * Lw / Nw) == pytest.approx(rho[0], rel=1e-13)
+    # the v1 marginal of a Maxwellian is the 1-D Gaussian of rho, u1 and T (the mesh sums over
+    # v2, v3 of a smooth Gaussian are exact to far below 1e-8 here); a marginal over another
+    # axis would carry u2 or u3 instead
+    v1 = (2 * Lw / Nw) * (np.arange(Nw) - Nw // 2)
+    g = 1.7 * (2 * np.pi * 1.2) ** -0.5 * np.exp(-(v1 - 0.3) ** 2 / (2 * 1.2))
+    assert np.max(np.abs(m - g)) < 1e-8 * g.max()
