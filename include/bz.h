@@ -510,14 +510,15 @@ int bz_batch_one_launch(bz_batch b);
  * the record. */
 bz_status bz_batch_timer(bz_batch b, int enable);
 bz_status bz_batch_timer_read(bz_batch b, double *conv_ms, int *launches);
-/* The FP64 core launches (bz_grid_init_ex) are timed separately by the same
- * switch: their summed time and count as of the last bz_batch_timer_read. */
+/* The separate FP64 core launches of the per-mesh form (BZ_BATCH_PER_MESH)
+ * are timed by the same switch: their summed time and count as of the last
+ * bz_batch_timer_read (none when the cores run inside the one launch). */
 bz_status bz_batch_core_timer(bz_batch b, double *core_ms, int *launches);
-/* Size of the FP64 core kernel's persistent grid in wavefronts (0, the
- * default: eight per compute unit).  The core runs on a stream of the batch
- * (default priority) alongside the FP32 convolution, forked from and joined
- * to the caller's stream.  Results do not depend on it.  Errors: BZ_EINVAL for
- * a negative count. */
+/* Size of the separate FP64 core kernel's persistent grid in wavefronts (0,
+ * the default: eight per compute unit), for the per-mesh form, where the
+ * cores run on a stream of the batch (default priority), forked from and
+ * joined to the caller's stream.  Results do not depend on it.  Errors:
+ * BZ_EINVAL for a negative count. */
 bz_status bz_batch_set_core_waves(bz_batch b, int waves);
 
 const char *bz_status_string(bz_status s);

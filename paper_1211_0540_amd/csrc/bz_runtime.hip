@@ -453,8 +453,9 @@ struct bz_batch_s {
     // the caller's stream by events (created on the first closure call)
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    // FP64 core: its own stream of default priority, forked from and joined to the caller's
-    // stream around the FP32 convolution; persistent grid (wavefronts, 0: the default)
+    // FP64 cores of the per-mesh form: their own stream of default priority, forked from and
+    // joined to the caller's stream around the FP32 convolution; persistent grid (wavefronts,
+    // 0: the default)
     hipStream_t core_stream = nullptr;
     hipEvent_t ev_cfork = nullptr, ev_cjoin = nullptr;
     int core_waves = 0;
@@ -1300,8 +1301,9 @@ static ConvPasses conv_passes(const Part &p, bool f64) {
     return ps;
 }
 
-// Batched modes: forward transforms of every mesh, the FP64 cores on their own stream, the
-// convolution (one launch for all meshes, or one per mesh), then the inverse transforms.
+// Batched modes: forward transforms of every mesh, the convolution (one launch for all meshes
+// and their FP64 cores, or one per mesh with the cores on their own stream), then the inverse
+// transforms.
 static bz_status collide_batched(bz_batch b, const double *d_f, double *d_Qt, char *ws, hipStream_t s,
                                  const unsigned char *skip, const long long *slot_off) {
     double2 *scratch = (double2 *)(ws + b->ws_scratch);
