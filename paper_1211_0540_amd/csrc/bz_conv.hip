@@ -338,20 +338,23 @@ struct CoreOut {
     static constexpr int n = hi - lo + 1;
 };
 
+// am, aj: the half-widths of the two rows inside the ball (wavefront-uniform); entries beyond
+// them are zero, so they are neither loaded nor multiplied.
 template <int R, int KIND>
-__device__ __forceinline__ void core_step(const double2 *pm, const double2 *pj, const lds_double *wl,
+__device__ __forceinline__ void core_step(const double2 *pm, const double2 *pj, int am, int aj, const lds_double *wl,
                                           double2 (&acc)[CoreOut<R, KIND>::n]) {
     constexpr int S = 2 * R + 1, LO = CoreOut<R, KIND>::lo, HI = CoreOut<R, KIND>::hi;
     double2 jr[S];
 #pragma unroll
-    for (int t = 0; t < S; ++t) jr[t] = pj[t * kWave];
+    for (int t = 0; t < S; ++t) jr[t] = abs(t - R) <= aj ? pj[t * kWave] : make_double2(0.0, 0.0);
 #pragma unroll
     for (int tm = 0; tm < S; ++tm) {
+        if (abs(tm - R) > am) continue;
         const double2 mv = pm[tm * kWave];
 #pragma unroll
         for (int tj = 0; tj < S; ++tj) {
             const int e = tm + tj - 2 * R;   // k3 - N/2
-            if (e >= LO && e <= HI) {
+            if (e >= LO && e <= HI && abs(tj - R) <= aj) {
                 const double wt = wl[tm * S + tj];
                 const double px = fma(mv.x, jr[tj].x, -(mv.y * jr[tj].y));
                 const double py = fma(mv.x, jr[tj].y, mv.y * jr[tj].x);
@@ -363,8 +366,8 @@ __device__ __forceinline__ void core_step(const double2 *pm, const double2 *pj, 
 }
 
 template <int R, int KIND>
-__device__ __forceinline__ void core_rows(int N, const double2 *G, const int *steps, const double *ws, int s0, int s1,
-                                          double2 *o, lds_char *wl) {
+__device__ __forceinline__ void core_rows(int N, const double2 *G, const int *steps, const int *ext, const double *ws,
+                                          int s0, int s1, double2 *o, lds_char *wl) {
     constexpr int S = 2 * R + 1, WS = core_wstride(R), CH = WS * 8 / 1024;
     constexpr int LO = CoreOut<R, KIND>::lo, NO = CoreOut<R, KIND>::n;
     const int h = N / 2;
@@ -375,11 +378,11 @@ __device__ __forceinline__ void core_rows(int N, const double2 *G, const int *st
     __builtin_amdgcn_s_waitcnt(0);
     int buf = 0;
     for (int s = s0; s < s1; ++s) {
-        const int st = steps[s];
-        const double2 *pm = G + (size_t)(st & 0xffff) * S * kWave;
-        const double2 *pj = G + (size_t)(st >> 16) * S * kWave;
+        const int st = steps[s], dm = st & 0xffff, dj = st >> 16;
+        const double2 *pm = G + (size_t)dm * S * kWave;
+        const double2 *pj = G + (size_t)dj * S * kWave;
         if (s + 1 < s1) prefetch_weights<CH>(ws + WS, wl + (buf ^ 1) * WS * 8);
-        core_step<R, KIND>(pm, pj, (const lds_double *)(wl + buf * WS * 8), acc);
+        core_step<R, KIND>(pm, pj, ext[dm], ext[dj], (const lds_double *)(wl + buf * WS * 8), acc);
         ws += WS;
         buf ^= 1;
         __builtin_amdgcn_s_waitcnt(0);
@@ -394,24 +397,24 @@ __device__ __forceinline__ void core_rows(int N, const double2 *G, const int *st
 // One core item: group g, output row, kind; rows of the group from cf, weights of
 // step s at w + s * core_wstride(R), outputs into out [G][N^3][64].
 template <int R>
-__device__ __forceinline__ void core_item(int N, int nD, const double2 *cf, const int *steps, const double *w,
-                                          double2 *out, const int4 item, lds_char *wl) {
+__device__ __forceinline__ void core_item(int N, int nD, const double2 *cf, const int *steps, const int *ext,
+                                          const double *w, double2 *out, const int4 item, lds_char *wl) {
     constexpr int S = 2 * R + 1, WS = core_wstride(R);
     const int lane = threadIdx.x;
     const int g = item.x, row = item.y & 0xffff, kind = (item.y >> 16) & 3, s0 = item.z, s1 = item.w;
     double2 *const o = out + ((size_t)g * N * N * N + (size_t)row * N) * kWave + lane;
     const double2 *const G = cf + (size_t)g * nD * S * kWave + lane;
     const double *ws = w + (size_t)s0 * WS;
-    if (kind == 2) core_rows<R, 2>(N, G, steps, ws, s0, s1, o, wl);
-    else if (kind == 0) core_rows<R, 0>(N, G, steps, ws, s0, s1, o, wl);
-    else core_rows<R, 1>(N, G, steps, ws, s0, s1, o, wl);
+    if (kind == 2) core_rows<R, 2>(N, G, steps, ext, ws, s0, s1, o, wl);
+    else if (kind == 0) core_rows<R, 0>(N, G, steps, ext, ws, s0, s1, o, wl);
+    else core_rows<R, 1>(N, G, steps, ext, ws, s0, s1, o, wl);
 }
 
 template <int R>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 k_conv_core(int N, int nD, const double2 *__restrict__ cf, const int4 *__restrict__ items, int n_items,
-            unsigned *__restrict__ counter, const int *__restrict__ steps, const double *__restrict__ w,
-            double2 *__restrict__ out, const unsigned char *__restrict__ skip) {
+            unsigned *__restrict__ counter, const int *__restrict__ steps, const int *__restrict__ ext,
+            const double *__restrict__ w, double2 *__restrict__ out, const unsigned char *__restrict__ skip) {
     __shared__ __attribute__((aligned(16))) double wbuf[2 * core_wstride(R)];
     lds_char *const wl = lds_ptr(&wbuf[0]);
     for (;;) {
@@ -419,7 +422,7 @@ k_conv_core(int N, int nD, const double2 *__restrict__ cf, const int4 *__restric
         if (it >= n_items) break;
         const int4 item = items[it];
         if (skip && skip[item.x]) continue;   // the closure serves every cell of the group
-        core_item<R>(N, nD, cf, steps, w, out, item, wl);
+        core_item<R>(N, nD, cf, steps, ext, w, out, item, wl);
     }
 }
 
@@ -440,8 +443,8 @@ __device__ __forceinline__ void multi_item(const MeshConvDesc &d, char *ws, int 
 
 template <int R>
 __device__ __forceinline__ void multi_core(const MeshConvDesc &d, char *ws, const int4 item, lds_char *wl) {
-    core_item<R>(d.N, d.nD, (const double2 *)(ws + d.cf_bytes), d.core_steps, d.core_w, (double2 *)(ws + d.cq_bytes),
-                 item, wl);
+    core_item<R>(d.N, d.nD, (const double2 *)(ws + d.cf_bytes), d.core_steps, d.core_ext, d.core_w,
+                 (double2 *)(ws + d.cq_bytes), item, wl);
 }
 
 // LDS of the one-launch kernel: the largest FP32 step's weights (N = 32: 3 KiB) or the largest
@@ -697,7 +700,7 @@ static unsigned persistent_grid(int n_items) {
 template <int R>
 hipError_t core_launch(const CoreLaunch &p, unsigned grid, hipStream_t s) {
     hipLaunchKernelGGL(k_conv_core<R>, dim3(grid), dim3(64), 0, s, p.N, p.nD, p.cf, p.items, p.n_items, p.counter,
-                       p.steps, p.w, p.out, p.skip);
+                       p.steps, p.ext, p.w, p.out, p.skip);
     return hipGetLastError();
 }
 

@@ -237,6 +237,7 @@ struct CoreSched {
     int r = 0;                        // floor(sqrt(r2)), the per-axis half-width
     int nD = 0;                       // rows in the disk
     std::vector<int> disk_idx;        // N*N: index of row (a, b) in the disk, -1 outside
+    std::vector<int> disk_ext;        // nD: the row's half-width in m3 inside the ball, floor(sqrt(r2 - rho^2))
     std::vector<int> row_steps;       // N*N: core steps of output row (k1, k2)
     std::vector<long long> row_soff;  // N*N: first step of the row in the step list
     std::vector<int> steps;           // per step: disk index of the m row | (disk index of the j row) << 16
@@ -370,6 +371,7 @@ struct MeshConvDesc {
     // at these workspace offsets, core steps and core weights (device)
     long long cf_bytes, cq_bytes;
     const int *core_steps;
+    const int *core_ext;         // per disk row: its half-width in m3 inside the ball
     const double *core_w;
     int nD, core_r;
 };
@@ -402,6 +404,7 @@ struct CoreLaunch {
     int n_items;
     unsigned *counter;           // device, zeroed by the launcher's fill kernel
     const int *steps;            // device, CoreSched::steps
+    const int *ext;              // device, CoreSched::disk_ext
     const double *w;             // core weight stream, core_wstride(r) doubles per step
     double2 *out;                // [G][N^3][64]
     const unsigned char *skip;   // device, per group (may be NULL)

@@ -301,7 +301,12 @@ static void build_core(bz_grid_s *g, int r2) {
     c.disk_idx.assign(N * N, -1);
     for (int a = 0; a < N; ++a)
         for (int b = 0; b < N; ++b)
-            if ((a - h) * (a - h) + (b - h) * (b - h) <= r2) c.disk_idx[a * N + b] = c.nD++;
+            if ((a - h) * (a - h) + (b - h) * (b - h) <= r2) {
+                c.disk_idx[a * N + b] = c.nD++;
+                int e = 0;
+                while ((e + 1) * (e + 1) <= r2 - (a - h) * (a - h) - (b - h) * (b - h)) ++e;
+                c.disk_ext.push_back(e);
+            }
     c.row_steps.assign(N * N, 0);
     c.row_soff.assign(N * N, 0);
     for (int k1 = 0; k1 < N; ++k1)
@@ -415,6 +420,7 @@ struct Part {
     int n_core_items = 0;
     int *d_core_steps = nullptr;
     int *d_disk_idx = nullptr;
+    int *d_disk_ext = nullptr;
     // workspace offsets (bytes)
     size_t ws_fh = 0, ws_qh = 0, ws_counter = 0;
     size_t ws_cf = 0, ws_cq = 0, ws_ccounter = 0;
@@ -757,7 +763,7 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
         std::memcpy(host.data() + o, src, bytes);
         return o;
     };
-    struct Offs { size_t f_off, fh_base, row, blk, zero, items, e3, core_items, core_steps, disk; };
+    struct Offs { size_t f_off, fh_base, row, blk, zero, items, e3, core_items, core_steps, disk, disk_ext; };
     std::vector<Offs> offs;
     size_t ws = 0, scratch = 0;
     for (Part &p : b->parts) {
@@ -852,6 +858,7 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
                 o.core_items = put(ci.data(), ci.size() * sizeof(int4));
                 o.core_steps = put(cs.steps.data(), cs.steps.size() * sizeof(int));
                 o.disk = put(cs.disk_idx.data(), cs.disk_idx.size() * sizeof(int));
+                o.disk_ext = put(cs.disk_ext.data(), cs.disk_ext.size() * sizeof(int));
             }
         }
         offs.push_back(o);
@@ -991,6 +998,7 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
             p.d_core_items = (int4 *)(base + offs[i].core_items);
             p.d_core_steps = (int *)(base + offs[i].core_steps);
             p.d_disk_idx = (int *)(base + offs[i].disk);
+            p.d_disk_ext = (int *)(base + offs[i].disk_ext);
         }
     }
     *out = b.release();
@@ -1049,6 +1057,7 @@ bz_status bz_batch_set_weights(bz_batch b, int grid_index, int kind, const void 
                 d[i].cf_bytes = (long long)p.ws_cf;
                 d[i].cq_bytes = (long long)p.ws_cq;
                 d[i].core_steps = p.d_core_steps;
+                d[i].core_ext = p.d_disk_ext;
                 d[i].core_w = (const double *)((const char *)p.w + core_base_bytes(p.g));
                 d[i].nD = cs.nD;
                 d[i].core_r = cs.r;
@@ -1334,7 +1343,7 @@ static bz_status collide_batched(bz_batch b, const double *d_f, double *d_Qt, ch
         }
         const CoreSched &cs = p.g->sched.core;
         const CoreLaunch co{p.g->N, cs.r, cs.nD, (const double2 *)(ws + p.ws_cf), p.d_core_items, p.n_core_items,
-                            (unsigned *)(ws + p.ws_ccounter), p.d_core_steps,
+                            (unsigned *)(ws + p.ws_ccounter), p.d_core_steps, p.d_disk_ext,
                             (const double *)((const char *)p.w + core_base_bytes(p.g)), (double2 *)(ws + p.ws_cq),
                             skip, b->core_waves};
         std::pair<hipEvent_t, hipEvent_t> ce{};
