@@ -572,8 +572,10 @@ class Collision:
     mode: one of MODE_NAMES or BZ_MODE_*; schedule: "symmetric" (conjugate
     symmetry halves the batched sum, the default) or "full"; fine_split: work
     items sized for a single 64-cell group to fill the device (for batches of
-    which the gated closure convolves only a few groups).  Weight buffers may be
-    shared between Collision objects through `weights_cache`.
+    which the gated closure convolves only a few groups); per_mesh: one
+    convolution launch per mesh (BZ_BATCH_PER_MESH) instead of the one launch for
+    all meshes and FP64 cores.  Weight buffers may be shared between Collision
+    objects through `weights_cache`.
     """
 
     def __init__(self, meshes, grid_of_cell, mode="batched_f32", weights_cache=None, device="cuda",
