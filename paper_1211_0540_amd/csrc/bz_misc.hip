@@ -10,27 +10,24 @@ namespace {
 // Projection.  C has rows dv^3 {1, v1, v2, v3, |v|^2}.  With C C^T = L L^T,
 // the rows of E = L^{-1} C are orthonormal and the minimiser of |Qt - Q|^2
 // subject to C Q = 0 is Q = Qt - E^T (E Qt), the same operator as
-// Qt - C^T (C C^T)^{-1} C Qt but applied through an orthonormal basis.  The
-// five moments are reduced in FP64 (per-thread sums, wavefront shuffles,
-// then LDS); the projection is applied twice, the second pass removing the
-// rounding residue of the first.
+// Qt - C^T (C C^T)^{-1} C Qt but applied through an orthonormal basis.  Per
+// cell the five raw moments s = C Qt are reduced in FP64 (per-thread sums,
+// wavefront shuffles, then LDS in a fixed order), mu = L^{-1} s and
+// nu = L^{-T} mu follow once per cell, and each value takes the correction
+// (C^T nu)_j = dv^3 (nu_0 + nu_1 v1 + nu_2 v2 + nu_3 v3 + nu_4 |v|^2); the
+// projection is applied twice, the second pass removing the rounding residue
+// of the first.
 // ---------------------------------------------------------------------------
 struct Linv {
     double a[25];
 };
 
-__device__ inline void basis(int N, double dv, const Linv &li, int j, double e[5]) {
+// the velocity of mesh point j
+__device__ inline void mesh_v(int N, double dv, int j, double &v1, double &v2, double &v3) {
     const int j1 = j / (N * N), j2 = (j / N) % N, j3 = j % N;
-    const double v1 = dv * (j1 - N / 2), v2 = dv * (j2 - N / 2), v3 = dv * (j3 - N / 2);
-    const double w = dv * dv * dv;
-    const double c[5] = {w, v1 * w, v2 * w, v3 * w, (v1 * v1 + v2 * v2 + v3 * v3) * w};
-#pragma unroll
-    for (int a = 0; a < 5; ++a) {
-        double s = 0.0;
-#pragma unroll
-        for (int b = 0; b <= a; ++b) s = fma(li.a[a * 5 + b], c[b], s);
-        e[a] = s;
-    }
+    v1 = dv * (j1 - N / 2);
+    v2 = dv * (j2 - N / 2);
+    v3 = dv * (j3 - N / 2);
 }
 
 __device__ inline double wave_sum(double x) {
@@ -41,16 +38,16 @@ __device__ inline double wave_sum(double x) {
 
 // One block of kProjThreads threads per cell.  Thread t owns the values j = t + i kProjThreads,
 // i < PER = ceil(N^3 / kProjThreads), and keeps them in registers through both passes, so the
-// cell is read and written once.  Indices and basis values are recomputed in every loop (the
+// cell is read and written once.  Indices and velocities are recomputed in every loop (the
 // empty asm hides the thread index from common-subexpression elimination, which would otherwise
-// keep PER indices and 5 PER basis values live across the passes and spill them).
+// keep PER indices and 3 PER velocities live across the passes and spill them).
 constexpr int kProjThreads = 1024;
 template <int N>
 __global__ void __launch_bounds__(kProjThreads) k_project(double dv, Linv li, double *__restrict__ q,
                                                           const long long *__restrict__ off) {
     constexpr int M = N * N * N, PER = (M + kProjThreads - 1) / kProjThreads;
     __shared__ double red[kProjThreads / 64][5];
-    __shared__ double mu[5];
+    __shared__ double nu[5];
     double *Q = q + off[blockIdx.x];
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double x[PER];
@@ -59,6 +56,7 @@ __global__ void __launch_bounds__(kProjThreads) k_project(double dv, Linv li, do
         const int j = threadIdx.x + i * kProjThreads;
         x[i] = j < M ? Q[j] : 0.0;
     }
+    const double w = dv * dv * dv;
     for (int pass = 0; pass < 2; ++pass) {
         double s[5] = {0, 0, 0, 0, 0};
         int tr = threadIdx.x;
@@ -67,10 +65,13 @@ __global__ void __launch_bounds__(kProjThreads) k_project(double dv, Linv li, do
         for (int i = 0; i < PER; ++i) {
             const int j = tr + i * kProjThreads;
             if (j < M) {
-                double e[5];
-                basis(N, dv, li, j, e);
-#pragma unroll
-                for (int a = 0; a < 5; ++a) s[a] = fma(e[a], x[i], s[a]);
+                double v1, v2, v3;
+                mesh_v(N, dv, j, v1, v2, v3);
+                s[0] += x[i];
+                s[1] = fma(v1, x[i], s[1]);
+                s[2] = fma(v2, x[i], s[2]);
+                s[3] = fma(v3, x[i], s[3]);
+                s[4] = fma(v1 * v1 + v2 * v2 + v3 * v3, x[i], s[4]);
             }
         }
 #pragma unroll
@@ -79,10 +80,23 @@ __global__ void __launch_bounds__(kProjThreads) k_project(double dv, Linv li, do
             if (lane == 0) red[wid][a] = t;
         }
         __syncthreads();
-        if (threadIdx.x < 5) {
-            double t = 0.0;
-            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w][threadIdx.x];
-            mu[threadIdx.x] = t;
+        if (threadIdx.x == 0) {
+            double t[5], m[5];
+            for (int b = 0; b < 5; ++b) {
+                double u = 0.0;
+                for (int v = 0; v < (int)(blockDim.x >> 6); ++v) u += red[v][b];
+                t[b] = u * w;   // C Qt
+            }
+            for (int a = 0; a < 5; ++a) {   // mu = L^{-1} C Qt
+                double u = 0.0;
+                for (int b = 0; b <= a; ++b) u = fma(li.a[a * 5 + b], t[b], u);
+                m[a] = u;
+            }
+            for (int b = 0; b < 5; ++b) {   // nu = L^{-T} mu, dv^3 folded in
+                double u = 0.0;
+                for (int a = b; a < 5; ++a) u = fma(li.a[a * 5 + b], m[a], u);
+                nu[b] = u * w;
+            }
         }
         __syncthreads();
         int tc = threadIdx.x;
@@ -91,11 +105,10 @@ __global__ void __launch_bounds__(kProjThreads) k_project(double dv, Linv li, do
         for (int i = 0; i < PER; ++i) {
             const int j = tc + i * kProjThreads;
             if (j < M) {
-                double e[5];
-                basis(N, dv, li, j, e);
-                double corr = 0.0;
-#pragma unroll
-                for (int a = 0; a < 5; ++a) corr = fma(e[a], mu[a], corr);
+                double v1, v2, v3;
+                mesh_v(N, dv, j, v1, v2, v3);
+                const double corr = fma(nu[4], v1 * v1 + v2 * v2 + v3 * v3,
+                                        fma(nu[3], v3, fma(nu[2], v2, fma(nu[1], v1, nu[0]))));
                 x[i] -= corr;
             }
         }
@@ -121,7 +134,7 @@ __global__ void k_axpy(size_t n, const double *__restrict__ a, const double *__r
         out[i] = y;
         bad |= !isfinite(y);
     }
-    if (bad) atomicOr(flag, 1u);
+    if (__syncthreads_or(bad ? 1 : 0) && threadIdx.x == 0) atomicOr(flag, 1u);
 }
 
 __global__ void k_heun_final(size_t n, const double *__restrict__ f, const double *__restrict__ fs,
@@ -133,7 +146,13 @@ __global__ void k_heun_final(size_t n, const double *__restrict__ f, const doubl
         bad |= !isfinite(y);
         neg |= y < 0.0;
     }
-    if (bad || neg) atomicOr(flag, (bad ? 1u : 0u) | (neg ? 2u : 0u));
+    // negative values are common in the far tails: one test per block, and the atomic only
+    // when the flag lacks the bit (atomics of every block on one word serialise the grid)
+    const int any_bad = __syncthreads_or(bad ? 1 : 0), any_neg = __syncthreads_or(neg ? 1 : 0);
+    if (threadIdx.x == 0 && (any_bad || any_neg)) {
+        const unsigned bits = (any_bad ? 1u : 0u) | (any_neg ? 2u : 0u);
+        if ((__atomic_load_n(flag, __ATOMIC_RELAXED) & bits) != bits) atomicOr(flag, bits);
+    }
 }
 
 __global__ void k_fill_u32(unsigned *p, int n, unsigned v) {
