@@ -78,20 +78,29 @@ def measured_traffic(cells):
 def core_products(N, r2):
     """Complex products per cell and evaluation of the FP64 core (r2 = 0: none): for every
     output row (k1, k2) within 2r of the centre, the pairs of disk rows m <= j with
-    m + j = k + N/2 (the core steps), (2r+1)^2 products each, or (r+1)(2r+1) on the derived
-    rows of the conjugate-symmetric schedule (only their outputs k3 <= N/2), which are
-    skipped when 2r < N/2."""
+    m + j = k + N/2 (the core steps), each the products of the two rows' entries inside the
+    ball (a row at distance rho from the centre has 2 floor(sqrt(r2 - rho^2)) + 1 of them), of
+    all outputs, or of the outputs k3 <= N/2 on the derived rows of the conjugate-symmetric
+    schedule, which are skipped when 2r < N/2."""
     if r2 < 1:
         return 0
     import numpy as np
     h = N // 2
-    r = int(np.floor(np.sqrt(r2)))
+    r = 0
     while (r + 1) ** 2 <= r2:
         r += 1
-    S = 2 * r + 1
     a = np.arange(N)
-    disk = ((a[:, None] - h) ** 2 + (a[None, :] - h) ** 2) <= r2
+    rho2 = (a[:, None] - h) ** 2 + (a[None, :] - h) ** 2
+    disk = rho2 <= r2
+    ext = np.floor(np.sqrt(np.maximum(r2 - rho2, 0) + 1e-9)).astype(int)
     pts = np.argwhere(disk)
+    t = np.arange(-r, r + 1)
+
+    def pairs(am, aj, half):
+        tm = t[np.abs(t) <= am][:, None]
+        tj = t[np.abs(t) <= aj][None, :]
+        return int(((tm + tj) <= 0).sum()) if half else tm.size * tj.size
+
     total = 0
     for k1 in range(max(0, h - 2 * r), min(N - 1, h + 2 * r) + 1):
         for k2 in range(max(0, h - 2 * r), min(N - 1, h + 2 * r) + 1):
@@ -102,8 +111,8 @@ def core_products(N, r2):
             ok = (j >= 0).all(1) & (j < N).all(1)
             ok[ok] &= disk[j[ok, 0], j[ok, 1]]
             m_le_j = (pts[:, 0] < j[:, 0]) | ((pts[:, 0] == j[:, 0]) & (pts[:, 1] <= j[:, 1]))
-            steps = int((ok & m_le_j).sum())
-            total += steps * (S * (r + 1) if derived else S * S)
+            for i in np.flatnonzero(ok & m_le_j):
+                total += pairs(ext[pts[i, 0], pts[i, 1]], ext[j[i, 0], j[i, 1]], derived)
     return total
 
 
