@@ -431,6 +431,18 @@ def mlp_profile_run(args, n_in=13824, hidden=1024, rows=512, cells=256):
     return 0
 
 
+def gpu_clocks():
+    """The GPU's current and maximum engine clock (rocm-smi, best effort): clocks as found."""
+    import subprocess
+    try:
+        out = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
+        d = json.loads(out.stdout)
+        card = next(iter(d.values()))
+        return {k: v for k, v in card.items() if "sclk" in k.lower()}
+    except Exception:
+        return None
+
+
 def cpu_model():
     """The host CPU's model name (Linux /proc/cpuinfo), or None."""
     try:
@@ -446,8 +458,8 @@ def cpu_model():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
@@ -634,7 +646,7 @@ def main():
             done += 1
         el = time.perf_counter() - t0
         cpu = {"value": done / el, "unit": "cell-collision evals/s", "cores": O.num_threads(), "kind": "oracle",
-               "cpu_model": cpu_model(),
+               "value_per_core": done / el / max(O.num_threads(), 1), "cpu_model": cpu_model(),
                "sample": f"{done} of the {nc} N=32 cells, one FP64 evaluation each (transform, O(N^6) sum, "
                          f"inverse, projection), {el:.1f} s"}
 
@@ -673,6 +685,7 @@ def main():
                      "traffic_gb_per_s": (traffic / (conv_avg_ms * 1e-3) / 1e9) if traffic else None,
                      "hbm_peak_gb_per_s": HBM_TBPS * 1e3},
         "cpu_baseline": cpu,
+        "gpu_clock": gpu_clocks(),
         "comparisons": comp,
     }
     print(json.dumps(out), flush=True)

@@ -503,6 +503,14 @@ bz_status bz_batch_autotune(bz_batch b, const double *d_f, double *d_Qt, void *d
  * for all its meshes and cores (see BZ_BATCH_PER_MESH), else 0 (also for
  * NULL). */
 int bz_batch_one_launch(bz_batch b);
+/* The variants remembered per (N, number of wavefront groups, mode) — by
+ * bz_batch_autotune or a load — as a text file of lines "N groups mode
+ * variant" (host only; a batch created later starts from a remembered
+ * variant).  bz_tuning_load merges a file into the process's memory, all of
+ * it or, on a malformed line, nothing.  Errors: BZ_EINVAL for a NULL path, a
+ * file that cannot be opened, written or parsed, or a variant out of range. */
+bz_status bz_tuning_save(const char *path);
+bz_status bz_tuning_load(const char *path);
 /* enable = 1: record a HIP event pair around every convolution launch of
  * this batch (on the stream the launch uses); enable = 0: stop recording.
  * bz_batch_timer_read synchronises on the recorded events, returns the

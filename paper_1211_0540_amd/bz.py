@@ -144,6 +144,8 @@ def lib():
         "bz_batch_timer_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
         "bz_batch_core_timer": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
         "bz_batch_one_launch": (ctypes.c_int, [_vp]),
+        "bz_tuning_save": (ctypes.c_int, [ctypes.c_char_p]),
+        "bz_tuning_load": (ctypes.c_int, [ctypes.c_char_p]),
         "bz_step_flags": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_uint), _vp]),
         "bz_status_str": (ctypes.c_char_p, [ctypes.c_int]),
         "bz_collide_batch_static": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
@@ -547,6 +549,14 @@ def bz_collide_batch_static(b: int, f, qt, stream=None) -> None:
     _dev(f, "f")
     _dev(qt, "Qt")
     _check(lib().bz_collide_batch_static(_vp(b), _vp(_ptr(f)), _vp(_ptr(qt)), _stream(stream)))
+
+
+def bz_tuning_save(path: str) -> None:
+    _check(lib().bz_tuning_save(str(path).encode()))
+
+
+def bz_tuning_load(path: str) -> None:
+    _check(lib().bz_tuning_load(str(path).encode()))
 
 
 def bz_batch_one_launch(b: int) -> bool:

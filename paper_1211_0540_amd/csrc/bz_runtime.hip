@@ -506,9 +506,26 @@ static bool timer_pair(bz_batch_s *b, std::pair<hipEvent_t, hipEvent_t> &ev, boo
     return true;
 }
 
-// variant chosen per (N, groups, mode) by bz_batch_autotune in this process
+// variant chosen per (N, groups, mode) by bz_batch_autotune in this process (or loaded by
+// bz_tuning_load), guarded by g_tuned_mu
 static std::vector<std::pair<long long, int>> g_tuned;
+static std::mutex g_tuned_mu;
 static long long tune_key(int N, int groups, int mode) { return ((long long)N << 40) | ((long long)groups << 8) | mode; }
+static void remember_variant(long long key, int v) {
+    std::lock_guard<std::mutex> lock(g_tuned_mu);
+    for (auto &kv : g_tuned)
+        if (kv.first == key) {
+            kv.second = v;
+            return;
+        }
+    g_tuned.emplace_back(key, v);
+}
+static int recalled_variant(long long key, int fallback) {
+    std::lock_guard<std::mutex> lock(g_tuned_mu);
+    for (auto &kv : g_tuned)
+        if (kv.first == key) return kv.second;
+    return fallback;
+}
 
 }  // namespace bz
 
@@ -748,9 +765,7 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
         p.groups = (int)((p.cells.size() + kWave - 1) / kWave);
         // untuned default: the output-slot variant with interleaved partials from N = 24 on,
         // the in-register FP64 total with interleaved partials below (measured on MI355X)
-        p.variant = p.g->N >= 24 ? 10 : 13;
-        for (auto &kv : g_tuned)
-            if (kv.first == tune_key(p.g->N, p.groups, mode)) p.variant = kv.second;
+        p.variant = recalled_variant(tune_key(p.g->N, p.groups, mode), p.g->N >= 24 ? 10 : 13);
         b->parts.push_back(std::move(p));
     }
     // host tables, then one device buffer for all of them
@@ -1192,14 +1207,7 @@ bz_status bz_batch_autotune(bz_batch b, const double *d_f, double *d_Qt, void *d
             if (rv > rb || (rv == rb && t[i][v] < t[i][best])) best = v;
         }
         p.variant = best;
-        const long long key = tune_key(p.g->N, p.groups, b->mode);
-        bool found = false;
-        for (auto &kv : g_tuned)
-            if (kv.first == key) {
-                kv.second = best;
-                found = true;
-            }
-        if (!found) g_tuned.emplace_back(key, best);
+        remember_variant(tune_key(p.g->N, p.groups, b->mode), best);
     }
     // one launch for every mesh (and the cores) or one launch per mesh with the variants just
     // chosen: the whole evaluation is timed both ways and the faster kept
@@ -1232,6 +1240,45 @@ bz_status bz_batch_autotune(bz_batch b, const double *d_f, double *d_Qt, void *d
 }
 
 int bz_batch_one_launch(bz_batch b) { return b && b->d_multi_items && !b->per_mesh_now ? 1 : 0; }
+
+bz_status bz_tuning_save(const char *path) {
+    if (!path) return fail(BZ_EINVAL, "bz_tuning_save: NULL path");
+    std::FILE *fp = std::fopen(path, "w");
+    if (!fp) return fail(BZ_EINVAL, "bz_tuning_save: cannot open the file for writing");
+    std::fprintf(fp, "# bz tuning: N groups mode variant\n");
+    {
+        std::lock_guard<std::mutex> lock(g_tuned_mu);
+        for (const auto &kv : g_tuned)
+            std::fprintf(fp, "%lld %lld %lld %d\n", kv.first >> 40, (kv.first >> 8) & 0xffffffffLL, kv.first & 0xff,
+                         kv.second);
+    }
+    const bool ok = std::fclose(fp) == 0;
+    return ok ? BZ_OK : fail(BZ_EINVAL, "bz_tuning_save: write failed");
+}
+
+bz_status bz_tuning_load(const char *path) {
+    if (!path) return fail(BZ_EINVAL, "bz_tuning_load: NULL path");
+    std::FILE *fp = std::fopen(path, "r");
+    if (!fp) return fail(BZ_EINVAL, "bz_tuning_load: cannot open the file");
+    std::vector<std::pair<long long, int>> got;
+    char line[256];
+    bool bad = false;
+    while (std::fgets(line, sizeof line, fp)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        long long N, groups, mode;
+        int v;
+        if (std::sscanf(line, "%lld %lld %lld %d", &N, &groups, &mode, &v) != 4 || N < kMinN || N > kMaxN ||
+            groups < 1 || groups > 0xffffffffLL || mode < 0 || mode > 0xff || v < 0 || v >= bz_variant_count()) {
+            bad = true;
+            break;
+        }
+        got.emplace_back(tune_key((int)N, (int)groups, (int)mode), v);
+    }
+    std::fclose(fp);
+    if (bad) return fail(BZ_EINVAL, "bz_tuning_load: malformed line (N groups mode variant)");
+    for (const auto &kv : got) remember_variant(kv.first, kv.second);   // the whole file or nothing
+    return BZ_OK;
+}
 
 size_t bz_batch_elems(bz_batch b) { return b ? b->elems : 0; }
 size_t bz_batch_cell_offset(bz_batch b, int cell) {

@@ -244,3 +244,32 @@ def test_inelastic_grid_parameters():
         with pytest.raises(bz.BzError) as e:
             bz.bz_grid_create(16, 6.0, lam, bz.BZ_CORE_DEFAULT, beta)
         assert e.value.status == st
+
+
+def test_tuning_file_round_trip_and_validation(tmp_path):
+    """Remembered variants survive a save and a load (host only); a later load overrides an
+    entry; a malformed file or an out-of-range variant is rejected whole."""
+    a = tmp_path / "a.txt"
+    a.write_text("# comment\n32 3 1 10\n16 9 1 13\n")
+    bz.bz_tuning_load(str(a))
+    b = tmp_path / "b.txt"
+    bz.bz_tuning_save(str(b))
+    rows = {tuple(map(int, l.split())) for l in b.read_text().splitlines() if l and not l.startswith("#")}
+    assert {(32, 3, 1, 10), (16, 9, 1, 13)} <= rows
+    c = tmp_path / "c.txt"
+    c.write_text("32 3 1 12\n")
+    bz.bz_tuning_load(str(c))
+    bz.bz_tuning_save(str(b))
+    rows = {tuple(map(int, l.split())) for l in b.read_text().splitlines() if l and not l.startswith("#")}
+    assert (32, 3, 1, 12) in rows and (32, 3, 1, 10) not in rows
+    for text in ("32 3 1\n", "32 3 1 99\n", "33 1 1 0\n", "x y z w\n", "24 2 1 11\n32 0 1 4\n"):
+        bad = tmp_path / "bad.txt"
+        bad.write_text(text)
+        with pytest.raises(bz.BzError) as e:
+            bz.bz_tuning_load(str(bad))
+        assert e.value.status == bz.BZ_EINVAL
+    bz.bz_tuning_save(str(b))
+    assert (24, 2, 1, 11) not in {tuple(map(int, l.split())) for l in b.read_text().splitlines()
+                                  if l and not l.startswith("#")}
+    with pytest.raises(bz.BzError):
+        bz.bz_tuning_load(str(tmp_path / "missing.txt"))
