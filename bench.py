@@ -432,7 +432,7 @@ def mlp_profile_run(args, n_in=13824, hidden=1024, rows=512, cells=256):
 
 
 def gpu_clocks():
-    """The GPU's current and maximum engine clock (rocm-smi, best effort): clocks as found."""
+    """The GPU engine clock as rocm-smi reports it (best effort), read after the timed legs."""
     import subprocess
     try:
         out = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
@@ -685,7 +685,7 @@ def main():
                      "traffic_gb_per_s": (traffic / (conv_avg_ms * 1e-3) / 1e9) if traffic else None,
                      "hbm_peak_gb_per_s": HBM_TBPS * 1e3},
         "cpu_baseline": cpu,
-        "gpu_clock": gpu_clocks(),
+        "gpu_clock_after_run": gpu_clocks(),
         "comparisons": comp,
     }
     print(json.dumps(out), flush=True)
