@@ -398,11 +398,13 @@ __device__ __forceinline__ void core_rows(int N, const double2 *G, const int *st
 // step s at w + s * core_wstride(R), outputs into out [G][N^3][64].
 template <int R>
 __device__ __forceinline__ void core_item(int N, int nD, const double2 *cf, const int *steps, const int *ext,
-                                          const double *w, double2 *out, const int4 item, lds_char *wl) {
+                                          const double *w, double2 *out, long long pstride, const int4 item,
+                                          lds_char *wl) {
     constexpr int S = 2 * R + 1, WS = core_wstride(R);
     const int lane = threadIdx.x;
-    const int g = item.x, row = item.y & 0xffff, kind = (item.y >> 16) & 3, s0 = item.z, s1 = item.w;
-    double2 *const o = out + ((size_t)g * N * N * N + (size_t)row * N) * kWave + lane;
+    const int g = item.x, row = item.y & 0xffff, kind = (item.y >> 16) & 3, piece = (item.y >> 20) & 0xf;
+    const int s0 = item.z, s1 = item.w;
+    double2 *const o = out + (size_t)piece * pstride + ((size_t)g * N * N * N + (size_t)row * N) * kWave + lane;
     const double2 *const G = cf + (size_t)g * nD * S * kWave + lane;
     const double *ws = w + (size_t)s0 * WS;
     if (kind == 2) core_rows<R, 2>(N, G, steps, ext, ws, s0, s1, o, wl);
@@ -414,7 +416,8 @@ template <int R>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 k_conv_core(int N, int nD, const double2 *__restrict__ cf, const int4 *__restrict__ items, int n_items,
             unsigned *__restrict__ counter, const int *__restrict__ steps, const int *__restrict__ ext,
-            const double *__restrict__ w, double2 *__restrict__ out, const unsigned char *__restrict__ skip) {
+            const double *__restrict__ w, double2 *__restrict__ out, long long pstride,
+            const unsigned char *__restrict__ skip) {
     __shared__ __attribute__((aligned(16))) double wbuf[2 * core_wstride(R)];
     lds_char *const wl = lds_ptr(&wbuf[0]);
     for (;;) {
@@ -422,7 +425,7 @@ k_conv_core(int N, int nD, const double2 *__restrict__ cf, const int4 *__restric
         if (it >= n_items) break;
         const int4 item = items[it];
         if (skip && skip[item.x]) continue;   // the closure serves every cell of the group
-        core_item<R>(N, nD, cf, steps, ext, w, out, item, wl);
+        core_item<R>(N, nD, cf, steps, ext, w, out, pstride, item, wl);
     }
 }
 
@@ -444,7 +447,7 @@ __device__ __forceinline__ void multi_item(const MeshConvDesc &d, char *ws, int 
 template <int R>
 __device__ __forceinline__ void multi_core(const MeshConvDesc &d, char *ws, const int4 item, lds_char *wl) {
     core_item<R>(d.N, d.nD, (const double2 *)(ws + d.cf_bytes), d.core_steps, d.core_ext, d.core_w,
-                 (double2 *)(ws + d.cq_bytes), item, wl);
+                 (double2 *)(ws + d.cq_bytes), d.cq_pstride, item, wl);
 }
 
 // LDS of the one-launch kernel: the largest FP32 step's weights (N = 32: 3 KiB) or the largest
@@ -467,7 +470,7 @@ k_conv_cells_f32_multi(const int4 *__restrict__ items, int n_items, unsigned *__
         const int mi = (item.y >> 24) & 0xf, pass = (item.y >> 20) & 0xf;
         const MeshConvDesc &d = desc[mi];
         if (item.y & kCoreItemBit) {
-            const int4 ci = make_int4(item.x, item.y & 0x3ffff, item.z, item.w);
+            const int4 ci = make_int4(item.x, item.y & 0xffffff, item.z, item.w);
             switch (d.core_r) {
             case 1: multi_core<1>(d, ws, ci, wl); break;
             case 2: multi_core<2>(d, ws, ci, wl); break;
@@ -700,7 +703,7 @@ static unsigned persistent_grid(int n_items) {
 template <int R>
 hipError_t core_launch(const CoreLaunch &p, unsigned grid, hipStream_t s) {
     hipLaunchKernelGGL(k_conv_core<R>, dim3(grid), dim3(64), 0, s, p.N, p.nD, p.cf, p.items, p.n_items, p.counter,
-                       p.steps, p.ext, p.w, p.out, p.skip);
+                       p.steps, p.ext, p.w, p.out, p.pstride, p.skip);
     return hipGetLastError();
 }
 

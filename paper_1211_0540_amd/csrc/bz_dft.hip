@@ -409,20 +409,24 @@ __global__ void __launch_bounds__(256) k_dftg_fwd3(const double2 *__restrict__ T
 // The core holds it for the direct rows and for k3 = 0 of the derived rows; elsewhere a derived
 // output is the conjugate of its mirror N - k (the core pairs are interior, and the weights even).
 template <int N>
-__device__ __forceinline__ void add_core(double2 (&x)[N], const double2 *__restrict__ core, int cr, size_t gl, int k2,
-                                         int k3) {
+__device__ __forceinline__ void add_core(double2 (&x)[N], const CoreAdd &ca, size_t gl, int k2, int k3) {
     constexpr int h = N / 2;
-    if (!core || abs(k2 - h) > 2 * cr || abs(k3 - h) > 2 * cr) return;
+    const int cr = ca.r;
+    if (!ca.core || abs(k2 - h) > 2 * cr || abs(k3 - h) > 2 * cr) return;
 #pragma unroll
     for (int k1 = 0; k1 < N; ++k1) {
         if (abs(k1 - h) > 2 * cr) continue;
-        double2 c;
-        if (herm_derived_row(N, k1, k2) && k3 >= 1) {
-            c = core[gl + ((size_t)((N - k1) * N + (N - k2)) * N + (N - k3)) * kWave];
-            c.y = -c.y;
-        } else {
-            c = core[gl + ((size_t)(k1 * N + k2) * N + k3) * kWave];
+        const bool mirrored = herm_derived_row(N, k1, k2) && k3 >= 1;
+        const size_t o = mirrored ? gl + ((size_t)((N - k1) * N + (N - k2)) * N + (N - k3)) * kWave
+                                  : gl + ((size_t)(k1 * N + k2) * N + k3) * kWave;
+        // the partial sums of the row's step pieces, in piece order
+        double2 c = ca.core[o];
+        for (int p = 1; p < ca.parts; ++p) {
+            const double2 t = ca.core[o + (size_t)p * ca.pstride];
+            c.x += t.x;
+            c.y += t.y;
         }
+        if (mirrored) c.y = -c.y;
         x[k1].x += c.x;
         x[k1].y += c.y;
     }
@@ -430,7 +434,7 @@ __device__ __forceinline__ void add_core(double2 (&x)[N], const double2 *__restr
 
 template <int N>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_dftg_inv1_herm(const double2 *__restrict__ qh, int nA, long long pstride,
-                                                        const double2 *__restrict__ core, int cr,
+                                                        const CoreAdd core,
                                                         double2 *__restrict__ S,
     const unsigned char *__restrict__ skip) {
     BZ_LINE_SETUP
@@ -486,14 +490,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
             x[k1] = make_double2(i.x + e.x, e.y - i.y);
         }
     }
-    add_core<N>(x, core, cr, gl, k2, k3);
+    add_core<N>(x, core, gl, k2, k3);
     line_dft<N, +1>(x, S + gl + (size_t)line * kWave, (size_t)N * N * kWave, 1.0);
 }
 
 // inverse, axis 1: line (k2, k3): sum of the partial buffers (k1, k2, k3) -> S (j1, k2, k3)
 template <int N>
 __global__ void __launch_bounds__(256) k_dftg_inv1(const double2 *__restrict__ qh, int nparts, long long pstride,
-                                                   const double2 *__restrict__ core, int cr,
+                                                   const CoreAdd core,
                                                    double2 *__restrict__ S,
     const unsigned char *__restrict__ skip) {
     BZ_LINE_SETUP
@@ -510,7 +514,7 @@ __global__ void __launch_bounds__(256) k_dftg_inv1(const double2 *__restrict__ q
         }
         x[j] = a;
     }
-    add_core<N>(x, core, cr, gb * kWave + lane, k2, k3);
+    add_core<N>(x, core, gb * kWave + lane, k2, k3);
     line_dft<N, +1>(x, S + off, (size_t)N * N * kWave, 1.0);
 }
 
@@ -575,10 +579,10 @@ hipError_t grouped_inverse(double L, int nc, const double2 *qh, int nparts, long
     const double dz = kPi / L;
     const double scale = pow(2.0 * kPi, -1.5) * dz * dz * dz;
     if (herm.on)
-        hipLaunchKernelGGL(k_dftg_inv1_herm<N>, grid, dim3(256), 0, s, qh, herm.nA, pstride, core.core, core.r, S,
+        hipLaunchKernelGGL(k_dftg_inv1_herm<N>, grid, dim3(256), 0, s, qh, herm.nA, pstride, core, S,
                            skip);
     else
-        hipLaunchKernelGGL(k_dftg_inv1<N>, grid, dim3(256), 0, s, qh, nparts, pstride, core.core, core.r, S, skip);
+        hipLaunchKernelGGL(k_dftg_inv1<N>, grid, dim3(256), 0, s, qh, nparts, pstride, core, S, skip);
     hipLaunchKernelGGL(k_dftg_inv2<N>, grid, dim3(256), 0, s, S, T, skip);
     hipLaunchKernelGGL(k_dftg_inv3<N>, grid, dim3(256), 0, s, T, nc, scale, qt, q_off, skip);
     return hipGetLastError();

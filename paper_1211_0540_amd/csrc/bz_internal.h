@@ -177,8 +177,10 @@ struct HermAssembly {
 // for the outputs k with every |k_d - N/2| <= 2r of the direct rows, and of the
 // derived rows at k3 = 0; NULL when the core is off.
 struct CoreAdd {
-    const double2 *core;
+    const double2 *core;         // `parts` partial sums [G][N^3][64], pstride apart (complex units)
     int r;
+    int parts;
+    long long pstride;
 };
 
 // ---------------------------------------------------------------------------
@@ -369,7 +371,7 @@ struct MeshConvDesc {
     ConvPasses ps;
     // FP64 core of the mesh (core_r = 0: none): rows [G][nD][2r+1][64] and sums [G][N^3][64]
     // at these workspace offsets, core steps and core weights (device)
-    long long cf_bytes, cq_bytes;
+    long long cf_bytes, cq_bytes, cq_pstride;
     const int *core_steps;
     const int *core_ext;         // per disk row: its half-width in m3 inside the ball
     const double *core_w;
@@ -377,6 +379,8 @@ struct MeshConvDesc {
 };
 // bit 28 of an item's row word marks an FP64 core item in the one-launch queue
 constexpr int kCoreItemBit = 1 << 28;
+// most step pieces of one core row (bits 20..23 of a core item's row word)
+constexpr int kCoreMaxParts = 4;
 struct MultiLaunch {
     const int4 *items;
     int n_items;
@@ -394,9 +398,9 @@ int conv_variant_count();
 int conv_variant_accuracy_rank(int v);
 hipError_t launch_conv_cells(const CellsLaunch &p, bool f64, hipStream_t s);
 
-// FP64 core sum of one mesh (CoreSched): items (group, output row | kind << 16, first step, end step),
-// longest first; kind 2 writes the outputs k3 - N/2 in [-2r, 2r], kind 0 those in [-2r, 0],
-// kind 1 those in [1, 2r].
+// FP64 core sum of one mesh (CoreSched): items (group, output row | kind << 16 | piece << 20, first
+// step, end step), longest first; kind 2 writes the outputs k3 - N/2 in [-2r, 2r], kind 0 those in
+// [-2r, 0], kind 1 those in [1, 2r]; piece p of a row's steps writes partial sum p.
 struct CoreLaunch {
     int N, r, nD;
     const double2 *cf;           // [G][nD][2r+1][64] FP64 core rows
@@ -406,7 +410,8 @@ struct CoreLaunch {
     const int *steps;            // device, CoreSched::steps
     const int *ext;              // device, CoreSched::disk_ext
     const double *w;             // core weight stream, core_wstride(r) doubles per step
-    double2 *out;                // [G][N^3][64]
+    double2 *out;                // partial sums [piece][G][N^3][64], pstride apart (complex units)
+    long long pstride;
     const unsigned char *skip;   // device, per group (may be NULL)
     int waves;                   // persistent grid in wavefronts (0: eight per CU)
 };

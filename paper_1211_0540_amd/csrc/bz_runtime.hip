@@ -418,6 +418,7 @@ struct Part {
     bool core = false;
     int4 *d_core_items = nullptr;
     int n_core_items = 0;
+    int core_parts = 1;              // step pieces per core row, each with its own partial sum
     int *d_core_steps = nullptr;
     int *d_disk_idx = nullptr;
     int *d_disk_ext = nullptr;
@@ -857,15 +858,31 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
                 // conjugate-symmetric schedule are conjugates of their mirrors except at k3 = 0, which
                 // the outputs k3 <= N/2 (item kind 0) reach when 2r >= N/2; other rows take all their
                 // outputs (kind 2).
+                // A row's steps are cut into core_parts pieces, each summed into its own partial
+                // buffer, so that no core item runs longer than the longest FP32 item of the mesh
+                // (a core step, up to (2r+1)^2 FP64 products and two row loads, is counted as twice
+                // (2r+1)^2 FP32 pairs).  That matters when few groups are convolved, as under the
+                // gated closure: a central core row of one group would otherwise outlast them.
+                int max_core = 0;
+                long long max_conv = 1;
+                for (int row = 0; row < N * N; ++row) max_core = std::max(max_core, cs.row_steps[row]);
+                for (const int4 &it : items)
+                    max_conv = std::max(max_conv, (long long)(it.w - it.z) * pairs_per_step(N));
+                const long long S2 = (long long)(2 * cs.r + 1) * (2 * cs.r + 1);
+                p.core_parts = (int)std::min<long long>(
+                    kCoreMaxParts, std::max<long long>(1, (2 * S2 * max_core + max_conv - 1) / max_conv));
                 std::vector<int4> ci;
                 for (int gq = 0; gq < p.groups; ++gq)
                     for (int k1 = std::max(0, h - 2 * cs.r); k1 <= std::min(N - 1, h + 2 * cs.r); ++k1)
                         for (int k2 = std::max(0, h - 2 * cs.r); k2 <= std::min(N - 1, h + 2 * cs.r); ++k2) {
                             const int row = k1 * N + k2;
-                            const int a = (int)cs.row_soff[row], e = a + cs.row_steps[row];
+                            const int a = (int)cs.row_soff[row], n = cs.row_steps[row];
                             const bool derived = herm_derived_row(N, k1, k2);
                             if (derived && 2 * cs.r < h) continue;
-                            ci.push_back(make_int4(gq, row | ((derived ? 0 : 2) << 16), a, e));
+                            // every piece is an item (an empty one writes zeros to its partial sum)
+                            for (int q = 0; q < p.core_parts; ++q)
+                                ci.push_back(make_int4(gq, row | ((derived ? 0 : 2) << 16) | (q << 20),
+                                                       a + (n * q) / p.core_parts, a + (n * (q + 1)) / p.core_parts));
                         }
                 std::stable_sort(ci.begin(), ci.end(), [](const int4 &x, const int4 &y) { return x.w - x.z > y.w - y.z; });
                 p.n_core_items = (int)ci.size();
@@ -903,7 +920,7 @@ bz_status bz_batch_create_ex(int n_cells, const int32_t *grid_of_cell, int n_gri
             p.ws_cf = ws;
             ws = align256(ws + (size_t)p.groups * cs.nD * (2 * cs.r + 1) * kWave * 16);
             p.ws_cq = ws;
-            ws = align256(ws + (size_t)p.groups * M * kWave * 16);
+            ws = align256(ws + (size_t)p.core_parts * p.groups * M * kWave * 16);
             p.ws_ccounter = ws;
             ws = align256(ws + 256);
         }
@@ -1071,6 +1088,7 @@ bz_status bz_batch_set_weights(bz_batch b, int grid_index, int kind, const void 
                 const CoreSched &cs = p.g->sched.core;
                 d[i].cf_bytes = (long long)p.ws_cf;
                 d[i].cq_bytes = (long long)p.ws_cq;
+                d[i].cq_pstride = (long long)p.groups * p.g->N * p.g->N * p.g->N * kWave;
                 d[i].core_steps = p.d_core_steps;
                 d[i].core_ext = p.d_disk_ext;
                 d[i].core_w = (const double *)((const char *)p.w + core_base_bytes(p.g));
@@ -1392,7 +1410,7 @@ static bz_status collide_batched(bz_batch b, const double *d_f, double *d_Qt, ch
         const CoreLaunch co{p.g->N, cs.r, cs.nD, (const double2 *)(ws + p.ws_cf), p.d_core_items, p.n_core_items,
                             (unsigned *)(ws + p.ws_ccounter), p.d_core_steps, p.d_disk_ext,
                             (const double *)((const char *)p.w + core_base_bytes(p.g)), (double2 *)(ws + p.ws_cq),
-                            skip, b->core_waves};
+                            (long long)p.groups * p.g->N * p.g->N * p.g->N * kWave, skip, b->core_waves};
         std::pair<hipEvent_t, hipEvent_t> ce{};
         if (b->timing) {
             if (!timer_pair(b, ce, true)) return fail(BZ_EDEVICE, "bz_collide_batch: hipEventCreate failed");
@@ -1430,7 +1448,7 @@ static bz_status collide_batched(bz_batch b, const double *d_f, double *d_Qt, ch
         const CoreSched &cs = p.g->sched.core;
         const long long *f_off = slot_off ? slot_off : p.d_f_off;
         const long long pstride = (long long)p.groups * p.g->N * p.g->N * p.g->N * kWave;
-        const CoreAdd cadd{p.core ? (const double2 *)(ws + p.ws_cq) : nullptr, cs.r};
+        const CoreAdd cadd{p.core ? (const double2 *)(ws + p.ws_cq) : nullptr, cs.r, p.core_parts, pstride};
         const HermAssembly herm{p.herm, p.parts};
         double2 *qh = (double2 *)(ws + p.ws_qh);
         // groups whose cells are all served by the closure (skip) need no transforms: the
