@@ -439,7 +439,9 @@ typedef struct {
 } bz_closure_stats;
 
 /* Workspace of the closure calls: bz_step_workspace_bytes plus the closure's
- * per-cell state, network input and output and the network workspace. */
+ * per-cell state, network input and output, its counters and gate cap, and
+ * the network workspace.  Zero it before the first closure call with it (the
+ * counters and the cap start from its contents). */
 size_t bz_closure_workspace_bytes(bz_batch b, const bz_closure *c);
 /* Gate and network input for every cell (used to harvest training data):
  * d_state[n_cells][10] = (rho, u1, u2, u3, T, d, gated, 0, |M|_2, 0),
