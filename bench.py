@@ -292,7 +292,7 @@ def uneven_leg(torch, np, bz, W, n32_step_ms, steps=5):
                                             for k, v in errs.items()}}
 
 
-def closure_leg(args, torch, np, bz, W, N=24, L=7.0, snapshots=600, relax_cells=512):
+def closure_leg(args, torch, np, bz, W, N=24, L=7.0, snapshots=900, relax_cells=768):
     """Harvest (f, Q) pairs on the shock problem and homogeneous relaxations on the
     N^3 mesh, train the N^3-1024-1024-N^3 network with the library's kernels, then
     time Strang steps of the 256-cell shock problem with and without the gated closure
