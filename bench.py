@@ -385,6 +385,37 @@ def served_errors(torch, np, bz, col, desc, f, work, N):
             "judge_tol": desc.judge_tol}
 
 
+def uneven_profile_run(args):
+    """Heun steps of the 1024-cell uneven batch only (one persistent convolution launch per
+    evaluation for all three meshes and their cores): one JSON line with the step and the
+    convolution time, for profiler runs."""
+    import numpy as np
+    import torch
+    from paper_1211_0540_amd import bz
+    from paper_1211_0540_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    batch = W.uneven_batch(n_cells=1024)
+    meshes = [(16, 6.0, 1.0), (24, 7.0, 1.0), (32, 8.0, 1.0)]
+    gidx = [{16: 0, 24: 1, 32: 2}[int(n)] for n in batch.Ns]
+    col = bz.Collision(meshes, gidx, "batched_f32")
+    f = torch.from_numpy(col.pack(batch.cells)).cuda()
+    for _ in range(args.warmup):
+        col.step(f, 0.01)
+    torch.cuda.synchronize()
+    bz.bz_batch_timer_read(col.batch)  # clear
+    bz.bz_batch_timer(col.batch, True)
+    total_ms, _ = timed_steps(torch, lambda: col.step(f, 0.01), args.steps)
+    bz.bz_batch_timer(col.batch, False)
+    col.check()
+    conv_ms, launches = bz.bz_batch_timer_read(col.batch)
+    print(json.dumps({"profile_uneven": True, "cells": len(batch.Ns), "one_launch": bz.bz_batch_one_launch(col.batch),
+                      "ms_per_step": total_ms / args.steps, "conv_avg_ms": conv_ms / max(launches, 1),
+                      "kernel_src_sha": conv_source_sha()}), flush=True)
+    col.close()
+    return 0
+
+
 def mlp_profile_run(args, n_in=13824, hidden=1024, rows=512, cells=256):
     """Training steps (forward, backward, Adam) and serving forwards of the closure network at
     its configured shape on seeded synthetic BF16 inputs; one JSON line with the times and the
@@ -467,6 +498,9 @@ def main():
                     help="timed steps only (default launch configuration, no comparisons, no CPU leg)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
+    ap.add_argument("--profile-uneven", action="store_true",
+                    help="only timed Heun steps of the 1024-cell uneven batch (N = 16, 24, 32) in the default "
+                         "launch form, for kernel traces and counters")
     ap.add_argument("--profile-mlp", action="store_true",
                     help="only the closure network's kernels: training steps of 512 rows and forwards of 256 "
                          "cells of the N=24 network on synthetic data")
@@ -477,6 +511,8 @@ def main():
         return 2
     if args.profile_mlp:
         return mlp_profile_run(args)
+    if args.profile_uneven:
+        return uneven_profile_run(args)
 
     import numpy as np
     import torch
