@@ -19,7 +19,8 @@
 //   with the symmetrised weight (see bz_internal.h), so a step costs 6 VALU
 //   operations per visited pair: 4 for the complex product fhat_m fhat_j and 2
 //   FMAs that add its weighted parts to a fresh per-output partial of the step,
-//   plus 2 additions per output and step into the running sums.  Work items are popped from an atomic
+//   plus 2 additions per output and step into the running sums (and 2 more that
+//   combine two interleaved partials, where a variant keeps two).  Work items are popped from an atomic
 //   queue ordered longest first, so the launch is persistent.  Every item names
 //   its pass of the conjugate-symmetric schedule (bz_internal.h): which fhat
 //   copy it reads, which weight stream and which output buffer it writes; the
