@@ -9,13 +9,9 @@
 //   forward   Z1 = X W1^T, Z2 = A1 W2^T, Y = A2 W3^T         (weights stored [out][in])
 //   backward  dA2 = dY W3, dA1 = dZ2 W2                       (transposed copies W3, W2)
 //             dW3 = dY^T A2, dW2 = dZ2^T A1, dW1 = dZ1^T X     (transposed activations)
-// Tile 128 x 128 x 64 per 256-thread workgroup (4 waves of 64 x 64, 32 MFMAs
-// each per k tile): two LDS buffers, the next k tile loaded into registers and
-// stored to the other buffer while the current one feeds the MFMAs, so one
-// barrier per k tile.  The rows of a tile are 128 bytes; 16-byte chunk c of
-// row r sits at chunk c ^ (r & 7), so that the 16 lanes that read one chunk
-// of 16 consecutive rows hit different banks.  K must be a multiple of 32 (a
-// last half tile is zero-filled).
+// Tile 128 x 128 per 256-thread workgroup (4 waves of 64 x 64, 16 MFMAs each per
+// 32-deep k tile), the k tiles staged through LDS by direct-to-LDS loads, several
+// tiles in flight (k_gemm_nt).  K must be a multiple of 32.
 #include <cmath>
 #include <new>
 #include <vector>
@@ -49,85 +45,37 @@ __device__ inline float gelu_prime(float z) {
 
 enum { EPI_F32 = 0, EPI_GELU = 1, EPI_PARTIAL = 2 };
 
-constexpr int TBM = 128, TBN = 128, TBK = 64;
-constexpr int kTileBytes = TBM * TBK * 2;   // one operand tile, 16 KiB
+constexpr int TBM = 128, TBN = 128, TBK = 32;
+constexpr int kXcds = 8;   // accelerator complex dies of the chip, each with its own L2
 
-// EPI_F32:  C32[m][n] = alpha * acc + (bias ? bias[n] : 0)
-// EPI_GELU: Z = acc + bias[n]; C32 = Z; Cbf = bf16(gelu(Z))
-// EPI_PARTIAL (split K): workgroup z of gridDim.z sums the k tiles
-//           [z nk / Z, (z + 1) nk / Z) and writes its raw sums to C32 + z M ldc;
-//           k_splitk_reduce then adds the Z slices in order and applies the epilogue.
+// Tile (tm, tn) and split slice tz of this workgroup.  Workgroup w of the launch (x fastest,
+// then y, then z) runs on XCD w % 8, and the eight XCDs have their own L2, so each XCD takes a
+// contiguous range of the tiles, ordered split slice slowest and, within a slice, along the
+// smaller operand fastest: the workgroups of one XCD then share the tiles of the larger
+// operand, which is read from memory about once instead of once per XCD.
+__device__ __forceinline__ void gemm_tile(int M, int N, int &tm, int &tn, int &tz) {
+    const int Tn = gridDim.x, Tm = gridDim.y, T = Tn * Tm * gridDim.z;
+    const int w = blockIdx.x + Tn * (blockIdx.y + Tm * blockIdx.z);
+    const int q = T / kXcds, r = T % kXcds, x = w % kXcds, l = w / kXcds;
+    const int t = x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+    const int mn = t % (Tm * Tn);
+    tz = t / (Tm * Tn);
+    if (N > M) {
+        tm = mn % Tm;
+        tn = mn / Tm;
+    } else {
+        tn = mn % Tn;
+        tm = mn / Tn;
+    }
+}
+
+// Epilogue of a 128 x 128 tile: wave (wm, wn) holds the 64 x 64 block acc[i][j] (16 x 16
+// MFMA tiles; lane l holds column l % 16, rows 4 (l / 16) .. 4 (l / 16) + 3).
 template <int EPI>
-__global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const unsigned short *__restrict__ A, int lda,
-                                                 const unsigned short *__restrict__ B, int ldb, float alpha,
-                                                 const float *__restrict__ bias, float *__restrict__ C32, int ldc,
-                                                 unsigned short *__restrict__ Cbf, int ldcb) {
-    // [buffer][A, B][128 rows x 8 chunks of 16 bytes], 64 KiB
-    __shared__ __attribute__((aligned(16))) uint4 lds[2][2][TBM * 8];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
-    // global -> register loads: thread t moves chunks 4 (t % 2) .. 4 (t % 2) + 3 of row t / 2 of each tile
-    const int lr = tid >> 1, lc = (tid & 1) * 4;
-    const int am = m0 + lr, bn = n0 + lr;
-    const bool aok = am < M, bok = bn < N;
-    const uint4 *ap = (const uint4 *)(A + (size_t)(aok ? am : 0) * lda);
-    const uint4 *bp = (const uint4 *)(B + (size_t)(bok ? bn : 0) * ldb);
-    const uint4 z4 = make_uint4(0, 0, 0, 0);
-    const int kc = K / 8;                      // 16-byte chunks per row
-    const int nk_all = (K + TBK - 1) / TBK;
-    const int kt0 = (int)((long long)nk_all * blockIdx.z / gridDim.z);
-    const int nk = (int)((long long)nk_all * (blockIdx.z + 1) / gridDim.z);
-    // the four chunks of each operand live in named registers (an indexed array would be
-    // placed in LDS by the compiler)
-    uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
-#define BZ_LD(r, p, ok, c) r = (ok) && o + (c) < kc ? (p)[o + (c)] : z4
-    auto load = [&](int kt) {
-        const int o = kt * (TBK / 8) + lc;   // first chunk index along K
-        BZ_LD(ra0, ap, aok, 0); BZ_LD(ra1, ap, aok, 1); BZ_LD(ra2, ap, aok, 2); BZ_LD(ra3, ap, aok, 3);
-        BZ_LD(rb0, bp, bok, 0); BZ_LD(rb1, bp, bok, 1); BZ_LD(rb2, bp, bok, 2); BZ_LD(rb3, bp, bok, 3);
-    };
-#undef BZ_LD
-    auto store = [&](int buf) {
-        uint4 *la = &lds[buf][0][lr * 8], *lb = &lds[buf][1][lr * 8];
-        const int sw = lr & 7;
-        la[(lc + 0) ^ sw] = ra0; la[(lc + 1) ^ sw] = ra1; la[(lc + 2) ^ sw] = ra2; la[(lc + 3) ^ sw] = ra3;
-        lb[(lc + 0) ^ sw] = rb0; lb[(lc + 1) ^ sw] = rb1; lb[(lc + 2) ^ sw] = rb2; lb[(lc + 3) ^ sw] = rb3;
-    };
-    f32x4 acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (kt0 < nk) {
-        load(kt0);
-        store(0);
-    }
-    __syncthreads();
-    int cur = 0;
-    for (int kt = kt0; kt < nk; ++kt) {
-        if (kt + 1 < nk) load(kt + 1);
-#pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
-            bf16x8 af[4], bfr[4];
-            const int ch = kk * 4 + (lane >> 4);   // this lane's k chunk of the 32-deep half
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int row = wm * 64 + i * 16 + (lane & 15);
-                af[i] = *(const bf16x8 *)&lds[cur][0][row * 8 + (ch ^ (row & 7))];
-                const int col = wn * 64 + i * 16 + (lane & 15);
-                bfr[i] = *(const bf16x8 *)&lds[cur][1][col * 8 + (ch ^ (col & 7))];
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
-        }
-        if (kt + 1 < nk) store(cur ^ 1);
-        __syncthreads();
-        cur ^= 1;
-    }
+__device__ __forceinline__ void gemm_epilogue(const f32x4 (&acc)[4][4], int M, int N, int m0, int n0, int tz, int wm,
+                                              int wn, int lane, float alpha, const float *__restrict__ bias,
+                                              float *__restrict__ C32, int ldc, unsigned short *__restrict__ Cbf,
+                                              int ldcb) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -140,7 +88,7 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const unsi
                 const int row = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + r;
                 if (row >= M) continue;
                 if (EPI == EPI_PARTIAL) {
-                    C32[((size_t)blockIdx.z * M + row) * ldc + col] = acc[i][j][r];
+                    C32[((size_t)tz * M + row) * ldc + col] = acc[i][j][r];
                     continue;
                 }
                 const float z = alpha * acc[i][j][r] + bcol;
@@ -152,6 +100,107 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const unsi
                 }
             }
         }
+}
+
+// k tiles of 128 x 32 per operand (rows of 64 bytes: four 16-byte chunks) are copied
+// global -> LDS by direct-to-LDS loads (global_load_lds_dwordx4: each lane moves 16 bytes, the
+// wavefront 1 KiB, landing contiguously at a wavefront-uniform LDS address), so no registers
+// carry them: kStages LDS stages of 16 KiB, the loads of tile kt + kStages - 1 issued while
+// tile kt feeds the MFMAs, one barrier per tile.  Chunk c of row r sits at slot
+// c ^ ((r >> 2) & 3), so that the lanes that read one chunk of consecutive rows hit different
+// groups of four banks; a lane's global address picks the chunk that belongs at its LDS
+// slot.  Rows past M or N read row M - 1 or N - 1 (their results are never stored).
+constexpr int kStages = 3;
+constexpr int kCPR = TBK / 8;                 // 16-byte chunks per tile row
+constexpr int kLPW = TBM * kCPR / 256;        // 1 KiB loads per wavefront, operand and tile
+__device__ __forceinline__ int lds_slot(int row, int c) { return c ^ ((row >> 2) & 3); }
+
+// EPI_F32:  C32[m][n] = alpha * acc + (bias ? bias[n] : 0)
+// EPI_GELU: Z = acc + bias[n]; C32 = Z; Cbf = bf16(gelu(Z))
+// EPI_PARTIAL (split K): workgroup z of gridDim.z sums the k tiles
+//           [z nk / Z, (z + 1) nk / Z) and writes its raw sums to C32 + z M ldc;
+//           k_splitk_reduce then adds the Z slices in order and applies the epilogue.
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const unsigned short *__restrict__ A, int lda,
+                                                 const unsigned short *__restrict__ B, int ldb, float alpha,
+                                                 const float *__restrict__ bias, float *__restrict__ C32, int ldc,
+                                                 unsigned short *__restrict__ Cbf, int ldcb) {
+    // [stage][A, B][128 rows x 4 chunks of 16 bytes], 48 KiB
+    __shared__ __attribute__((aligned(16))) uint4 lds[kStages][2][TBM * kCPR];
+    typedef __attribute__((address_space(3))) char lds_char;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave >> 1, wn = wave & 1;
+    int tm, tn, tz;
+    gemm_tile(M, N, tm, tn, tz);
+    const int m0 = tm * TBM, n0 = tn * TBN;
+    const int nk_all = K / TBK;
+    const int kt0 = (int)((long long)nk_all * tz / gridDim.z);
+    const int nk = (int)((long long)nk_all * (tz + 1) / gridDim.z);
+    // this lane's chunk of each of the wavefront's 1 KiB loads per operand: LDS chunk
+    // p = (kLPW wave + i) 64 + lane of a tile, row p / kCPR, slot p % kCPR
+    const unsigned short *ga[kLPW], *gb[kLPW];
+#pragma unroll
+    for (int i = 0; i < kLPW; ++i) {
+        const int p = (kLPW * wave + i) * 64 + lane, row = p / kCPR, c = lds_slot(row, p % kCPR);
+        ga[i] = A + (size_t)min(m0 + row, M - 1) * lda + c * 8;
+        gb[i] = B + (size_t)min(n0 + row, N - 1) * ldb + c * 8;
+    }
+    lds_char *const base = (lds_char *)&lds[0][0][0];
+    auto issue = [&](int kt, int st) {
+        lds_char *da = base + (size_t)(st * 2 + 0) * (TBM * kCPR * 16) + (size_t)(kLPW * wave) * 1024;
+        lds_char *db = base + (size_t)(st * 2 + 1) * (TBM * kCPR * 16) + (size_t)(kLPW * wave) * 1024;
+        const int ko = kt * TBK;
+#pragma unroll
+        for (int i = 0; i < kLPW; ++i) {
+            __builtin_amdgcn_global_load_lds((const void *)(ga[i] + ko), (void __attribute__((address_space(3))) *)(da + i * 1024),
+                                             16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void *)(gb[i] + ko), (void __attribute__((address_space(3))) *)(db + i * 1024),
+                                             16, 0, 0);
+        }
+    };
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int st = 0; st < kStages - 1; ++st)
+        if (kt0 + st < nk) issue(kt0 + st, st);
+    for (int kt = kt0; kt < nk; ++kt) {
+        const int st = (kt - kt0) % kStages;
+        // this wavefront's loads of tile kt have landed once at most those of the tiles after
+        // it are outstanding (loads complete in issue order)
+        if (kt + kStages - 2 < nk) {
+            constexpr int n = (kStages - 2) * 2 * kLPW;
+            static_assert(n < 64, "vmcnt field");
+            __builtin_amdgcn_s_waitcnt((n & 0xF) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+        } else {
+            __builtin_amdgcn_s_waitcnt(0x0 | (0x7 << 4) | (0xF << 8));
+        }
+        // every wavefront's part of tile kt is in LDS, and every wavefront is done with tile
+        // kt - 1, whose stage the next loads overwrite.  A bare s_barrier: __syncthreads()
+        // adds a release fence, which waits for every outstanding load, the later tiles' too.
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (kt + kStages - 1 < nk) issue(kt + kStages - 1, (kt - kt0 + kStages - 1) % kStages);
+        bf16x8 af[4], bfr[4];
+        const int ch = lane >> 4;   // this lane's k chunk of the tile
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = wm * 64 + i * 16 + (lane & 15);
+            af[i] = *(const bf16x8 *)&lds[st][0][row * kCPR + lds_slot(row, ch)];
+            const int col = wn * 64 + i * 16 + (lane & 15);
+            bfr[i] = *(const bf16x8 *)&lds[st][1][col * kCPR + lds_slot(col, ch)];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    gemm_epilogue<EPI>(acc, M, N, m0, n0, tz, wm, wn, lane, alpha, bias, C32, ldc, Cbf, ldcb);
 }
 
 // Sum of the Z split-K slices P[z][M][N] in order z = 0, 1, ..., then the epilogue of EPI.
@@ -363,15 +412,15 @@ static size_t work_bytes(const bz_mlp_s *n, int B) {
 
 // C = alpha A B^T (+ bias, epilogue).  A product with fewer output tiles than
 // there are compute units and a long K is split over K into up to kMaxSplit
-// slices (at least 4 k tiles each) when the workspace slice buffer holds them.
+// slices (at least 256 deep each) when the workspace slice buffer holds them.
 static hipError_t gemm(int epi, int M, int N, int K, const unsigned short *A, int lda, const unsigned short *B, int ldb,
                        float alpha, const float *bias, float *C32, int ldc, unsigned short *Cbf, int ldcb,
                        const WorkView &wv, hipStream_t s) {
     dim3 grid((N + TBN - 1) / TBN, (M + TBM - 1) / TBM);
-    const int tiles = (int)(grid.x * grid.y), nk = (K + TBK - 1) / TBK;
+    const int tiles = (int)(grid.x * grid.y);
     int split = 1;
     if (tiles < 128) {
-        split = std::min(std::min(kMaxSplit, nk / 4), (256 + tiles - 1) / tiles);
+        split = std::min(std::min(kMaxSplit, K / 256), (256 + tiles - 1) / tiles);
         const size_t cap = wv.split_floats / ((size_t)M * N);
         if ((size_t)split > cap) split = (int)cap;
     }
