@@ -300,15 +300,29 @@ __global__ void __launch_bounds__(1024) k_col_sums(int rows, int cols, const uns
     }
 }
 
+// The three weight matrices' BF16 copies: master entries [off[k], off[k] + len[k]) go to
+// dst[k][i - off[k]].
+struct Bf16Copies {
+    size_t off[3], len[3];
+    unsigned short *dst[3];
+};
+
+// One Adam step over all parameters, which also writes the BF16 copy of every updated weight
+// (the same rounding as k_f32_to_bf16), so the copies need no second pass over the masters.
 __global__ void k_adam(size_t n, float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
-                       const float *__restrict__ g, float lr, float b1, float b2, float eps, float c1, float c2) {
+                       const float *__restrict__ g, float lr, float b1, float b2, float eps, float c1, float c2,
+                       Bf16Copies bc) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const float gi = g[i];
         const float mi = b1 * m[i] + (1.f - b1) * gi;
         const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
         m[i] = mi;
         v[i] = vi;
-        w[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+        const float wi = w[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+        w[i] = wi;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (i - bc.off[k] < bc.len[k]) bc.dst[k][i - bc.off[k]] = f2bf(wi);
     }
 }
 
@@ -452,14 +466,21 @@ static hipError_t transpose(int R, int C, const unsigned short *in, unsigned sho
     return hipGetLastError();
 }
 
+// W2^T and W3^T from the BF16 copies of W2 and W3
+static hipError_t refresh_transposes(const bz_mlp_s *n, const ParamView &pv, hipStream_t s) {
+    const size_t H = n->n_hid, O = n->n_out;
+    hipError_t e = transpose((int)H, (int)H, pv.W2, pv.W2t, s);
+    if (e == hipSuccess) e = transpose((int)O, (int)H, pv.W3, pv.W3t, s);
+    return e == hipSuccess ? hipGetLastError() : e;
+}
+
 static hipError_t refresh_bf16(const bz_mlp_s *n, const ParamView &pv, hipStream_t s) {
     const size_t H = n->n_hid, O = n->n_out, I = n->n_in;
     hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid1(H * I)), dim3(256), 0, s, H * I, pv.master + n->oW1, pv.W1);
     hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid1(H * H)), dim3(256), 0, s, H * H, pv.master + n->oW2, pv.W2);
     hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid1(O * H)), dim3(256), 0, s, O * H, pv.master + n->oW3, pv.W3);
-    hipError_t e = transpose((int)H, (int)H, pv.W2, pv.W2t, s);
-    if (e == hipSuccess) e = transpose((int)O, (int)H, pv.W3, pv.W3t, s);
-    return e == hipSuccess ? hipGetLastError() : e;
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? refresh_transposes(n, pv, s) : e;
 }
 
 static hipError_t forward(const bz_mlp_s *n, const ParamView &pv, const unsigned short *X, int B, const WorkView &wv,
@@ -593,10 +614,12 @@ bz_status bz_mlp_adam(bz_mlp n, void *d_params, const float *d_grad, int step, f
     ParamView pv = param_view(n, d_params);
     const float b1 = 0.9f, b2 = 0.999f;
     const float c1 = 1.0f / (1.0f - std::pow(b1, (float)step)), c2 = 1.0f / (1.0f - std::pow(b2, (float)step));
+    const size_t H = n->n_hid, O = n->n_out, I = n->n_in;
+    const Bf16Copies bc{{n->oW1, n->oW2, n->oW3}, {H * I, H * H, O * H}, {pv.W1, pv.W2, pv.W3}};
     hipLaunchKernelGGL(k_adam, dim3(grid1(n->n_params)), dim3(256), 0, s, n->n_params, pv.master, pv.m, pv.v, d_grad,
-                       lr, b1, b2, 1e-8f, c1, c2);
+                       lr, b1, b2, 1e-8f, c1, c2, bc);
     BZ_HIP(hipGetLastError(), "bz_mlp_adam");
-    BZ_HIP(refresh_bf16(n, pv, s), "bz_mlp_adam: bf16 copies");
+    BZ_HIP(refresh_transposes(n, pv, s), "bz_mlp_adam: transposed bf16 copies");
     return BZ_OK;
 }
 
