@@ -219,9 +219,44 @@ __global__ void __launch_bounds__(256) k_splitk_reduce(int M, int N, int Z, cons
     }
 }
 
-// out[c][r] = in[r][c] for an R x C BF16 matrix (32 x 32 tiles through LDS).
+// out[c][r] = in[r][c] for an R x C BF16 matrix, R and C multiples of 8, 16-byte aligned
+// rows.  Each wavefront moves a 64 x 64 tile and each lane an 8 x 8 block of it through its
+// registers: lane l takes block row l / 8 and block column l % 8, so that 8 lanes read 128
+// contiguous bytes of an input row and write 128 contiguous bytes of an output row.
 __global__ void __launch_bounds__(256) k_transpose_bf16(int R, int C, const unsigned short *__restrict__ in,
                                                         unsigned short *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int tiles_c = (C + 63) / 64;
+    const int tr = tile / tiles_c, tc = tile - tr * tiles_c;
+    const int r = tr * 64 + (lane >> 3) * 8, c = tc * 64 + (lane & 7) * 8;
+    if (r >= R || c >= C) return;
+    unsigned a[8][4];   // rows r .. r + 7, columns c .. c + 7, two per word
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const uint4 u = *(const uint4 *)(in + (size_t)(r + i) * C + c);
+        a[i][0] = u.x;
+        a[i][1] = u.y;
+        a[i][2] = u.z;
+        a[i][3] = u.w;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        // column c + j: element j of each row, i.e. half j % 2 of word j / 2
+        unsigned w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const unsigned lo = (a[2 * k][j / 2] >> (16 * (j % 2))) & 0xFFFFu;
+            const unsigned hi = (a[2 * k + 1][j / 2] >> (16 * (j % 2))) & 0xFFFFu;
+            w[k] = lo | (hi << 16);
+        }
+        *(uint4 *)(out + (size_t)(c + j) * R + r) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
+// The same for any R, C and alignment: 32 x 32 tiles through LDS, one element per access.
+__global__ void __launch_bounds__(256) k_transpose_bf16_any(int R, int C, const unsigned short *__restrict__ in,
+                                                            unsigned short *__restrict__ out) {
     __shared__ unsigned short t[32][33];
     const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
@@ -282,21 +317,35 @@ __global__ void k_gelu_bwd(size_t n, const float *__restrict__ dA, const float *
 // db[n] = alpha * sum_m bf2f(D[m][n])  (D is rows x cols BF16).  A block of 64 x 16
 // threads owns 64 columns; thread (c, t) sums the rows r = t (mod 16) of its column,
 // then the 16 partial sums are added in order.
-__global__ void __launch_bounds__(1024) k_col_sums(int rows, int cols, const unsigned short *__restrict__ D,
-                                                   float alpha, float *__restrict__ db) {
+// db[c] = alpha * sum over rows of D[r][c] (BF16 [rows][cols], cols a multiple of 8, 16-byte
+// aligned rows).  A block of 128 threads sums 64 columns: thread (tr, q) adds columns
+// 8q .. 8q + 7 of the rows tr, tr + 16, ... (one 16-byte load per row; 8 threads read 128
+// contiguous bytes of a row), then the 16 row-group partials are added in order.
+__global__ void __launch_bounds__(128) k_col_sums(int rows, int cols, const unsigned short *__restrict__ D,
+                                                  float alpha, float *__restrict__ db) {
     __shared__ float part[16][64];
-    const int tc = threadIdx.x & 63, tr = threadIdx.x >> 6;
+    const int tc = (threadIdx.x & 7) * 8, tr = threadIdx.x >> 3;
     const int c = blockIdx.x * 64 + tc;
-    float s = 0.f;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (c < cols)
-        for (int r = tr; r < rows; r += 16) s += bf2f(D[(size_t)r * cols + c]);
-    part[tr][tc] = s;
+        for (int r = tr; r < rows; r += 16) {
+            const uint4 u = *(const uint4 *)(D + (size_t)r * cols + c);
+            const unsigned w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                s[2 * k] += bf2f((unsigned short)(w[k] & 0xFFFFu));
+                s[2 * k + 1] += bf2f((unsigned short)(w[k] >> 16));
+            }
+        }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) part[tr][tc + k] = s[k];
     __syncthreads();
-    if (tr == 0 && c < cols) {
+    const int cc = blockIdx.x * 64 + threadIdx.x;
+    if (threadIdx.x < 64 && cc < cols) {
         float t = 0.f;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) t += part[i][tc];
-        db[c] = alpha * t;
+        for (int i = 0; i < 16; ++i) t += part[i][threadIdx.x];
+        db[cc] = alpha * t;
     }
 }
 
@@ -462,7 +511,18 @@ static hipError_t gemm(int epi, int M, int N, int K, const unsigned short *A, in
 }
 
 static hipError_t transpose(int R, int C, const unsigned short *in, unsigned short *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_transpose_bf16, dim3((C + 31) / 32, (R + 31) / 32), dim3(256), 0, s, R, C, in, out);
+    if (R % 8 || C % 8 || ((uintptr_t)in | (uintptr_t)out) % 16) {
+        hipLaunchKernelGGL(k_transpose_bf16_any, dim3((C + 31) / 32, (R + 31) / 32), dim3(256), 0, s, R, C, in, out);
+        return hipGetLastError();
+    }
+    const long long tiles = (long long)((R + 63) / 64) * ((C + 63) / 64);
+    hipLaunchKernelGGL(k_transpose_bf16, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, R, C, in, out);
+    return hipGetLastError();
+}
+
+static hipError_t col_sums(int rows, int cols, const unsigned short *D, float alpha, float *db, hipStream_t s) {
+    if (cols % 8 || (uintptr_t)D % 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_col_sums, dim3((cols + 63) / 64), dim3(128), 0, s, rows, cols, D, alpha, db);
     return hipGetLastError();
 }
 
@@ -507,21 +567,21 @@ static hipError_t backward(const bz_mlp_s *n, const ParamView &pv, const unsigne
     hipError_t e = transpose(B, O, wv.dY, wv.tA, s);
     if (e == hipSuccess) e = transpose(B, H, wv.A2, wv.tB, s);
     if (e == hipSuccess) e = gemm(EPI_F32, O, H, B, wv.tA, B, wv.tB, B, gs, nullptr, g + n->oW3, H, nullptr, 0, wv, s);
-    hipLaunchKernelGGL(k_col_sums, dim3((O + 63) / 64), dim3(1024), 0, s, B, O, wv.dY, gs, g + n->ob3);
+    if (e == hipSuccess) e = col_sums(B, O, wv.dY, gs, g + n->ob3, s);
     if (e == hipSuccess) e = gemm(EPI_F32, B, H, O, wv.dY, O, pv.W3t, O, gs, nullptr, wv.dA, H, nullptr, 0, wv, s);
     hipLaunchKernelGGL(k_gelu_bwd, dim3(grid1((size_t)B * H)), dim3(256), 0, s, (size_t)B * H, wv.dA, wv.Z2, wv.dZ);
     // layer 2 (dZ holds the true gradient dL/dZ2)
     if (e == hipSuccess) e = transpose(B, H, wv.dZ, wv.tA, s);
     if (e == hipSuccess) e = transpose(B, H, wv.A1, wv.tB, s);
     if (e == hipSuccess) e = gemm(EPI_F32, H, H, B, wv.tA, B, wv.tB, B, 1.f, nullptr, g + n->oW2, H, nullptr, 0, wv, s);
-    hipLaunchKernelGGL(k_col_sums, dim3((H + 63) / 64), dim3(1024), 0, s, B, H, wv.dZ, 1.f, g + n->ob2);
+    if (e == hipSuccess) e = col_sums(B, H, wv.dZ, 1.f, g + n->ob2, s);
     if (e == hipSuccess) e = gemm(EPI_F32, B, H, H, wv.dZ, H, pv.W2t, H, 1.f, nullptr, wv.dA, H, nullptr, 0, wv, s);
     hipLaunchKernelGGL(k_gelu_bwd, dim3(grid1((size_t)B * H)), dim3(256), 0, s, (size_t)B * H, wv.dA, wv.Z1, wv.dZ);
     // layer 1
     if (e == hipSuccess) e = transpose(B, H, wv.dZ, wv.tA, s);
     if (e == hipSuccess) e = transpose(B, I, X, wv.tB, s);
     if (e == hipSuccess) e = gemm(EPI_F32, H, I, B, wv.tA, B, wv.tB, B, 1.f, nullptr, g + n->oW1, I, nullptr, 0, wv, s);
-    hipLaunchKernelGGL(k_col_sums, dim3((H + 63) / 64), dim3(1024), 0, s, B, H, wv.dZ, 1.f, g + n->ob1);
+    if (e == hipSuccess) e = col_sums(B, H, wv.dZ, 1.f, g + n->ob1, s);
     return e == hipSuccess ? hipGetLastError() : e;
 }
 
