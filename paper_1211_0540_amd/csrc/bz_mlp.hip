@@ -358,17 +358,43 @@ struct Bf16Copies {
 
 // One Adam step over all parameters, which also writes the BF16 copy of every updated weight
 // (the same rounding as k_f32_to_bf16), so the copies need no second pass over the masters.
-__global__ void k_adam(size_t n, float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+// The first 4 n4 parameters four per thread and access (16-byte loads and stores; the matrices
+// start and end at multiples of four, so a group of four lies inside one matrix or outside all
+// three), the rest one at a time (n4 = 0 when a buffer is not 16-byte aligned).
+__device__ __forceinline__ float adam_one(float &w, float &m, float &v, float g, float lr, float b1, float b2,
+                                          float eps, float c1, float c2) {
+    m = b1 * m + (1.f - b1) * g;
+    v = b2 * v + (1.f - b2) * g * g;
+    w = w - lr * (m * c1) / (sqrtf(v * c2) + eps);
+    return w;
+}
+__global__ void k_adam(size_t n, size_t n4, float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
                        const float *__restrict__ g, float lr, float b1, float b2, float eps, float c1, float c2,
                        Bf16Copies bc) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const float gi = g[i];
-        const float mi = b1 * m[i] + (1.f - b1) * gi;
-        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n4; q += stride) {
+        float4 wq = ((float4 *)w)[q], mq = ((float4 *)m)[q], vq = ((float4 *)v)[q];
+        const float4 gq = ((const float4 *)g)[q];
+        adam_one(wq.x, mq.x, vq.x, gq.x, lr, b1, b2, eps, c1, c2);
+        adam_one(wq.y, mq.y, vq.y, gq.y, lr, b1, b2, eps, c1, c2);
+        adam_one(wq.z, mq.z, vq.z, gq.z, lr, b1, b2, eps, c1, c2);
+        adam_one(wq.w, mq.w, vq.w, gq.w, lr, b1, b2, eps, c1, c2);
+        ((float4 *)w)[q] = wq;
+        ((float4 *)m)[q] = mq;
+        ((float4 *)v)[q] = vq;
+        const size_t i = 4 * q;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (i - bc.off[k] < bc.len[k])
+                *(uint2 *)(bc.dst[k] + (i - bc.off[k])) =
+                    make_uint2(f2bf(wq.x) | ((unsigned)f2bf(wq.y) << 16), f2bf(wq.z) | ((unsigned)f2bf(wq.w) << 16));
+    }
+    for (size_t i = 4 * n4 + blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+        float wi = w[i], mi = m[i], vi = v[i];
+        adam_one(wi, mi, vi, g[i], lr, b1, b2, eps, c1, c2);
+        w[i] = wi;
         m[i] = mi;
         v[i] = vi;
-        const float wi = w[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
-        w[i] = wi;
 #pragma unroll
         for (int k = 0; k < 3; ++k)
             if (i - bc.off[k] < bc.len[k]) bc.dst[k][i - bc.off[k]] = f2bf(wi);
@@ -676,8 +702,10 @@ bz_status bz_mlp_adam(bz_mlp n, void *d_params, const float *d_grad, int step, f
     const float c1 = 1.0f / (1.0f - std::pow(b1, (float)step)), c2 = 1.0f / (1.0f - std::pow(b2, (float)step));
     const size_t H = n->n_hid, O = n->n_out, I = n->n_in;
     const Bf16Copies bc{{n->oW1, n->oW2, n->oW3}, {H * I, H * H, O * H}, {pv.W1, pv.W2, pv.W3}};
-    hipLaunchKernelGGL(k_adam, dim3(grid1(n->n_params)), dim3(256), 0, s, n->n_params, pv.master, pv.m, pv.v, d_grad,
-                       lr, b1, b2, 1e-8f, c1, c2, bc);
+    const bool al = ((uintptr_t)d_grad | (uintptr_t)d_params) % 16 == 0;
+    const size_t n4 = al ? n->n_params / 4 : 0;
+    hipLaunchKernelGGL(k_adam, dim3(grid1(al ? n4 : n->n_params)), dim3(256), 0, s, n->n_params, n4, pv.master, pv.m,
+                       pv.v, d_grad, lr, b1, b2, 1e-8f, c1, c2, bc);
     BZ_HIP(hipGetLastError(), "bz_mlp_adam");
     BZ_HIP(refresh_transposes(n, pv, s), "bz_mlp_adam: transposed bf16 copies");
     return BZ_OK;
