@@ -55,20 +55,37 @@ __device__ inline unsigned short f2bf(float x) {
     return (unsigned short)(u >> 16);
 }
 
-// one block per cell
+// One block of kSurThreads per cell; every thread keeps its PER values of f (then f - M) in
+// registers, so f is read once and the Maxwellian evaluated once per point.
+constexpr int kSurThreads = 1024;
 template <int N>
-__global__ void __launch_bounds__(256) k_prepare(double dv, const double *__restrict__ f,
-                                                 const long long *__restrict__ f_off, double gate, double inv_s_in,
-                                                 int judge_every, int phase, const unsigned *__restrict__ stats,
-                                                 double *__restrict__ state, unsigned short *__restrict__ x) {
-    __shared__ double red[4];
-    const int c = blockIdx.x, M = N * N * N;
+__global__ void __launch_bounds__(kSurThreads) k_prepare(double dv, const double *__restrict__ f,
+                                                         const long long *__restrict__ f_off, double gate,
+                                                         double inv_s_in, int judge_every, int phase,
+                                                         const unsigned *__restrict__ stats,
+                                                         double *__restrict__ state, unsigned short *__restrict__ x) {
+    constexpr int M = N * N * N, PER = (M + kSurThreads - 1) / kSurThreads;
+    __shared__ double red[kSurThreads / 64];
+    const int c = blockIdx.x;
     const double *F = f + f_off[c];
     const double w = dv * dv * dv;
+    double fv[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int j = threadIdx.x + i * kSurThreads;
+        fv[i] = j < M ? F[j] : 0.0;
+    }
+    // each pass recomputes its indices and velocities from an opaque copy of the thread index,
+    // so that the compiler does not keep them live across the passes (and spill them)
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
-    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+    int t0 = threadIdx.x;
+    asm volatile("" : "+v"(t0));
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int j = t0 + i * kSurThreads;
+        if (j >= M) continue;
         const double v1 = dv * (j / (N * N) - N / 2), v2 = dv * ((j / N) % N - N / 2), v3 = dv * (j % N - N / 2);
-        const double q = F[j];
+        const double q = fv[i];
         s0 += q;
         s1 += v1 * q;
         s2 += v2 * q;
@@ -80,16 +97,18 @@ __global__ void __launch_bounds__(256) k_prepare(double dv, const double *__rest
     const double e = block_sum(s4, red) * w / rho;
     const double T = (e - (u1 * u1 + u2 * u2 + u3 * u3)) / 3.0;
     const double nrm = rho * pow(2.0 * M_PI * T, -1.5);
-    auto maxwell = [&](int j) {
+    double dd = 0, mm = 0;
+    int t1 = threadIdx.x;
+    asm volatile("" : "+v"(t1));
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int j = t1 + i * kSurThreads;
+        if (j >= M) continue;
         const double a = dv * (j / (N * N) - N / 2) - u1, b = dv * ((j / N) % N - N / 2) - u2,
                      cc = dv * (j % N - N / 2) - u3;
-        return nrm * exp(-(a * a + b * b + cc * cc) / (2.0 * T));
-    };
-    double dd = 0, mm = 0;
-    for (int j = threadIdx.x; j < M; j += blockDim.x) {
-        const double Mj = maxwell(j);
-        const double dj = F[j] - Mj;
-        dd += dj * dj;
+        const double Mj = nrm * exp(-(a * a + b * b + cc * cc) / (2.0 * T));
+        fv[i] -= Mj;   // f - M from here on
+        dd += fv[i] * fv[i];
         mm += Mj * Mj;
     }
     const double D2 = block_sum(dd, red), M2 = block_sum(mm, red);
@@ -97,8 +116,11 @@ __global__ void __launch_bounds__(256) k_prepare(double dv, const double *__rest
     // network input: the direction of f - M scaled to unit RMS, and in the corner entry
     // (v = (-L, -L, -L), where f - M is negligible) the amplitude d / s_in
     const double sx = D2 > 0 ? sqrt((double)M / D2) : 0.0;
-    for (int j = threadIdx.x; j < M; j += blockDim.x)
-        x[(size_t)c * M + j] = f2bf((float)(j == 0 ? d * inv_s_in : (F[j] - maxwell(j)) * sx));
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int j = threadIdx.x + i * kSurThreads;
+        if (j < M) x[(size_t)c * M + j] = f2bf((float)(j == 0 ? d * inv_s_in : fv[i] * sx));
+    }
     if (threadIdx.x == 0) {
         if (stats) {
             const unsigned long long cap = *(const unsigned long long *)(stats + kStCap);
@@ -179,11 +201,11 @@ __device__ inline void basis5(double dv, const Basis &li, int j, double e[5]) {
 
 // one block per cell: select the closure or the convolution, judge sampled cells
 template <int N>
-__global__ void __launch_bounds__(256) k_finish(double dv, Basis li, const double *__restrict__ state,
-                                                const float *__restrict__ y, double s_out, double floor_,
-                                                double tol, const long long *__restrict__ q_off,
-                                                double *__restrict__ q, unsigned *__restrict__ stats) {
-    __shared__ double red[4];
+__global__ void __launch_bounds__(kSurThreads) k_finish(double dv, Basis li, const double *__restrict__ state,
+                                                        const float *__restrict__ y, double s_out, double floor_,
+                                                        double tol, const long long *__restrict__ q_off,
+                                                        double *__restrict__ q, unsigned *__restrict__ stats) {
+    __shared__ double red[kSurThreads / 64];
     const int c = blockIdx.x, M = N * N * N;
     const double *st = state + (size_t)c * kState;
     const bool gated = st[6] != 0.0, judged = st[7] != 0.0;
@@ -275,8 +297,8 @@ hipError_t launch_sur_prepare(int N, double dv, int n, const double *f, const lo
                               double s_in, int judge_every, int phase, const unsigned *stats, double *state,
                               unsigned short *x, hipStream_t s) {
 #define BZ_PREP(NN)                                                                                             \
-    hipLaunchKernelGGL(k_prepare<NN>, dim3(n), dim3(256), 0, s, dv, f, f_off, gate, 1.0 / s_in, judge_every, \
-                       phase, stats, state, x)
+    hipLaunchKernelGGL(k_prepare<NN>, dim3(n), dim3(kSurThreads), 0, s, dv, f, f_off, gate, 1.0 / s_in,      \
+                       judge_every, phase, stats, state, x)
     BZ_SUR_FOR_N(BZ_PREP)
 #undef BZ_PREP
     return hipGetLastError();
@@ -294,8 +316,8 @@ hipError_t launch_sur_finish(int N, double dv, const double *linv, int n, const 
     Basis li;
     for (int i = 0; i < 25; ++i) li.a[i] = linv[i];
 #define BZ_FIN(NN)                                                                                              \
-    hipLaunchKernelGGL(k_finish<NN>, dim3(n), dim3(256), 0, s, dv, li, state, y, s_out, floor_, tol, q_off, q, \
-                       stats)
+    hipLaunchKernelGGL(k_finish<NN>, dim3(n), dim3(kSurThreads), 0, s, dv, li, state, y, s_out, floor_, tol,  \
+                       q_off, q, stats)
     BZ_SUR_FOR_N(BZ_FIN)
 #undef BZ_FIN
     hipLaunchKernelGGL(k_judge_close, dim3(1), dim3(64), 0, s, stats);
