@@ -90,6 +90,40 @@ def test_adam_step_matches_oracle(dev):
     bz.bz_mlp_free(n)
 
 
+
+def test_unaligned_buffers_give_the_same_results(dev):
+    """The transposes and Adam use 16-byte accesses on 16-byte aligned buffers and an
+    element-wise path otherwise: an input or gradient buffer one element off alignment must
+    give bitwise the same gradients, parameters and BF16 weight copies."""
+    n_in, n_h, n_out, B = 64, 96, 64, 64
+    rng = np.random.default_rng(7)
+    X = rng.standard_normal((B, n_in))
+    T = rng.standard_normal((B, n_out))
+    xb = torch.from_numpy(to_bf16_bits(X).view(np.int16)).to(dev)
+    x_off = torch.zeros(B * n_in + 1, dtype=torch.int16, device=dev)[1:].view(B, n_in)
+    x_off.copy_(xb)
+    assert x_off.data_ptr() % 16 != 0
+    t = torch.from_numpy(T.astype(np.float32)).to(dev)
+    runs = []
+    for x, off in ((xb, False), (x_off, True)):
+        n, params, work, _ = setup(n_in, n_h, n_out, B, 8, dev)
+        P = bz.bz_mlp_param_count(n)
+        grad = torch.zeros(P + 1, dtype=torch.float32, device=dev)[1:] if off else \
+            torch.zeros(P, dtype=torch.float32, device=dev)
+        assert (grad.data_ptr() % 16 != 0) == off
+        loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        for step in (1, 2):
+            bz.bz_mlp_backward(n, params, x, t, B, grad, loss, work)
+            bz.bz_mlp_adam(n, params, grad, step, 1e-3)
+        y = torch.zeros(B, n_out, dtype=torch.float32, device=dev)
+        bz.bz_mlp_forward(n, params, x, B, y, work)
+        runs.append((grad.clone(), bz.bz_mlp_get_params(n, params), y.clone()))
+        bz.bz_mlp_free(n)
+    (g0, p0, y0), (g1, p1, y1) = runs
+    assert torch.equal(g0, g1)
+    assert np.array_equal(p0, p1)
+    assert torch.equal(y0, y1)   # the forward reads the BF16 copies Adam wrote
+
 def test_training_reduces_loss(dev):
     n_in, n_h, n_out, B = 128, 128, 64, 64
     n, params, work, p = setup(n_in, n_h, n_out, B, 6, dev)
