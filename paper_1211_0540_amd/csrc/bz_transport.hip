@@ -35,18 +35,20 @@ __device__ inline double minmod(double a, double b) {
     return a * b > 0.0 ? (a > 0.0 ? fmin(a, b) : fmax(a, b)) : 0.0;
 }
 
-// sigma_w = sum_{v1 < 0} |v1| f_0 dv^3 / in_norm, one block, fixed reduction order.
-// N is a template parameter so that the loop has a fixed trip count and its loads are issued together
+// sigma_w = sum_{v1 < 0} |v1| f_0 dv^3 / in_norm, one block of 1024 threads over the half of the
+// wall cell with v1 < 0, fixed reduction order.  N is a template parameter so that the loop has
+// a fixed trip count and its loads are issued together
 template <int N>
-__global__ void __launch_bounds__(256) k_wall_sigma(double dv, const double *__restrict__ f0, double in_norm,
-                                                    double *__restrict__ sigma) {
-    __shared__ double red[4];
-    constexpr int M = N * N * N;
+__global__ void __launch_bounds__(1024) k_wall_sigma(double dv, const double *__restrict__ f0, double in_norm,
+                                                     double *__restrict__ sigma) {
+    __shared__ double red[16];
+    // v1 < 0 exactly on the first half of the cell (k1 < N/2)
+    constexpr int H = N * N * N / 2;
     double s = 0.0;
-#pragma unroll 8
-    for (int k = threadIdx.x; k < M; k += 256) {
+#pragma unroll 4
+    for (int k = threadIdx.x; k < H; k += 1024) {
         const double v1 = dv * (k / (N * N) - N / 2);
-        if (v1 < 0.0) s = fma(-v1, f0[k], s);
+        s = fma(-v1, f0[k], s);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
@@ -116,10 +118,10 @@ static hipError_t transport_rk2_n(const bz_transport_s *t, double *f, double dt,
     const double dv = 2.0 * t->L / N;
     const size_t n = (size_t)t->nx * M;
     const unsigned blocks = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_wall_sigma<N>, dim3(1), dim3(256), 0, s, dv, f, t->in_norm, sigma);
+    hipLaunchKernelGGL(k_wall_sigma<N>, dim3(1), dim3(1024), 0, s, dv, f, t->in_norm, sigma);
     hipLaunchKernelGGL(k_transport_stage<N>, dim3(blocks), dim3(256), 0, s, t->nx, dv, t->d_dx, dt, f, f, 0.0, 1.0,
                        t->d_tab, sigma, fs);
-    hipLaunchKernelGGL(k_wall_sigma<N>, dim3(1), dim3(256), 0, s, dv, fs, t->in_norm, sigma);
+    hipLaunchKernelGGL(k_wall_sigma<N>, dim3(1), dim3(1024), 0, s, dv, fs, t->in_norm, sigma);
     // each thread reads f and fs at its own index only for the base term, so f may be the output
     hipLaunchKernelGGL(k_transport_stage<N>, dim3(blocks), dim3(256), 0, s, t->nx, dv, t->d_dx, dt, fs, f, 0.5, 0.5,
                        t->d_tab, sigma, f);
