@@ -36,14 +36,103 @@ __device__ inline double wave_sum(double x) {
     return x;
 }
 
-// One block of kProjThreads threads per cell.  Thread t owns the values j = t + i kProjThreads,
+// Two layouts of the cell over a block's threads, both keeping every value in registers through
+// both passes (the cell is read and written once).
+// N <= 24: one block per cell, N^2 threads rounded up to whole wavefronts: thread t < N^2 owns
+// the column (j2, j3) = (t / N, t % N), its N values j = t + N^2 j1, so v2 and v3 are fixed per
+// thread and v1 = dv (j1 - N/2) needs no index arithmetic; the threads past N^2 hold zeros.
+// Smaller blocks also let a CU hold several cells, whose phases (loads, reductions, stores)
+// then overlap: 16 against 36 us at N=16 and 36 against 45 us at N=24 for the flat layout
+// below.  From N = 28 on, N values per thread no longer fit the registers of the wider block
+// without spilling, and the flat layout is faster.
+constexpr int kProjThreads = 1024;
+template <int N>
+constexpr int proj_threads() {
+    return (N * N + 63) / 64 * 64;
+}
+template <int N>
+__global__ void __launch_bounds__(proj_threads<N>()) k_project_cols(double dv, Linv li, double *__restrict__ q,
+                                                               const long long *__restrict__ off) {
+    constexpr int P = N * N;
+    static_assert(proj_threads<N>() <= kProjThreads, "one thread per column");
+    __shared__ double red[kProjThreads / 64][5];
+    __shared__ double nu[5];
+    double *Q = q + off[blockIdx.x];
+    const int t = threadIdx.x, wid = t >> 6, lane = t & 63;
+    const bool own = t < P;
+    const double v2 = dv * (t / N - N / 2), v3 = dv * (t % N - N / 2), r23 = v2 * v2 + v3 * v3;
+    double x[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = own ? Q[t + P * i] : 0.0;
+    const double w = dv * dv * dv;
+    for (int pass = 0; pass < 2; ++pass) {
+        // dv and each v1 through an empty asm, so that the N values of v1 (and v1^2) are
+        // computed one at a time where they are used rather than kept live together
+        double s[5] = {0, 0, 0, 0, 0};
+        double dva = dv;
+        asm volatile("" : "+v"(dva));
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            double v1 = dva * (i - N / 2);
+            asm volatile("" : "+v"(v1));
+            s[0] += x[i];
+            s[1] = fma(v1, x[i], s[1]);
+            s[2] = fma(v2, x[i], s[2]);
+            s[3] = fma(v3, x[i], s[3]);
+            s[4] = fma(fma(v1, v1, r23), x[i], s[4]);
+        }
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            double u = wave_sum(s[a]);
+            if (lane == 0) red[wid][a] = u;
+        }
+        __syncthreads();
+        if (t == 0) {
+            double tt[5], m[5];
+            for (int b = 0; b < 5; ++b) {
+                double u = 0.0;
+                for (int v = 0; v < (int)(blockDim.x >> 6); ++v) u += red[v][b];
+                tt[b] = u * w;   // C Qt
+            }
+            for (int a = 0; a < 5; ++a) {   // mu = L^{-1} C Qt
+                double u = 0.0;
+                for (int b = 0; b <= a; ++b) u = fma(li.a[a * 5 + b], tt[b], u);
+                m[a] = u;
+            }
+            for (int b = 0; b < 5; ++b) {   // nu = L^{-T} mu, dv^3 folded in
+                double u = 0.0;
+                for (int a = b; a < 5; ++a) u = fma(li.a[a * 5 + b], m[a], u);
+                nu[b] = u * w;
+            }
+        }
+        __syncthreads();
+        // (the threads past N^2 keep their zeros for the second pass's sums)
+        const double c0 = fma(nu[3], v3, fma(nu[2], v2, nu[0]));
+        double dvb = dv;
+        asm volatile("" : "+v"(dvb));
+        if (own) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                double v1 = dvb * (i - N / 2);
+                asm volatile("" : "+v"(v1));
+                x[i] -= fma(nu[4], fma(v1, v1, r23), fma(nu[1], v1, c0));
+            }
+        }
+        __syncthreads();
+    }
+    if (own) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) Q[t + P * i] = x[i];
+    }
+}
+
+// N >= 28: one block of kProjThreads threads per cell.  Thread t owns the values j = t + i kProjThreads,
 // i < PER = ceil(N^3 / kProjThreads), and keeps them in registers through both passes, so the
 // cell is read and written once.  Indices and velocities are recomputed in every loop (the
 // empty asm hides the thread index from common-subexpression elimination, which would otherwise
 // keep PER indices and 3 PER velocities live across the passes and spill them).
-constexpr int kProjThreads = 1024;
 template <int N>
-__global__ void __launch_bounds__(kProjThreads) k_project(double dv, Linv li, double *__restrict__ q,
+__global__ void __launch_bounds__(kProjThreads) k_project_flat(double dv, Linv li, double *__restrict__ q,
                                                           const long long *__restrict__ off) {
     constexpr int M = N * N * N, PER = (M + kProjThreads - 1) / kProjThreads;
     __shared__ double red[kProjThreads / 64][5];
@@ -311,6 +400,15 @@ __global__ void __launch_bounds__(256) k_expand_plain(int N, const double *__res
 
 }  // namespace
 
+
+template <int N>
+static void project_launch(int ncells, double dv, const Linv &li, double *q, const long long *d_off, hipStream_t s) {
+    if constexpr (N <= 24)
+        hipLaunchKernelGGL(k_project_cols<N>, dim3(ncells), dim3(proj_threads<N>()), 0, s, dv, li, q, d_off);
+    else
+        hipLaunchKernelGGL(k_project_flat<N>, dim3(ncells), dim3(kProjThreads), 0, s, dv, li, q, d_off);
+}
+
 hipError_t launch_project(int N, double dv, const double *linv, int ncells, double *q, const long long *d_off,
                           hipStream_t s) {
     if (ncells <= 0) return hipSuccess;
@@ -318,7 +416,7 @@ hipError_t launch_project(int N, double dv, const double *linv, int ncells, doub
     for (int i = 0; i < 25; ++i) li.a[i] = linv[i];
     switch (N) {
 #define BZ_PROJ(n) \
-    case n: hipLaunchKernelGGL(k_project<n>, dim3(ncells), dim3(kProjThreads), 0, s, dv, li, q, d_off); break;
+    case n: project_launch<n>(ncells, dv, li, q, d_off, s); break;
         BZ_PROJ(8) BZ_PROJ(12) BZ_PROJ(16) BZ_PROJ(20) BZ_PROJ(24) BZ_PROJ(28) BZ_PROJ(32)
 #undef BZ_PROJ
     default: return hipErrorInvalidValue;
