@@ -13,8 +13,8 @@
 // width dx_0 copy cell 0 (slope 0 there); the wall face flux is v1 sigma_w M_w for
 // v1 > 0 and v1 f_0 for v1 < 0 with sigma_w = sum_{v1<0}|v1| f_0 / sum_{v1>0} v1 M_w,
 // so the net wall mass flux is zero.  Right end: ghosts of width dx_{nx-1} hold M_far.
-// Memory-bound (5 reads + 1-2 reads + 1 write of 8 bytes per (cell, velocity));
-// negligible next to the collision step.
+// Memory-bound (a window of 12 stencil reads per 8 cells of one velocity, the base term and
+// one write of 8 bytes per (cell, velocity)); small next to the collision step.
 #include <cmath>
 #include <new>
 #include <vector>
