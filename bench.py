@@ -385,6 +385,48 @@ def served_errors(torch, np, bz, col, desc, f, work, N):
             "judge_tol": desc.judge_tol}
 
 
+def closure_profile_run(args, N=24, L=7.0):
+    """Strang steps of the 256-cell N=24 shock problem with the gated closure (gate 0.05, one
+    group in 16 judged) after a short harvest (60 shock snapshots) and 300 training steps, then
+    the same number of plain steps: one JSON line with both step times, for profiler runs.  The
+    served fraction, and so the step time, depends on the training; the bench's closure leg
+    trains the network fully."""
+    import torch
+    from paper_1211_0540_amd import bz
+    from paper_1211_0540_amd import workloads as W
+    from paper_1211_0540_amd.closure import ClosureModel
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    lam, nx, eps = 1.0, 256, 0.1
+    m = ClosureModel(N, L, lam, hidden=1024, seed=1211)
+    m.harvest_shock(snapshots=60, every=1, keep=0.1)
+    m.fit(steps=300, batch=512, lr=1e-3)
+    m.release_data()
+    dt = 0.5 / nx / L
+    f0 = torch.from_numpy(W.shock_initial(nx, N, L).ravel().copy()).cuda()
+    c = bz.Collision([(N, L, lam)], [0] * nx, "batched_f32", weights_cache=m.wcache)
+    cf = bz.Collision([(N, L, lam)], [0] * nx, "batched_f32", weights_cache=m.wcache, fine_split=True)
+    t = bz.bz_transport_create(c.grids[0], nx, 1.0, 2.0, 1.0, 0.0, 1.0)
+    d = m.desc(gate=0.05, judge_every=16)
+    work = torch.zeros(bz.bz_closure_workspace_bytes(cf.batch, d) + bz.bz_transport_workspace_bytes(t) + 256,
+                       dtype=torch.uint8, device="cuda")
+    f, g = f0.clone(), f0.clone()
+    for _ in range(args.warmup):
+        bz.bz_closure_strang_step(cf.batch, t, d, f, dt, eps, work)
+        c.strang_step(t, dt, eps, g)
+    total_c, _ = timed_steps(torch, lambda: bz.bz_closure_strang_step(cf.batch, t, d, f, dt, eps, work), args.steps)
+    total_p, _ = timed_steps(torch, lambda: c.strang_step(t, dt, eps, g), args.steps)
+    st = bz.bz_closure_read_stats(cf.batch, d, work)
+    evals = 2 * nx * (args.steps + args.warmup)
+    print(json.dumps({"profile_closure": True, "cells": nx, "N": N, "closure_ms_per_step": total_c / args.steps,
+                      "plain_ms_per_step": total_p / args.steps, "served_fraction": st["served"] / evals,
+                      "judged": st["judged"], "judge_failed": st["failed"]}), flush=True)
+    bz.bz_transport_free(t)
+    c.close()
+    cf.close()
+    return 0
+
+
 def uneven_profile_run(args):
     """Heun steps of the 1024-cell uneven batch only (one persistent convolution launch per
     evaluation for all three meshes and their cores): one JSON line with the step and the
@@ -498,6 +540,9 @@ def main():
                     help="timed steps only (default launch configuration, no comparisons, no CPU leg)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
+    ap.add_argument("--profile-closure", action="store_true",
+                    help="only Strang steps of the 256-cell N=24 shock problem with the gated closure, after a "
+                         "short harvest and training, for kernel traces")
     ap.add_argument("--profile-uneven", action="store_true",
                     help="only timed Heun steps of the 1024-cell uneven batch (N = 16, 24, 32) in the default "
                          "launch form, for kernel traces and counters")
@@ -513,6 +558,8 @@ def main():
         return mlp_profile_run(args)
     if args.profile_uneven:
         return uneven_profile_run(args)
+    if args.profile_closure:
+        return closure_profile_run(args)
 
     import numpy as np
     import torch
