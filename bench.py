@@ -75,6 +75,20 @@ def measured_traffic(cells):
     return d.get("traffic_bytes_per_launch")
 
 
+def measured_valu_insts(cells):
+    """Wavefront VALU instructions per launch of the same kernel (rocprofv3 --pmc SQ_INSTS_VALU
+    pass of `bench.py --profile-run`) from the same committed summary, under the same
+    conditions as measured_traffic."""
+    try:
+        with open(os.path.join(ROOT, TRAFFIC_FILE)) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_src_sha") != conv_source_sha() or d.get("cells") != cells:
+        return None
+    return d.get("sq_insts_valu_per_launch")
+
+
 def core_products(N, r2):
     """Complex products per cell and evaluation of the FP64 core (r2 = 0: none): for every
     output row (k1, k2) within 2r of the centre, the pairs of disk rows m <= j with
@@ -734,6 +748,7 @@ def main():
                          f"inverse, projection), {el:.1f} s"}
 
     traffic = measured_traffic(nc)
+    valu = measured_valu_insts(nc)
     kernel = "k_conv_cells_f32_multi (FP32 items + FP64 core items)" if one_launch else "k_conv_cells_f32<32>"
     out = {
         "metric": METRIC,
@@ -766,9 +781,13 @@ def main():
                      "frac_incl_fp64_core": (fp32_flops + core_flops) / (conv_avg_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
                      "effective_tflops": 10.0 * P * nc / (conv_avg_ms * 1e-3) / 1e12,
                      "traffic_gb_per_s": (traffic / (conv_avg_ms * 1e-3) / 1e9) if traffic else None,
-                     "hbm_peak_gb_per_s": HBM_TBPS * 1e3},
+                     "hbm_peak_gb_per_s": HBM_TBPS * 1e3,
+                     "valu_insts_per_launch": valu,
+                     # one wave64 VALU instruction per SIMD every 4 cycles (1024 SIMDs): the mean shader
+                     # clock the launch needs at least to issue them in its measured time
+                     "valu_issue_clock_ghz_min": (valu / 1024 * 4 / (conv_avg_ms * 1e-3) / 1e9) if valu else None},
         "cpu_baseline": cpu,
-        "gpu_clock_after_run": gpu_clocks(),
+        "gpu_clock_idle_after_run": gpu_clocks(),
         "comparisons": comp,
     }
     print(json.dumps(out), flush=True)
